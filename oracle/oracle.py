@@ -1,0 +1,162 @@
+"""ctypes front end of the plain FP64 CPU oracle (test infrastructure only).
+
+The arithmetic lives in ``tmx_oracle.c`` (plain loops, FP64, OpenMP over
+sites) and ``nn_oracle.py`` (the learned preconditioner).  This module only
+marshals numpy arrays.  It must never be imported by the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tmx_oracle.c")
+_LIB = os.path.join(_HERE, "libtmx_oracle.so")
+_lib = None
+
+
+def build_oracle(force: bool = True) -> str:
+    """Compile the C oracle with gcc (-O2, IEEE arithmetic, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas",
+             "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def load_library():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build_oracle(force=True)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    D = ctypes.c_double
+    L = ctypes.c_long
+    lib.orc_gammas.argtypes = [P, P]
+    lib.orc_hop.argtypes = [P, I, P, P, P, I, I]
+    lib.orc_clover.argtypes = [P, P, D, D, P]
+    lib.orc_site_block.argtypes = [P, L, D, D, D, D, I, P]
+    lib.orc_apply_D.argtypes = [P, I, P, P, D, D, D, D, I, P, P]
+    lib.orc_mhat.argtypes = [P, I, P, P, D, D, D, D, I, I, P, P]
+    lib.orc_mhat.restype = I
+    lib.orc_mhat_dag.argtypes = [P, I, P, P, D, D, D, D, I, I, P, P]
+    lib.orc_mhat_dag.restype = I
+    lib.orc_mdagm.argtypes = [P, I, P, P, D, D, D, D, I, I, D, P, P]
+    lib.orc_mdagm.restype = I
+    lib.orc_cg.argtypes = [P, I, P, P, D, D, D, D, I, I, D, P, P, D, I, ctypes.POINTER(D)]
+    lib.orc_cg.restype = I
+    lib.orc_residual.argtypes = [P, I, P, P, D, D, D, D, I, I, D, P, P]
+    lib.orc_residual.restype = D
+    lib.orc_residual_mhat.argtypes = [P, I, P, P, D, D, D, D, I, I, I, P, P]
+    lib.orc_residual_mhat.restype = D
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+class Oracle:
+    """FP64 oracle of one gauge field and parameter set.
+
+    dims = (Lx, Ly, Lz, Lt); U in the layout of ``synth.gauge_links``.
+    Parameters are the bare ones (kappa, csw, mu, mubar, epsbar); the hopping
+    normalisation factors 2*kappa are applied inside the oracle.
+    """
+
+    def __init__(self, dims, U, kappa, csw, mu=0.0, mubar=0.0, epsbar=0.0, t_bc=-1, T=None):
+        self.lib = load_library()
+        self.dims = tuple(int(d) for d in dims)
+        self.L = np.asarray(self.dims, dtype=np.int32)
+        self.V = int(np.prod(self.dims))
+        self.Vh = self.V // 2
+        self.U = _c(U).reshape(self.V, 4, 3, 3)
+        self.kappa, self.csw = float(kappa), float(csw)
+        self.mu, self.mubar, self.epsbar = float(mu), float(mubar), float(epsbar)
+        self.t_bc = int(t_bc)
+        if T is None:
+            T = np.empty((self.V, 12, 12), dtype=np.complex128)
+            self.lib.orc_clover(_ptr(self.L), _ptr(self.U), self.kappa, self.csw, _ptr(T))
+        self.T = _c(T).reshape(self.V, 12, 12)
+
+    # -- pieces --------------------------------------------------------
+    @staticmethod
+    def gammas():
+        lib = load_library()
+        g = np.empty((5, 4, 4), dtype=np.complex128)
+        s = np.empty((4, 4, 4, 4), dtype=np.complex128)
+        lib.orc_gammas(_ptr(g), _ptr(s))
+        return g, s
+
+    def hop(self, psi, out_parity=-1):
+        psi = _c(psi)
+        nf = psi.size // (12 * self.V)
+        out = np.empty_like(psi)
+        self.lib.orc_hop(_ptr(self.L), self.t_bc, _ptr(self.U), _ptr(psi), _ptr(out), nf, out_parity)
+        return out
+
+    def site_block(self, lex, nf=1, sgn=1):
+        n = 12 * nf
+        B = np.empty((n, n), dtype=np.complex128)
+        self.lib.orc_site_block(_ptr(self.T), int(lex), self.kappa, sgn * self.mu, sgn * self.mubar,
+                                self.epsbar, nf, _ptr(B))
+        return B
+
+    # -- operators -----------------------------------------------------
+    def D(self, psi, nf=1, sgn=1):
+        psi = _c(psi)
+        out = np.empty_like(psi)
+        self.lib.orc_apply_D(_ptr(self.L), self.t_bc, _ptr(self.U), _ptr(self.T), self.kappa, sgn * self.mu,
+                             sgn * self.mubar, self.epsbar, nf, _ptr(psi), _ptr(out))
+        return out
+
+    def mhat(self, v, nf=1, sgn=1, dagger=False):
+        v = _c(v)
+        out = np.empty_like(v)
+        fn = self.lib.orc_mhat_dag if dagger else self.lib.orc_mhat
+        bad = fn(_ptr(self.L), self.t_bc, _ptr(self.U), _ptr(self.T), self.kappa, self.mu, self.mubar,
+                 self.epsbar, nf, sgn, _ptr(v), _ptr(out))
+        if bad:
+            raise FloatingPointError("singular site block")
+        return out
+
+    def mdagm(self, v, nf=1, sgn=1, shift=0.0):
+        v = _c(v)
+        out = np.empty_like(v)
+        bad = self.lib.orc_mdagm(_ptr(self.L), self.t_bc, _ptr(self.U), _ptr(self.T), self.kappa, self.mu,
+                                 self.mubar, self.epsbar, nf, sgn, float(shift), _ptr(v), _ptr(out))
+        if bad:
+            raise FloatingPointError("singular site block")
+        return out
+
+    def cg(self, b, nf=1, sgn=1, shift=0.0, tol=1e-10, maxiter=10000):
+        b = _c(b)
+        x = np.empty_like(b)
+        rel = ctypes.c_double(0)
+        it = self.lib.orc_cg(_ptr(self.L), self.t_bc, _ptr(self.U), _ptr(self.T), self.kappa, self.mu,
+                             self.mubar, self.epsbar, nf, sgn, float(shift), _ptr(b), _ptr(x), float(tol),
+                             int(maxiter), ctypes.byref(rel))
+        return x, it, rel.value
+
+    def residual(self, b, x, nf=1, sgn=1, shift=0.0):
+        b, x = _c(b), _c(x)
+        return self.lib.orc_residual(_ptr(self.L), self.t_bc, _ptr(self.U), _ptr(self.T), self.kappa, self.mu,
+                                     self.mubar, self.epsbar, nf, sgn, float(shift), _ptr(b), _ptr(x))
+
+    def residual_mhat(self, b, x, nf=1, sgn=1, dagger=False):
+        b, x = _c(b), _c(x)
+        return self.lib.orc_residual_mhat(_ptr(self.L), self.t_bc, _ptr(self.U), _ptr(self.T), self.kappa,
+                                          self.mu, self.mubar, self.epsbar, nf, sgn, int(bool(dagger)),
+                                          _ptr(b), _ptr(x))
