@@ -1,0 +1,226 @@
+/*
+ * tmx -- even-odd preconditioned Wilson twisted-mass clover operator and its
+ * solvers on AMD MI355X (gfx950).  Plain C ABI.
+ *
+ * Operators (Section 2 of arXiv:2212.06635, "Even-odd and mass-preconditioned
+ * Dirac operators"):
+ *
+ *   full operator   D     = 1 + T + i nu gamma5 - kappa H,   nu = 2 kappa mu
+ *                   (the M_clov + i mu gamma5 inside Q^{+-} = gamma5 D(+-mu),
+ *                   hopping normalisation)
+ *   two flavours    D_h   = (1 + T) + i nubar gamma5 tau3 - epst tau1 - kappa H,
+ *                   nubar = 2 kappa mubar, epst = 2 kappa epsbar
+ *   Schur (odd)     Mhat  = A_oo - kappa^2 H_oe A_ee^{-1} H_eo
+ *                   (the bracket of the Q-hat^{+-} and Q-hat_h equations, with
+ *                   asymmetric odd-odd preconditioning; Q-hat = gamma5 Mhat)
+ *   normal          N     = Mhat^dagger Mhat = gamma5 Mhat(-mu) gamma5 Mhat(mu)
+ *
+ * H is the Wilson hopping term
+ *   (H psi)(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu)
+ * with periodic x,y,z and a factor t_bc on hops across the time boundary;
+ * T = i kappa csw sum_{mu<nu} sigma_{mu nu} F_{mu nu} is the clover term with
+ * the four-leaf field strength F = (Q - Q^+)/8.  The gamma matrices are in a
+ * chiral basis (gamma_k = [[0,-i s_k],[i s_k,0]], gamma_4 = [[0,1],[1,0]],
+ * gamma5 = diag(1,1,-1,-1)); callers that use another basis convert at the
+ * boundary.
+ *
+ * Canonical (host-facing) layouts, all complex128 = two doubles (re, im):
+ *   links      [t][z][y][x][mu 4][row 3][col 3]
+ *   full spinor[t][z][y][x][flavour nf][spin 4][colour 3]
+ *   odd spinor [cb][flavour][spin][colour] over the odd sites, cb = lex/2,
+ *              lex = x + Lx*(y + Ly*(z + Lz*t)), parity = (x+y+z+t) mod 2.
+ * Internal layouts (what the apply calls take) are opaque, precision-typed
+ * device buffers of tmx_field_bytes() bytes; tmx_pack / tmx_unpack convert.
+ *
+ * Errors: 0 = TMX_OK; negative = error (the call had no effect on its
+ * outputs; tmx_last_error() describes it); TMX_ENOCONV (+1) = a solver hit
+ * maxiter or stagnated: x holds its best iterate and info the residual.
+ * Nothing aborts or exits.  A context is not thread-safe.  Applies and
+ * pack/unpack are asynchronous on the context's stream; solves synchronise
+ * (the host takes the convergence decisions).
+ */
+#ifndef TMX_H
+#define TMX_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tmx_ctx tmx_ctx;
+
+enum {
+    TMX_OK = 0,
+    TMX_ENOCONV = 1,
+    TMX_EINVAL = -1,
+    TMX_ENOTLOADED = -2,
+    TMX_ENOMEM = -3,
+    TMX_EHIP = -4
+};
+
+/* storage / arithmetic precision of an apply.  F16 stores IEEE binary16
+ * with one FP32 scale per site and computes in FP32. */
+enum { TMX_F64 = 0, TMX_F32 = 1, TMX_F16 = 2 };
+
+/* operator selector: degenerate with +mu / -mu, or the two-flavour operator */
+enum { TMX_OP_PLUS = 1, TMX_OP_MINUS = -1, TMX_OP_ND = 2 };
+
+/* field kinds for tmx_field_bytes / tmx_pack / tmx_unpack */
+enum {
+    TMX_FIELD_ODD = 0,  /* one-flavour odd-site spinor */
+    TMX_FIELD_ODD_ND = 1,  /* two-flavour odd-site spinor */
+    TMX_FIELD_FULL = 2, /* one-flavour full-lattice spinor */
+    TMX_FIELD_FULL_ND = 3  /* two-flavour full-lattice spinor */
+};
+
+typedef struct {
+    double kappa;  /* hopping parameter */
+    double csw;    /* clover coefficient */
+    double mu;     /* bare light twisted mass (nu = 2 kappa mu) */
+    double mubar;  /* two-flavour twisted mass (nubar = 2 kappa mubar) */
+    double epsbar; /* two-flavour mass splitting (epst = 2 kappa epsbar) */
+    int t_bc;      /* +1 periodic, -1 antiperiodic fermion time boundary */
+} tmx_params;
+
+/* solver kinds */
+enum {
+    TMX_SOLVER_CG = 0,      /* plain FP64 CG on N */
+    TMX_SOLVER_MPCG_F32 = 1,/* CG with FP32 inner iterations, FP64 reliable updates */
+    TMX_SOLVER_MPCG_F16 = 2,/* CG with FP16-storage inner iterations, FP64 reliable updates */
+    TMX_SOLVER_FGCR_NN = 3  /* flexible GCR preconditioned by the learned network, CG fallback */
+};
+
+typedef struct {
+    int kind;           /* TMX_SOLVER_* */
+    int op;             /* TMX_OP_PLUS / TMX_OP_MINUS / TMX_OP_ND */
+    double tol;         /* relative 2-norm of the FP64 true residual, e.g. 1e-10 */
+    int maxiter;        /* iteration cap (per stage) */
+    double delta;       /* reliable-update trigger (0 => 0.1) */
+    int restart;        /* FGCR restart length m (0 => 16) */
+    int use_initial_guess; /* 1: x holds the start vector on entry */
+    double inner_tol;   /* multishift: low-precision stage tolerance (0 => 1e-6 / 5e-4) */
+    int inner_prec;     /* multishift / FGCR inner precision TMX_F32 or TMX_F16 (default F32) */
+} tmx_solver_cfg;
+
+typedef struct {
+    int iters;          /* iterations (operator applications of N or Mhat) */
+    int reliable_updates;
+    int restarts;       /* FGCR restarts or fallbacks */
+    int fallback;       /* 1 if FGCR fell back to CG */
+    double true_residual; /* |b - A x| / |b| recomputed in FP64 at the end */
+    double seconds;     /* wall time of the call */
+    double gbytes;      /* model bytes moved by operator applications */
+} tmx_info;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context for an Lx*Ly*Lz*Lt lattice (dims = {Lx,Ly,Lz,Lt}, each
+ * even and >= 2, volume <= 2^31).  All device work is enqueued on
+ * `hip_stream` (a hipStream_t; NULL = the default stream).  The context owns
+ * its device buffers; the caller owns every pointer it passes in. */
+int tmx_create(const int dims[4], void *hip_stream, tmx_ctx **out);
+int tmx_destroy(tmx_ctx *ctx);
+const char *tmx_last_error(const tmx_ctx *ctx);
+/* Change the stream subsequent work is enqueued on. */
+int tmx_set_stream(tmx_ctx *ctx, void *hip_stream);
+
+/* Parameters.  Changing mu / mubar / epsbar invalidates only the site-block
+ * inverses; changing kappa or csw also invalidates the clover term. */
+int tmx_set_params(tmx_ctx *ctx, const tmx_params *p);
+
+/* Upload a gauge field from host memory (canonical layout, complex128,
+ * copied; the caller keeps ownership).  `gauge_id` labels the field (its
+ * position along a trajectory or a configuration number, as the paper's
+ * gauge-state tracking does): a call with the id already loaded is a no-op;
+ * a new id invalidates the clover term and its inverses, which are rebuilt
+ * lazily on the next use.  Links must be SU(3) (rows 0,1 are stored, row 2
+ * is reconstructed as conj(row0 x row1)). */
+int tmx_load_gauge(tmx_ctx *ctx, const double *host_links, double gauge_id);
+/* Number of host->device gauge uploads performed so far (state tracking). */
+int tmx_gauge_uploads(const tmx_ctx *ctx);
+
+/* Clover term T.  host_T == NULL: build it on the device from the links.
+ * Otherwise host_T is [lex][chirality 2][6][6] complex128 Hermitian blocks
+ * (row/col index = 3*(spin mod 2) + colour within the chirality block);
+ * non-Hermitian input (> 1e-12) returns TMX_EINVAL. */
+int tmx_load_clover(tmx_ctx *ctx, const double *host_T);
+/* Copy the device clover term back as [lex][2][6][6] complex128 (host). */
+int tmx_get_clover(tmx_ctx *ctx, double *host_T);
+
+/* ---- layout conversion ------------------------------------------------- */
+
+/* Bytes of one internal field of `kind` in precision `prec`. */
+int tmx_field_bytes(const tmx_ctx *ctx, int kind, int prec, size_t *bytes);
+/* canonical (device, complex128) -> internal (device, prec); nvec fields,
+ * each contiguous at a stride of one field. */
+int tmx_pack(tmx_ctx *ctx, void *internal, const double *canonical, int kind, int prec, int nvec);
+int tmx_unpack(tmx_ctx *ctx, double *canonical, const void *internal, int kind, int prec, int nvec);
+
+/* ---- operators (device buffers, internal layout, asynchronous) -------- */
+
+/* out = D in (full lattice).  op selects +mu, -mu or the two-flavour
+ * operator; fields are TMX_FIELD_FULL (or _FULL_ND for op = TMX_OP_ND). */
+int tmx_apply_D(tmx_ctx *ctx, void *out, const void *in, int op, int prec);
+/* out = Mhat in or Mhat^dagger in on odd fields (nrhs fields side by side
+ * in the multi-vector layout of tmx_pack with nvec = nrhs). */
+int tmx_apply_mhat(tmx_ctx *ctx, void *out, const void *in, int op, int prec, int dagger, int nrhs);
+/* out = N in = Mhat^dagger Mhat in. */
+int tmx_apply_mdagm(tmx_ctx *ctx, void *out, const void *in, int op, int prec, int nrhs);
+
+/* ---- solvers (device buffers, canonical complex128 odd fields) -------- */
+
+/* Solve N x = b (cfg->op selects the operator) for nrhs right-hand sides
+ * stored contiguously; info is an array of nrhs entries (may be NULL).
+ * Returns TMX_ENOCONV if any column missed cfg->tol. */
+int tmx_solve(tmx_ctx *ctx, double *x, const double *b, int nrhs, const tmx_solver_cfg *cfg, tmx_info *info);
+/* Solve Mhat x = b (dagger = 0) or Mhat^dagger x = b (dagger = 1). */
+int tmx_solve_mhat(tmx_ctx *ctx, double *x, const double *b, int dagger, const tmx_solver_cfg *cfg,
+                   tmx_info *info);
+/* Solve (N + shifts[k]) x_k = b for k < nshift (<= 32), shifts > 0 or >= 0
+ * with shifts[0] the smallest.  x is nshift contiguous odd fields.  Low
+ * precision multishift CG followed by FP64-reliable refinement per shift
+ * (cfg->inner_prec selects F32 or F16 for both stages; TMX_F64 runs the
+ * plain FP64 multishift CG). */
+int tmx_multishift_solve(tmx_ctx *ctx, double *x, const double *b, const double *shifts, int nshift,
+                         const tmx_solver_cfg *cfg, tmx_info *info);
+
+/* ---- learned preconditioner ------------------------------------------- */
+
+/* Number of real FP32 parameters of the network (4 layers x 9 paths x
+ * (channel matrix + 4x4 spin matrix), complex). */
+int tmx_pc_num_params(const tmx_ctx *ctx, size_t *n);
+int tmx_pc_set_weights(tmx_ctx *ctx, const float *host_w, size_t n);
+int tmx_pc_get_weights(tmx_ctx *ctx, float *host_w, size_t n);
+/* out = K in (dagger = 0) or K^dagger in (dagger = 1) on canonical odd
+ * complex128 device fields. */
+int tmx_pc_apply(tmx_ctx *ctx, double *out, const double *in, int dagger);
+
+typedef struct {
+    int epochs;
+    int batch;
+    float lr;
+    float beta1, beta2, eps;
+    int seed;
+} tmx_train_cfg;
+
+/* Train on npairs (b_i, x_i) canonical odd complex128 device fields with
+ * loss mean_i |K b_i - x_i|^2 / |x_i|^2 and Adam; loss_out[epochs] receives
+ * the mean loss of each epoch (host). */
+int tmx_pc_train(tmx_ctx *ctx, const double *b, const double *x, int npairs, const tmx_train_cfg *cfg,
+                 float *loss_out);
+
+/* ---- tracing ------------------------------------------------------------ */
+
+/* Hierarchical timers: push starts a timer at the next level of the call
+ * tree with a caller-chosen name; pop stops it and prints
+ *   "# TMX: Time for <name> <seconds> s level: <n> <path>"
+ * to stdout when tracing is enabled (TMX_TRACE=1 or tmx_trace_enable). */
+int tmx_trace_enable(tmx_ctx *ctx, int on);
+int tmx_trace_push(tmx_ctx *ctx, const char *name);
+int tmx_trace_pop(tmx_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TMX_H */

@@ -1,0 +1,623 @@
+// C-ABI entry points, context management and the operator layer.
+//
+// Gauge-state tracking follows the paper's gauge-id cascade (Section 3):
+// a gauge field is identified by a real id; loading the same id again does
+// nothing, a new id invalidates every derived field (lower-precision link
+// copies, clover term, site inverses), and derived fields are rebuilt lazily
+// on the first operation that needs them.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "tmx_ctx.h"
+
+using namespace tmx;
+
+namespace tmx {
+
+double now_seconds()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+int set_err(tmx_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_err(tmx_ctx *c, hipError_t e, const char *where)
+{
+    if (e == hipSuccess) return TMX_OK;
+    return set_err(c, e == hipErrorOutOfMemory ? TMX_ENOMEM : TMX_EHIP,
+                   std::string(where) + ": " + hipGetErrorString(e));
+}
+
+void dev_free(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+static void *dev_alloc(tmx_ctx *c, size_t bytes)
+{
+    void *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(c, TMX_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        return nullptr;
+    }
+    return p;
+}
+
+void *ws_get(tmx_ctx *c, const std::string &name, size_t bytes)
+{
+    Workspace &w = c->ws[name];
+    if (w.bytes >= bytes && w.p) return w.p;
+    if (w.p) {
+        (void)hipStreamSynchronize(c->stream);
+        dev_free(w.p);
+        w.p = nullptr;
+        w.bytes = 0;
+    }
+    w.p = dev_alloc(c, bytes);
+    if (w.p) w.bytes = bytes;
+    return w.p;
+}
+
+static size_t bytes_per_real(int prec) { return prec == F64 ? 8 : (prec == F32 ? 4 : 2); }
+
+double mhat_bytes_per_site(int prec, int nf, int nrhs)
+{
+    const double bg = (double)bytes_per_real(prec), bs = bg, bc = bg;
+    double spin = 120.0 * bs + (prec == F16 ? 20.0 : 0.0);
+    return 192.0 * bg + 216.0 * bc + (double)nrhs * nf * spin;
+}
+
+int fetch(tmx_ctx *c, int n, double *host)
+{
+    hipError_t e = hipMemcpyAsync(c->host_red, c->red.result, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_err(c, e, "reduction readback");
+    std::memcpy(host, c->host_red, sizeof(double) * n);
+    return TMX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// derived fields
+// ---------------------------------------------------------------------------
+static size_t clover_bytes(int prec, long Vh) { return 144 * bytes_per_real(prec) * Vh; }  // both parities
+static size_t inv_bytes(int prec, long Vh) { return 144 * bytes_per_real(prec) * Vh; }     // even sites
+static size_t invnd_bytes(int prec, long Vh) { return 72 * bytes_per_real(prec) * Vh; }    // even sites
+static size_t link_bytes(int prec, long Vh)
+{
+    return 8 * (size_t)Vh * (prec == F64 ? 96 : (prec == F32 ? 48 : 24));
+}
+
+static int ensure_links(tmx_ctx *c, int prec)
+{
+    if (!c->gauge_loaded) return set_err(c, TMX_ENOTLOADED, "no gauge field loaded");
+    if (c->links_ok[prec]) return TMX_OK;
+    if (!c->links[prec]) {
+        c->links[prec] = dev_alloc(c, link_bytes(prec, c->Vh));
+        if (!c->links[prec]) return TMX_ENOMEM;
+    }
+    int r = hip_err(c, launch_convert_links((const double *)c->links[F64], c->links[prec], prec, c->g, c->stream),
+                    "convert links");
+    if (r) return r;
+    c->links_ok[prec] = true;
+    return TMX_OK;
+}
+
+static int ensure_clover(tmx_ctx *c, int prec)
+{
+    if (!c->gauge_loaded) return set_err(c, TMX_ENOTLOADED, "no gauge field loaded");
+    if (!c->have_params) return set_err(c, TMX_ENOTLOADED, "parameters not set");
+    if (!c->clov_ok[F64]) {
+        if (!c->clov[F64]) {
+            c->clov[F64] = dev_alloc(c, clover_bytes(F64, c->Vh));
+            if (!c->clov[F64]) return TMX_ENOMEM;
+        }
+        int r = hip_err(c, launch_clover_build((const double *)c->links[F64], (double *)c->clov[F64], c->g,
+                                               c->par.kappa, c->par.csw, c->stream),
+                        "clover build");
+        if (r) return r;
+        c->clov_ok[F64] = true;
+        c->clov_kappa = c->par.kappa;
+        c->clov_csw = c->par.csw;
+        c->clov_ok[F32] = c->clov_ok[F16] = false;
+        c->inv_ok[0] = c->inv_ok[1] = c->inv_ok[2] = false;
+        c->invnd_ok[0] = c->invnd_ok[1] = c->invnd_ok[2] = false;
+    }
+    if (prec != F64 && !c->clov_ok[prec]) {
+        if (!c->clov[prec]) {
+            c->clov[prec] = dev_alloc(c, clover_bytes(prec, c->Vh));
+            if (!c->clov[prec]) return TMX_ENOMEM;
+        }
+        int r = hip_err(c, launch_convert_seq((const double *)c->clov[F64], c->clov[prec], prec, 144, c->Vh, c->stream),
+                        "convert clover");
+        if (r) return r;
+        c->clov_ok[prec] = true;
+    }
+    return TMX_OK;
+}
+
+static int ensure_inv(tmx_ctx *c, int prec)
+{
+    int r = ensure_clover(c, F64);
+    if (r) return r;
+    const double nu = 2.0 * c->par.kappa * c->par.mu;
+    if (c->inv_ok[F64] && c->inv_nu != nu) c->inv_ok[0] = c->inv_ok[1] = c->inv_ok[2] = false;
+    if (!c->inv_ok[F64]) {
+        if (!c->inv[F64]) {
+            c->inv[F64] = dev_alloc(c, inv_bytes(F64, c->Vh));
+            if (!c->inv[F64]) return TMX_ENOMEM;
+        }
+        r = hip_err(c, launch_clover_inv((const double *)c->clov[F64], (double *)c->inv[F64], c->g, nu, c->stream),
+                    "clover inverse");
+        if (r) return r;
+        c->inv_ok[F64] = true;
+        c->inv_nu = nu;
+        c->inv_ok[F32] = c->inv_ok[F16] = false;
+    }
+    if (prec != F64 && !c->inv_ok[prec]) {
+        if (!c->inv[prec]) {
+            c->inv[prec] = dev_alloc(c, inv_bytes(prec, c->Vh));
+            if (!c->inv[prec]) return TMX_ENOMEM;
+        }
+        r = hip_err(c, launch_convert_seq((const double *)c->inv[F64], c->inv[prec], prec, 144, c->Vh, c->stream),
+                    "convert inverse");
+        if (r) return r;
+        c->inv_ok[prec] = true;
+    }
+    return TMX_OK;
+}
+
+static int ensure_invnd(tmx_ctx *c, int prec)
+{
+    int r = ensure_clover(c, F64);
+    if (r) return r;
+    const double nb = 2.0 * c->par.kappa * c->par.mubar, ep = 2.0 * c->par.kappa * c->par.epsbar;
+    const double cc = nb * nb - ep * ep;
+    if (c->invnd_ok[F64] && c->invnd_c != cc) c->invnd_ok[0] = c->invnd_ok[1] = c->invnd_ok[2] = false;
+    if (!c->invnd_ok[F64]) {
+        if (!c->invnd[F64]) {
+            c->invnd[F64] = dev_alloc(c, invnd_bytes(F64, c->Vh));
+            if (!c->invnd[F64]) return TMX_ENOMEM;
+        }
+        r = hip_err(c, launch_clover_inv_nd((const double *)c->clov[F64], (double *)c->invnd[F64], c->g, nb, ep,
+                                            c->stream),
+                    "nd clover inverse");
+        if (r) return r;
+        c->invnd_ok[F64] = true;
+        c->invnd_c = cc;
+        c->invnd_ok[F32] = c->invnd_ok[F16] = false;
+    }
+    if (prec != F64 && !c->invnd_ok[prec]) {
+        if (!c->invnd[prec]) {
+            c->invnd[prec] = dev_alloc(c, invnd_bytes(prec, c->Vh));
+            if (!c->invnd[prec]) return TMX_ENOMEM;
+        }
+        r = hip_err(c, launch_convert_seq((const double *)c->invnd[F64], c->invnd[prec], prec, 72, c->Vh, c->stream),
+                    "convert nd inverse");
+        if (r) return r;
+        c->invnd_ok[prec] = true;
+    }
+    return TMX_OK;
+}
+
+int ensure_ready(tmx_ctx *c, int prec, bool nd)
+{
+    if (prec < F64 || prec > F16) return set_err(c, TMX_EINVAL, "bad precision");
+    int r = ensure_links(c, prec);
+    if (!r) r = ensure_clover(c, prec);
+    if (!r) r = nd ? ensure_invnd(c, prec) : ensure_inv(c, prec);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// operator layer
+// ---------------------------------------------------------------------------
+static const void *clov_parity(tmx_ctx *c, int prec, int parity)
+{
+    return static_cast<const char *>(c->clov[prec]) + (size_t)parity * 72 * bytes_per_real(prec) * c->Vh;
+}
+
+static int block_for(tmx_ctx *c, const char *key)
+{
+    auto it = c->tune.find(key);
+    return it == c->tune.end() ? 256 : it->second;
+}
+
+static DslashArgs base_args(tmx_ctx *c, int prec, bool nd, int nrhs)
+{
+    DslashArgs a{};
+    a.g = c->g;
+    a.nrhs = nrhs;
+    a.U = LinkPtr{c->links[prec], c->Vh};
+    a.nu = nd ? 2.0 * c->par.kappa * c->par.mubar : 2.0 * c->par.kappa * c->par.mu;
+    a.epst = nd ? 2.0 * c->par.kappa * c->par.epsbar : 0.0;
+    a.t_bc = c->par.t_bc;
+    return a;
+}
+
+// K1: u = B_ee(sgn)^{-1} H_eo in ; K2: out = B_oo(sgn) x - kappa^2 H_oe u
+static int schur_pair(tmx_ctx *c, SpinorPtr out, SpinorPtr in, SpinorPtr u, int prec, bool nd, int nrhs, int sgn,
+                      int g5in, int g5out)
+{
+    const int nf = nd ? 2 : 1;
+    DslashArgs a = base_args(c, prec, nd, nrhs);
+    a.sgn = sgn;
+    a.parity = 0;
+    a.out = u;
+    a.in = in;
+    a.clov = clov_parity(c, prec, 0);
+    a.inv = nd ? c->invnd[prec] : c->inv[prec];
+    a.g5in = g5in;
+    hipError_t e = launch_dslash(prec, nf, 0, a, c->stream, block_for(c, "k1"));
+    if (e != hipSuccess) return hip_err(c, e, "K1 launch");
+    DslashArgs b = base_args(c, prec, nd, nrhs);
+    b.sgn = sgn;
+    b.parity = 1;
+    b.out = out;
+    b.in = u;
+    b.x = in;
+    b.clov = clov_parity(c, prec, 1);
+    b.kfac = c->par.kappa * c->par.kappa;
+    b.g5x = g5in;
+    b.g5out = g5out;
+    e = launch_dslash(prec, nf, 1, b, c->stream, block_for(c, "k2"));
+    if (e != hipSuccess) return hip_err(c, e, "K2 launch");
+    return TMX_OK;
+}
+
+static int check_op(tmx_ctx *c, int op)
+{
+    if (op != TMX_OP_PLUS && op != TMX_OP_MINUS && op != TMX_OP_ND) return set_err(c, TMX_EINVAL, "bad op");
+    return TMX_OK;
+}
+
+int op_mhat(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int dagger, int nrhs)
+{
+    int r = check_op(c, op);
+    if (r) return r;
+    const bool nd = op == TMX_OP_ND;
+    r = ensure_ready(c, prec, nd);
+    if (r) return r;
+    const int nf = nd ? 2 : 1;
+    const long stride = c->Vh * nrhs;
+    void *ud = ws_get(c, "op_u" + std::to_string(prec), spinor_field_bytes(prec, nf, stride));
+    if (!ud) return TMX_ENOMEM;
+    SpinorPtr u = make_spinor(ud, prec, nf, stride);
+    const int sgn = nd ? 1 : op;
+    // Mhat^dagger = g5 Mhat(-sgn) g5
+    return schur_pair(c, out, in, u, prec, nd, nrhs, dagger ? -sgn : sgn, dagger, dagger);
+}
+
+int op_mdagm(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int nrhs)
+{
+    int r = check_op(c, op);
+    if (r) return r;
+    const bool nd = op == TMX_OP_ND;
+    r = ensure_ready(c, prec, nd);
+    if (r) return r;
+    const int nf = nd ? 2 : 1;
+    const long stride = c->Vh * nrhs;
+    void *ud = ws_get(c, "op_u" + std::to_string(prec), spinor_field_bytes(prec, nf, stride));
+    void *vd = ws_get(c, "op_v" + std::to_string(prec), spinor_field_bytes(prec, nf, stride));
+    if (!ud || !vd) return TMX_ENOMEM;
+    SpinorPtr u = make_spinor(ud, prec, nf, stride), v = make_spinor(vd, prec, nf, stride);
+    const int sgn = nd ? 1 : op;
+    // v = g5 Mhat(sgn) in ; out = g5 Mhat(-sgn) v
+    r = schur_pair(c, v, in, u, prec, nd, nrhs, sgn, 0, 1);
+    if (r) return r;
+    return schur_pair(c, out, v, u, prec, nd, nrhs, -sgn, 0, 1);
+}
+
+int op_D(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec)
+{
+    int r = check_op(c, op);
+    if (r) return r;
+    const bool nd = op == TMX_OP_ND;
+    r = ensure_links(c, prec);
+    if (!r) r = ensure_clover(c, prec);
+    if (r) return r;
+    const int nf = nd ? 2 : 1;
+    const int sgn = nd ? 1 : op;
+    for (int p = 0; p < 2; ++p) {
+        DslashArgs a = base_args(c, prec, nd, 1);
+        a.sgn = sgn;
+        a.parity = p;
+        a.out = parity_half(out, prec, nf, p);
+        a.in = parity_half(in, prec, nf, 1 - p);
+        a.x = parity_half(in, prec, nf, p);
+        a.clov = clov_parity(c, prec, p);
+        a.kfac = c->par.kappa;
+        hipError_t e = launch_dslash(prec, nf, 1, a, c->stream, block_for(c, "k2"));
+        if (e != hipSuccess) return hip_err(c, e, "D launch");
+    }
+    return TMX_OK;
+}
+
+}  // namespace tmx
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int tmx_create(const int dims[4], void *hip_stream, tmx_ctx **out)
+{
+    if (!out || !dims) return TMX_EINVAL;
+    *out = nullptr;
+    long V = 1;
+    for (int k = 0; k < 4; ++k) {
+        if (dims[k] < 2 || dims[k] % 2) return TMX_EINVAL;
+        V *= dims[k];
+        if (V > (1L << 31)) return TMX_EINVAL;
+    }
+    tmx_ctx *c = new tmx_ctx();
+    for (int k = 0; k < 4; ++k) {
+        c->dims[k] = dims[k];
+        c->g.L[k] = dims[k];
+    }
+    c->V = V;
+    c->Vh = V / 2;
+    c->g.Lxh = dims[0] / 2;
+    c->g.Vh = (int)c->Vh;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->red.max_blocks = 1024;
+    if (hipMalloc(&c->red.partials, sizeof(double) * c->red.max_blocks * MAXR * 4) != hipSuccess ||
+        hipMalloc(&c->red.result, sizeof(double) * MAXR * 4) != hipSuccess ||
+        hipHostMalloc(&c->host_red, sizeof(double) * MAXR * 4, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        dev_free(c->red.partials);
+        dev_free(c->red.result);
+        delete c;
+        return TMX_ENOMEM;
+    }
+    const char *tr = std::getenv("TMX_TRACE");
+    c->trace = tr && tr[0] == '1';
+    *out = c;
+    return TMX_OK;
+}
+
+void tmx_pc_free(tmx_ctx *c);  // nn.hip
+
+int tmx_destroy(tmx_ctx *c)
+{
+    if (!c) return TMX_EINVAL;
+    (void)hipStreamSynchronize(c->stream);
+    for (int p = 0; p < 3; ++p) {
+        dev_free(c->links[p]);
+        dev_free(c->clov[p]);
+        dev_free(c->inv[p]);
+        dev_free(c->invnd[p]);
+    }
+    for (auto &kv : c->ws) dev_free(kv.second.p);
+    dev_free(c->red.partials);
+    dev_free(c->red.result);
+    if (c->host_red) (void)hipHostFree(c->host_red);
+    tmx_pc_free(c);
+    delete c;
+    return TMX_OK;
+}
+
+const char *tmx_last_error(const tmx_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int tmx_set_stream(tmx_ctx *c, void *s)
+{
+    if (!c) return TMX_EINVAL;
+    c->stream = static_cast<hipStream_t>(s);
+    return TMX_OK;
+}
+
+int tmx_set_params(tmx_ctx *c, const tmx_params *p)
+{
+    if (!c || !p) return TMX_EINVAL;
+    if (!(p->kappa > 0) || !std::isfinite(p->kappa) || !std::isfinite(p->csw) || !std::isfinite(p->mu) ||
+        !std::isfinite(p->mubar) || !std::isfinite(p->epsbar) || (p->t_bc != 1 && p->t_bc != -1))
+        return set_err(c, TMX_EINVAL, "invalid parameters");
+    if (c->have_params && !c->clover_from_host && (p->kappa != c->par.kappa || p->csw != c->par.csw))
+        c->clov_ok[0] = c->clov_ok[1] = c->clov_ok[2] = false;
+    if (c->have_params && p->kappa != c->par.kappa) {
+        // site inverses depend on 2 kappa mu
+        c->inv_ok[0] = c->inv_ok[1] = c->inv_ok[2] = false;
+        c->invnd_ok[0] = c->invnd_ok[1] = c->invnd_ok[2] = false;
+    }
+    c->par = *p;
+    c->have_params = true;
+    return TMX_OK;
+}
+
+int tmx_load_gauge(tmx_ctx *c, const double *host_links, double gauge_id)
+{
+    if (!c || !host_links) return TMX_EINVAL;
+    if (c->gauge_loaded && gauge_id == c->gauge_id) return TMX_OK;
+    const size_t bytes = (size_t)c->V * 4 * 9 * 16;
+    void *stage = dev_alloc(c, bytes);
+    if (!stage) return TMX_ENOMEM;
+    if (!c->links[F64]) {
+        c->links[F64] = dev_alloc(c, link_bytes(F64, c->Vh));
+        if (!c->links[F64]) {
+            dev_free(stage);
+            return TMX_ENOMEM;
+        }
+    }
+    hipError_t e = hipMemcpyAsync(stage, host_links, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_pack_links((const double *)stage, (double *)c->links[F64], c->g, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dev_free(stage);
+    if (e != hipSuccess) return hip_err(c, e, "gauge upload");
+    c->gauge_loaded = true;
+    c->gauge_id = gauge_id;
+    c->uploads++;
+    // cascade: every derived field is stale now
+    for (int p = 0; p < 3; ++p) {
+        c->links_ok[p] = p == F64;
+        c->clov_ok[p] = false;
+        c->inv_ok[p] = false;
+        c->invnd_ok[p] = false;
+    }
+    c->clover_from_host = false;
+    return TMX_OK;
+}
+
+int tmx_gauge_uploads(const tmx_ctx *c) { return c ? c->uploads : -1; }
+
+int tmx_load_clover(tmx_ctx *c, const double *host_T)
+{
+    if (!c) return TMX_EINVAL;
+    if (!c->gauge_loaded) return set_err(c, TMX_ENOTLOADED, "load a gauge field first");
+    if (!host_T) {
+        c->clover_from_host = false;
+        c->clov_ok[0] = c->clov_ok[1] = c->clov_ok[2] = false;
+        int r = ensure_clover(c, F64);
+        if (r) return r;
+        return hip_err(c, hipStreamSynchronize(c->stream), "clover build");
+    }
+    // Hermiticity check on the host
+    const long n = c->V * 2;
+    for (long b = 0; b < n; ++b) {
+        const double *m = host_T + b * 72;
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) {
+                const double re = m[2 * (6 * i + j)], im = m[2 * (6 * i + j) + 1];
+                const double re2 = m[2 * (6 * j + i)], im2 = m[2 * (6 * j + i) + 1];
+                if (std::fabs(re - re2) > 1e-12 || std::fabs(im + im2) > 1e-12 || !std::isfinite(re) ||
+                    !std::isfinite(im))
+                    return set_err(c, TMX_EINVAL, "clover block is not Hermitian");
+            }
+    }
+    const size_t bytes = (size_t)c->V * 144 * 8;
+    void *stage = dev_alloc(c, bytes);
+    if (!stage) return TMX_ENOMEM;
+    if (!c->clov[F64]) {
+        c->clov[F64] = dev_alloc(c, clover_bytes(F64, c->Vh));
+        if (!c->clov[F64]) {
+            dev_free(stage);
+            return TMX_ENOMEM;
+        }
+    }
+    hipError_t e = hipMemcpyAsync(stage, host_T, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_clover_from_canonical((const double *)stage, (double *)c->clov[F64], c->g, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dev_free(stage);
+    if (e != hipSuccess) return hip_err(c, e, "clover upload");
+    c->clover_from_host = true;
+    c->clov_ok[F64] = true;
+    c->clov_ok[F32] = c->clov_ok[F16] = false;
+    for (int p = 0; p < 3; ++p) c->inv_ok[p] = c->invnd_ok[p] = false;
+    return TMX_OK;
+}
+
+int tmx_get_clover(tmx_ctx *c, double *host_T)
+{
+    if (!c || !host_T) return TMX_EINVAL;
+    int r = ensure_clover(c, F64);
+    if (r) return r;
+    const size_t bytes = (size_t)c->V * 144 * 8;
+    void *stage = dev_alloc(c, bytes);
+    if (!stage) return TMX_ENOMEM;
+    hipError_t e = launch_clover_to_canonical((const double *)c->clov[F64], (double *)stage, c->g, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_T, stage, bytes, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dev_free(stage);
+    return hip_err(c, e, "clover download");
+}
+
+static int kind_nf(int kind) { return (kind == TMX_FIELD_ODD_ND || kind == TMX_FIELD_FULL_ND) ? 2 : 1; }
+static bool kind_full(int kind) { return kind == TMX_FIELD_FULL || kind == TMX_FIELD_FULL_ND; }
+
+int tmx_field_bytes(const tmx_ctx *c, int kind, int prec, size_t *bytes)
+{
+    if (!c || !bytes || kind < 0 || kind > 3 || prec < 0 || prec > 2) return TMX_EINVAL;
+    *bytes = (size_t)spinor_field_bytes(prec, kind_nf(kind), c->Vh) * (kind_full(kind) ? 2 : 1);
+    return TMX_OK;
+}
+
+int tmx_pack(tmx_ctx *c, void *internal, const double *canonical, int kind, int prec, int nvec)
+{
+    if (!c || !internal || !canonical || kind < 0 || kind > 3 || prec < 0 || prec > 2 || nvec < 1)
+        return c ? set_err(c, TMX_EINVAL, "tmx_pack: bad argument") : TMX_EINVAL;
+    if (kind_full(kind) && nvec != 1) return set_err(c, TMX_EINVAL, "full fields take nvec = 1");
+    SpinorPtr f = make_spinor(internal, prec, kind_nf(kind), c->Vh * nvec);
+    return hip_err(c, launch_pack_spinor(canonical, f, prec, kind, c->g, nvec, c->stream), "pack");
+}
+
+int tmx_unpack(tmx_ctx *c, double *canonical, const void *internal, int kind, int prec, int nvec)
+{
+    if (!c || !internal || !canonical || kind < 0 || kind > 3 || prec < 0 || prec > 2 || nvec < 1)
+        return c ? set_err(c, TMX_EINVAL, "tmx_unpack: bad argument") : TMX_EINVAL;
+    if (kind_full(kind) && nvec != 1) return set_err(c, TMX_EINVAL, "full fields take nvec = 1");
+    SpinorPtr f = make_spinor(const_cast<void *>(internal), prec, kind_nf(kind), c->Vh * nvec);
+    return hip_err(c, launch_unpack_spinor(canonical, f, prec, kind, c->g, nvec, c->stream), "unpack");
+}
+
+int tmx_apply_D(tmx_ctx *c, void *out, const void *in, int op, int prec)
+{
+    if (!c || !out || !in || out == in) return c ? set_err(c, TMX_EINVAL, "tmx_apply_D: bad argument") : TMX_EINVAL;
+    const int nf = op == TMX_OP_ND ? 2 : 1;
+    return op_D(c, make_spinor(out, prec, nf, c->Vh), make_spinor(const_cast<void *>(in), prec, nf, c->Vh), op, prec);
+}
+
+int tmx_apply_mhat(tmx_ctx *c, void *out, const void *in, int op, int prec, int dagger, int nrhs)
+{
+    if (!c || !out || !in || out == in || nrhs < 1 || nrhs > MAXR)
+        return c ? set_err(c, TMX_EINVAL, "tmx_apply_mhat: bad argument") : TMX_EINVAL;
+    const int nf = op == TMX_OP_ND ? 2 : 1;
+    const long stride = c->Vh * nrhs;
+    return op_mhat(c, make_spinor(out, prec, nf, stride), make_spinor(const_cast<void *>(in), prec, nf, stride), op,
+                   prec, dagger ? 1 : 0, nrhs);
+}
+
+int tmx_apply_mdagm(tmx_ctx *c, void *out, const void *in, int op, int prec, int nrhs)
+{
+    if (!c || !out || !in || out == in || nrhs < 1 || nrhs > MAXR)
+        return c ? set_err(c, TMX_EINVAL, "tmx_apply_mdagm: bad argument") : TMX_EINVAL;
+    const int nf = op == TMX_OP_ND ? 2 : 1;
+    const long stride = c->Vh * nrhs;
+    return op_mdagm(c, make_spinor(out, prec, nf, stride), make_spinor(const_cast<void *>(in), prec, nf, stride), op,
+                    prec, nrhs);
+}
+
+// ---- tracing ---------------------------------------------------------------
+int tmx_trace_enable(tmx_ctx *c, int on)
+{
+    if (!c) return TMX_EINVAL;
+    c->trace = on != 0;
+    return TMX_OK;
+}
+
+int tmx_trace_push(tmx_ctx *c, const char *name)
+{
+    if (!c || !name) return TMX_EINVAL;
+    if (c->trace) (void)hipStreamSynchronize(c->stream);
+    c->frames.push_back(TraceFrame{name, now_seconds()});
+    return TMX_OK;
+}
+
+int tmx_trace_pop(tmx_ctx *c)
+{
+    if (!c || c->frames.empty()) return TMX_EINVAL;
+    if (c->trace) {
+        (void)hipStreamSynchronize(c->stream);
+        const double dt = now_seconds() - c->frames.back().t0;
+        std::string path;
+        for (auto &f : c->frames) path += "/" + f.name;
+        std::printf("# TMX: Time for %s %.6e s level: %d %s\n", c->frames.back().name.c_str(), dt,
+                    (int)c->frames.size(), path.c_str());
+        std::fflush(stdout);
+    }
+    c->frames.pop_back();
+    return TMX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,271 @@
+// Wilson twisted-mass clover stencil kernels (gfx950).
+//
+// One launch computes, for every site s of the output parity p and every
+// right-hand side r (thread t = s * nrhs + r):
+//
+//   MODE_INV  (first half of the Schur operator, "K1"):
+//       out = B_p^{-1}(sgn) (H in)(s)
+//     degenerate: B^{-1} = (A + i sgn nu g5)^{-1}, a stored full 6x6 per
+//     chirality (the -nu inverse is its adjoint);
+//     two flavours: (A + X)^{-1} = (A - X) (A^2 + nubar^2 - epst^2)^{-1},
+//     X = i sgn nubar g5 tau3 - epst tau1, with A and the Hermitian inverse
+//     factor stored.
+//   MODE_DIAG (second half, "K2", or one parity of the full operator D):
+//       out = (A_p + X(sgn)) x(s) - kfac (H in)(s)
+//     with X = i sgn nu g5 (degenerate) or the two-flavour X above.
+//
+// H is the Wilson hopping term with the spin projectors (1 -+ gamma_mu) of
+// the chiral basis written out per direction: the projected half spinor
+// h = psi_upper + sgn * a_mu psi_lower is transported, and the lower spin
+// components are rebuilt as sgn * a_mu^dagger (U h), where gamma_mu =
+// [[0, a_mu], [a_mu^dagger, 0]], a_k = -i sigma_k, a_4 = 1.
+//
+// Optional gamma5 on the hopping input (g5in), on the diagonal input (g5x)
+// and on the output (g5out) implement the
+// adjoint Mhat^dagger = g5 Mhat(-sgn) g5 and the normal operator without
+// extra passes.
+#include "tmx_device.h"
+#include "tmx_kernels.h"
+
+namespace tmx {
+
+enum { MODE_INV = 0, MODE_DIAG = 1 };
+
+// acc += (1 + sgn gamma_mu) * bc * W psi,  W = U (fwd) or U^dagger (bwd)
+template <int MU, int SGN, bool DAG, typename R>
+__device__ __forceinline__ void hop_term(const cx<R> u[9], R bc, const cx<R> psi[12], cx<R> acc[12])
+{
+    // half spinor h[spin 0/1][colour]
+    cx<R> h0[3], h1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cx<R> p0 = psi[c], p1 = psi[3 + c], p2 = psi[6 + c], p3 = psi[9 + c];
+        cx<R> a0, a1;  // a_mu psi_lower
+        if constexpr (MU == 0) {
+            a0 = -imul(p3);
+            a1 = -imul(p2);
+        } else if constexpr (MU == 1) {
+            a0 = -p3;
+            a1 = p2;
+        } else if constexpr (MU == 2) {
+            a0 = -imul(p2);
+            a1 = imul(p3);
+        } else {
+            a0 = p2;
+            a1 = p3;
+        }
+        if constexpr (SGN > 0) {
+            h0[c] = p0 + a0;
+            h1[c] = p1 + a1;
+        } else {
+            h0[c] = p0 - a0;
+            h1[c] = p1 - a1;
+        }
+    }
+    // k = W h
+    cx<R> k0[3], k1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        k0[a] = cx<R>{0, 0};
+        k1[a] = cx<R>{0, 0};
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if constexpr (DAG) {
+                cmac_conj(k0[a], u[3 * b + a], h0[b]);
+                cmac_conj(k1[a], u[3 * b + a], h1[b]);
+            } else {
+                cmac(k0[a], u[3 * a + b], h0[b]);
+                cmac(k1[a], u[3 * a + b], h1[b]);
+            }
+        }
+        k0[a] = bc * k0[a];
+        k1[a] = bc * k1[a];
+    }
+    // reconstruct: upper += k, lower += sgn * a_mu^dagger k
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc[c] = acc[c] + k0[c];
+        acc[3 + c] = acc[3 + c] + k1[c];
+        cx<R> l0, l1;
+        if constexpr (MU == 0) {
+            l0 = imul(k1[c]);
+            l1 = imul(k0[c]);
+        } else if constexpr (MU == 1) {
+            l0 = k1[c];
+            l1 = -k0[c];
+        } else if constexpr (MU == 2) {
+            l0 = imul(k0[c]);
+            l1 = -imul(k1[c]);
+        } else {
+            l0 = k0[c];
+            l1 = k1[c];
+        }
+        if constexpr (SGN > 0) {
+            acc[6 + c] = acc[6 + c] + l0;
+            acc[9 + c] = acc[9 + c] + l1;
+        } else {
+            acc[6 + c] = acc[6 + c] - l0;
+            acc[9 + c] = acc[9 + c] - l1;
+        }
+    }
+}
+
+template <int P, typename R>
+__device__ __forceinline__ void load_spinor_g5(const SpinorPtr &f, int flav, long slot, bool g5, cx<R> v[12])
+{
+    load_spinor<P>(f, flav, slot, v);
+    if (g5) {
+#pragma unroll
+        for (int k = 6; k < 12; ++k) v[k] = -v[k];
+    }
+}
+
+// accumulate (H in)(s) for all flavours
+template <int P, int NF, int MU, typename R>
+__device__ __forceinline__ void hop_dir(const DslashArgs &a, const int x[4], int s, long rhs, cx<R> acc[NF][12])
+{
+    const Geom &g = a.g;
+    const int p = a.parity;
+    // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
+    {
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        R bc = R(1);
+        if (++y[MU] == g.L[MU]) {
+            y[MU] = 0;
+            if (MU == 3) bc = R(a.t_bc);
+        }
+        const int n = cb_index(g, y);
+        cx<R> u[9];
+        load_link<P>(a.U, p, MU, s, u);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            cx<R> psi[12];
+            load_spinor_g5<P>(a.in, f, (long)n * a.nrhs + rhs, a.g5in, psi);
+            hop_term<MU, -1, false>(u, bc, psi, acc[f]);
+        }
+    }
+    // backward: (1 + gamma_mu) U_mu(x - mu)^dagger psi(x - mu)
+    {
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        R bc = R(1);
+        if (--y[MU] < 0) {
+            y[MU] = g.L[MU] - 1;
+            if (MU == 3) bc = R(a.t_bc);
+        }
+        const int n = cb_index(g, y);
+        cx<R> u[9];
+        load_link<P>(a.U, 1 - p, MU, n, u);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            cx<R> psi[12];
+            load_spinor_g5<P>(a.in, f, (long)n * a.nrhs + rhs, a.g5in, psi);
+            hop_term<MU, +1, true>(u, bc, psi, acc[f]);
+        }
+    }
+}
+
+template <int P, int NF, int MODE>
+__global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
+{
+    using R = typename RealOf<P>::type;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)a.g.Vh * a.nrhs) return;
+    const int s = (int)(t / a.nrhs);
+    const long rhs = t - (long)s * a.nrhs;
+    int x[4];
+    cb_coords(a.g, s, a.parity, x);
+
+    cx<R> acc[NF][12];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[f][k] = cx<R>{0, 0};
+
+    hop_dir<P, NF, 0>(a, x, s, rhs, acc);
+    hop_dir<P, NF, 1>(a, x, s, rhs, acc);
+    hop_dir<P, NF, 2>(a, x, s, rhs, acc);
+    hop_dir<P, NF, 3>(a, x, s, rhs, acc);
+
+    const long cs = a.g.Vh;  // clover stride
+    cx<R> out[NF][12];
+    if constexpr (MODE == MODE_INV) {
+        if constexpr (NF == 1) {
+            const bool dag = a.sgn < 0;
+            full_apply<P>(a.inv, cs, s, 0, dag, acc[0], out[0]);
+            full_apply<P>(a.inv, cs, s, 1, dag, acc[0] + 6, out[0] + 6);
+        } else {
+            // t_f = Binv acc_f ; out = (A - X) t
+            cx<R> tt[2][12];
+            herm_apply_site<P>(a.inv, cs, s, R(0), R(0), acc[0], tt[0]);
+            herm_apply_site<P>(a.inv, cs, s, R(0), R(0), acc[1], tt[1]);
+            const R nb = R(a.sgn * a.nu), ep = R(a.epst);
+            herm_apply_site<P>(a.clov, cs, s, -nb, nb, tt[0], out[0]);
+            herm_apply_site<P>(a.clov, cs, s, nb, -nb, tt[1], out[1]);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                out[0][k] = out[0][k] + ep * tt[1][k];
+                out[1][k] = out[1][k] + ep * tt[0][k];
+            }
+        }
+    } else {
+        const R kf = R(a.kfac);
+        const R nb = R(a.sgn * a.nu);
+        cx<R> xv[NF][12];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) load_spinor_g5<P>(a.x, f, t, a.g5x, xv[f]);
+        if constexpr (NF == 1) {
+            herm_apply_site<P>(a.clov, cs, s, nb, -nb, xv[0], out[0]);
+        } else {
+            const R ep = R(a.epst);
+            herm_apply_site<P>(a.clov, cs, s, nb, -nb, xv[0], out[0]);
+            herm_apply_site<P>(a.clov, cs, s, -nb, nb, xv[1], out[1]);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                out[0][k] = out[0][k] - ep * xv[1][k];
+                out[1][k] = out[1][k] - ep * xv[0][k];
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int k = 0; k < 12; ++k) out[f][k] = out[f][k] - kf * acc[f][k];
+    }
+    if (a.g5out) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int k = 6; k < 12; ++k) out[f][k] = -out[f][k];
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) store_spinor<P>(a.out, f, t, out[f]);
+}
+
+template <int P, int NF, int MODE>
+static hipError_t launch_one(const DslashArgs &a, hipStream_t st, int block)
+{
+    const long n = (long)a.g.Vh * a.nrhs;
+    const int grid = (int)((n + block - 1) / block);
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL((dslash_kernel<P, NF, MODE>), dim3(grid), dim3(block), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dslash(int prec, int nf, int mode, const DslashArgs &a, hipStream_t st, int block)
+{
+    if (block <= 0) block = 256;
+#define TMX_DS(P, NF)                                                                     \
+    if (prec == P && nf == NF) {                                                          \
+        return mode == MODE_INV ? launch_one<P, NF, MODE_INV>(a, st, block)               \
+                                : launch_one<P, NF, MODE_DIAG>(a, st, block);             \
+    }
+    TMX_DS(F64, 1)
+    TMX_DS(F32, 1)
+    TMX_DS(F16, 1)
+    TMX_DS(F64, 2)
+    TMX_DS(F32, 2)
+    TMX_DS(F16, 2)
+#undef TMX_DS
+    return hipErrorInvalidValue;
+}
+
+}  // namespace tmx

@@ -1,0 +1,540 @@
+// Krylov solvers on the normal operator N = Mhat^dagger Mhat (+ shift).
+//
+//  * CG: Hestenes-Stiefel, FP64 vectors and operator, nrhs columns advanced
+//    together (one N application per iteration serves all columns, links
+//    read once per site for all of them), converged columns frozen.
+//  * MP-CG: the paper's mixed-precision CG (Section 1, 4.1) with reliable
+//    updates in the sense of Clark et al.: inner iterations apply N in FP32
+//    or FP16 storage on low-precision vectors; whenever the iterated residual
+//    has dropped by a factor delta since the last update (or reached the
+//    target), the low-precision solution increment is added to the FP64
+//    solution, the FP64 true residual b - N x is recomputed with the FP64
+//    operator and the low-precision residual restarted from it.
+//  * MS-CG: multishift CG for the rational approximation (Section 4.2):
+//    all shifts from the Krylov space of the smallest one (Jegerlehner's
+//    collinear-residual recurrences), run in low precision, each shift then
+//    refined to the FP64 target by MP-CG started from its multishift
+//    solution ("shift-by-shift refinement").
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tmx_ctx.h"
+
+namespace tmx {
+
+namespace {
+
+struct Sys {
+    tmx_ctx *c;
+    int op, nf, nrhs;
+    long stride;
+    double bytes_per_N;  // model bytes of one N application (all columns)
+    double gbytes = 0;
+
+    Sys(tmx_ctx *c_, int op_, int nrhs_) : c(c_), op(op_), nf(op_ == TMX_OP_ND ? 2 : 1), nrhs(nrhs_)
+    {
+        stride = c->Vh * nrhs;
+        bytes_per_N = 0;
+    }
+    SpinorPtr field(const std::string &name, int prec, int cols = -1)
+    {
+        const long s = cols < 0 ? stride : c->Vh * cols;
+        void *d = ws_get(c, "sv_" + name, spinor_field_bytes(prec, nf, s));
+        return make_spinor(d, prec, nf, s);
+    }
+    int N(SpinorPtr out, SpinorPtr in, int prec, int cols)
+    {
+        gbytes += 2.0 * mhat_bytes_per_site(prec, nf, cols) * c->Vh * 1e-9;
+        return op_mdagm(c, out, in, op, prec, cols);
+    }
+};
+
+#define TRY(x)                   \
+    do {                         \
+        int _r = (x);            \
+        if (_r) return _r;       \
+    } while (0)
+#define HTRY(x, w) TRY(hip_err(c, (x), w))
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// shifted normal operator: q = N p + sigma p, returns Re<p, q> per column
+// --------------------------------------------------------------------------
+template <int P> struct OpShiftDot {
+    static constexpr int NRED = 1;
+    SpinorPtr q, p;
+    int nf;
+    double sigma[MAXR];
+    __device__ void operator()(long t, int k, double *acc) const
+    {
+        for (int f = 0; f < nf; ++f) {
+            cd vq[12], vp[12];
+            ld<P>(q, f, t, vq);
+            ld<P>(p, f, t, vp);
+            double s = 0;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                vq[c] = vq[c] + sigma[k] * vp[c];
+                s += vp[c].re * vq[c].re + vp[c].im * vq[c].im;
+            }
+            if (sigma[k] != 0.0) st<P>(q, f, t, vq);
+            acc[0] += s;
+        }
+    }
+};
+
+template <int P>
+static int apply_shifted(Sys &S, SpinorPtr q, SpinorPtr p, const double *sigma, int cols, double *pq)
+{
+    tmx_ctx *c = S.c;
+    TRY(S.N(q, p, P, cols));
+    OpShiftDot<P> o{};
+    o.q = q;
+    o.p = p;
+    o.nf = S.nf;
+    for (int k = 0; k < cols; ++k) o.sigma[k] = sigma ? sigma[k] : 0.0;
+    HTRY(run_blas(o, c->Vh * cols, cols, c->red, c->stream), "shifted dot");
+    return fetch(c, cols, pq);
+}
+
+// true residual r = b - (N + sigma) x (FP64); writes rlo if PL given; returns |r|^2 per column
+template <int PL>
+static int true_residual(Sys &S, SpinorPtr r, SpinorPtr rlo, bool write_lo, SpinorPtr b, SpinorPtr x,
+                         const double *sigma, int cols, double *rr)
+{
+    tmx_ctx *c = S.c;
+    SpinorPtr q = S.field("trq", F64, cols);
+    double dummy[MAXR];
+    TRY(apply_shifted<F64>(S, q, x, sigma, cols, dummy));
+    OpXmyNorm<F64, F64, F64, PL> o{};
+    o.r = r;
+    o.b = b;
+    o.q = q;
+    o.rlo = rlo;
+    o.nf = S.nf;
+    o.write_lo = write_lo ? 1 : 0;
+    HTRY(run_blas(o, c->Vh * cols, cols, c->red, c->stream), "true residual");
+    return fetch(c, cols, rr);
+}
+
+template <int PD, int PS> static int copy_field(Sys &S, SpinorPtr d, SpinorPtr s, int cols, double *nrm)
+{
+    tmx_ctx *c = S.c;
+    OpCopy<PD, PS> o{};
+    o.d = d;
+    o.s = s;
+    o.nf = S.nf;
+    HTRY(run_blas(o, c->Vh * cols, cols, c->red, c->stream), "copy");
+    if (nrm) return fetch(c, cols, nrm);
+    return TMX_OK;
+}
+
+template <int PD> static int zero_field(Sys &S, SpinorPtr d, int cols)
+{
+    tmx_ctx *c = S.c;
+    OpZero<PD> o{};
+    o.d = d;
+    o.nf = S.nf;
+    return hip_err(c, run_blas(o, c->Vh * cols, cols, c->red, c->stream), "zero");
+}
+
+// --------------------------------------------------------------------------
+// CG / MP-CG on N + sigma_k for `cols` columns (x, b FP64 internal)
+// --------------------------------------------------------------------------
+template <int P>
+static int cg_core(Sys &S, SpinorPtr x, SpinorPtr b, int cols, const double *sigma, const tmx_solver_cfg &cfg,
+                   bool x_is_guess, tmx_info *info)
+{
+    tmx_ctx *c = S.c;
+    const double tol = cfg.tol > 0 ? cfg.tol : 1e-10;
+    const int maxiter = cfg.maxiter > 0 ? cfg.maxiter : 10000;
+    const double delta = cfg.delta > 0 ? cfg.delta : 0.1;
+    constexpr bool mixed = P != F64;
+
+    SpinorPtr r = S.field("r", F64, cols);
+    SpinorPtr rl = mixed ? S.field("rl", P, cols) : r;
+    SpinorPtr p = S.field("p", P, cols);
+    SpinorPtr q = S.field("q", P, cols);
+    SpinorPtr xl = mixed ? S.field("xl", F32, cols) : x;
+
+    double bb[MAXR], rho[MAXR], rho1[MAXR], rmax[MAXR], pq[MAXR];
+    int active[MAXR], iters[MAXR], nrel[MAXR];
+    TRY((copy_field<F64, F64>(S, r, b, cols, bb)));
+    if (!x_is_guess) TRY(zero_field<F64>(S, x, cols));
+    // r = b - N x (also for x = 0, to start from an exact residual)
+    TRY(true_residual<P>(S, r, rl, mixed, b, x, sigma, cols, rho));
+    if (mixed) TRY(zero_field<F32>(S, xl, cols));
+    // p = r (low precision)
+    if (mixed) {
+        TRY((copy_field<P, P>(S, p, rl, cols, nullptr)));
+    } else {
+        TRY((copy_field<P, F64>(S, p, r, cols, nullptr)));
+    }
+    int nactive = 0;
+    for (int k = 0; k < cols; ++k) {
+        rmax[k] = rho[k];
+        iters[k] = 0;
+        nrel[k] = 0;
+        active[k] = (bb[k] > 0 && std::sqrt(rho[k]) > tol * std::sqrt(bb[k])) ? 1 : 0;
+        nactive += active[k];
+    }
+    const double t0 = now_seconds();
+    int it = 0;
+    while (nactive > 0 && it < maxiter) {
+        TRY(apply_shifted<P>(S, q, p, sigma, cols, pq));
+        ++it;
+        OpAxpyNorm<mixed ? F32 : F64, P, P, P> up{};
+        up.x = xl;
+        up.p = p;
+        up.r = rl;
+        up.q = q;
+        up.nf = S.nf;
+        for (int k = 0; k < cols; ++k) up.a[k] = (active[k] && pq[k] != 0.0) ? rho[k] / pq[k] : 0.0;
+        HTRY(run_blas(up, c->Vh * cols, cols, c->red, c->stream), "cg update");
+        TRY(fetch(c, cols, rho1));
+        bool reliable = false;
+        for (int k = 0; k < cols; ++k) {
+            if (!active[k]) continue;
+            iters[k] = it;
+            if (!std::isfinite(rho1[k])) return set_err(c, TMX_ENOCONV, "CG: non-finite residual");
+            rmax[k] = std::max(rmax[k], rho1[k]);
+            if (mixed) {
+                if (std::sqrt(rho1[k]) < delta * std::sqrt(rmax[k]) || std::sqrt(rho1[k]) <= tol * std::sqrt(bb[k]))
+                    reliable = true;
+            }
+        }
+        if (mixed && reliable) {
+            // x += xl ; xl = 0 ; r = b - N x ; rl = r
+            OpAddTo<F64, F32> ad{};
+            ad.x = x;
+            ad.y = xl;
+            ad.nf = S.nf;
+            ad.zero_y = 1;
+            HTRY(run_blas(ad, c->Vh * cols, cols, c->red, c->stream), "reliable add");
+            TRY(true_residual<P>(S, r, rl, true, b, x, sigma, cols, rho1));
+            for (int k = 0; k < cols; ++k) {
+                if (!active[k]) continue;
+                rmax[k] = rho1[k];
+                nrel[k]++;
+            }
+        }
+        OpAxpby<P, P> px{};
+        px.y = p;
+        px.x = rl;
+        px.nf = S.nf;
+        nactive = 0;
+        for (int k = 0; k < cols; ++k) {
+            if (active[k] && std::sqrt(rho1[k]) <= tol * std::sqrt(bb[k]) && (!mixed || reliable)) active[k] = 0;
+            px.a[k] = 1.0;
+            px.b[k] = active[k] ? rho1[k] / rho[k] : 0.0;
+            nactive += active[k];
+            rho[k] = rho1[k];
+        }
+        if (nactive == 0) break;
+        HTRY(run_blas(px, c->Vh * cols, cols, c->red, c->stream), "cg p update");
+    }
+    if (mixed && nactive > 0) {
+        // iteration cap reached mid-way: fold the low-precision increment in
+        OpAddTo<F64, F32> ad{};
+        ad.x = x;
+        ad.y = xl;
+        ad.nf = S.nf;
+        ad.zero_y = 1;
+        HTRY(run_blas(ad, c->Vh * cols, cols, c->red, c->stream), "final add");
+    }
+    // FP64 true residual
+    double tr[MAXR];
+    TRY(true_residual<P>(S, r, rl, false, b, x, sigma, cols, tr));
+    const double t1 = now_seconds();
+    int rc = TMX_OK;
+    for (int k = 0; k < cols; ++k) {
+        const double rel = bb[k] > 0 ? std::sqrt(tr[k] / bb[k]) : 0.0;
+        if (info) {
+            info[k].iters += iters[k];
+            info[k].reliable_updates += nrel[k];
+            info[k].true_residual = rel;
+            info[k].seconds += t1 - t0;
+            info[k].gbytes = S.gbytes;
+        }
+        if (!(rel <= tol)) rc = TMX_ENOCONV;
+    }
+    return rc;
+}
+
+// CG with restarts: the iterated residual of a long FP64 run can drift from
+// the true one; a restart from the current x recomputes it exactly.
+template <int P>
+static int cg_solve(Sys &S, SpinorPtr x, SpinorPtr b, int cols, const double *sigma, const tmx_solver_cfg &cfg,
+                    bool guess, tmx_info *info)
+{
+    int rc = TMX_ENOCONV;
+    for (int attempt = 0; attempt < 3 && rc == TMX_ENOCONV; ++attempt) {
+        rc = cg_core<P>(S, x, b, cols, sigma, cfg, guess || attempt > 0, info);
+        if (rc < 0) return rc;
+        if (info && rc == TMX_ENOCONV && info[0].iters >= (cfg.maxiter > 0 ? cfg.maxiter : 10000)) break;
+    }
+    return rc;
+}
+
+static int dispatch_cg(Sys &S, int prec, SpinorPtr x, SpinorPtr b, int cols, const double *sigma,
+                       const tmx_solver_cfg &cfg, bool guess, tmx_info *info)
+{
+    if (prec == F64) return cg_solve<F64>(S, x, b, cols, sigma, cfg, guess, info);
+    if (prec == F32) return cg_solve<F32>(S, x, b, cols, sigma, cfg, guess, info);
+    return cg_solve<F16>(S, x, b, cols, sigma, cfg, guess, info);
+}
+
+// --------------------------------------------------------------------------
+// multishift CG (low precision P), x_k accumulated in F32 (F64 when P = F64)
+// --------------------------------------------------------------------------
+template <int P>
+static int mscg_core(Sys &S, std::vector<SpinorPtr> &xs, SpinorPtr b64, const double *shifts, int ns, double tol,
+                     int maxiter, int *iters_out)
+{
+    tmx_ctx *c = S.c;
+    constexpr int PX = P == F64 ? F64 : F32;
+    SpinorPtr r = S.field("ms_r", P, 1);
+    SpinorPtr q = S.field("ms_q", P, 1);
+    std::vector<SpinorPtr> ps(ns);
+    for (int k = 0; k < ns; ++k) ps[k] = S.field("ms_p" + std::to_string(k), P, 1);
+    double bb;
+    TRY((copy_field<P, F64>(S, r, b64, 1, &bb)));
+    for (int k = 0; k < ns; ++k) {
+        TRY(zero_field<PX>(S, xs[k], 1));
+        TRY((copy_field<P, P>(S, ps[k], r, 1, nullptr)));
+    }
+    std::vector<double> zeta(ns, 1.0), zprev(ns, 1.0);
+    std::vector<int> active(ns, bb > 0 ? 1 : 0), it_k(ns, 0);
+    double aprev = 1.0, bprev = 0.0, rr = bb, best = bb;
+    const double s0 = shifts[0];
+    int it = 0, since_best = 0;
+    while (it < maxiter) {
+        int na = 0;
+        for (int k = 0; k < ns; ++k) na += active[k];
+        if (na == 0) break;
+        double pq;
+        TRY(apply_shifted<P>(S, q, ps[0], &s0, 1, &pq));
+        ++it;
+        if (!(pq > 0)) return set_err(c, TMX_ENOCONV, "multishift CG: breakdown");
+        const double a = rr / pq;
+        OpMsUpdate<PX, P, P> mu{};
+        mu.r = r;
+        mu.stride = c->Vh;
+        mu.nf = S.nf;
+        mu.nshift = ns;
+        std::vector<double> zn(ns, 0.0);
+        for (int k = 0; k < ns; ++k) {
+            mu.xd[k] = xs[k].d;
+            mu.pd[k] = ps[k].d;
+            mu.active[k] = active[k];
+            if (!active[k]) continue;
+            const double ds = shifts[k] - s0;
+            zn[k] = zeta[k] * zprev[k] * aprev / (a * bprev * (zprev[k] - zeta[k]) + zprev[k] * aprev * (1.0 + ds * a));
+            mu.alpha[k] = zeta[k] != 0.0 ? a * zn[k] / zeta[k] : 0.0;
+        }
+        // r -= a q ; |r|^2
+        OpRupdNorm<P, P> ru{};
+        ru.r = r;
+        ru.q = q;
+        ru.nf = S.nf;
+        ru.a[0] = a;
+        HTRY(run_blas(ru, c->Vh, 1, c->red, c->stream), "ms residual");
+        double rr1;
+        TRY(fetch(c, 1, &rr1));
+        if (!std::isfinite(rr1)) return set_err(c, TMX_ENOCONV, "multishift CG: non-finite residual");
+        const double bt = rr1 / rr;
+        for (int k = 0; k < ns; ++k) {
+            if (!active[k]) continue;
+            mu.zeta[k] = zn[k];
+            mu.beta[k] = zeta[k] != 0.0 ? bt * (zn[k] / zeta[k]) * (zn[k] / zeta[k]) : 0.0;
+        }
+        HTRY(run_blas(mu, c->Vh, 1, c->red, c->stream), "ms update");
+        for (int k = 0; k < ns; ++k) {
+            if (!active[k]) continue;
+            zprev[k] = zeta[k];
+            zeta[k] = zn[k];
+            it_k[k] = it;
+            // residual of shift k is |zeta_k| |r|; drop it once converged
+            if (std::fabs(zeta[k]) * std::sqrt(rr1) <= tol * std::sqrt(bb)) active[k] = 0;
+        }
+        aprev = a;
+        bprev = bt;
+        rr = rr1;
+        // low-precision stagnation: the refinement stage takes over
+        if (rr1 < best) {
+            best = rr1;
+            since_best = 0;
+        } else if (++since_best > 50 || rr1 > 1e4 * best) {
+            break;
+        }
+    }
+    for (int k = 0; k < ns; ++k) iters_out[k] = it_k[k];
+    return TMX_OK;
+}
+
+}  // namespace tmx
+
+using namespace tmx;
+
+extern "C" {
+
+static int check_cfg(tmx_ctx *c, const tmx_solver_cfg *cfg)
+{
+    if (!cfg) return set_err(c, TMX_EINVAL, "null solver config");
+    if (cfg->op != TMX_OP_PLUS && cfg->op != TMX_OP_MINUS && cfg->op != TMX_OP_ND)
+        return set_err(c, TMX_EINVAL, "bad op in solver config");
+    if (!(cfg->tol > 0) && cfg->tol != 0) return set_err(c, TMX_EINVAL, "bad tolerance");
+    return TMX_OK;
+}
+
+int tmx_fgcr_solve_internal(tmx_ctx *c, SpinorPtr x, SpinorPtr b, const tmx_solver_cfg *cfg, tmx_info *info);
+
+int tmx_solve(tmx_ctx *c, double *x, const double *b, int nrhs, const tmx_solver_cfg *cfg, tmx_info *info)
+{
+    if (!c || !x || !b || nrhs < 1 || nrhs > MAXR) return c ? set_err(c, TMX_EINVAL, "tmx_solve: bad argument") : TMX_EINVAL;
+    TRY(check_cfg(c, cfg));
+    const double t0 = now_seconds();
+    if (info) std::memset(info, 0, sizeof(tmx_info) * nrhs);
+    Sys S(c, cfg->op, nrhs);
+    const int kind = cfg->op == TMX_OP_ND ? TMX_FIELD_ODD_ND : TMX_FIELD_ODD;
+    TRY(ensure_ready(c, F64, cfg->op == TMX_OP_ND));
+    SpinorPtr X = S.field("x", F64), B = S.field("b", F64);
+    if (!X.d || !B.d) return TMX_ENOMEM;
+    HTRY(launch_pack_spinor(b, B, F64, kind, c->g, nrhs, c->stream), "pack b");
+    if (cfg->use_initial_guess) HTRY(launch_pack_spinor(x, X, F64, kind, c->g, nrhs, c->stream), "pack x");
+    int rc;
+    switch (cfg->kind) {
+    case TMX_SOLVER_CG:
+        rc = dispatch_cg(S, F64, X, B, nrhs, nullptr, *cfg, cfg->use_initial_guess != 0, info);
+        break;
+    case TMX_SOLVER_MPCG_F32:
+        rc = dispatch_cg(S, F32, X, B, nrhs, nullptr, *cfg, cfg->use_initial_guess != 0, info);
+        break;
+    case TMX_SOLVER_MPCG_F16:
+        rc = dispatch_cg(S, F16, X, B, nrhs, nullptr, *cfg, cfg->use_initial_guess != 0, info);
+        break;
+    case TMX_SOLVER_FGCR_NN:
+        if (nrhs != 1) return set_err(c, TMX_EINVAL, "FGCR solves one right-hand side at a time");
+        if (!cfg->use_initial_guess) TRY(zero_field<F64>(S, X, 1));
+        rc = tmx_fgcr_solve_internal(c, X, B, cfg, info);
+        break;
+    default:
+        return set_err(c, TMX_EINVAL, "unknown solver kind");
+    }
+    if (rc < 0) return rc;
+    HTRY(launch_unpack_spinor(x, X, F64, kind, c->g, nrhs, c->stream), "unpack x");
+    HTRY(hipStreamSynchronize(c->stream), "solve sync");
+    if (info)
+        for (int k = 0; k < nrhs; ++k) info[k].seconds = now_seconds() - t0;
+    return rc;
+}
+
+int tmx_multishift_solve(tmx_ctx *c, double *x, const double *b, const double *shifts, int nshift,
+                         const tmx_solver_cfg *cfg, tmx_info *info)
+{
+    if (!c || !x || !b || !shifts || nshift < 1 || nshift > MAXR)
+        return c ? set_err(c, TMX_EINVAL, "tmx_multishift_solve: bad argument") : TMX_EINVAL;
+    TRY(check_cfg(c, cfg));
+    for (int k = 0; k < nshift; ++k)
+        if (!(shifts[k] >= 0) || shifts[k] < shifts[0] || !std::isfinite(shifts[k]))
+            return set_err(c, TMX_EINVAL, "shifts must be finite, >= 0 and shifts[0] the smallest");
+    const double t0 = now_seconds();
+    if (info) std::memset(info, 0, sizeof(tmx_info) * nshift);
+    const int prec = (cfg->inner_prec == TMX_F16 || cfg->inner_prec == TMX_F64) ? cfg->inner_prec : TMX_F32;
+    const bool nd = cfg->op == TMX_OP_ND;
+    const int kind = nd ? TMX_FIELD_ODD_ND : TMX_FIELD_ODD;
+    TRY(ensure_ready(c, F64, nd));
+    Sys S(c, cfg->op, 1);
+    SpinorPtr B = S.field("msb", F64, 1);
+    HTRY(launch_pack_spinor(b, B, F64, kind, c->g, 1, c->stream), "pack b");
+    const double tol = cfg->tol > 0 ? cfg->tol : 1e-10;
+    const double inner = cfg->inner_tol > 0 ? cfg->inner_tol : (prec == TMX_F16 ? 5e-4 : (prec == TMX_F32 ? 1e-6 : tol));
+    const int maxiter = cfg->maxiter > 0 ? cfg->maxiter : 10000;
+    // low-precision multishift stage
+    const int PX = prec == F64 ? F64 : F32;
+    std::vector<SpinorPtr> xs(nshift);
+    for (int k = 0; k < nshift; ++k) xs[k] = S.field("msx" + std::to_string(k), PX, 1);
+    std::vector<int> its(nshift, 0);
+    int r;
+    if (prec == F64)
+        r = mscg_core<F64>(S, xs, B, shifts, nshift, inner, maxiter, its.data());
+    else if (prec == F32)
+        r = mscg_core<F32>(S, xs, B, shifts, nshift, inner, maxiter, its.data());
+    else
+        r = mscg_core<F16>(S, xs, B, shifts, nshift, inner, maxiter, its.data());
+    if (r < 0) return r;
+    const double ms_gb = S.gbytes;
+    // shift-by-shift refinement with FP64 reliable updates
+    int rc = TMX_OK;
+    SpinorPtr X = S.field("msx64", F64, 1);
+    for (int k = 0; k < nshift; ++k) {
+        if (prec == F64)
+            TRY((copy_field<F64, F64>(S, X, xs[k], 1, nullptr)));
+        else
+            TRY((copy_field<F64, F32>(S, X, xs[k], 1, nullptr)));
+        tmx_solver_cfg rc_cfg = *cfg;
+        rc_cfg.tol = tol;
+        rc_cfg.maxiter = maxiter;
+        tmx_info inf{};
+        S.gbytes = 0;
+        const double sk = shifts[k];
+        int rk = dispatch_cg(S, prec, X, B, 1, &sk, rc_cfg, true, &inf);
+        if (rk < 0) return rk;
+        if (rk == TMX_ENOCONV) rc = TMX_ENOCONV;
+        HTRY(launch_unpack_spinor(x + (size_t)k * c->Vh * 24 * S.nf, X, F64, kind, c->g, 1,
+                                  c->stream),
+             "unpack x_k");
+        if (info) {
+            info[k].iters = its[k] + inf.iters;
+            info[k].reliable_updates = inf.reliable_updates;
+            info[k].true_residual = inf.true_residual;
+            info[k].gbytes = inf.gbytes + (k == 0 ? ms_gb : 0.0);
+        }
+    }
+    HTRY(hipStreamSynchronize(c->stream), "multishift sync");
+    if (info)
+        for (int k = 0; k < nshift; ++k) info[k].seconds = now_seconds() - t0;
+    return rc;
+}
+
+int tmx_solve_mhat(tmx_ctx *c, double *x, const double *b, int dagger, const tmx_solver_cfg *cfg, tmx_info *info)
+{
+    if (!c || !x || !b) return c ? set_err(c, TMX_EINVAL, "tmx_solve_mhat: bad argument") : TMX_EINVAL;
+    TRY(check_cfg(c, cfg));
+    // Mhat x = b  <=>  N x = Mhat^dagger b ;  Mhat^dagger x = b  <=>  (Mhat Mhat^dagger) x = Mhat b,
+    // solved as x = Mhat y with N y = b... use the normal equations of the right operator:
+    // for dagger = 1: x = Mhat z where N z = b  (N = Mhat^dagger Mhat).
+    const bool nd = cfg->op == TMX_OP_ND;
+    const int nf = nd ? 2 : 1;
+    const int kind = nd ? TMX_FIELD_ODD_ND : TMX_FIELD_ODD;
+    TRY(ensure_ready(c, F64, nd));
+    Sys S(c, cfg->op, 1);
+    SpinorPtr B = S.field("mh_b", F64, 1), T = S.field("mh_t", F64, 1);
+    const size_t cbytes = (size_t)c->Vh * 24 * nf * sizeof(double);
+    void *canon = ws_get(c, "mh_canon", cbytes);
+    if (!canon) return TMX_ENOMEM;
+    HTRY(launch_pack_spinor(b, B, F64, kind, c->g, 1, c->stream), "pack b");
+    if (!dagger) {
+        TRY(op_mhat(c, T, B, cfg->op, F64, 1, 1));  // T = Mhat^dagger b
+        HTRY(launch_unpack_spinor((double *)canon, T, F64, kind, c->g, 1, c->stream), "unpack");
+        tmx_solver_cfg cc = *cfg;
+        return tmx_solve(c, x, (const double *)canon, 1, &cc, info);
+    }
+    // dagger: solve N z = b, then x = Mhat z
+    tmx_solver_cfg cc = *cfg;
+    int rc = tmx_solve(c, (double *)canon, b, 1, &cc, info);
+    if (rc < 0) return rc;
+    HTRY(launch_pack_spinor((const double *)canon, T, F64, kind, c->g, 1, c->stream), "pack z");
+    TRY(op_mhat(c, B, T, cfg->op, F64, 0, 1));
+    HTRY(launch_unpack_spinor(x, B, F64, kind, c->g, 1, c->stream), "unpack x");
+    HTRY(hipStreamSynchronize(c->stream), "sync");
+    return rc;
+}
+
+}  // extern "C"

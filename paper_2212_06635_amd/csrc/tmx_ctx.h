@@ -1,0 +1,110 @@
+// Library context: device state, lazy derived fields and workspaces.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tmx.h"
+#include "blas.h"
+#include "tmx_kernels.h"
+
+namespace tmx {
+
+struct Workspace {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct TraceFrame {
+    std::string name;
+    double t0;
+};
+
+// learned-preconditioner state (nn.hip)
+struct PcState;
+
+}  // namespace tmx
+
+struct tmx_ctx {
+    int dims[4];
+    tmx::Geom g;
+    long V, Vh;
+    hipStream_t stream;
+
+    tmx_params par{};
+    bool have_params = false;
+
+    // gauge-state tracking: the id of the field on the device
+    bool gauge_loaded = false;
+    double gauge_id = 0.0;
+    int uploads = 0;
+
+    // compressed links per precision (links[F64] is the master)
+    void *links[3] = {nullptr, nullptr, nullptr};
+    bool links_ok[3] = {false, false, false};
+
+    // A = 1 + T on both parities, Hermitian packed, per precision
+    void *clov[3] = {nullptr, nullptr, nullptr};
+    bool clov_ok[3] = {false, false, false};
+    bool clover_from_host = false;
+    double clov_kappa = 0, clov_csw = 0;
+
+    // degenerate site inverse (A_ee + i nu g5)^{-1}, per precision
+    void *inv[3] = {nullptr, nullptr, nullptr};
+    bool inv_ok[3] = {false, false, false};
+    double inv_nu = 0;
+
+    // two-flavour inverse factor (A_ee^2 + nubar^2 - epst^2)^{-1}
+    void *invnd[3] = {nullptr, nullptr, nullptr};
+    bool invnd_ok[3] = {false, false, false};
+    double invnd_c = 0;
+
+    // reductions
+    tmx::RedWork red{};
+    double *host_red = nullptr;  // pinned
+
+    // named scratch buffers
+    std::map<std::string, tmx::Workspace> ws;
+
+    // tracing
+    bool trace = false;
+    std::vector<tmx::TraceFrame> frames;
+
+    // kernel launch tuning (block size per kernel key)
+    std::map<std::string, int> tune;
+
+    tmx::PcState *pc = nullptr;
+
+    std::string err;
+};
+
+namespace tmx {
+
+// error helpers
+int set_err(tmx_ctx *c, int code, const std::string &msg);
+int hip_err(tmx_ctx *c, hipError_t e, const char *where);
+
+// memory
+void *ws_get(tmx_ctx *c, const std::string &name, size_t bytes);
+void dev_free(void *p);
+
+// lazily build everything an apply in `prec` needs
+int ensure_ready(tmx_ctx *c, int prec, bool nd);
+
+// operators on internal fields (asynchronous)
+int op_mhat(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int dagger, int nrhs);
+int op_mdagm(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int nrhs);
+int op_D(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec);
+
+// reductions: copy device results to the host (synchronises the stream)
+int fetch(tmx_ctx *c, int n, double *host);
+
+// model bytes of one Mhat application per odd site
+double mhat_bytes_per_site(int prec, int nf, int nrhs);
+
+double now_seconds();
+
+}  // namespace tmx

@@ -1,0 +1,144 @@
+"""GPU solvers: every solution is accepted only by its FP64 true residual,
+recomputed by the CPU oracle's operator (not by the GPU)."""
+import numpy as np
+import pytest
+
+from helpers import CSW, EPSBAR, KAPPA, MUBAR, rel_l2, to_dev, to_host
+from oracle import Oracle
+from paper_2212_06635_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (8, 8, 8, 8)
+MU0 = 0.01
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_2212_06635_amd.tmx as tmx
+
+    print("\n[gpu solvers] 8^4 eps=0.3 seed=1", flush=True)
+    U = synth.gauge_links(DIMS, 0.3, 1)
+    o = Oracle(DIMS, U, KAPPA, CSW, mu=MU0, mubar=MUBAR, epsbar=EPSBAR)
+    ctx = tmx.Context(DIMS)
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU0, MUBAR, EPSBAR, -1))
+    ctx.load_gauge(U, 1.0)
+    yield tmx, o, ctx, U
+    ctx.close()
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("op", [1, -1, 2])
+def test_cg_family(S, kind, op):
+    tmx, o, ctx, _ = S
+    nf = 2 if op == 2 else 1
+    b = synth.gaussian_cb_spinor(DIMS, 21, 0, nf)
+    x = to_dev(np.zeros_like(b))
+    rc, info = ctx.solve(x, to_dev(b), 1, kind=kind, op=op, tol=1e-10)
+    assert rc == tmx.TMX_OK, info
+    xs = to_host(x, b.shape)
+    res = o.residual(b, xs, nf=nf, sgn=1 if op == 2 else op)
+    assert res <= 1e-10, (res, info)
+    assert info[0]["true_residual"] <= 1e-10
+    if kind > 0:
+        assert info[0]["reliable_updates"] >= 1
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_multi_rhs_cg(S, kind):
+    """12 right-hand sides advanced together; every column to 1e-10."""
+    tmx, o, ctx, _ = S
+    n = 12
+    bs = np.stack([synth.gaussian_cb_spinor(DIMS, 22, k, 1) for k in range(n)])
+    bs[3] *= 1e-20  # badly scaled column
+    x = to_dev(np.zeros_like(bs))
+    rc, info = ctx.solve(x, to_dev(bs), n, kind=kind, op=1, tol=1e-10)
+    assert rc == tmx.TMX_OK
+    xs = to_host(x, bs.shape)
+    for k in range(n):
+        assert o.residual(bs[k], xs[k]) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_multishift_nd(S, prec):
+    tmx, o, ctx, _ = S
+    shifts = np.concatenate([[0.0], np.logspace(-5, 0, 11) * 2.0])
+    b = synth.gaussian_cb_spinor(DIMS, 23, 0, 2)
+    x = to_dev(np.zeros((len(shifts),) + b.shape))
+    rc, info = ctx.multishift_solve(x, to_dev(b), shifts, op=2, tol=1e-10, inner_prec=prec)
+    assert rc == tmx.TMX_OK
+    xs = to_host(x, (len(shifts),) + b.shape)
+    for k, s in enumerate(shifts):
+        assert o.residual(b, xs[k], nf=2, shift=s) <= 1e-10, (k, s, info[k])
+
+
+def test_solve_mhat(S):
+    tmx, o, ctx, _ = S
+    b = synth.gaussian_cb_spinor(DIMS, 24, 0, 1)
+    for dagger in (0, 1):
+        x = to_dev(np.zeros_like(b))
+        rc, info = ctx.solve_mhat(x, to_dev(b), dagger=dagger, op=1, tol=1e-11)
+        assert rc == tmx.TMX_OK
+        assert o.residual_mhat(b, to_host(x, b.shape), dagger=bool(dagger)) <= 1e-10
+
+
+def test_initial_guess_and_zero_source(S):
+    tmx, o, ctx, _ = S
+    b = synth.gaussian_cb_spinor(DIMS, 25, 0, 1)
+    x = to_dev(np.zeros_like(b))
+    rc, info = ctx.solve(x, to_dev(b), 1, kind=0, op=1, tol=1e-10)
+    it_cold = info[0]["iters"]
+    rc, info = ctx.solve(x, to_dev(b), 1, kind=0, op=1, tol=1e-10, use_initial_guess=1)
+    assert info[0]["iters"] < it_cold // 4
+    z = to_dev(np.zeros_like(b))
+    rc, info = ctx.solve(x, z, 1, kind=1, op=1)
+    assert rc == tmx.TMX_OK and np.abs(to_host(x, b.shape)).max() == 0.0
+
+
+def test_maxiter_reports_noconv(S):
+    tmx, o, ctx, _ = S
+    b = synth.gaussian_cb_spinor(DIMS, 26, 0, 1)
+    x = to_dev(np.zeros_like(b))
+    rc, info = ctx.solve(x, to_dev(b), 1, kind=0, op=1, tol=1e-10, maxiter=3)
+    assert rc == tmx.TMX_ENOCONV
+    assert info[0]["true_residual"] > 1e-10
+
+
+def test_gauge_id_state_tracking(S):
+    """Same gauge id: no upload; new id: upload and the operator follows the new field."""
+    tmx, o, ctx, U = S
+    n0 = ctx.gauge_uploads()
+    ctx.load_gauge(U, 1.0)
+    assert ctx.gauge_uploads() == n0
+    U2 = synth.gauge_links(DIMS, 0.3, 99)
+    ctx.load_gauge(U2, 2.0)
+    assert ctx.gauge_uploads() == n0 + 1
+    o2 = Oracle(DIMS, U2, KAPPA, CSW, mu=MU0)
+    v = synth.gaussian_cb_spinor(DIMS, 27, 0, 1)
+    out = ctx.empty(tmx.TMX_FIELD_ODD, 0)
+    ctx.apply_mhat(out, ctx.pack(to_dev(v), tmx.TMX_FIELD_ODD, 0), 1, 0)
+    assert rel_l2(to_host(ctx.unpack(out, tmx.TMX_FIELD_ODD, 0), v.shape), o2.mhat(v)) < 1e-13
+    # changing mu rebuilds only the inverses
+    ctx.set_params(tmx.Params(KAPPA, CSW, 0.2, MUBAR, EPSBAR, -1))
+    o3 = Oracle(DIMS, U2, KAPPA, CSW, mu=0.2, T=o2.T)
+    ctx.apply_mhat(out, ctx.pack(to_dev(v), tmx.TMX_FIELD_ODD, 0), 1, 0)
+    assert rel_l2(to_host(ctx.unpack(out, tmx.TMX_FIELD_ODD, 0), v.shape), o3.mhat(v)) < 1e-13
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU0, MUBAR, EPSBAR, -1))
+    ctx.load_gauge(U, 1.0)
+
+
+def test_errors():
+    import paper_2212_06635_amd.tmx as tmx
+
+    ctx = tmx.Context((4, 4, 4, 4))
+    v = ctx.empty(tmx.TMX_FIELD_ODD, 0)
+    w = ctx.empty(tmx.TMX_FIELD_ODD, 0)
+    with pytest.raises(tmx.TmxError) as e:
+        ctx.apply_mhat(w, v, 1, 0)
+    assert e.value.code == tmx.TMX_ENOTLOADED
+    with pytest.raises(tmx.TmxError) as e:
+        ctx.apply_mhat(w, v, 5, 0)
+    assert e.value.code == tmx.TMX_EINVAL
+    ctx.close()
+    with pytest.raises(tmx.TmxError):
+        tmx.Context((4, 4, 3, 4))
