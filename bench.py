@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the twisted-mass clover hot path on one MI355X.
+
+One step = one pass over the hot path on a 32^3x64 synthetic gauge field
+(kappa = 0.1394, csw = 1.69, mu = 0.00072; two-flavour mubar = 0.1246,
+epsbar = 0.1315; links U = proj_SU3(exp(i 0.25 H)), seed 4):
+
+  * Schur operator Mhat applied to a Gaussian source in FP64, FP32 and FP16
+    storage (NAPPLY applications each), the normal operator N in FP64 and
+    the two-flavour Mhat_h in FP32;
+  * plain FP64 CG on N to a 1e-10 FP64 true residual;
+  * mixed-precision CG (FP32 and FP16-storage inner iterations, FP64
+    reliable updates) to the same FP64 true residual.
+
+The headline value is the FP64 Schur-operator bandwidth: model bytes of one
+Mhat application (links, spinors and clover blocks each read once per
+stencil pass) divided by its measured time (HIP events on the library's
+stream), summed over all timed steps.  All inputs are resident in HBM before
+the timed region.  Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Schur dslash GB/s (% HBM peak); CG time-to-1e-10, plain vs mixed+learned PC"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+KAPPA, CSW, MU, MUBAR, EPSBAR = 0.1394, 1.69, 0.00072, 0.1246, 0.1315
+NAPPLY = 20
+
+# algorithmic bytes per output site of one stencil launch (each input read
+# once): bytes per real b; F16 adds a 4-byte scale per spinor read/write
+def kernel_bytes_per_site(kernel: str) -> float:
+    prec = "f64" if "f64" in kernel else ("f32" if "f32" in kernel else "f16")
+    b = {"f64": 8, "f32": 4, "f16": 2}[prec]
+    nd = "_nd" in kernel
+    nrhs = int(kernel.split("_r")[-1]) if "_r" in kernel else 1
+    nf = 2 if nd else 1
+    norm = 4 if prec == "f16" else 0
+    if kernel.startswith("K1"):
+        fixed = 96 * b + (144 * b)  # 8 links x 12 reals; inverse blocks (deg: 2 full 6x6; nd: A + B Hermitian)
+        spin = nf * (48 * b + 2 * norm)  # read in, write out
+    else:
+        fixed = 96 * b + 72 * b  # links; Hermitian A_oo
+        spin = nf * (72 * b + 3 * norm)  # read hop input and x, write out
+    return fixed + nrhs * spin
+
+
+def mhat_bytes_per_site(prec: str, nf: int = 1) -> float:
+    k = "_nd" if nf == 2 else ""
+    return kernel_bytes_per_site(f"K1_{prec}{k}") + kernel_bytes_per_site(f"K2_{prec}{k}")
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(dims, U, b, napply):
+    """The FP64 oracle timed on the host cores on a bounded sample."""
+    from oracle import Oracle
+    from oracle.oracle import num_threads
+
+    t = time.perf_counter()
+    o = Oracle(dims, U, KAPPA, CSW, mu=MU)
+    log(f"oracle clover built in {time.perf_counter() - t:.1f}s")
+    o.mhat(b)  # warm
+    t = time.perf_counter()
+    for _ in range(napply):
+        o.mhat(b)
+    dt = (time.perf_counter() - t) / napply
+    Vh = o.Vh
+    gbs = mhat_bytes_per_site("f64") * Vh / dt / 1e9
+    return o, {"value": gbs, "unit": "GB/s", "cores": num_threads(), "kind": "oracle",
+               "sample": f"{napply} FP64 Mhat applications at {'x'.join(map(str, dims))} "
+                         f"({dt:.3f} s each, same model bytes as the GPU figure)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dims", default="32,32,32,64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-applies", type=int, default=3)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one MI355X: the path is built and validated for a single GPU "
+              "(multi-GPU sharding is a design note only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2212_06635_amd.tmx as tmx
+    from paper_2212_06635_amd import synth
+
+    dims = tuple(int(x) for x in args.dims.split(","))
+    torch.cuda.set_device(0)
+    log(f"generating {dims} gauge field")
+    U = synth.gauge_links(dims, 0.25, 4)
+    b = synth.gaussian_cb_spinor(dims, 4, 0)
+    b2 = synth.gaussian_cb_spinor(dims, 4, 1, 2)
+    ctx = tmx.Context(dims)
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU, MUBAR, EPSBAR, -1))
+    ctx.load_gauge(U, 4.0)
+    Vh = ctx.Vh
+    bd = torch.from_numpy(b.reshape(-1)).cuda()
+    b2d = torch.from_numpy(b2.reshape(-1)).cuda()
+    src = {p: ctx.pack(bd, tmx.TMX_FIELD_ODD, p) for p in (0, 1, 2)}
+    dst = {p: ctx.empty(tmx.TMX_FIELD_ODD, p) for p in (0, 1, 2)}
+    src_nd = ctx.pack(b2d, tmx.TMX_FIELD_ODD_ND, 1)
+    dst_nd = ctx.empty(tmx.TMX_FIELD_ODD_ND, 1)
+    x = torch.zeros_like(bd)
+    names = {0: "f64", 1: "f32", 2: "f16"}
+    log("setup done")
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        return e0, e1
+
+    def step():
+        ev = {}
+        for p in (0, 1, 2):
+            ev[names[p]] = timed(lambda: [ctx.apply_mhat(dst[p], src[p], 1, p) for _ in range(NAPPLY)])
+        ev["N_f64"] = timed(lambda: [ctx.apply_mdagm(dst[0], src[0], 1, 0) for _ in range(NAPPLY)])
+        ev["nd_f32"] = timed(lambda: [ctx.apply_mhat(dst_nd, src_nd, 2, 1) for _ in range(NAPPLY)])
+        solves = {}
+        for kind, nm in ((tmx.TMX_SOLVER_CG, "cg_f64"), (tmx.TMX_SOLVER_MPCG_F32, "mpcg_f32"),
+                         (tmx.TMX_SOLVER_MPCG_F16, "mpcg_f16")):
+            x.zero_()
+            t = time.perf_counter()
+            rc, info = ctx.solve(x, bd, 1, kind=kind, op=1, tol=1e-10)
+            solves[nm] = {"seconds": time.perf_counter() - t, "iters": info[0]["iters"],
+                          "reliable_updates": info[0]["reliable_updates"],
+                          "true_residual": info[0]["true_residual"], "rc": rc}
+        return ev, solves
+
+    for w in range(args.warmup):
+        step()
+        log(f"warmup step {w + 1}/{args.warmup} done")
+    ctx.kstats_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs, last = [], None
+    for k in range(args.steps):
+        ev, last = step()
+        evs.append(ev)
+        log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ks = ctx.kstats()
+    ctx.kstats_enable(False)
+
+    def gbs(key, per_site):
+        ms = sum(e[key][0].elapsed_time(e[key][1]) for e in evs)
+        return per_site * Vh * NAPPLY * len(evs) / (ms * 1e-3) / 1e9, ms / (NAPPLY * len(evs))
+
+    dslash = {}
+    for p in ("f64", "f32", "f16"):
+        g, ms = gbs(p, mhat_bytes_per_site(p))
+        dslash[p] = {"GBps": round(g, 1), "pct_hbm_peak": round(100 * g / HBM_PEAK_GBS, 1), "ms": round(ms, 4)}
+    g, ms = gbs("N_f64", 2 * mhat_bytes_per_site("f64"))
+    dslash["N_f64"] = {"GBps": round(g, 1), "pct_hbm_peak": round(100 * g / HBM_PEAK_GBS, 1), "ms": round(ms, 4)}
+    g, ms = gbs("nd_f32", mhat_bytes_per_site("f32", 2))
+    dslash["nd_f32"] = {"GBps": round(g, 1), "pct_hbm_peak": round(100 * g / HBM_PEAK_GBS, 1), "ms": round(ms, 4)}
+
+    # dominant stencil kernel of the timed region (largest summed time)
+    dom = max(ks.items(), key=lambda kv: kv[1][1])
+    dname, (dcount, dms) = dom
+    per_launch_bytes = kernel_bytes_per_site(dname) * Vh
+    avg_ms = dms / dcount
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dname,
+                "avg_launch_ms": round(avg_ms, 4), "launches": dcount,
+                "bytes_per_launch": per_launch_bytes}
+
+    out = {
+        "metric": METRIC,
+        "value": dslash["f64"]["GBps"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round((t1 - t0) * 1e3 / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "32^3x64 Wilson twisted-mass clover: Schur Mhat apply + CG / MP-CG to 1e-10"
+                   if dims == (32, 32, 32, 64) else f"{'x'.join(map(str, dims))} twisted-mass clover",
+                   "lattice": list(dims), "kappa": KAPPA, "csw": CSW, "mu": MU, "mubar": MUBAR,
+                   "epsbar": EPSBAR, "link_eps": 0.25, "seed": 4, "t_bc": "antiperiodic"},
+        "pct_hbm_peak": dslash["f64"]["pct_hbm_peak"],
+        "dslash": dslash,
+        "solves": last,
+        "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in ks.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        o, cb = cpu_baseline(dims, U, b, args.cpu_applies)
+        out["cpu_baseline"] = cb
+        # the plain-CG solution of the last step, checked by the oracle's operator
+        x.zero_()
+        ctx.solve(x, bd, 1, kind=tmx.TMX_SOLVER_MPCG_F16, op=1, tol=1e-10)
+        out["solves"]["mpcg_f16"]["oracle_true_residual"] = o.residual(b, x.cpu().numpy().reshape(b.shape))
+    else:
+        out["cpu_baseline"] = None
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -210,6 +210,17 @@ typedef struct {
 int tmx_pc_train(tmx_ctx *ctx, const double *b, const double *x, int npairs, const tmx_train_cfg *cfg,
                  float *loss_out);
 
+/* ---- kernel timing -------------------------------------------------------- */
+
+/* Bracket every stencil kernel launch with HIP events on the context's
+ * stream (on != 0) and clear the accumulated statistics; on = 0 stops
+ * recording.  Adds one event pair per launch. */
+int tmx_kstats_enable(tmx_ctx *ctx, int on);
+/* Statistics of kernel idx (0-based, in name order): name ("K1_f64",
+ * "K2_f32_nd_r12", ...), launch count and summed duration in ms.
+ * Synchronises on the recorded events.  TMX_EINVAL past the last kernel. */
+int tmx_kstats_get(tmx_ctx *ctx, int idx, char *name, size_t name_len, long *count, double *total_ms);
+
 /* ---- tracing ------------------------------------------------------------ */
 
 /* Hierarchical timers: push starts a timer at the next level of the call

@@ -39,6 +39,8 @@ def load_library():
     I = ctypes.c_int
     D = ctypes.c_double
     L = ctypes.c_long
+    lib.orc_num_threads.argtypes = []
+    lib.orc_num_threads.restype = I
     lib.orc_gammas.argtypes = [P, P]
     lib.orc_hop.argtypes = [P, I, P, P, P, I, I]
     lib.orc_clover.argtypes = [P, P, D, D, P]
@@ -58,6 +60,10 @@ def load_library():
     lib.orc_residual_mhat.restype = D
     _lib = lib
     return lib
+
+
+def num_threads() -> int:
+    return int(load_library().orc_num_threads())
 
 
 def _ptr(a: np.ndarray):

@@ -31,6 +31,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -136,6 +137,9 @@ static void init_gammas(void)
                 }
     gam_ready = 1;
 }
+
+/* number of OpenMP threads the oracle's parallel loops use */
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 /* export: gamma matrices (5*16 complex) and sigma (16*16 complex) */
 void orc_gammas(cplx *g, cplx *sig)

@@ -233,7 +233,64 @@ static const void *clov_parity(tmx_ctx *c, int prec, int parity)
 static int block_for(tmx_ctx *c, const char *key)
 {
     auto it = c->tune.find(key);
-    return it == c->tune.end() ? 256 : it->second;
+    return it == c->tune.end() ? c->default_block : it->second;
+}
+
+static hipEvent_t kev_get(tmx_ctx *c)
+{
+    if (!c->kpool.empty()) {
+        hipEvent_t e = c->kpool.back();
+        c->kpool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+static void kstat_collect(tmx_ctx *c)
+{
+    for (auto &k : c->kpending) {
+        float ms = 0.f;
+        if (k.a && k.b && hipEventSynchronize(k.b) == hipSuccess && hipEventElapsedTime(&ms, k.a, k.b) == hipSuccess) {
+            KStat &st = c->kstats[k.name];
+            st.count++;
+            st.ms += ms;
+        } else {
+            (void)hipGetLastError();
+        }
+        if (k.a) c->kpool.push_back(k.a);
+        if (k.b) c->kpool.push_back(k.b);
+    }
+    c->kpending.clear();
+}
+
+void kstat_begin(tmx_ctx *c, const std::string &name)
+{
+    if (!c->kstats_on) return;
+    if (c->kpending.size() > 4096) kstat_collect(c);
+    KEvent k{name, kev_get(c), nullptr};
+    if (k.a) (void)hipEventRecord(k.a, c->stream);
+    c->kpending.push_back(k);
+}
+
+void kstat_end(tmx_ctx *c)
+{
+    if (!c->kstats_on || c->kpending.empty()) return;
+    KEvent &k = c->kpending.back();
+    k.b = kev_get(c);
+    if (k.b) (void)hipEventRecord(k.b, c->stream);
+}
+
+static std::string kname(const char *k, int prec, bool nd, int nrhs)
+{
+    static const char *pn[3] = {"f64", "f32", "f16"};
+    std::string s = std::string(k) + "_" + pn[prec] + (nd ? "_nd" : "");
+    if (nrhs > 1) s += "_r" + std::to_string(nrhs);
+    return s;
 }
 
 static DslashArgs base_args(tmx_ctx *c, int prec, bool nd, int nrhs)
@@ -245,6 +302,7 @@ static DslashArgs base_args(tmx_ctx *c, int prec, bool nd, int nrhs)
     a.nu = nd ? 2.0 * c->par.kappa * c->par.mubar : 2.0 * c->par.kappa * c->par.mu;
     a.epst = nd ? 2.0 * c->par.kappa * c->par.epsbar : 0.0;
     a.t_bc = c->par.t_bc;
+    a.xcd = c->xcd_remap;
     return a;
 }
 
@@ -261,7 +319,9 @@ static int schur_pair(tmx_ctx *c, SpinorPtr out, SpinorPtr in, SpinorPtr u, int 
     a.clov = clov_parity(c, prec, 0);
     a.inv = nd ? c->invnd[prec] : c->inv[prec];
     a.g5in = g5in;
+    kstat_begin(c, kname("K1", prec, nd, nrhs));
     hipError_t e = launch_dslash(prec, nf, 0, a, c->stream, block_for(c, "k1"));
+    kstat_end(c);
     if (e != hipSuccess) return hip_err(c, e, "K1 launch");
     DslashArgs b = base_args(c, prec, nd, nrhs);
     b.sgn = sgn;
@@ -273,7 +333,9 @@ static int schur_pair(tmx_ctx *c, SpinorPtr out, SpinorPtr in, SpinorPtr u, int 
     b.kfac = c->par.kappa * c->par.kappa;
     b.g5x = g5in;
     b.g5out = g5out;
+    kstat_begin(c, kname("K2", prec, nd, nrhs));
     e = launch_dslash(prec, nf, 1, b, c->stream, block_for(c, "k2"));
+    kstat_end(c);
     if (e != hipSuccess) return hip_err(c, e, "K2 launch");
     return TMX_OK;
 }
@@ -385,6 +447,12 @@ int tmx_create(const int dims[4], void *hip_stream, tmx_ctx **out)
     }
     const char *tr = std::getenv("TMX_TRACE");
     c->trace = tr && tr[0] == '1';
+    // launch-shape overrides for sweeps (the autotuner sets per-kernel values)
+    if (const char *e = std::getenv("TMX_DSLASH_BLOCK")) {
+        int b = std::atoi(e);
+        if (b >= 64 && b <= 256 && b % 64 == 0) c->default_block = b;
+    }
+    if (const char *e = std::getenv("TMX_DSLASH_XCD")) c->xcd_remap = std::atoi(e) != 0;
     *out = c;
     return TMX_OK;
 }
@@ -402,6 +470,8 @@ int tmx_destroy(tmx_ctx *c)
         dev_free(c->invnd[p]);
     }
     for (auto &kv : c->ws) dev_free(kv.second.p);
+    kstat_collect(c);
+    for (hipEvent_t e : c->kpool) (void)hipEventDestroy(e);
     dev_free(c->red.partials);
     dev_free(c->red.result);
     if (c->host_red) (void)hipHostFree(c->host_red);
@@ -586,6 +656,32 @@ int tmx_apply_mdagm(tmx_ctx *c, void *out, const void *in, int op, int prec, int
     const long stride = c->Vh * nrhs;
     return op_mdagm(c, make_spinor(out, prec, nf, stride), make_spinor(const_cast<void *>(in), prec, nf, stride), op,
                     prec, nrhs);
+}
+
+// ---- kernel timing -----------------------------------------------------------
+int tmx_kstats_enable(tmx_ctx *c, int on)
+{
+    if (!c) return TMX_EINVAL;
+    kstat_collect(c);
+    c->kstats.clear();
+    c->kstats_on = on != 0;
+    return TMX_OK;
+}
+
+int tmx_kstats_get(tmx_ctx *c, int idx, char *name, size_t name_len, long *count, double *total_ms)
+{
+    if (!c || idx < 0) return TMX_EINVAL;
+    kstat_collect(c);
+    if (idx >= (int)c->kstats.size()) return TMX_EINVAL;
+    auto it = c->kstats.begin();
+    std::advance(it, idx);
+    if (name && name_len) {
+        std::strncpy(name, it->first.c_str(), name_len - 1);
+        name[name_len - 1] = 0;
+    }
+    if (count) *count = it->second.count;
+    if (total_ms) *total_ms = it->second.ms;
+    return TMX_OK;
 }
 
 // ---- tracing ---------------------------------------------------------------

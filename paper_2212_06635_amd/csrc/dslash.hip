@@ -31,6 +31,20 @@ namespace tmx {
 
 enum { MODE_INV = 0, MODE_DIAG = 1 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  With xcd != 0 the launch index is remapped so that XCD k works on one
+// contiguous 1/8 of the sites: neighbours in y, z and t then mostly hit the
+// L2 that already holds them.  (The map is a permutation of the blocks for
+// any grid, so the result never depends on the dispatch order.)
+__device__ __forceinline__ int xcd_block(int xcd)
+{
+    const int b = blockIdx.x;
+    if (!xcd) return b;
+    const int nb = gridDim.x, q = nb / 8, r = nb % 8;
+    const int k = b % 8, i = b / 8;
+    return k * q + (k < r ? k : r) + i;
+}
+
 // acc += (1 + sgn gamma_mu) * bc * W psi,  W = U (fwd) or U^dagger (bwd)
 template <int MU, int SGN, bool DAG, typename R>
 __device__ __forceinline__ void hop_term(const cx<R> u[9], R bc, const cx<R> psi[12], cx<R> acc[12])
@@ -143,6 +157,8 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, const int x[4], int
             load_spinor_g5<P>(a.in, f, (long)n * a.nrhs + rhs, a.g5in, psi);
             hop_term<MU, -1, false>(u, bc, psi, acc[f]);
         }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) reg_fence(acc[f], 12);
     }
     // backward: (1 + gamma_mu) U_mu(x - mu)^dagger psi(x - mu)
     {
@@ -161,6 +177,8 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, const int x[4], int
             load_spinor_g5<P>(a.in, f, (long)n * a.nrhs + rhs, a.g5in, psi);
             hop_term<MU, +1, true>(u, bc, psi, acc[f]);
         }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) reg_fence(acc[f], 12);
     }
 }
 
@@ -168,7 +186,7 @@ template <int P, int NF, int MODE>
 __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 {
     using R = typename RealOf<P>::type;
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long t = (long)xcd_block(a.xcd) * blockDim.x + threadIdx.x;
     if (t >= (long)a.g.Vh * a.nrhs) return;
     const int s = (int)(t / a.nrhs);
     const long rhs = t - (long)s * a.nrhs;
@@ -181,54 +199,85 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[f][k] = cx<R>{0, 0};
 
+    // one direction at a time (register fences inside hop_dir): holding every
+    // neighbour's data at once would need ~8x the registers and drop
+    // occupancy to one wave per SIMD
     hop_dir<P, NF, 0>(a, x, s, rhs, acc);
     hop_dir<P, NF, 1>(a, x, s, rhs, acc);
     hop_dir<P, NF, 2>(a, x, s, rhs, acc);
     hop_dir<P, NF, 3>(a, x, s, rhs, acc);
 
     const long cs = a.g.Vh;  // clover stride
+    // site-block epilogue, one chirality block at a time (register fences
+    // keep the two blocks' matrices from being live together)
     cx<R> out[NF][12];
     if constexpr (MODE == MODE_INV) {
         if constexpr (NF == 1) {
             const bool dag = a.sgn < 0;
             full_apply<P>(a.inv, cs, s, 0, dag, acc[0], out[0]);
+            reg_fence(out[0], 6);
             full_apply<P>(a.inv, cs, s, 1, dag, acc[0] + 6, out[0] + 6);
         } else {
-            // t_f = Binv acc_f ; out = (A - X) t
-            cx<R> tt[2][12];
-            herm_apply_site<P>(a.inv, cs, s, R(0), R(0), acc[0], tt[0]);
-            herm_apply_site<P>(a.inv, cs, s, R(0), R(0), acc[1], tt[1]);
+            // (A + X)^{-1} acc = (A - X) t,  t_f = Binv acc_f  (per chirality)
             const R nb = R(a.sgn * a.nu), ep = R(a.epst);
-            herm_apply_site<P>(a.clov, cs, s, -nb, nb, tt[0], out[0]);
-            herm_apply_site<P>(a.clov, cs, s, nb, -nb, tt[1], out[1]);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                out[0][k] = out[0][k] + ep * tt[1][k];
-                out[1][k] = out[1][k] + ep * tt[0][k];
+            for (int c = 0; c < 2; ++c) {
+                const R tw = c == 0 ? nb : -nb;  // i nubar g5 tau3 on flavour 0
+                cx<R> t0[6], t1[6];
+                herm_apply_c<P>(a.inv, cs, s, c, R(0), acc[0] + 6 * c, t0);
+                herm_apply_c<P>(a.inv, cs, s, c, R(0), acc[1] + 6 * c, t1);
+                reg_fence(t0, 6);
+                reg_fence(t1, 6);
+                herm_apply_c<P>(a.clov, cs, s, c, -tw, t0, out[0] + 6 * c);
+                herm_apply_c<P>(a.clov, cs, s, c, tw, t1, out[1] + 6 * c);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    out[0][6 * c + k] = out[0][6 * c + k] + ep * t1[k];
+                    out[1][6 * c + k] = out[1][6 * c + k] + ep * t0[k];
+                }
+                reg_fence(out[0] + 6 * c, 6);
+                reg_fence(out[1] + 6 * c, 6);
             }
         }
     } else {
         const R kf = R(a.kfac);
         const R nb = R(a.sgn * a.nu);
-        cx<R> xv[NF][12];
+        const R g5s = a.g5x ? R(-1) : R(1);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) load_spinor_g5<P>(a.x, f, t, a.g5x, xv[f]);
-        if constexpr (NF == 1) {
-            herm_apply_site<P>(a.clov, cs, s, nb, -nb, xv[0], out[0]);
-        } else {
-            const R ep = R(a.epst);
-            herm_apply_site<P>(a.clov, cs, s, nb, -nb, xv[0], out[0]);
-            herm_apply_site<P>(a.clov, cs, s, -nb, nb, xv[1], out[1]);
+        for (int c = 0; c < 2; ++c) {
+            const R tw = c == 0 ? nb : -nb;
+            const R gx = c == 0 ? R(1) : g5s;  // gamma5 on the diagonal input
+            if constexpr (NF == 1) {
+                cx<R> xv[6];
+                load_chiral<P>(a.x, 0, t, c, xv);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                out[0][k] = out[0][k] - ep * xv[1][k];
-                out[1][k] = out[1][k] - ep * xv[0][k];
+                for (int k = 0; k < 6; ++k) xv[k] = gx * xv[k];
+                herm_apply_c<P>(a.clov, cs, s, c, tw, xv, out[0] + 6 * c);
+            } else {
+                const R ep = R(a.epst);
+                cx<R> x0[6], x1[6];
+                load_chiral<P>(a.x, 0, t, c, x0);
+                load_chiral<P>(a.x, 1, t, c, x1);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    x0[k] = gx * x0[k];
+                    x1[k] = gx * x1[k];
+                }
+                herm_apply_c<P>(a.clov, cs, s, c, tw, x0, out[0] + 6 * c);
+                herm_apply_c<P>(a.clov, cs, s, c, -tw, x1, out[1] + 6 * c);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    out[0][6 * c + k] = out[0][6 * c + k] - ep * x1[k];
+                    out[1][6 * c + k] = out[1][6 * c + k] - ep * x0[k];
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) out[f][6 * c + k] = out[f][6 * c + k] - kf * acc[f][6 * c + k];
+                reg_fence(out[f] + 6 * c, 6);
             }
         }
-#pragma unroll
-        for (int f = 0; f < NF; ++f)
-#pragma unroll
-            for (int k = 0; k < 12; ++k) out[f][k] = out[f][k] - kf * acc[f][k];
     }
     if (a.g5out) {
 #pragma unroll

@@ -23,6 +23,16 @@ struct TraceFrame {
     double t0;
 };
 
+// per-kernel timing with HIP events on the context's stream
+struct KEvent {
+    std::string name;
+    hipEvent_t a, b;
+};
+struct KStat {
+    long count = 0;
+    double ms = 0;
+};
+
 // learned-preconditioner state (nn.hip)
 struct PcState;
 
@@ -73,8 +83,16 @@ struct tmx_ctx {
     bool trace = false;
     std::vector<tmx::TraceFrame> frames;
 
+    // kernel timing
+    bool kstats_on = false;
+    std::vector<tmx::KEvent> kpending;
+    std::vector<hipEvent_t> kpool;
+    std::map<std::string, tmx::KStat> kstats;
+
     // kernel launch tuning (block size per kernel key)
     std::map<std::string, int> tune;
+    int default_block = 64;
+    int xcd_remap = 1;
 
     tmx::PcState *pc = nullptr;
 
@@ -106,5 +124,9 @@ int fetch(tmx_ctx *c, int n, double *host);
 double mhat_bytes_per_site(int prec, int nf, int nrhs);
 
 double now_seconds();
+
+// kernel-timing brackets around a launch (no-ops unless enabled)
+void kstat_begin(tmx_ctx *c, const std::string &name);
+void kstat_end(tmx_ctx *c);
 
 }  // namespace tmx

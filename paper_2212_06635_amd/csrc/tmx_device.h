@@ -56,6 +56,16 @@ template <typename R> __device__ __forceinline__ void cmac_conj(cx<R> &a, cx<R> 
     a.im = fma(-b.im, c.re, a.im);
 }
 
+// Register fence: an empty asm that "modifies" the values forces everything
+// that produces them to be computed before any later memory operation (the
+// asm is volatile, so it is ordered with loads and stores).  Used to keep a
+// stencil from holding every neighbour's data in registers at once.
+template <typename R> __device__ __forceinline__ void reg_fence(cx<R> *v, int n)
+{
+#pragma unroll
+    for (int i = 0; i < n; ++i) asm volatile("" : "+v"(v[i].re), "+v"(v[i].im));
+}
+
 // -------------------------------------------------------------------------
 // lattice geometry of one parity
 // -------------------------------------------------------------------------
@@ -322,6 +332,60 @@ __device__ __forceinline__ void herm_apply(const void *base, long stride, long s
     const int off = chir * 36 / reals_per_vec<P>();
     const char *b = static_cast<const char *>(base) + (size_t)off * stride * 16;
     load_seq<P, 36>(b, stride, s, a);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) o[i] = cx<R>{a[i] * v[i].re - twist * v[i].im, a[i] * v[i].im + twist * v[i].re};
+    int k = 6;
+#pragma unroll
+    for (int i = 1; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+            cx<R> l{a[k], a[k + 1]};
+            k += 2;
+            cmac(o[i], l, v[j]);
+            cmac_conj(o[j], l, v[i]);
+        }
+}
+
+// Load the 6 components (2 spins x 3 colours) of chirality block chir of a
+// spinor: components 6 chir .. 6 chir + 5.
+template <int P, typename R>
+__device__ __forceinline__ void load_chiral(const SpinorPtr &f, int flav, long s, int chir, cx<R> *v)
+{
+    const char *base = static_cast<const char *>(f.d) + (size_t)flav * spinor_vecs<P>() * f.stride * 16;
+    R t[12];
+    if constexpr (P == F64) {
+        load_seq<P, 12>(base + (size_t)6 * chir * f.stride * 16, f.stride, s, t);
+    } else if constexpr (P == F32) {
+        load_seq<P, 12>(base + (size_t)3 * chir * f.stride * 16, f.stride, s, t);
+    } else {
+        // halves 12 chir .. 12 chir + 11 live in 16-byte vectors chir and chir + 1
+        R w[16];
+        load_seq<P, 16>(base + (size_t)chir * f.stride * 16, f.stride, s, w);
+        const float sc = f.nrm[flav * f.stride + s];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) t[k] = (chir ? w[k + 4] : w[k]) * sc;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = cx<R>{t[2 * k], t[2 * k + 1]};
+}
+
+// o = (A_chir + i twist) v for one chirality block of a Hermitian-packed site
+// record (FP16: the 36 halves of a block straddle 16-byte vectors, so five
+// vectors are read and the block picked out at offset 4 chir).
+template <int P, typename R>
+__device__ __forceinline__ void herm_apply_c(const void *base, long stride, long s, int chir, R twist,
+                                             const cx<R> *v, cx<R> *o)
+{
+    R a[36];
+    if constexpr (P == F16) {
+        R w[40];
+        load_seq<P, 40>(static_cast<const char *>(base) + (size_t)4 * chir * stride * 16, stride, s, w);
+#pragma unroll
+        for (int k = 0; k < 36; ++k) a[k] = chir ? w[k + 4] : w[k];
+    } else {
+        const int off = chir * 36 / reals_per_vec<P>();
+        load_seq<P, 36>(static_cast<const char *>(base) + (size_t)off * stride * 16, stride, s, a);
+    }
 #pragma unroll
     for (int i = 0; i < 6; ++i) o[i] = cx<R>{a[i] * v[i].re - twist * v[i].im, a[i] * v[i].im + twist * v[i].re};
     int k = 6;

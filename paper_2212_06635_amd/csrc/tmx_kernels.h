@@ -24,6 +24,7 @@ struct DslashArgs {
     int sgn;           // sign of the twist
     int t_bc;          // fermion time boundary factor
     int g5in, g5x, g5out;
+    int xcd;           // XCD-aware block order
 };
 
 hipError_t launch_dslash(int prec, int nf, int mode, const DslashArgs &a, hipStream_t st, int block);

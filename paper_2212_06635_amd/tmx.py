@@ -93,6 +93,8 @@ def _load():
         "tmx_pc_get_weights": ([P, P, Z], I),
         "tmx_pc_apply": ([P, P, P, I], I),
         "tmx_pc_train": ([P, P, P, I, ctypes.POINTER(tmx_train_cfg), P], I),
+        "tmx_kstats_enable": ([P, I], I),
+        "tmx_kstats_get": ([P, I, ctypes.c_char_p, Z, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(D)], I),
         "tmx_trace_enable": ([P, I], I),
         "tmx_trace_push": ([P, ctypes.c_char_p], I),
         "tmx_trace_pop": ([P], I),
@@ -277,6 +279,24 @@ class Context:
         loss = np.zeros(epochs, dtype=np.float32)
         self.check(lib.tmx_pc_train(self.h, _ptr(b), _ptr(x), npairs, ctypes.byref(cfg), loss.ctypes.data))
         return loss
+
+    # -- kernel timing --------------------------------------------------------
+    def kstats_enable(self, on=True):
+        return self.check(lib.tmx_kstats_enable(self.h, int(on)))
+
+    def kstats(self):
+        """{kernel name: (launches, total ms)} recorded with HIP events."""
+        out = {}
+        i = 0
+        buf = ctypes.create_string_buffer(128)
+        while True:
+            n = ctypes.c_long()
+            ms = ctypes.c_double()
+            if lib.tmx_kstats_get(self.h, i, buf, 128, ctypes.byref(n), ctypes.byref(ms)) != TMX_OK:
+                break
+            out[buf.value.decode()] = (n.value, ms.value)
+            i += 1
+        return out
 
     # -- tracing ----------------------------------------------------------------
     def trace_enable(self, on=True):
