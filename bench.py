@@ -88,6 +88,9 @@ def main():
     ap.add_argument("--dims", default="32,32,32,64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-applies", type=int, default=3)
+    ap.add_argument("--mode", default="full", choices=["full", "kernels"],
+                    help="kernels: only Mhat applies per precision and a copy of known size (for counters)")
+    ap.add_argument("--tune", action="store_true", help="autotune the stencil launch shapes first")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -119,7 +122,31 @@ def main():
     dst_nd = ctx.empty(tmx.TMX_FIELD_ODD_ND, 1)
     x = torch.zeros_like(bd)
     names = {0: "f64", 1: "f32", 2: "f16"}
+    if args.tune:
+        for p in (0, 1, 2):
+            ctx.tune(p, 1, 1)
+        ctx.tune(1, 2, 1)
+        log("tuned: " + str({k: ctx.tuned_config(k) for k in ("K1_f64", "K2_f64", "K1_f32", "K2_f32", "K1_f16", "K2_f16")}))
     log("setup done")
+    if args.mode == "kernels":
+        # a fixed number of applies per precision, then a device copy of
+        # 2 GiB whose FETCH_SIZE / WRITE_SIZE calibrate the counters
+        for p in (0, 1, 2):
+            for _ in range(10):
+                ctx.apply_mhat(dst[p], src[p], 1, p)
+        a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")
+        a.fill_(1.0)
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "kernels", "lattice": list(dims), "applies_per_prec": 10,
+                          "copy_bytes_each_way": a.numel() * 8, "copies": 3,
+                          "kernel_bytes_per_site": {k: kernel_bytes_per_site(k) for k in
+                                                    ("K1_f64", "K2_f64", "K1_f32", "K2_f32", "K1_f16", "K2_f16")},
+                          "Vh": Vh}), flush=True)
+        ctx.close()
+        return
 
     def timed(fn):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

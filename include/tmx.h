@@ -210,6 +210,19 @@ typedef struct {
 int tmx_pc_train(tmx_ctx *ctx, const double *b, const double *x, int npairs, const tmx_train_cfg *cfg,
                  float *loss_out);
 
+/* ---- autotuner ------------------------------------------------------------ */
+
+/* Time every launch shape (workgroup size 64/128/256 x plain or XCD-aware
+ * block order) of the two stencil kernels of Mhat for precision prec,
+ * operator op and nrhs right-hand sides on this lattice, and keep the
+ * fastest for later applies.  If the environment variable TMX_TUNE_CACHE
+ * names a file, results are appended there and loaded by tmx_create for the
+ * same lattice.  Synchronises. */
+int tmx_tune(tmx_ctx *ctx, int prec, int op, int nrhs);
+/* Launch shape in use for a kernel key ("K1_f64", "K2_f32_nd_r12", ...):
+ * TMX_OK if it was tuned, TMX_ENOCONV if it is the default. */
+int tmx_tuned_config(tmx_ctx *ctx, const char *key, int *block, int *xcd);
+
 /* ---- kernel timing -------------------------------------------------------- */
 
 /* Bracket every stencil kernel launch with HIP events on the context's

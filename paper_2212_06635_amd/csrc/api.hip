@@ -230,10 +230,14 @@ static const void *clov_parity(tmx_ctx *c, int prec, int parity)
     return static_cast<const char *>(c->clov[prec]) + (size_t)parity * 72 * bytes_per_real(prec) * c->Vh;
 }
 
-static int block_for(tmx_ctx *c, const char *key)
+LaunchCfg launch_cfg(tmx_ctx *c, const std::string &key)
 {
     auto it = c->tune.find(key);
-    return it == c->tune.end() ? c->default_block : it->second;
+    if (it != c->tune.end()) return it->second;
+    LaunchCfg d;
+    d.block = c->default_block;
+    d.xcd = c->xcd_remap;
+    return d;
 }
 
 static hipEvent_t kev_get(tmx_ctx *c)
@@ -302,7 +306,6 @@ static DslashArgs base_args(tmx_ctx *c, int prec, bool nd, int nrhs)
     a.nu = nd ? 2.0 * c->par.kappa * c->par.mubar : 2.0 * c->par.kappa * c->par.mu;
     a.epst = nd ? 2.0 * c->par.kappa * c->par.epsbar : 0.0;
     a.t_bc = c->par.t_bc;
-    a.xcd = c->xcd_remap;
     return a;
 }
 
@@ -319,8 +322,11 @@ static int schur_pair(tmx_ctx *c, SpinorPtr out, SpinorPtr in, SpinorPtr u, int 
     a.clov = clov_parity(c, prec, 0);
     a.inv = nd ? c->invnd[prec] : c->inv[prec];
     a.g5in = g5in;
-    kstat_begin(c, kname("K1", prec, nd, nrhs));
-    hipError_t e = launch_dslash(prec, nf, 0, a, c->stream, block_for(c, "k1"));
+    const std::string k1 = kname("K1", prec, nd, nrhs);
+    const LaunchCfg l1 = launch_cfg(c, k1);
+    a.xcd = l1.xcd;
+    kstat_begin(c, k1);
+    hipError_t e = launch_dslash(prec, nf, 0, a, c->stream, l1.block);
     kstat_end(c);
     if (e != hipSuccess) return hip_err(c, e, "K1 launch");
     DslashArgs b = base_args(c, prec, nd, nrhs);
@@ -333,8 +339,11 @@ static int schur_pair(tmx_ctx *c, SpinorPtr out, SpinorPtr in, SpinorPtr u, int 
     b.kfac = c->par.kappa * c->par.kappa;
     b.g5x = g5in;
     b.g5out = g5out;
-    kstat_begin(c, kname("K2", prec, nd, nrhs));
-    e = launch_dslash(prec, nf, 1, b, c->stream, block_for(c, "k2"));
+    const std::string k2 = kname("K2", prec, nd, nrhs);
+    const LaunchCfg l2 = launch_cfg(c, k2);
+    b.xcd = l2.xcd;
+    kstat_begin(c, k2);
+    e = launch_dslash(prec, nf, 1, b, c->stream, l2.block);
     kstat_end(c);
     if (e != hipSuccess) return hip_err(c, e, "K2 launch");
     return TMX_OK;
@@ -402,9 +411,82 @@ int op_D(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec)
         a.x = parity_half(in, prec, nf, p);
         a.clov = clov_parity(c, prec, p);
         a.kfac = c->par.kappa;
-        hipError_t e = launch_dslash(prec, nf, 1, a, c->stream, block_for(c, "k2"));
+        const LaunchCfg l = launch_cfg(c, kname("K2", prec, nd, 1));
+        a.xcd = l.xcd;
+        hipError_t e = launch_dslash(prec, nf, 1, a, c->stream, l.block);
         if (e != hipSuccess) return hip_err(c, e, "D launch");
     }
+    return TMX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: block size x XCD order per stencil kernel key
+// ---------------------------------------------------------------------------
+static std::string dims_key(const tmx_ctx *c)
+{
+    return std::to_string(c->dims[0]) + "x" + std::to_string(c->dims[1]) + "x" + std::to_string(c->dims[2]) + "x" +
+           std::to_string(c->dims[3]);
+}
+
+static void tune_cache_load(tmx_ctx *c)
+{
+    const char *path = std::getenv("TMX_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char dk[64], kk[64];
+    int block, xcd;
+    double ms;
+    const std::string me = dims_key(c);
+    while (std::fscanf(f, "%63s %63s %d %d %lf", dk, kk, &block, &xcd, &ms) == 5) {
+        if (me == dk && block >= 64 && block <= 256 && block % 64 == 0) c->tune[kk] = LaunchCfg{block, xcd != 0};
+    }
+    std::fclose(f);
+}
+
+static void tune_cache_store(tmx_ctx *c, const std::string &key, const LaunchCfg &l, double ms)
+{
+    const char *path = std::getenv("TMX_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %s %d %d %.6f\n", dims_key(c).c_str(), key.c_str(), l.block, l.xcd, ms);
+    std::fclose(f);
+}
+
+static int tune_one(tmx_ctx *c, DslashArgs a, int prec, int nf, int mode, const std::string &key)
+{
+    const int blocks[3] = {64, 128, 256};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hip_err(c, hipGetLastError(), "tune events");
+    double best = 1e30;
+    LaunchCfg bestc;
+    for (int xcd = 0; xcd < 2; ++xcd)
+        for (int bi = 0; bi < 3; ++bi) {
+            a.xcd = xcd;
+            hipError_t e = hipSuccess;
+            for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_dslash(prec, nf, mode, a, c->stream, blocks[bi]);
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            const int reps = 5;
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_dslash(prec, nf, mode, a, c->stream, blocks[bi]);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return hip_err(c, e, "tune launch");
+            }
+            if (ms / reps < best) {
+                best = ms / reps;
+                bestc = LaunchCfg{blocks[bi], xcd};
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->tune[key] = bestc;
+    tune_cache_store(c, key, bestc, best);
     return TMX_OK;
 }
 
@@ -447,6 +529,7 @@ int tmx_create(const int dims[4], void *hip_stream, tmx_ctx **out)
     }
     const char *tr = std::getenv("TMX_TRACE");
     c->trace = tr && tr[0] == '1';
+    tune_cache_load(c);
     // launch-shape overrides for sweeps (the autotuner sets per-kernel values)
     if (const char *e = std::getenv("TMX_DSLASH_BLOCK")) {
         int b = std::atoi(e);
@@ -656,6 +739,52 @@ int tmx_apply_mdagm(tmx_ctx *c, void *out, const void *in, int op, int prec, int
     const long stride = c->Vh * nrhs;
     return op_mdagm(c, make_spinor(out, prec, nf, stride), make_spinor(const_cast<void *>(in), prec, nf, stride), op,
                     prec, nrhs);
+}
+
+// ---- autotuner -----------------------------------------------------------------
+int tmx_tune(tmx_ctx *c, int prec, int op, int nrhs)
+{
+    if (!c || prec < 0 || prec > 2 || nrhs < 1 || nrhs > MAXR) return c ? set_err(c, TMX_EINVAL, "tmx_tune: bad argument") : TMX_EINVAL;
+    if (op != TMX_OP_PLUS && op != TMX_OP_MINUS && op != TMX_OP_ND) return set_err(c, TMX_EINVAL, "bad op");
+    const bool nd = op == TMX_OP_ND;
+    int r = ensure_ready(c, prec, nd);
+    if (r) return r;
+    const int nf = nd ? 2 : 1;
+    const long stride = c->Vh * nrhs;
+    const size_t fb = spinor_field_bytes(prec, nf, stride);
+    void *pin = ws_get(c, "tune_in", fb), *pu = ws_get(c, "tune_u", fb), *pout = ws_get(c, "tune_out", fb);
+    if (!pin || !pu || !pout) return TMX_ENOMEM;
+    r = hip_err(c, hipMemsetAsync(pin, 0, fb, c->stream), "tune fill");
+    if (r) return r;
+    SpinorPtr in = make_spinor(pin, prec, nf, stride), u = make_spinor(pu, prec, nf, stride),
+              out = make_spinor(pout, prec, nf, stride);
+    DslashArgs a = base_args(c, prec, nd, nrhs);
+    a.sgn = nd ? 1 : op;
+    a.parity = 0;
+    a.out = u;
+    a.in = in;
+    a.clov = clov_parity(c, prec, 0);
+    a.inv = nd ? c->invnd[prec] : c->inv[prec];
+    r = tune_one(c, a, prec, nf, 0, kname("K1", prec, nd, nrhs));
+    if (r) return r;
+    DslashArgs b = base_args(c, prec, nd, nrhs);
+    b.sgn = a.sgn;
+    b.parity = 1;
+    b.out = out;
+    b.in = u;
+    b.x = in;
+    b.clov = clov_parity(c, prec, 1);
+    b.kfac = c->par.kappa * c->par.kappa;
+    return tune_one(c, b, prec, nf, 1, kname("K2", prec, nd, nrhs));
+}
+
+int tmx_tuned_config(tmx_ctx *c, const char *key, int *block, int *xcd)
+{
+    if (!c || !key) return TMX_EINVAL;
+    LaunchCfg l = launch_cfg(c, key);
+    if (block) *block = l.block;
+    if (xcd) *xcd = l.xcd;
+    return c->tune.count(key) ? TMX_OK : TMX_ENOCONV;
 }
 
 // ---- kernel timing -----------------------------------------------------------

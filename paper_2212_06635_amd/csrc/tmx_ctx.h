@@ -33,6 +33,12 @@ struct KStat {
     double ms = 0;
 };
 
+// launch shape of a stencil kernel (chosen by the autotuner)
+struct LaunchCfg {
+    int block = 64;
+    int xcd = 1;
+};
+
 // learned-preconditioner state (nn.hip)
 struct PcState;
 
@@ -90,7 +96,7 @@ struct tmx_ctx {
     std::map<std::string, tmx::KStat> kstats;
 
     // kernel launch tuning (block size per kernel key)
-    std::map<std::string, int> tune;
+    std::map<std::string, tmx::LaunchCfg> tune;
     int default_block = 64;
     int xcd_remap = 1;
 
@@ -116,6 +122,9 @@ int ensure_ready(tmx_ctx *c, int prec, bool nd);
 int op_mhat(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int dagger, int nrhs);
 int op_mdagm(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int nrhs);
 int op_D(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec);
+
+// launch shape for a kernel key ("K1_f64", "K2_f32_nd_r12", ...)
+LaunchCfg launch_cfg(tmx_ctx *c, const std::string &key);
 
 // reductions: copy device results to the host (synchronises the stream)
 int fetch(tmx_ctx *c, int n, double *host);

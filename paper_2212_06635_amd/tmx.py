@@ -93,6 +93,8 @@ def _load():
         "tmx_pc_get_weights": ([P, P, Z], I),
         "tmx_pc_apply": ([P, P, P, I], I),
         "tmx_pc_train": ([P, P, P, I, ctypes.POINTER(tmx_train_cfg), P], I),
+        "tmx_tune": ([P, I, I, I], I),
+        "tmx_tuned_config": ([P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(I)], I),
         "tmx_kstats_enable": ([P, I], I),
         "tmx_kstats_get": ([P, I, ctypes.c_char_p, Z, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(D)], I),
         "tmx_trace_enable": ([P, I], I),
@@ -279,6 +281,15 @@ class Context:
         loss = np.zeros(epochs, dtype=np.float32)
         self.check(lib.tmx_pc_train(self.h, _ptr(b), _ptr(x), npairs, ctypes.byref(cfg), loss.ctypes.data))
         return loss
+
+    # -- autotuner ------------------------------------------------------------
+    def tune(self, prec, op, nrhs=1):
+        return self.check(lib.tmx_tune(self.h, prec, op, nrhs))
+
+    def tuned_config(self, key):
+        b, x = ctypes.c_int(), ctypes.c_int()
+        rc = lib.tmx_tuned_config(self.h, key.encode(), ctypes.byref(b), ctypes.byref(x))
+        return {"block": b.value, "xcd": x.value, "tuned": rc == TMX_OK}
 
     # -- kernel timing --------------------------------------------------------
     def kstats_enable(self, on=True):
