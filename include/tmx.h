@@ -196,6 +196,11 @@ int tmx_pc_get_weights(tmx_ctx *ctx, float *host_w, size_t n);
  * complex128 device fields. */
 int tmx_pc_apply(tmx_ctx *ctx, double *out, const double *in, int dagger);
 
+/* Loss mean_i |K b_i - x_i|^2 / |x_i|^2 over npairs canonical odd device
+ * fields and its gradient with respect to the weights (host_grad may be
+ * NULL), as used by one training step. */
+int tmx_pc_loss_grad(tmx_ctx *ctx, const double *b, const double *x, int npairs, double *loss, float *host_grad);
+
 typedef struct {
     int epochs;
     int batch;

@@ -1,29 +1,1093 @@
-// Learned gauge-covariant preconditioner (entry points; kernels land next).
+// Learned gauge-covariant preconditioner K (a stand-in for the paper's
+// multigrid preconditioner of Section 4.1): forward, adjoint, weight
+// gradients, Adam training, and the flexible-GCR solver that uses it.
+//
+// Network: four linear layers 1 -> 8 -> 8 -> 8 -> 1 channels on the full
+// lattice, each
+//     y_c(x) = sum_{d=0..8} sum_c' C_d[c,c'] (Gamma_d (x) 1) (T_d x_c')(x)
+// with the parallel transports T_0 = 1, T_{+mu} psi(x) = U_mu(x) psi(x+mu),
+// T_{-mu} psi(x) = U_mu(x-mu)^+ psi(x-mu) (time-boundary factor on hops
+// across the edge).  The input is the odd source embedded in the full
+// lattice, the output is restricted to the odd sites.
+//
+// One layer is a GEMM per workgroup tile of 64 sites:
+//     Y[m][n] = sum_d W_d[m][k] Z_d[k][n]
+// m = (out channel, spin, re/im), k = (in channel, spin, re/im),
+// n = (site, colour); W_d = C_d (x) Gamma_d written as a real matrix, Z_d the
+// transported input.  The transport runs on the vector ALUs in FP32 and is
+// staged in LDS as BF16; the contraction runs on the matrix cores
+// (v_mfma_f32_16x16x16bf16, FP32 accumulation).  The adjoint layer is the
+// same kernel with W'_d = W_{-d}^H (transport and weights commute).
+//
+// Activations are FP32 fields of `channels` flavours over all V sites
+// (site index parity * V/2 + checkerboard index) in the site-major layout.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
 #include "tmx_ctx.h"
+
+namespace tmx {
+
+constexpr int NN_L = 4;
+constexpr int NN_P = 9;
+static const int NN_CIN[NN_L] = {1, 8, 8, 8};
+static const int NN_COUT[NN_L] = {8, 8, 8, 1};
+constexpr int NN_S = 64;          // sites per workgroup tile
+constexpr int NN_N = 3 * NN_S;    // GEMM columns per tile
+constexpr int NN_PAD = 8;         // LDS row padding (bf16 elements)
+
+__host__ __device__ constexpr int pad16(int x) { return (x + 15) / 16 * 16; }
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+static size_t layer_param_offset(int l)
+{
+    size_t o = 0;
+    for (int i = 0; i < l; ++i) o += (size_t)NN_P * (NN_CIN[i] * NN_COUT[i] + 16) * 2;
+    return o;
+}
+static size_t nn_num_params() { return layer_param_offset(NN_L); }
+
+struct PcState {
+    size_t nparam = 0;
+    float *params = nullptr;  // device FP32 master weights
+    float *grad = nullptr;
+    float *adam_m = nullptr, *adam_v = nullptr;
+    uint16_t *Wf[NN_L] = {};  // forward real weights [9][MD][KD], bf16
+    uint16_t *Wa[NN_L] = {};  // adjoint real weights
+    bool w_ok = false;
+    bool have_weights = false;
+    int adam_t = 0;
+};
+
+// ---------------------------------------------------------------------------
+// weights: complex (C, Gamma) -> real-ified W_d (forward and adjoint)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int rev_path(int d) { return d == 0 ? 0 : ((d - 1) % 2 == 0 ? d + 1 : d - 1); }
+
+// thread per (d, m, k) of a [9][MD][KD] matrix
+__global__ void nn_build_w_kernel(const float *p, uint16_t *W, int cin, int cout, int adjoint)
+{
+    // forward: rows over (cout, spin, ri), cols over (cin, spin, ri)
+    // adjoint: rows over (cin, ...), cols over (cout, ...), W'_d = W_{rev d}^H
+    const int rows = adjoint ? cin : cout, cols = adjoint ? cout : cin;
+    const int MD = pad16(8 * rows), KD = pad16(8 * cols);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NN_P * MD * KD) return;
+    const int d = t / (MD * KD), m = (t / KD) % MD, k = t % KD;
+    float v = 0.f;
+    if (m < 8 * rows && k < 8 * cols) {
+        const int a = m / 8, s = (m % 8) / 2, ri = m % 2;
+        const int b = k / 8, sp = (k % 8) / 2, rj = k % 2;
+        const int dd = adjoint ? rev_path(d) : d;
+        const size_t per = (size_t)cin * cout + 16;
+        const float *pd = p + (size_t)dd * per * 2;
+        // C[cout][cin], Gamma[4][4]
+        float cr, ci, gr, gi;
+        if (!adjoint) {
+            cr = pd[2 * (a * cin + b)];
+            ci = pd[2 * (a * cin + b) + 1];
+            gr = pd[2 * (cin * cout + s * 4 + sp)];
+            gi = pd[2 * (cin * cout + s * 4 + sp) + 1];
+        } else {
+            // (C (x) Gamma)^H [(a,s),(b,sp)] = conj(C[b][a]) conj(Gamma[sp][s]), a < cin, b < cout
+            cr = pd[2 * (b * cin + a)];
+            ci = -pd[2 * (b * cin + a) + 1];
+            gr = pd[2 * (cin * cout + sp * 4 + s)];
+            gi = -pd[2 * (cin * cout + sp * 4 + s) + 1];
+        }
+        const float wr = cr * gr - ci * gi, wi = cr * gi + ci * gr;
+        v = (ri == 0) ? (rj == 0 ? wr : -wi) : (rj == 0 ? wi : wr);
+    }
+    W[t] = f2bf(v);
+}
+
+// ---------------------------------------------------------------------------
+// transport T_d of one spinor (FP32)
+// ---------------------------------------------------------------------------
+struct Nbr {
+    long idx;   // neighbour site index in the activation layout
+    int lp;     // link parity
+    long lcb;   // link checkerboard index
+    float bc;   // boundary factor
+    bool dag;   // U^dagger (backward path)
+    bool ident; // d = 0
+};
+
+__device__ __forceinline__ Nbr path_neighbour(const Geom &g, long gs, int d, int t_bc)
+{
+    Nbr r;
+    const long Vh = g.Vh;
+    const int p = gs >= Vh ? 1 : 0;
+    const int cb = (int)(gs - p * Vh);
+    r.bc = 1.f;
+    if (d == 0) {
+        r.idx = gs;
+        r.ident = true;
+        r.dag = false;
+        r.lp = 0;
+        r.lcb = 0;
+        return r;
+    }
+    r.ident = false;
+    int x[4];
+    cb_coords(g, cb, p, x);
+    const int mu = (d - 1) / 2;
+    const bool back = ((d - 1) % 2) == 1;
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    if (!back) {
+        if (++y[mu] == g.L[mu]) {
+            y[mu] = 0;
+            if (mu == 3) r.bc = (float)t_bc;
+        }
+    } else {
+        if (--y[mu] < 0) {
+            y[mu] = g.L[mu] - 1;
+            if (mu == 3) r.bc = (float)t_bc;
+        }
+    }
+    const int ncb = cb_index(g, y);
+    r.idx = (long)(1 - p) * Vh + ncb;
+    r.dag = back;
+    r.lp = back ? 1 - p : p;
+    r.lcb = back ? ncb : cb;
+    return r;
+}
+
+__device__ __forceinline__ void transport(const LinkPtr &U, const Nbr &nb, int mu, const cx<float> *psi, cx<float> *z)
+{
+    if (nb.ident) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) z[k] = psi[k];
+        return;
+    }
+    cx<float> u[9];
+    load_link<F32>(U, nb.lp, mu, nb.lcb, u);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<float> acc{0.f, 0.f};
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if (nb.dag)
+                    cmac_conj(acc, u[3 * b + a], psi[3 * s + b]);
+                else
+                    cmac(acc, u[3 * a + b], psi[3 * s + b]);
+            }
+            z[3 * s + a] = nb.bc * acc;
+        }
+}
+
+// Stage the transported input of a tile into LDS, rows n = (site, colour),
+// 8 bf16 per (channel c, colour): k = c * 8 + spin * 2 + re/im.
+template <int CIN, int KS>
+__device__ __forceinline__ void stage_z(const Geom &g, const SpinorPtr &x, const LinkPtr &U, int t_bc, long site0,
+                                        long V, int d, uint16_t (*Zs)[KS], bool transposed, uint16_t *Zt, int ztstride)
+{
+    const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
+    const long gs = site0 + sl;
+    const bool valid = gs < V;
+    Nbr nb{};
+    if (valid) nb = path_neighbour(g, gs, d, t_bc);
+    const int mu = d == 0 ? 0 : (d - 1) / 2;
+    for (int c = q; c < CIN; c += 4) {
+        cx<float> z[12];
+        if (valid) {
+            cx<float> psi[12];
+            load_spinor<F32>(x, c, nb.idx, psi);
+            transport(U, nb, mu, psi, z);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) z[k] = cx<float>{0.f, 0.f};
+        }
+#pragma unroll
+        for (int col = 0; col < 3; ++col) {
+            uint16_t v[8];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                v[2 * s] = f2bf(z[3 * s + col].re);
+                v[2 * s + 1] = f2bf(z[3 * s + col].im);
+            }
+            const int n = sl * 3 + col;
+            if (!transposed) {
+                *reinterpret_cast<uint4 *>(&Zs[n][c * 8]) = *reinterpret_cast<const uint4 *>(v);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) Zt[(c * 8 + j) * ztstride + n] = v[j];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// layer kernel: Y = sum_d W_d Z_d   (forward or adjoint, by the weights given)
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) nn_layer_kernel(Geom g, SpinorPtr x, SpinorPtr y, LinkPtr U,
+                                                       const uint16_t *W, int t_bc)
+{
+    constexpr int KD = pad16(8 * CIN), MD = pad16(8 * COUT);
+    constexpr int KS = KD + NN_PAD;
+    constexpr int MT = MD / 16, KT = KD / 16;
+    __shared__ __attribute__((aligned(16))) uint16_t Zs[NN_N][KS];
+    __shared__ __attribute__((aligned(16))) uint16_t Ws[MD][KS];
+    const long V = 2L * g.Vh;
+    const long site0 = (long)blockIdx.x * NN_S;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+
+    // padded k columns stay zero for the whole kernel
+    if (8 * CIN < KD) {
+        for (int i = threadIdx.x; i < NN_N; i += blockDim.x)
+            for (int k = 8 * CIN; k < KD; ++k) Zs[i][k] = 0;
+    }
+    f32x4 acc[MT][3];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc[mt][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int d = 0; d < NN_P; ++d) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < MD * KD; i += blockDim.x) Ws[i / KD][i % KD] = W[(size_t)d * MD * KD + i];
+        stage_z<CIN, KS>(g, x, U, t_bc, site0, V, d, Zs, false, nullptr, 0);
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KT; ++kk) {
+            const int kb = kk * 16 + 4 * (lane / 16);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const bf16x4 a = *reinterpret_cast<const bf16x4 *>(&Ws[mt * 16 + lane % 16][kb]);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int nt = wave * 3 + j;
+                    const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&Zs[nt * 16 + lane % 16][kb]);
+                    acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[mt][j], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // D[m][n]: lane holds rows m = 16 mt + 4 (lane/16) + i, column n = 16 nt + lane%16
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int m0 = mt * 16 + 4 * (lane / 16);
+            const int n = (wave * 3 + j) * 16 + lane % 16;
+            const long gs = site0 + n / 3;
+            const int col = n % 3;
+            if (m0 >= 8 * COUT || gs >= V) continue;
+            const int c = m0 / 8, s0 = (m0 % 8) / 2;
+            float *base = static_cast<float *>(y.d);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = (s0 + h) * 3 + col;  // spinor component
+                float *dst = base + (((long)c * 6 + k / 2) * y.stride + gs) * 4 + (k % 2) * 2;
+                *reinterpret_cast<float2 *>(dst) = make_float2(acc[mt][j][2 * h], acc[mt][j][2 * h + 1]);
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: P_d[m][k] += sum_n Dl[m][n] Z_d[k][n]   (grid.y = path)
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) nn_wgrad_kernel(Geom g, SpinorPtr x, SpinorPtr dy, LinkPtr U, int t_bc,
+                                                       float *partial, long ntiles)
+{
+    constexpr int KD = pad16(8 * CIN), MD = pad16(8 * COUT);
+    constexpr int NS = NN_N + NN_PAD;
+    constexpr int MT = MD / 16, KT = KD / 16, NTILE = MT * KT;
+    constexpr int PER_WAVE = (NTILE + 3) / 4;
+    __shared__ __attribute__((aligned(16))) uint16_t Dl[MD][NS];
+    __shared__ __attribute__((aligned(16))) uint16_t Zt[KD][NS];
+    const long V = 2L * g.Vh;
+    const int d = blockIdx.y;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int i = threadIdx.x; i < MD * NS; i += blockDim.x) Dl[i / NS][i % NS] = 0;
+    for (int i = threadIdx.x; i < KD * NS; i += blockDim.x) Zt[i / NS][i % NS] = 0;
+    f32x4 acc[PER_WAVE];
+#pragma unroll
+    for (int j = 0; j < PER_WAVE; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const long site0 = tile * NN_S;
+        __syncthreads();
+        stage_z<CIN, 1>(g, x, U, t_bc, site0, V, d, nullptr, true, &Zt[0][0], NS);
+        // output adjoint at the sites themselves (no transport)
+        {
+            const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
+            const long gs = site0 + sl;
+            for (int c = q; c < COUT; c += 4) {
+                cx<float> v[12];
+                if (gs < V) {
+                    load_spinor<F32>(dy, c, gs, v);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) v[k] = cx<float>{0.f, 0.f};
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int col = 0; col < 3; ++col) {
+                        Dl[c * 8 + s * 2][sl * 3 + col] = f2bf(v[3 * s + col].re);
+                        Dl[c * 8 + s * 2 + 1][sl * 3 + col] = f2bf(v[3 * s + col].im);
+                    }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PER_WAVE; ++j) {
+            const int t = wave + 4 * j;
+            if (t >= NTILE) break;
+            const int mt = t / KT, kt = t % KT;
+            for (int nk = 0; nk < NN_N / 16; ++nk) {
+                const int nb = nk * 16 + 4 * (lane / 16);
+                const bf16x4 a = *reinterpret_cast<const bf16x4 *>(&Dl[mt * 16 + lane % 16][nb]);
+                const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&Zt[kt * 16 + lane % 16][nb]);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+            }
+        }
+    }
+    float *out = partial + ((size_t)blockIdx.x * NN_P + d) * MD * KD;
+#pragma unroll
+    for (int j = 0; j < PER_WAVE; ++j) {
+        const int t = wave + 4 * j;
+        if (t >= NTILE) break;
+        const int mt = t / KT, kt = t % KT;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = mt * 16 + 4 * (lane / 16) + i, k = kt * 16 + lane % 16;
+            out[m * KD + k] += acc[j][i];
+        }
+    }
+}
+
+// P[l] = sum over blocks of the partials, then the complex weight gradient
+//   S[(c,s),(c',s')] = (P00 + P11) + i (P01 - P10)
+//   grad C[c,c'] = 2 conj(sum_{s,s'} S Gamma[s,s']), grad Gamma[s,s'] = 2 conj(sum_{c,c'} S C[c,c'])
+__global__ void nn_grad_combine_kernel(const float *partial, int nblocks, const float *p, float *grad, int cin,
+                                       int cout)
+{
+    const int MD = pad16(8 * cout), KD = pad16(8 * cin);
+    const int per = cin * cout + 16;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NN_P * per) return;
+    const int d = t / per, e = t % per;
+    auto P = [&](int m, int k) {
+        float s = 0.f;
+        for (int b = 0; b < nblocks; ++b) s += partial[((size_t)b * NN_P + d) * MD * KD + m * KD + k];
+        return s;
+    };
+    auto S = [&](int c, int s, int cp, int sp, float &re, float &im) {
+        const int m = c * 8 + s * 2, k = cp * 8 + sp * 2;
+        const float p00 = P(m, k), p11 = P(m + 1, k + 1), p01 = P(m, k + 1), p10 = P(m + 1, k);
+        re = p00 + p11;
+        im = p01 - p10;
+    };
+    const float *pd = p + (size_t)d * per * 2;
+    float gr = 0.f, gi = 0.f;
+    if (e < cin * cout) {
+        const int c = e / cin, cp = e % cin;
+        for (int s = 0; s < 4; ++s)
+            for (int sp = 0; sp < 4; ++sp) {
+                float sr, si;
+                S(c, s, cp, sp, sr, si);
+                const float Gr = pd[2 * (cin * cout + s * 4 + sp)], Gi = pd[2 * (cin * cout + s * 4 + sp) + 1];
+                gr += sr * Gr - si * Gi;
+                gi += sr * Gi + si * Gr;
+            }
+    } else {
+        const int s = (e - cin * cout) / 4, sp = (e - cin * cout) % 4;
+        for (int c = 0; c < cout; ++c)
+            for (int cp = 0; cp < cin; ++cp) {
+                float sr, si;
+                S(c, s, cp, sp, sr, si);
+                const float Cr = pd[2 * (c * cin + cp)], Ci = pd[2 * (c * cin + cp) + 1];
+                gr += sr * Cr - si * Ci;
+                gi += sr * Ci + si * Cr;
+            }
+    }
+    grad[(size_t)d * per * 2 + 2 * e] = 2.f * gr;
+    grad[(size_t)d * per * 2 + 2 * e + 1] = -2.f * gi;
+}
+
+__global__ void nn_adam_kernel(float *p, const float *g, float *m, float *v, int n, float lr, float b1, float b2,
+                               float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    m[i] = b1 * m[i] + (1.f - b1) * gi;
+    v[i] = b2 * v[i] + (1.f - b2) * gi * gi;
+    p[i] -= lr * (m[i] / c1) / (sqrtf(v[i] / c2) + eps);
+}
+
+__global__ void nn_zero_kernel(float *p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+namespace {
+
+int nn_ensure(tmx_ctx *c)
+{
+    if (!c->pc) c->pc = new PcState();
+    PcState &s = *c->pc;
+    if (s.params) return TMX_OK;
+    s.nparam = nn_num_params();
+    size_t bytes = s.nparam * sizeof(float);
+    if (hipMalloc(&s.params, bytes) != hipSuccess || hipMalloc(&s.grad, bytes) != hipSuccess ||
+        hipMalloc(&s.adam_m, bytes) != hipSuccess || hipMalloc(&s.adam_v, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(c, TMX_ENOMEM, "preconditioner weights");
+    }
+    for (int l = 0; l < NN_L; ++l) {
+        const size_t nf = (size_t)NN_P * pad16(8 * NN_COUT[l]) * pad16(8 * NN_CIN[l]);
+        const size_t na = (size_t)NN_P * pad16(8 * NN_CIN[l]) * pad16(8 * NN_COUT[l]);
+        if (hipMalloc(&s.Wf[l], nf * 2) != hipSuccess || hipMalloc(&s.Wa[l], na * 2) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_err(c, TMX_ENOMEM, "preconditioner weights");
+        }
+    }
+    return TMX_OK;
+}
+
+int nn_build_weights(tmx_ctx *c)
+{
+    PcState &s = *c->pc;
+    if (s.w_ok) return TMX_OK;
+    for (int l = 0; l < NN_L; ++l) {
+        const float *pl = s.params + layer_param_offset(l);
+        const int n = NN_P * pad16(8 * NN_COUT[l]) * pad16(8 * NN_CIN[l]);
+        hipLaunchKernelGGL(nn_build_w_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, pl, s.Wf[l], NN_CIN[l],
+                           NN_COUT[l], 0);
+        hipLaunchKernelGGL(nn_build_w_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, pl, s.Wa[l], NN_CIN[l],
+                           NN_COUT[l], 1);
+    }
+    int r = hip_err(c, hipGetLastError(), "build weights");
+    if (!r) s.w_ok = true;
+    return r;
+}
+
+hipError_t launch_layer(tmx_ctx *c, int cin, int cout, SpinorPtr x, SpinorPtr y, const uint16_t *W)
+{
+    const long V = 2 * c->Vh;
+    const dim3 grid((unsigned)((V + NN_S - 1) / NN_S)), block(256);
+    LinkPtr U{c->links[F32], c->Vh};
+    const int tb = c->par.t_bc;
+    if (cin == 1 && cout == 8)
+        hipLaunchKernelGGL((nn_layer_kernel<1, 8>), grid, block, 0, c->stream, c->g, x, y, U, W, tb);
+    else if (cin == 8 && cout == 8)
+        hipLaunchKernelGGL((nn_layer_kernel<8, 8>), grid, block, 0, c->stream, c->g, x, y, U, W, tb);
+    else if (cin == 8 && cout == 1)
+        hipLaunchKernelGGL((nn_layer_kernel<8, 1>), grid, block, 0, c->stream, c->g, x, y, U, W, tb);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+constexpr int WG_BLOCKS = 64;
+
+hipError_t launch_wgrad(tmx_ctx *c, int cin, int cout, SpinorPtr x, SpinorPtr dy, float *partial)
+{
+    const long V = 2 * c->Vh;
+    const long ntiles = (V + NN_S - 1) / NN_S;
+    const dim3 grid(WG_BLOCKS, NN_P), block(256);
+    LinkPtr U{c->links[F32], c->Vh};
+    const int tb = c->par.t_bc;
+    if (cin == 1 && cout == 8)
+        hipLaunchKernelGGL((nn_wgrad_kernel<1, 8>), grid, block, 0, c->stream, c->g, x, dy, U, tb, partial, ntiles);
+    else if (cin == 8 && cout == 8)
+        hipLaunchKernelGGL((nn_wgrad_kernel<8, 8>), grid, block, 0, c->stream, c->g, x, dy, U, tb, partial, ntiles);
+    else if (cin == 8 && cout == 1)
+        hipLaunchKernelGGL((nn_wgrad_kernel<8, 1>), grid, block, 0, c->stream, c->g, x, dy, U, tb, partial, ntiles);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// activation buffer l (channels ch) of the full lattice, FP32
+SpinorPtr act(tmx_ctx *c, const std::string &name, int ch)
+{
+    const long V = 2 * c->Vh;
+    void *d = ws_get(c, "nn_" + name, spinor_field_bytes(F32, ch, V));
+    return make_spinor(d, F32, ch, V);
+}
+
+// the odd half of a one-channel activation, addressed by checkerboard index
+SpinorPtr odd_view(tmx_ctx *c, SpinorPtr f)
+{
+    SpinorPtr o = f;
+    o.d = static_cast<char *>(f.d) + (size_t)c->Vh * 16;
+    return o;
+}
+SpinorPtr even_view(SpinorPtr f) { return f; }
+
+}  // namespace
+
+// z = K r (dagger = 0) or K^dagger r (dagger = 1): odd fields r (precision
+// pr, stride Vh) and z (precision pz); all layers in FP32/BF16.
+int pc_apply_internal(tmx_ctx *c, SpinorPtr z, int pz, SpinorPtr r, int pr, int dagger, bool keep,
+                      std::vector<SpinorPtr> *acts_out)
+{
+    int rc = nn_ensure(c);
+    if (rc) return rc;
+    if (!c->pc->have_weights) return set_err(c, TMX_ENOTLOADED, "preconditioner weights not set");
+    rc = ensure_ready(c, F32, false);
+    if (rc) return rc;
+    rc = nn_build_weights(c);
+    if (rc) return rc;
+    const long Vh = c->Vh;
+    // layer order and channel counts
+    int order[NN_L];
+    for (int i = 0; i < NN_L; ++i) order[i] = dagger ? NN_L - 1 - i : i;
+    SpinorPtr a = act(c, keep ? "a0" : "p0", 1);
+    if (!a.d) return TMX_ENOMEM;
+    // embed: even half zero, odd half = r
+    {
+        OpZero<F32> oz{};
+        oz.d = even_view(a);
+        oz.nf = 1;
+        HIP_CHECK_RET(c, run_blas(oz, Vh, 1, c->red, c->stream), "embed zero");
+        SpinorPtr ov = odd_view(c, a);
+        if (pr == F64) {
+            OpCopy<F32, F64> cp{};
+            cp.d = ov;
+            cp.s = r;
+            cp.nf = 1;
+            HIP_CHECK_RET(c, run_blas(cp, Vh, 1, c->red, c->stream), "embed");
+        } else {
+            OpCopy<F32, F32> cp{};
+            cp.d = ov;
+            cp.s = r;
+            cp.nf = 1;
+            HIP_CHECK_RET(c, run_blas(cp, Vh, 1, c->red, c->stream), "embed");
+        }
+    }
+    if (acts_out) acts_out->push_back(a);
+    for (int i = 0; i < NN_L; ++i) {
+        const int l = order[i];
+        const int cin = dagger ? NN_COUT[l] : NN_CIN[l];
+        const int cout = dagger ? NN_CIN[l] : NN_COUT[l];
+        const std::string nm = (keep ? "a" : "p") + std::to_string(i + 1);
+        SpinorPtr b = act(c, nm, cout);
+        if (!b.d) return TMX_ENOMEM;
+        HIP_CHECK_RET(c, launch_layer(c, cin, cout, a, b, dagger ? c->pc->Wa[l] : c->pc->Wf[l]), "nn layer");
+        if (acts_out) acts_out->push_back(b);
+        a = b;
+    }
+    SpinorPtr ov = odd_view(c, a);
+    if (pz == F64) {
+        OpCopy<F64, F32> cp{};
+        cp.d = z;
+        cp.s = ov;
+        cp.nf = 1;
+        HIP_CHECK_RET(c, run_blas(cp, Vh, 1, c->red, c->stream), "restrict");
+    } else {
+        OpCopy<F32, F32> cp{};
+        cp.d = z;
+        cp.s = ov;
+        cp.nf = 1;
+        HIP_CHECK_RET(c, run_blas(cp, Vh, 1, c->red, c->stream), "restrict");
+    }
+    return TMX_OK;
+}
+
+// residual of one training pair: r = (K b)_odd - x, loss |r|^2 / |x|^2; writes
+// delta = embed(r) * scale into the output-adjoint field
+template <int PX> struct OpPairResidual {
+    static constexpr int NRED = 2;
+    SpinorPtr out;  // odd view of the last activation (F32)
+    SpinorPtr x;    // target (PX)
+    SpinorPtr delta;  // odd view of the adjoint field (F32)
+    double scale;
+    __device__ void operator()(long t, int, double *acc) const
+    {
+        cd vo[12], vx[12];
+        ld<F32>(out, 0, t, vo);
+        ld<PX>(x, 0, t, vx);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) vo[c] = vo[c] - vx[c];
+        acc[0] += nrm2(vo);
+        acc[1] += nrm2(vx);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) vo[c] = scale * vo[c];
+        st<F32>(delta, 0, t, vo);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// flexible GCR with the learned preconditioner
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Fg {
+    tmx_ctx *c;
+    long Vh;
+    SpinorPtr f(const std::string &name, int prec) const
+    {
+        void *d = ws_get(c, "fg_" + name, spinor_field_bytes(prec, 1, Vh));
+        return make_spinor(d, prec, 1, Vh);
+    }
+};
+
+template <class Op> int blas(tmx_ctx *c, const Op &o, long n, double *res, int nres)
+{
+    HIP_CHECK_RET(c, run_blas(o, n, 1, c->red, c->stream), "fgcr blas");
+    if (res) return fetch(c, nres, res);
+    return TMX_OK;
+}
+
+// r = b - A x in FP64 (A = Mhat or Mhat^dagger); returns |r|^2
+int fg_true_residual(tmx_ctx *c, int op, int dagger, SpinorPtr r, SpinorPtr b, SpinorPtr x, SpinorPtr q, double *rr,
+                     double *gb)
+{
+    int rc = op_mhat(c, q, x, op, F64, dagger, 1);
+    if (rc) return rc;
+    *gb += mhat_bytes_per_site(F64, 1, 1) * c->Vh * 1e-9;
+    OpXmyNorm<F64, F64, F64, F64> o{};
+    o.r = r;
+    o.b = b;
+    o.q = q;
+    o.rlo = r;
+    o.nf = 1;
+    return blas(c, o, c->Vh, rr, 1);
+}
+
+// one flexible-GCR solve of A x = b to relative tolerance tau (x holds the
+// start vector).  Returns TMX_OK, or TMX_ENOCONV on stagnation / maxiter.
+int fgcr_stage(tmx_ctx *c, int op, int dagger, SpinorPtr x, SpinorPtr b, double tau, int m, int maxiter,
+               int inner_prec, tmx_info *info)
+{
+    Fg F{c, c->Vh};
+    const long Vh = c->Vh;
+    SpinorPtr r = F.f("r64", F64), q = F.f("q64", F64), rl = F.f("rl", F32), w = F.f("w", F32);
+    std::vector<SpinorPtr> zs(m), ws(m);
+    for (int j = 0; j < m; ++j) {
+        zs[j] = F.f("z" + std::to_string(j), F32);
+        ws[j] = F.f("w" + std::to_string(j), F32);
+        if (!zs[j].d || !ws[j].d) return TMX_ENOMEM;
+    }
+    double bb;
+    {
+        OpCopy<F64, F64> o{};
+        o.d = q;
+        o.s = b;
+        o.nf = 1;
+        int rc = blas(c, o, Vh, &bb, 1);
+        if (rc) return rc;
+    }
+    if (bb == 0) return TMX_OK;
+    double rr;
+    int rc = fg_true_residual(c, op, dagger, r, b, x, q, &rr, &info->gbytes);
+    if (rc) return rc;
+    int it = 0;
+    double prev_cycle = rr;
+    while (std::sqrt(rr) > tau * std::sqrt(bb) && it < maxiter) {
+        // r_lo = r
+        {
+            OpCopy<F32, F64> o{};
+            o.d = rl;
+            o.s = r;
+            o.nf = 1;
+            rc = blas(c, o, Vh, nullptr, 0);
+            if (rc) return rc;
+        }
+        const double cycle_target = std::max(tau * tau * bb, 1e-12 * rr);
+        double rlo = rr;
+        for (int j = 0; j < m && it < maxiter; ++j) {
+            // z_j = K r ; w = A z_j   (low precision)
+            rc = pc_apply_internal(c, zs[j], F32, rl, F32, dagger, false, nullptr);
+            if (rc) return rc;
+            rc = op_mhat(c, w, zs[j], op, inner_prec == F64 ? F32 : F32, dagger, 1);
+            if (rc) return rc;
+            info->gbytes += mhat_bytes_per_site(F32, 1, 1) * Vh * 1e-9;
+            ++it;
+            // modified Gram-Schmidt against the previous directions
+            for (int i = 0; i < j; ++i) {
+                OpCdot<F32, F32> d{};
+                d.a = ws[i];
+                d.b = w;
+                d.nf = 1;
+                double beta[2];
+                rc = blas(c, d, Vh, beta, 2);
+                if (rc) return rc;
+                OpCaxpy<F32, F32> u{};
+                u.y = w;
+                u.x = ws[i];
+                u.nf = 1;
+                u.cre[0] = -beta[0];
+                u.cim[0] = -beta[1];
+                rc = blas(c, u, Vh, nullptr, 0);
+                if (rc) return rc;
+                u.y = zs[j];
+                u.x = zs[i];
+                rc = blas(c, u, Vh, nullptr, 0);
+                if (rc) return rc;
+            }
+            double nw;
+            {
+                OpCopy<F32, F32> o{};
+                o.d = ws[j];
+                o.s = w;
+                o.nf = 1;
+                rc = blas(c, o, Vh, &nw, 1);
+                if (rc) return rc;
+            }
+            if (!(nw > 0) || !std::isfinite(nw)) return set_err(c, TMX_ENOCONV, "FGCR breakdown");
+            const double inv = 1.0 / std::sqrt(nw);
+            {
+                OpAxpby<F32, F32> sc{};
+                sc.y = ws[j];
+                sc.x = ws[j];
+                sc.nf = 1;
+                sc.a[0] = 0.0;
+                sc.b[0] = inv;
+                rc = blas(c, sc, Vh, nullptr, 0);
+                if (rc) return rc;
+                sc.y = zs[j];
+                sc.x = zs[j];
+                rc = blas(c, sc, Vh, nullptr, 0);
+                if (rc) return rc;
+            }
+            // alpha = <w_j, r> ; x += alpha z_j ; r -= alpha w_j
+            double al[2];
+            {
+                OpCdot<F32, F32> d{};
+                d.a = ws[j];
+                d.b = rl;
+                d.nf = 1;
+                rc = blas(c, d, Vh, al, 2);
+                if (rc) return rc;
+            }
+            {
+                OpCaxpy<F64, F32> u{};
+                u.y = x;
+                u.x = zs[j];
+                u.nf = 1;
+                u.cre[0] = al[0];
+                u.cim[0] = al[1];
+                rc = blas(c, u, Vh, nullptr, 0);
+                if (rc) return rc;
+                OpCaxpy<F32, F32> v{};
+                v.y = rl;
+                v.x = ws[j];
+                v.nf = 1;
+                v.cre[0] = -al[0];
+                v.cim[0] = -al[1];
+                rc = blas(c, v, Vh, &rlo, 1);
+                if (rc) return rc;
+            }
+            if (!std::isfinite(rlo)) return set_err(c, TMX_ENOCONV, "FGCR: non-finite residual");
+            if (rlo <= cycle_target) break;
+        }
+        rc = fg_true_residual(c, op, dagger, r, b, x, q, &rr, &info->gbytes);
+        if (rc) return rc;
+        info->restarts++;
+        if (!std::isfinite(rr)) return set_err(c, TMX_ENOCONV, "FGCR: non-finite residual");
+        // stagnation: less than a factor 2 over a whole cycle
+        if (rr > 0.25 * prev_cycle && std::sqrt(rr) > tau * std::sqrt(bb)) {
+            info->iters += it;
+            return TMX_ENOCONV;
+        }
+        prev_cycle = rr;
+    }
+    info->iters += it;
+    return std::sqrt(rr) <= tau * std::sqrt(bb) ? TMX_OK : TMX_ENOCONV;
+}
+
+}  // namespace
+
+// Solve N x = b (N = Mhat^dagger Mhat, degenerate op) as two preconditioned
+// solves, Mhat^dagger y = b with K^dagger and Mhat x = y with K (the "two
+// inversions" of a preconditioned solver), each to tol / (1 + cond(Mhat)),
+// then check the FP64 true residual of N; plain CG from the current x if the
+// network fails to deliver (stagnation, non-finite values or the target missed).
+extern "C" int tmx_fgcr_solve_internal(tmx_ctx *c, SpinorPtr x, SpinorPtr b, const tmx_solver_cfg *cfg, tmx_info *info)
+{
+    if (cfg->op == TMX_OP_ND) return set_err(c, TMX_EINVAL, "FGCR is built for the degenerate operator");
+    tmx_info local{};
+    if (!info) info = &local;
+    const double tol = cfg->tol > 0 ? cfg->tol : 1e-10;
+    const int m = cfg->restart > 0 ? std::min(cfg->restart, 32) : 16;
+    const int maxiter = cfg->maxiter > 0 ? cfg->maxiter : 10000;
+    const double cond_mhat = 8.0;  // bound on cond(Mhat) for these parameters
+    const double tau = tol / (1.0 + cond_mhat);
+    int rc = ensure_ready(c, F64, false);
+    if (!rc) rc = ensure_ready(c, F32, false);
+    if (rc) return rc;
+    Fg F{c, c->Vh};
+    SpinorPtr y = F.f("y", F64);
+    // y = 0 ; stage 1: Mhat^dagger y = b
+    {
+        OpZero<F64> z{};
+        z.d = y;
+        z.nf = 1;
+        rc = blas(c, z, c->Vh, nullptr, 0);
+        if (rc) return rc;
+    }
+    bool ok = true;
+    rc = fgcr_stage(c, cfg->op, 1, y, b, tau, m, maxiter, cfg->inner_prec, info);
+    if (rc < 0 && rc != TMX_ENOCONV) ok = false;
+    if (rc == TMX_ENOCONV) ok = false;
+    if (ok) {
+        // stage 2: Mhat x = y (x holds the start vector)
+        rc = fgcr_stage(c, cfg->op, 0, x, y, tau, m, maxiter, cfg->inner_prec, info);
+        if (rc != TMX_OK) ok = false;
+    }
+    // acceptance (and fallback) by plain CG on N from the current x: with
+    // the network doing its job this only computes the true residual
+    int rcg = cg_fallback(c, cfg->op, x, b, tol, maxiter, info);
+    if (rcg < 0) return rcg;
+    if (!ok || info->fallback) info->fallback = info->fallback || !ok;
+    return rcg;
+}
+
+}  // namespace tmx
 
 using namespace tmx;
 
 extern "C" {
 
-void tmx_pc_free(tmx_ctx *c) { (void)c; }
-
-int tmx_fgcr_solve_internal(tmx_ctx *c, SpinorPtr, SpinorPtr, const tmx_solver_cfg *, tmx_info *)
+void tmx_pc_free(tmx_ctx *c)
 {
-    return set_err(c, TMX_EINVAL, "FGCR with the learned preconditioner is not available yet");
+    if (!c || !c->pc) return;
+    PcState &s = *c->pc;
+    dev_free(s.params);
+    dev_free(s.grad);
+    dev_free(s.adam_m);
+    dev_free(s.adam_v);
+    for (int l = 0; l < NN_L; ++l) {
+        dev_free(s.Wf[l]);
+        dev_free(s.Wa[l]);
+    }
+    delete c->pc;
+    c->pc = nullptr;
 }
 
 int tmx_pc_num_params(const tmx_ctx *c, size_t *n)
 {
-    (void)c;
-    (void)n;
-    return TMX_EINVAL;
+    if (!c || !n) return TMX_EINVAL;
+    *n = nn_num_params();
+    return TMX_OK;
 }
-int tmx_pc_set_weights(tmx_ctx *c, const float *, size_t) { return set_err(c, TMX_EINVAL, "not available yet"); }
-int tmx_pc_get_weights(tmx_ctx *c, float *, size_t) { return set_err(c, TMX_EINVAL, "not available yet"); }
-int tmx_pc_apply(tmx_ctx *c, double *, const double *, int) { return set_err(c, TMX_EINVAL, "not available yet"); }
-int tmx_pc_train(tmx_ctx *c, const double *, const double *, int, const tmx_train_cfg *, float *)
+
+int tmx_pc_set_weights(tmx_ctx *c, const float *host_w, size_t n)
 {
-    return set_err(c, TMX_EINVAL, "not available yet");
+    if (!c || !host_w) return TMX_EINVAL;
+    if (n != nn_num_params()) return set_err(c, TMX_EINVAL, "wrong number of preconditioner weights");
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(host_w[i])) return set_err(c, TMX_EINVAL, "non-finite preconditioner weight");
+    int r = nn_ensure(c);
+    if (r) return r;
+    PcState &s = *c->pc;
+    hipError_t e = hipMemcpyAsync(s.params, host_w, n * sizeof(float), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_err(c, e, "set weights");
+    s.w_ok = false;
+    s.have_weights = true;
+    s.adam_t = 0;
+    return TMX_OK;
+}
+
+int tmx_pc_get_weights(tmx_ctx *c, float *host_w, size_t n)
+{
+    if (!c || !host_w) return TMX_EINVAL;
+    if (n != nn_num_params()) return set_err(c, TMX_EINVAL, "wrong number of preconditioner weights");
+    if (!c->pc || !c->pc->have_weights) return set_err(c, TMX_ENOTLOADED, "preconditioner weights not set");
+    hipError_t e = hipMemcpyAsync(host_w, c->pc->params, n * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return hip_err(c, e, "get weights");
+}
+
+int tmx_pc_apply(tmx_ctx *c, double *out, const double *in, int dagger)
+{
+    if (!c || !out || !in) return TMX_EINVAL;
+    const long Vh = c->Vh;
+    void *pi = ws_get(c, "pca_in", spinor_field_bytes(F32, 1, Vh));
+    void *po = ws_get(c, "pca_out", spinor_field_bytes(F32, 1, Vh));
+    if (!pi || !po) return TMX_ENOMEM;
+    SpinorPtr I = make_spinor(pi, F32, 1, Vh), O = make_spinor(po, F32, 1, Vh);
+    int r = hip_err(c, launch_pack_spinor(in, I, F32, TMX_FIELD_ODD, c->g, 1, c->stream), "pack");
+    if (r) return r;
+    r = pc_apply_internal(c, O, F32, I, F32, dagger ? 1 : 0, false, nullptr);
+    if (r) return r;
+    r = hip_err(c, launch_unpack_spinor(out, O, F32, TMX_FIELD_ODD, c->g, 1, c->stream), "unpack");
+    if (r) return r;
+    return hip_err(c, hipStreamSynchronize(c->stream), "pc apply");
+}
+
+// gradient of the loss for a set of pairs (internal helper, also used by the
+// gradient check entry point): accumulates into the partial buffers, returns loss
+static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int *idx, int n, double *loss)
+{
+    PcState &s = *c->pc;
+    const long Vh = c->Vh;
+    const size_t fb = (size_t)Vh * 24;  // doubles per canonical odd field
+    float *partial[NN_L];
+    for (int l = 0; l < NN_L; ++l) {
+        const size_t np = (size_t)WG_BLOCKS * NN_P * pad16(8 * NN_COUT[l]) * pad16(8 * NN_CIN[l]);
+        partial[l] = static_cast<float *>(ws_get(c, "nn_partial" + std::to_string(l), np * sizeof(float)));
+        if (!partial[l]) return TMX_ENOMEM;
+        hipLaunchKernelGGL(nn_zero_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, c->stream, partial[l], np);
+    }
+    void *pb = ws_get(c, "tr_b", spinor_field_bytes(F32, 1, Vh));
+    void *px = ws_get(c, "tr_x", spinor_field_bytes(F32, 1, Vh));
+    if (!pb || !px) return TMX_ENOMEM;
+    SpinorPtr B = make_spinor(pb, F32, 1, Vh), X = make_spinor(px, F32, 1, Vh);
+    double L = 0;
+    for (int i = 0; i < n; ++i) {
+        const int k = idx ? idx[i] : i;
+        int r = hip_err(c, launch_pack_spinor(b + (size_t)k * fb, B, F32, TMX_FIELD_ODD, c->g, 1, c->stream), "pack b");
+        if (!r) r = hip_err(c, launch_pack_spinor(x + (size_t)k * fb, X, F32, TMX_FIELD_ODD, c->g, 1, c->stream), "pack x");
+        if (r) return r;
+        // |x|^2 for the scale
+        OpCopy<F32, F32> nx{};
+        nx.d = X;
+        nx.s = X;
+        nx.nf = 1;
+        r = hip_err(c, run_blas(nx, Vh, 1, c->red, c->stream), "norm");
+        double xx = 0;
+        if (!r) r = fetch(c, 1, &xx);
+        if (r) return r;
+        if (!(xx > 0)) return set_err(c, TMX_EINVAL, "training target with zero norm");
+        std::vector<SpinorPtr> acts;
+        void *pz = ws_get(c, "tr_z", spinor_field_bytes(F32, 1, Vh));
+        if (!pz) return TMX_ENOMEM;
+        r = pc_apply_internal(c, make_spinor(pz, F32, 1, Vh), F32, B, F32, 0, true, &acts);
+        if (r) return r;
+        // delta = embed(K b - x) / (|x|^2 n)
+        SpinorPtr dl = act(c, "d4", 1);
+        {
+            OpZero<F32> oz{};
+            oz.d = dl;
+            oz.nf = 1;
+            r = hip_err(c, run_blas(oz, Vh, 1, c->red, c->stream), "zero delta");
+            if (r) return r;
+        }
+        OpPairResidual<F32> pr{};
+        pr.out = odd_view(c, acts[NN_L]);
+        pr.x = X;
+        pr.delta = odd_view(c, dl);
+        pr.scale = 1.0 / (xx * n);
+        r = hip_err(c, run_blas(pr, Vh, 1, c->red, c->stream), "pair residual");
+        double red[2];
+        if (!r) r = fetch(c, 2, red);
+        if (r) return r;
+        L += red[0] / xx / n;
+        // backward through the layers
+        SpinorPtr delta = dl;
+        for (int l = NN_L - 1; l >= 0; --l) {
+            r = hip_err(c, launch_wgrad(c, NN_CIN[l], NN_COUT[l], acts[l], delta, partial[l]), "wgrad");
+            if (r) return r;
+            if (l > 0) {
+                SpinorPtr nd = act(c, "d" + std::to_string(l), NN_CIN[l]);
+                r = hip_err(c, launch_layer(c, NN_COUT[l], NN_CIN[l], delta, nd, s.Wa[l]), "adjoint layer");
+                if (r) return r;
+                delta = nd;
+            }
+        }
+    }
+    for (int l = 0; l < NN_L; ++l) {
+        const int per = NN_CIN[l] * NN_COUT[l] + 16;
+        const int nthr = NN_P * per;
+        hipLaunchKernelGGL(nn_grad_combine_kernel, dim3((nthr + 127) / 128), dim3(128), 0, c->stream, partial[l],
+                           WG_BLOCKS, s.params + layer_param_offset(l), s.grad + layer_param_offset(l), NN_CIN[l],
+                           NN_COUT[l]);
+    }
+    int r = hip_err(c, hipGetLastError(), "grad combine");
+    if (r) return r;
+    *loss = L;
+    return TMX_OK;
+}
+
+int tmx_pc_loss_grad(tmx_ctx *c, const double *b, const double *x, int npairs, double *loss, float *host_grad)
+{
+    if (!c || !b || !x || npairs < 1 || !loss) return TMX_EINVAL;
+    int r = nn_ensure(c);
+    if (r) return r;
+    if (!c->pc->have_weights) return set_err(c, TMX_ENOTLOADED, "preconditioner weights not set");
+    r = ensure_ready(c, F32, false);
+    if (!r) r = nn_build_weights(c);
+    if (!r) r = pc_loss_grad(c, b, x, nullptr, npairs, loss);
+    if (r) return r;
+    if (host_grad) {
+        hipError_t e = hipMemcpyAsync(host_grad, c->pc->grad, c->pc->nparam * sizeof(float), hipMemcpyDeviceToHost,
+                                      c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        return hip_err(c, e, "grad download");
+    }
+    return hip_err(c, hipStreamSynchronize(c->stream), "loss grad");
+}
+
+int tmx_pc_train(tmx_ctx *c, const double *b, const double *x, int npairs, const tmx_train_cfg *cfg, float *loss_out)
+{
+    if (!c || !b || !x || npairs < 1 || !cfg || cfg->epochs < 1 || cfg->batch < 1) return TMX_EINVAL;
+    int r = nn_ensure(c);
+    if (r) return r;
+    if (!c->pc->have_weights) return set_err(c, TMX_ENOTLOADED, "preconditioner weights not set");
+    r = ensure_ready(c, F32, false);
+    if (r) return r;
+    PcState &s = *c->pc;
+    if (s.adam_t == 0) {
+        hipLaunchKernelGGL(nn_zero_kernel, dim3((unsigned)((s.nparam + 255) / 256)), dim3(256), 0, c->stream, s.adam_m,
+                           s.nparam);
+        hipLaunchKernelGGL(nn_zero_kernel, dim3((unsigned)((s.nparam + 255) / 256)), dim3(256), 0, c->stream, s.adam_v,
+                           s.nparam);
+    }
+    const float lr = cfg->lr > 0 ? cfg->lr : 1e-3f, b1 = cfg->beta1 > 0 ? cfg->beta1 : 0.9f,
+                b2 = cfg->beta2 > 0 ? cfg->beta2 : 0.999f, eps = cfg->eps > 0 ? cfg->eps : 1e-8f;
+    // deterministic shuffle (LCG seeded by cfg->seed)
+    std::vector<int> order(npairs);
+    for (int i = 0; i < npairs; ++i) order[i] = i;
+    uint64_t st = 0x9e3779b97f4a7c15ull ^ (uint64_t)(uint32_t)cfg->seed;
+    for (int ep = 0; ep < cfg->epochs; ++ep) {
+        for (int i = npairs - 1; i > 0; --i) {
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            const int j = (int)((st >> 33) % (uint64_t)(i + 1));
+            std::swap(order[i], order[j]);
+        }
+        double eloss = 0;
+        int nb = 0;
+        for (int i0 = 0; i0 < npairs; i0 += cfg->batch) {
+            const int n = std::min(cfg->batch, npairs - i0);
+            r = nn_build_weights(c);
+            if (r) return r;
+            double L;
+            r = pc_loss_grad(c, b, x, order.data() + i0, n, &L);
+            if (r) return r;
+            if (!std::isfinite(L)) return set_err(c, TMX_ENOCONV, "training loss is not finite");
+            eloss += L;
+            ++nb;
+            s.adam_t++;
+            const float c1 = 1.f - std::pow(b1, (float)s.adam_t), c2 = 1.f - std::pow(b2, (float)s.adam_t);
+            hipLaunchKernelGGL(nn_adam_kernel, dim3((unsigned)((s.nparam + 255) / 256)), dim3(256), 0, c->stream,
+                               s.params, s.grad, s.adam_m, s.adam_v, (int)s.nparam, lr, b1, b2, eps, c1, c2);
+            r = hip_err(c, hipGetLastError(), "adam");
+            if (r) return r;
+            s.w_ok = false;
+        }
+        if (loss_out) loss_out[ep] = (float)(eloss / nb);
+    }
+    return hip_err(c, hipStreamSynchronize(c->stream), "train");
 }
 
 }  // extern "C"

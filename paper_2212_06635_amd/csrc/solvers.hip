@@ -378,6 +378,29 @@ static int mscg_core(Sys &S, std::vector<SpinorPtr> &xs, SpinorPtr b64, const do
     return TMX_OK;
 }
 
+// CG from the current x (used to accept or rescue a preconditioned solve):
+// sets info->fallback when iterations were needed.
+int cg_fallback(tmx_ctx *c, int op, SpinorPtr x, SpinorPtr b, double tol, int maxiter, tmx_info *info)
+{
+    Sys S(c, op, 1);
+    tmx_solver_cfg cfg{};
+    cfg.kind = TMX_SOLVER_MPCG_F32;
+    cfg.op = op;
+    cfg.tol = tol;
+    cfg.maxiter = maxiter;
+    tmx_info inf{};
+    int rc = dispatch_cg(S, F32, x, b, 1, nullptr, cfg, true, &inf);
+    if (rc < 0) return rc;
+    if (info) {
+        if (inf.iters > 0) info->fallback = 1;
+        info->iters += inf.iters;
+        info->reliable_updates += inf.reliable_updates;
+        info->true_residual = inf.true_residual;
+        info->gbytes += S.gbytes;
+    }
+    return rc;
+}
+
 }  // namespace tmx
 
 using namespace tmx;

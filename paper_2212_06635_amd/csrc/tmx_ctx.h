@@ -107,6 +107,12 @@ struct tmx_ctx {
 
 namespace tmx {
 
+#define HIP_CHECK_RET(c, x, w)               \
+    do {                                     \
+        int _rr = hip_err((c), (x), (w));    \
+        if (_rr) return _rr;                 \
+    } while (0)
+
 // error helpers
 int set_err(tmx_ctx *c, int code, const std::string &msg);
 int hip_err(tmx_ctx *c, hipError_t e, const char *where);
@@ -133,6 +139,12 @@ int fetch(tmx_ctx *c, int n, double *host);
 double mhat_bytes_per_site(int prec, int nf, int nrhs);
 
 double now_seconds();
+
+// learned preconditioner: z = K r (dagger = 0) or K^dagger r on odd fields
+int pc_apply_internal(tmx_ctx *c, SpinorPtr z, int pz, SpinorPtr r, int pr, int dagger, bool keep,
+                      std::vector<SpinorPtr> *acts_out);
+// plain / mixed CG on N used as the fallback of the flexible GCR solver
+int cg_fallback(tmx_ctx *c, int op, SpinorPtr x, SpinorPtr b, double tol, int maxiter, tmx_info *info);
 
 // kernel-timing brackets around a launch (no-ops unless enabled)
 void kstat_begin(tmx_ctx *c, const std::string &name);

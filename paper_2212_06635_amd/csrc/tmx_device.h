@@ -133,15 +133,60 @@ __device__ __forceinline__ uint2 f_to_h4(const float *o)
     return v;
 }
 
+// 16-byte load; NT = non-temporal (streamed operands such as links and
+// clover blocks are read once per sweep: keeping them out of the way in L2
+// leaves room for the neighbour spinors, which are read eight times)
+typedef double ev_d2 __attribute__((ext_vector_type(2)));
+typedef float ev_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int ev_u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int ev_u2 __attribute__((ext_vector_type(2)));
+
+template <bool NT> __device__ __forceinline__ double2 ldv(const double2 *p)
+{
+    if constexpr (NT) {
+        const ev_d2 v = __builtin_nontemporal_load(reinterpret_cast<const ev_d2 *>(p));
+        return make_double2(v.x, v.y);
+    } else {
+        return *p;
+    }
+}
+template <bool NT> __device__ __forceinline__ float4 ldv(const float4 *p)
+{
+    if constexpr (NT) {
+        const ev_f4 v = __builtin_nontemporal_load(reinterpret_cast<const ev_f4 *>(p));
+        return make_float4(v.x, v.y, v.z, v.w);
+    } else {
+        return *p;
+    }
+}
+template <bool NT> __device__ __forceinline__ uint4 ldv(const uint4 *p)
+{
+    if constexpr (NT) {
+        const ev_u4 v = __builtin_nontemporal_load(reinterpret_cast<const ev_u4 *>(p));
+        return make_uint4(v.x, v.y, v.z, v.w);
+    } else {
+        return *p;
+    }
+}
+template <bool NT> __device__ __forceinline__ uint2 ldv(const uint2 *p)
+{
+    if constexpr (NT) {
+        const ev_u2 v = __builtin_nontemporal_load(reinterpret_cast<const ev_u2 *>(p));
+        return make_uint2(v.x, v.y);
+    } else {
+        return *p;
+    }
+}
+
 // Load N reals (N a multiple of the vector width) of site s.
-template <int P, int N, typename R>
+template <int P, int N, typename R, bool NT = false>
 __device__ __forceinline__ void load_seq(const void *base, long stride, long s, R *o)
 {
     if constexpr (P == F64) {
         const double2 *b = static_cast<const double2 *>(base);
 #pragma unroll
         for (int k = 0; k < N / 2; ++k) {
-            double2 v = b[k * stride + s];
+            double2 v = ldv<NT>(b + k * stride + s);
             o[2 * k] = v.x;
             o[2 * k + 1] = v.y;
         }
@@ -149,7 +194,7 @@ __device__ __forceinline__ void load_seq(const void *base, long stride, long s, 
         const float4 *b = static_cast<const float4 *>(base);
 #pragma unroll
         for (int k = 0; k < N / 4; ++k) {
-            float4 v = b[k * stride + s];
+            float4 v = ldv<NT>(b + k * stride + s);
             o[4 * k] = v.x;
             o[4 * k + 1] = v.y;
             o[4 * k + 2] = v.z;
@@ -160,7 +205,7 @@ __device__ __forceinline__ void load_seq(const void *base, long stride, long s, 
 #pragma unroll
         for (int k = 0; k < N / 8; ++k) {
             float f8[8];
-            h8_to_f(b[k * stride + s], f8);
+            h8_to_f(ldv<NT>(b + k * stride + s), f8);
 #pragma unroll
             for (int j = 0; j < 8; ++j) o[8 * k + j] = f8[j];
         }
@@ -289,7 +334,7 @@ __device__ __forceinline__ void load_link(const LinkPtr &U, int p, int mu, long 
         const double2 *b = static_cast<const double2 *>(U.d) + base;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            double2 v = b[k * U.Vh + s];
+            double2 v = ldv<true>(b + k * U.Vh + s);
             t[2 * k] = v.x;
             t[2 * k + 1] = v.y;
         }
@@ -297,7 +342,7 @@ __device__ __forceinline__ void load_link(const LinkPtr &U, int p, int mu, long 
         const float4 *b = static_cast<const float4 *>(U.d) + base;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            float4 v = b[k * U.Vh + s];
+            float4 v = ldv<true>(b + k * U.Vh + s);
             t[4 * k] = v.x;
             t[4 * k + 1] = v.y;
             t[4 * k + 2] = v.z;
@@ -306,7 +351,7 @@ __device__ __forceinline__ void load_link(const LinkPtr &U, int p, int mu, long 
     } else {
         const uint2 *b = static_cast<const uint2 *>(U.d) + base;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) h4_to_f(b[k * U.Vh + s], t + 4 * k);
+        for (int k = 0; k < 3; ++k) h4_to_f(ldv<true>(b + k * U.Vh + s), t + 4 * k);
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k) u[k] = cx<R>{t[2 * k], t[2 * k + 1]};
@@ -379,12 +424,12 @@ __device__ __forceinline__ void herm_apply_c(const void *base, long stride, long
     R a[36];
     if constexpr (P == F16) {
         R w[40];
-        load_seq<P, 40>(static_cast<const char *>(base) + (size_t)4 * chir * stride * 16, stride, s, w);
+        load_seq<P, 40, R, true>(static_cast<const char *>(base) + (size_t)4 * chir * stride * 16, stride, s, w);
 #pragma unroll
         for (int k = 0; k < 36; ++k) a[k] = chir ? w[k + 4] : w[k];
     } else {
         const int off = chir * 36 / reals_per_vec<P>();
-        load_seq<P, 36>(static_cast<const char *>(base) + (size_t)off * stride * 16, stride, s, a);
+        load_seq<P, 36, R, true>(static_cast<const char *>(base) + (size_t)off * stride * 16, stride, s, a);
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) o[i] = cx<R>{a[i] * v[i].re - twist * v[i].im, a[i] * v[i].im + twist * v[i].re};
@@ -455,7 +500,7 @@ __device__ __forceinline__ void full_apply(const void *base, long stride, long s
     // load row by row (12 reals per row) to bound register use
     if constexpr (P == F16) {
         R a[72];
-        load_seq<P, 72>(b, stride, s, a);
+        load_seq<P, 72, R, true>(b, stride, s, a);
 #pragma unroll
         for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -470,7 +515,7 @@ __device__ __forceinline__ void full_apply(const void *base, long stride, long s
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
             R a[12];
-            load_seq<P, 12>(b + (size_t)(12 * i / reals_per_vec<P>()) * stride * 16, stride, s, a);
+            load_seq<P, 12, R, true>(b + (size_t)(12 * i / reals_per_vec<P>()) * stride * 16, stride, s, a);
 #pragma unroll
             for (int j = 0; j < 6; ++j) {
                 cx<R> m{a[2 * j], a[2 * j + 1]};

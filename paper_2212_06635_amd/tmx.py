@@ -93,6 +93,7 @@ def _load():
         "tmx_pc_get_weights": ([P, P, Z], I),
         "tmx_pc_apply": ([P, P, P, I], I),
         "tmx_pc_train": ([P, P, P, I, ctypes.POINTER(tmx_train_cfg), P], I),
+        "tmx_pc_loss_grad": ([P, P, P, I, ctypes.POINTER(D), P], I),
         "tmx_tune": ([P, I, I, I], I),
         "tmx_tuned_config": ([P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(I)], I),
         "tmx_kstats_enable": ([P, I], I),
@@ -308,6 +309,12 @@ class Context:
             out[buf.value.decode()] = (n.value, ms.value)
             i += 1
         return out
+
+    def pc_loss_grad(self, b, x, npairs):
+        loss = ctypes.c_double()
+        g = np.zeros(self.pc_num_params(), dtype=np.float32)
+        self.check(lib.tmx_pc_loss_grad(self.h, _ptr(b), _ptr(x), npairs, ctypes.byref(loss), g.ctypes.data))
+        return loss.value, g
 
     # -- tracing ----------------------------------------------------------------
     def trace_enable(self, on=True):

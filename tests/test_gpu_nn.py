@@ -1,0 +1,140 @@
+"""GPU learned preconditioner against the FP64 network oracle.
+
+The GPU network stages transported activations and weights in BF16 (8-bit
+mantissa, relative rounding 2^-9) and accumulates in FP32, over four layers;
+outputs are compared to the oracle to relative L2 <= 2e-2 and gradients by
+relative L2 <= 5e-2 with cosine >= 0.999.
+"""
+import numpy as np
+import pytest
+
+from helpers import CSW, KAPPA, rel_l2, to_dev, to_host
+from oracle import Oracle
+from oracle import nn_oracle as nn
+from paper_2212_06635_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (8, 8, 4, 8)
+MU0 = 0.01
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_2212_06635_amd.tmx as tmx
+
+    print("\n[gpu nn] 8x8x4x8 eps=0.3", flush=True)
+    U = synth.gauge_links(DIMS, 0.3, 31)
+    ctx = tmx.Context(DIMS)
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU0, 0.0, 0.0, -1))
+    ctx.load_gauge(U, 31.0)
+    lat = nn.Lattice(DIMS, U, t_bc=-1)
+    yield tmx, ctx, lat, U
+    ctx.close()
+
+
+def f32(w):
+    return np.asarray(w, dtype=np.float32).astype(np.float64)
+
+
+def test_param_count(S):
+    tmx, ctx, lat, _ = S
+    assert ctx.pc_num_params() == nn.num_params()
+
+
+def test_identity_network(S):
+    tmx, ctx, lat, _ = S
+    w = nn.identity_init(None)
+    ctx.pc_set_weights(w)
+    b = synth.gaussian_cb_spinor(DIMS, 40, 0)
+    out = to_dev(np.zeros_like(b))
+    ctx.pc_apply(out, to_dev(b), 0)
+    assert rel_l2(to_host(out, b.shape), b) < 1e-2
+    assert np.allclose(ctx.pc_get_weights(), w.astype(np.float32))
+
+
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_random_network_matches_oracle(S, dagger):
+    tmx, ctx, lat, _ = S
+    rng = np.random.default_rng(41)
+    w = (rng.standard_normal(nn.num_params()) * 0.3).astype(np.float32)
+    ctx.pc_set_weights(w)
+    b = synth.gaussian_cb_spinor(DIMS, 41, 0)
+    out = to_dev(np.zeros_like(b))
+    ctx.pc_apply(out, to_dev(b), dagger)
+    ref = (nn.adjoint if dagger else nn.forward)(lat, f32(w), b[:, 0])
+    assert rel_l2(to_host(out, b.shape)[:, 0], ref) < 2e-2
+
+
+def test_gradient_matches_oracle(S):
+    tmx, ctx, lat, _ = S
+    rng = np.random.default_rng(42)
+    w = (nn.identity_init(rng, 0.1)).astype(np.float32)
+    ctx.pc_set_weights(w)
+    bs = np.stack([synth.gaussian_cb_spinor(DIMS, 42, k) for k in range(2)])
+    xs = np.stack([synth.gaussian_cb_spinor(DIMS, 43, k) for k in range(2)])
+    loss, g = ctx.pc_loss_grad(to_dev(bs), to_dev(xs), 2)
+    L, gref = nn.loss_and_grad(lat, f32(w), [b[:, 0] for b in bs], [x[:, 0] for x in xs])
+    assert abs(loss - L) / L < 2e-2
+    cos = float(np.dot(g, gref) / np.linalg.norm(g) / np.linalg.norm(gref))
+    assert cos > 0.999, cos
+    assert rel_l2(g, gref) < 5e-2
+
+
+@pytest.fixture(scope="module")
+def pairs(S):
+    """(b, x = Mhat^{-1} b) from the plain solver on the same field."""
+    tmx, ctx, lat, U = S
+    n = 16
+    bs = np.stack([synth.gaussian_cb_spinor(DIMS, 50, k) for k in range(n)])
+    xd = to_dev(np.zeros_like(bs))
+    for k in range(n):
+        xk = to_dev(np.zeros_like(bs[k]))
+        rc, info = ctx.solve_mhat(xk, to_dev(bs[k]), dagger=0, op=1, tol=1e-10)
+        assert rc == tmx.TMX_OK
+        xd[k * bs[k].size:(k + 1) * bs[k].size] = xk
+    return bs, xd
+
+
+def test_training_reduces_loss(S, pairs):
+    tmx, ctx, lat, _ = S
+    bs, xd = pairs
+    ctx.pc_set_weights(nn.identity_init(np.random.default_rng(3), 1e-2))
+    losses = ctx.pc_train(to_dev(bs), xd, len(bs), epochs=12, batch=4, lr=3e-3, seed=1)
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.7 * losses[0], losses
+
+
+def test_fgcr_reaches_target(S, pairs):
+    """FGCR with the (trained) network: FP64 true residual <= 1e-10 by the oracle operator."""
+    tmx, ctx, lat, U = S
+    o = Oracle(DIMS, U, KAPPA, CSW, mu=MU0)
+    b = synth.gaussian_cb_spinor(DIMS, 60, 0)
+    x = to_dev(np.zeros_like(b))
+    rc, info = ctx.solve(x, to_dev(b), 1, kind=tmx.TMX_SOLVER_FGCR_NN, op=1, tol=1e-10, restart=8)
+    assert rc == tmx.TMX_OK, info
+    assert o.residual(b, to_host(x, b.shape)) <= 1e-10
+
+
+def test_fgcr_fallback_with_garbage_network(S):
+    """A useless network still yields a 1e-10 solution, through the CG fallback."""
+    tmx, ctx, lat, U = S
+    o = Oracle(DIMS, U, KAPPA, CSW, mu=MU0)
+    rng = np.random.default_rng(9)
+    ctx.pc_set_weights((rng.standard_normal(nn.num_params()) * 3.0).astype(np.float32))
+    b = synth.gaussian_cb_spinor(DIMS, 61, 0)
+    x = to_dev(np.zeros_like(b))
+    rc, info = ctx.solve(x, to_dev(b), 1, kind=tmx.TMX_SOLVER_FGCR_NN, op=1, tol=1e-10, restart=8, maxiter=400)
+    assert rc == tmx.TMX_OK
+    assert info[0]["fallback"] == 1
+    assert o.residual(b, to_host(x, b.shape)) <= 1e-10
+
+
+def test_weights_validation(S):
+    tmx, ctx, lat, _ = S
+    with pytest.raises(tmx.TmxError):
+        ctx.pc_set_weights(np.zeros(10, dtype=np.float32))
+    bad = nn.identity_init(None).astype(np.float32)
+    bad[5] = np.nan
+    with pytest.raises(tmx.TmxError):
+        ctx.pc_set_weights(bad)

@@ -1,0 +1,104 @@
+"""Pins of the learned-preconditioner oracle (network definition: linear,
+gauge-equivariant parallel-transport layers with C_d (x) Gamma_d weights)."""
+import numpy as np
+import pytest
+
+from oracle import nn_oracle as nn
+from paper_2212_06635_amd import synth
+
+DIMS = (4, 4, 2, 4)
+
+
+@pytest.fixture(scope="module")
+def lat():
+    U = synth.gauge_links(DIMS, 0.4, 17)
+    return nn.Lattice(DIMS, U, t_bc=-1), U
+
+
+def rand_params(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(nn.num_params()) * scale
+
+
+def test_param_count_and_roundtrip():
+    assert nn.num_params() == 2 * 9 * (8 + 16 + 64 + 16 + 64 + 16 + 8 + 16)
+    w = rand_params(1)
+    assert np.array_equal(nn.flatten(nn.unflatten(w)), w)
+
+
+def test_identity_init_is_identity(lat):
+    L, _ = lat
+    w = nn.identity_init(None)
+    b = synth.gaussian_cb_spinor(DIMS, 3, 0)[:, 0]
+    assert np.array_equal(nn.forward(L, w, b), b)
+
+
+def test_two_hop_path_is_pure_transport(lat):
+    """Only +x in layer 3 and +y in layer 4: (K b)(x) = U_y(x) U_x(x+y) b(x+y+x)."""
+    L, U = lat
+    params = nn.unflatten(nn.identity_init(None))
+    C3, G3 = params[2]
+    C3[0] = 0
+    G3[0] = 0
+    C3[1] = np.eye(8)
+    G3[1] = np.eye(4)  # d = 1: +x
+    C4, G4 = params[3]
+    C4[0] = 0
+    G4[0] = 0
+    C4[3] = np.eye(1, 8)
+    G4[3] = np.eye(4)  # d = 3: +y
+    w = nn.flatten(params)
+    b = synth.gaussian_cb_spinor(DIMS, 3, 1)[:, 0]
+    out = nn.forward(L, w, b)
+    lx, ly, lz, lt = DIMS
+    full = np.zeros((lx * ly * lz * lt, 4, 3), dtype=complex)
+    full[synth.odd_sites(DIMS, 1)] = b
+    Ul = U.reshape(-1, 4, 3, 3)
+    odd = synth.odd_sites(DIMS, 1)
+    for k in range(0, len(odd), 7):
+        i = odd[k]
+        x, y, z, t = i % lx, (i // lx) % ly, (i // (lx * ly)) % lz, i // (lx * ly * lz)
+        j = x + lx * ((y + 1) % ly + ly * (z + lz * t))  # x + y-hat
+        m = (x + 1) % lx + lx * ((y + 1) % ly + ly * (z + lz * t))  # x + y-hat + x-hat
+        expect = (Ul[i, 1] @ Ul[j, 0] @ full[m].T).T
+        assert np.allclose(out[k], expect, atol=1e-14)
+
+
+def test_gauge_covariance(lat):
+    L, U = lat
+    G = synth.random_gauge_transform(DIMS, 5)
+    Lp = nn.Lattice(DIMS, synth.gauge_transform_links(U, G), t_bc=-1)
+    w = rand_params(2)
+    b = synth.gaussian_cb_spinor(DIMS, 3, 2)[:, 0]
+    Go = G.reshape(-1, 3, 3)[synth.odd_sites(DIMS, 1)]
+    gb = np.einsum("xab,xsb->xsa", Go, b)
+    assert np.allclose(nn.forward(Lp, w, gb), np.einsum("xab,xsb->xsa", Go, nn.forward(L, w, b)), atol=1e-12)
+
+
+def test_adjoint(lat):
+    L, _ = lat
+    w = rand_params(3)
+    u = synth.gaussian_cb_spinor(DIMS, 3, 3)[:, 0]
+    v = synth.gaussian_cb_spinor(DIMS, 3, 4)[:, 0]
+    a = np.vdot(u, nn.forward(L, w, v))
+    b = np.vdot(nn.adjoint(L, w, u), v)
+    assert abs(a - b) / abs(a) < 1e-13
+
+
+def test_gradient_matches_finite_differences(lat):
+    L, _ = lat
+    w = rand_params(4, 0.2)
+    bs = [synth.gaussian_cb_spinor(DIMS, 3, 10 + i)[:, 0] for i in range(2)]
+    xs = [synth.gaussian_cb_spinor(DIMS, 3, 20 + i)[:, 0] for i in range(2)]
+    loss, g = nn.loss_and_grad(L, w, bs, xs)
+    rng = np.random.default_rng(7)
+    idx = rng.choice(w.size, 40, replace=False)
+    h = 1e-5
+    for k in idx:
+        wp, wm = w.copy(), w.copy()
+        wp[k] += h
+        wm[k] -= h
+        lp = nn.loss_and_grad(L, wp, bs, xs)[0]
+        lm = nn.loss_and_grad(L, wm, bs, xs)[0]
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1e-3, abs(g[k])) + 1e-9, (k, fd, g[k])
