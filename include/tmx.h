@@ -88,7 +88,10 @@ enum {
     TMX_SOLVER_CG = 0,      /* plain FP64 CG on N */
     TMX_SOLVER_MPCG_F32 = 1,/* CG with FP32 inner iterations, FP64 reliable updates */
     TMX_SOLVER_MPCG_F16 = 2,/* CG with FP16-storage inner iterations, FP64 reliable updates */
-    TMX_SOLVER_FGCR_NN = 3  /* flexible GCR preconditioned by the learned network, CG fallback */
+    TMX_SOLVER_FGCR_NN = 3, /* two flexible-GCR solves (Mhat^dagger with K^dagger, Mhat with K), restarted;
+                               CG acceptance and fallback */
+    TMX_SOLVER_PCG_NN = 4   /* flexible CG on N preconditioned by K K^dagger (learned network), inner
+                               precision cfg->inner_prec (F32 / F16) with FP64 reliable updates */
 };
 
 typedef struct {
@@ -196,10 +199,11 @@ int tmx_pc_get_weights(tmx_ctx *ctx, float *host_w, size_t n);
  * complex128 device fields. */
 int tmx_pc_apply(tmx_ctx *ctx, double *out, const double *in, int dagger);
 
-/* Loss mean_i |K b_i - x_i|^2 / |x_i|^2 over npairs canonical odd device
- * fields and its gradient with respect to the weights (host_grad may be
+/* Training loss (loss_kind as in tmx_train_cfg) over npairs canonical odd
+ * device fields and its gradient with respect to the weights (host_grad may be
  * NULL), as used by one training step. */
-int tmx_pc_loss_grad(tmx_ctx *ctx, const double *b, const double *x, int npairs, double *loss, float *host_grad);
+int tmx_pc_loss_grad(tmx_ctx *ctx, const double *b, const double *x, int npairs, int loss_kind, double *loss,
+                     float *host_grad);
 
 typedef struct {
     int epochs;
@@ -207,10 +211,19 @@ typedef struct {
     float lr;
     float beta1, beta2, eps;
     int seed;
+    int loss_kind; /* TMX_LOSS_RESIDUAL (default) or TMX_LOSS_SOLUTION */
 } tmx_train_cfg;
 
+/* training losses over pairs (b_i, x_i = Mhat^{-1} b_i):
+ *   residual: mean_i |Mhat (K b_i - x_i)|^2 / |b_i|^2  = |Mhat K b_i - b_i|^2 / |b_i|^2
+ *   solution: mean_i |K b_i - x_i|^2 / |x_i|^2
+ * The residual loss controls E = Mhat K - 1 on all modes, which is what a
+ * preconditioner needs; the solution loss weights the high modes of Mhat
+ * down by Mhat^{-1}. */
+enum { TMX_LOSS_RESIDUAL = 0, TMX_LOSS_SOLUTION = 1 };
+
 /* Train on npairs (b_i, x_i) canonical odd complex128 device fields with
- * loss mean_i |K b_i - x_i|^2 / |x_i|^2 and Adam; loss_out[epochs] receives
+ * the loss selected by cfg->loss_kind and Adam; loss_out[epochs] receives
  * the mean loss of each epoch (host). */
 int tmx_pc_train(tmx_ctx *ctx, const double *b, const double *x, int npairs, const tmx_train_cfg *cfg,
                  float *loss_out);

@@ -181,8 +181,14 @@ def adjoint(lat: Lattice, w, u):
     return lat.restrict_odd(f)
 
 
-def loss_and_grad(lat: Lattice, w, bs, xs):
-    """L = mean_i |K b_i - x_i|^2 / |x_i|^2 and its gradient with respect to the flat real weights."""
+def loss_and_grad(lat: Lattice, w, bs, xs, mhat=None, mhat_dag=None):
+    """Training loss and its gradient with respect to the flat real weights.
+
+    Without operators: the solution loss  L = mean_i |K b_i - x_i|^2 / |x_i|^2.
+    With mhat / mhat_dag (callables on odd fields (Vh, 4, 3)): the residual
+    loss  L = mean_i |Mhat (K b_i - x_i)|^2 / |b_i|^2, whose output adjoint is
+    Mhat^dagger Mhat (K b_i - x_i) / (|b_i|^2 n).
+    """
     params = unflatten(w)
     n = len(bs)
     L = 0.0
@@ -190,9 +196,15 @@ def loss_and_grad(lat: Lattice, w, bs, xs):
     for b, x in zip(bs, xs):
         out, acts = forward(lat, w, b, keep=True)
         r = out - np.asarray(x).reshape(out.shape)
-        xx = np.vdot(x, x).real
-        L += np.vdot(r, r).real / xx / n
-        delta = lat.embed_odd(r / xx / n)
+        if mhat is None:
+            xx = np.vdot(x, x).real
+            L += np.vdot(r, r).real / xx / n
+            delta = lat.embed_odd(r / xx / n)
+        else:
+            bb = np.vdot(b, b).real
+            q = mhat(r)
+            L += np.vdot(q, q).real / bb / n
+            delta = lat.embed_odd(mhat_dag(q) / bb / n)
         for li in range(len(params) - 1, -1, -1):
             C, G = params[li]
             xin = acts[li]

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -236,6 +237,92 @@ __device__ __forceinline__ void stage_z(const Geom &g, const SpinorPtr &x, const
 // ---------------------------------------------------------------------------
 // layer kernel: Y = sum_d W_d Z_d   (forward or adjoint, by the weights given)
 // ---------------------------------------------------------------------------
+// Staged data of one thread for one path: the neighbour spinors of its
+// channels and the raw link rows, held in registers while the matrix cores
+// work on the previous path (software pipelining across the nine paths).
+template <int CIN> struct Staged {
+    cx<float> psi[(CIN + 3) / 4][12];
+    float4 lk[3];
+    Nbr nb;
+    bool valid;
+};
+
+template <int CIN>
+__device__ __forceinline__ void stage_load(const Geom &g, const SpinorPtr &x, const LinkPtr &U, int t_bc, long site0,
+                                           long V, int d, Staged<CIN> &st)
+{
+    const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
+    const long gs = site0 + sl;
+    st.valid = gs < V;
+    if (!st.valid) return;
+    st.nb = path_neighbour(g, gs, d, t_bc);
+    if (!st.nb.ident) {
+        const int mu = (d - 1) / 2;
+        const float4 *b = static_cast<const float4 *>(U.d) + (long)(st.nb.lp * 4 + mu) * 3 * U.Vh;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) st.lk[k] = ldv<true>(b + k * U.Vh + st.nb.lcb);
+    }
+#pragma unroll
+    for (int i = 0; i < (CIN + 3) / 4; ++i) {
+        const int c = q + 4 * i;
+        if (c < CIN) load_spinor<F32>(x, c, st.nb.idx, st.psi[i]);
+    }
+}
+
+template <int CIN, int KS>
+__device__ __forceinline__ void stage_store(const Staged<CIN> &st, uint16_t (*Zs)[KS])
+{
+    const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
+    cx<float> u[9];
+    if (st.valid && !st.nb.ident) {
+        const float t[12] = {st.lk[0].x, st.lk[0].y, st.lk[0].z, st.lk[0].w, st.lk[1].x, st.lk[1].y,
+                             st.lk[1].z, st.lk[1].w, st.lk[2].x, st.lk[2].y, st.lk[2].z, st.lk[2].w};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) u[k] = cx<float>{t[2 * k], t[2 * k + 1]};
+        u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+        u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+        u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+    }
+#pragma unroll
+    for (int i = 0; i < (CIN + 3) / 4; ++i) {
+        const int c = q + 4 * i;
+        if (c >= CIN) continue;
+        cx<float> z[12];
+        if (!st.valid) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) z[k] = cx<float>{0.f, 0.f};
+        } else if (st.nb.ident) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) z[k] = st.psi[i][k];
+        } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    cx<float> acc{0.f, 0.f};
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        if (st.nb.dag)
+                            cmac_conj(acc, u[3 * b + a], st.psi[i][3 * s + b]);
+                        else
+                            cmac(acc, u[3 * a + b], st.psi[i][3 * s + b]);
+                    }
+                    z[3 * s + a] = st.nb.bc * acc;
+                }
+        }
+#pragma unroll
+        for (int col = 0; col < 3; ++col) {
+            uint16_t v[8];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                v[2 * s] = f2bf(z[3 * s + col].re);
+                v[2 * s + 1] = f2bf(z[3 * s + col].im);
+            }
+            *reinterpret_cast<uint4 *>(&Zs[sl * 3 + col][c * 8]) = *reinterpret_cast<const uint4 *>(v);
+        }
+    }
+}
+
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) nn_layer_kernel(Geom g, SpinorPtr x, SpinorPtr y, LinkPtr U,
                                                        const uint16_t *W, int t_bc)
@@ -243,16 +330,15 @@ __global__ void __launch_bounds__(256) nn_layer_kernel(Geom g, SpinorPtr x, Spin
     constexpr int KD = pad16(8 * CIN), MD = pad16(8 * COUT);
     constexpr int KS = KD + NN_PAD;
     constexpr int MT = MD / 16, KT = KD / 16;
-    __shared__ __attribute__((aligned(16))) uint16_t Zs[NN_N][KS];
-    __shared__ __attribute__((aligned(16))) uint16_t Ws[MD][KS];
+    __shared__ __attribute__((aligned(16))) uint16_t Zs[2][NN_N][KS];
     const long V = 2L * g.Vh;
     const long site0 = (long)blockIdx.x * NN_S;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
 
     // padded k columns stay zero for the whole kernel
     if (8 * CIN < KD) {
-        for (int i = threadIdx.x; i < NN_N; i += blockDim.x)
-            for (int k = 8 * CIN; k < KD; ++k) Zs[i][k] = 0;
+        for (int i = threadIdx.x; i < 2 * NN_N; i += blockDim.x)
+            for (int k = 8 * CIN; k < KD; ++k) Zs[i / NN_N][i % NN_N][k] = 0;
     }
     f32x4 acc[MT][3];
 #pragma unroll
@@ -260,25 +346,36 @@ __global__ void __launch_bounds__(256) nn_layer_kernel(Geom g, SpinorPtr x, Spin
 #pragma unroll
         for (int j = 0; j < 3; ++j) acc[mt][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    Staged<CIN> st;
+    stage_load<CIN>(g, x, U, t_bc, site0, V, 0, st);
+    stage_store<CIN, KS>(st, Zs[0]);
+    __syncthreads();
     for (int d = 0; d < NN_P; ++d) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < MD * KD; i += blockDim.x) Ws[i / KD][i % KD] = W[(size_t)d * MD * KD + i];
-        stage_z<CIN, KS>(g, x, U, t_bc, site0, V, d, Zs, false, nullptr, 0);
-        __syncthreads();
+        // weight fragments of path d straight from L2 (shared by every tile)
+        bf16x4 wa[MT][KT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int kk = 0; kk < KT; ++kk)
+                wa[mt][kk] = *reinterpret_cast<const bf16x4 *>(
+                    W + ((size_t)d * MD + mt * 16 + lane % 16) * KD + kk * 16 + 4 * (lane / 16));
+        // the next path's neighbour data is in flight while the matrix cores run
+        if (d + 1 < NN_P) stage_load<CIN>(g, x, U, t_bc, site0, V, d + 1, st);
+        const int cur = d & 1;
 #pragma unroll
         for (int kk = 0; kk < KT; ++kk) {
             const int kb = kk * 16 + 4 * (lane / 16);
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const bf16x4 a = *reinterpret_cast<const bf16x4 *>(&Ws[mt * 16 + lane % 16][kb]);
+            for (int j = 0; j < 3; ++j) {
+                const int nt = wave * 3 + j;
+                const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&Zs[cur][nt * 16 + lane % 16][kb]);
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const int nt = wave * 3 + j;
-                    const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&Zs[nt * 16 + lane % 16][kb]);
-                    acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[mt][j], 0, 0, 0);
-                }
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[mt][kk], b, acc[mt][j], 0, 0, 0);
             }
         }
+        if (d + 1 < NN_P) stage_store<CIN, KS>(st, Zs[cur ^ 1]);
+        __syncthreads();
     }
     // D[m][n]: lane holds rows m = 16 mt + 4 (lane/16) + i, column n = 16 nt + lane%16
 #pragma unroll
@@ -493,6 +590,7 @@ hipError_t launch_layer(tmx_ctx *c, int cin, int cout, SpinorPtr x, SpinorPtr y,
     const dim3 grid((unsigned)((V + NN_S - 1) / NN_S)), block(256);
     LinkPtr U{c->links[F32], c->Vh};
     const int tb = c->par.t_bc;
+    kstat_begin(c, "NN_" + std::to_string(cin) + "x" + std::to_string(cout));
     if (cin == 1 && cout == 8)
         hipLaunchKernelGGL((nn_layer_kernel<1, 8>), grid, block, 0, c->stream, c->g, x, y, U, W, tb);
     else if (cin == 8 && cout == 8)
@@ -501,6 +599,7 @@ hipError_t launch_layer(tmx_ctx *c, int cin, int cout, SpinorPtr x, SpinorPtr y,
         hipLaunchKernelGGL((nn_layer_kernel<8, 1>), grid, block, 0, c->stream, c->g, x, y, U, W, tb);
     else
         return hipErrorInvalidValue;
+    kstat_end(c);
     return hipGetLastError();
 }
 
@@ -570,6 +669,12 @@ int pc_apply_internal(tmx_ctx *c, SpinorPtr z, int pz, SpinorPtr r, int pr, int 
         SpinorPtr ov = odd_view(c, a);
         if (pr == F64) {
             OpCopy<F32, F64> cp{};
+            cp.d = ov;
+            cp.s = r;
+            cp.nf = 1;
+            HIP_CHECK_RET(c, run_blas(cp, Vh, 1, c->red, c->stream), "embed");
+        } else if (pr == F16) {
+            OpCopy<F32, F16> cp{};
             cp.d = ov;
             cp.s = r;
             cp.nf = 1;
@@ -802,6 +907,9 @@ int fgcr_stage(tmx_ctx *c, int op, int dagger, SpinorPtr x, SpinorPtr b, double 
         rc = fg_true_residual(c, op, dagger, r, b, x, q, &rr, &info->gbytes);
         if (rc) return rc;
         info->restarts++;
+        if (c->trace)
+            std::printf("# TMX: fgcr dagger=%d cycle %d iters %d inner |r|/|b| %.3e true %.3e\n", dagger,
+                        info->restarts, it, std::sqrt(rlo / bb), std::sqrt(rr / bb));
         if (!std::isfinite(rr)) return set_err(c, TMX_ENOCONV, "FGCR: non-finite residual");
         // stagnation: less than a factor 2 over a whole cycle
         if (rr > 0.25 * prev_cycle && std::sqrt(rr) > tau * std::sqrt(bb)) {
@@ -937,7 +1045,8 @@ int tmx_pc_apply(tmx_ctx *c, double *out, const double *in, int dagger)
 
 // gradient of the loss for a set of pairs (internal helper, also used by the
 // gradient check entry point): accumulates into the partial buffers, returns loss
-static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int *idx, int n, double *loss)
+static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int *idx, int n, int loss_kind,
+                        double *loss)
 {
     PcState &s = *c->pc;
     const long Vh = c->Vh;
@@ -959,16 +1068,16 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
         int r = hip_err(c, launch_pack_spinor(b + (size_t)k * fb, B, F32, TMX_FIELD_ODD, c->g, 1, c->stream), "pack b");
         if (!r) r = hip_err(c, launch_pack_spinor(x + (size_t)k * fb, X, F32, TMX_FIELD_ODD, c->g, 1, c->stream), "pack x");
         if (r) return r;
-        // |x|^2 for the scale
+        // |x|^2 (solution loss) or |b|^2 (residual loss) for the scale
         OpCopy<F32, F32> nx{};
-        nx.d = X;
-        nx.s = X;
+        nx.d = loss_kind == TMX_LOSS_SOLUTION ? X : B;
+        nx.s = nx.d;
         nx.nf = 1;
         r = hip_err(c, run_blas(nx, Vh, 1, c->red, c->stream), "norm");
         double xx = 0;
         if (!r) r = fetch(c, 1, &xx);
         if (r) return r;
-        if (!(xx > 0)) return set_err(c, TMX_EINVAL, "training target with zero norm");
+        if (!(xx > 0)) return set_err(c, TMX_EINVAL, "training pair with zero norm");
         std::vector<SpinorPtr> acts;
         void *pz = ws_get(c, "tr_z", spinor_field_bytes(F32, 1, Vh));
         if (!pz) return TMX_ENOMEM;
@@ -983,16 +1092,50 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
             r = hip_err(c, run_blas(oz, Vh, 1, c->red, c->stream), "zero delta");
             if (r) return r;
         }
-        OpPairResidual<F32> pr{};
-        pr.out = odd_view(c, acts[NN_L]);
-        pr.x = X;
-        pr.delta = odd_view(c, dl);
-        pr.scale = 1.0 / (xx * n);
-        r = hip_err(c, run_blas(pr, Vh, 1, c->red, c->stream), "pair residual");
-        double red[2];
-        if (!r) r = fetch(c, 2, red);
-        if (r) return r;
-        L += red[0] / xx / n;
+        if (loss_kind == TMX_LOSS_SOLUTION) {
+            OpPairResidual<F32> pr{};
+            pr.out = odd_view(c, acts[NN_L]);
+            pr.x = X;
+            pr.delta = odd_view(c, dl);
+            pr.scale = 1.0 / (xx * n);
+            r = hip_err(c, run_blas(pr, Vh, 1, c->red, c->stream), "pair residual");
+            double red[2];
+            if (!r) r = fetch(c, 2, red);
+            if (r) return r;
+            L += red[0] / xx / n;
+        } else {
+            // e = K b - x ; q = Mhat e ; loss |q|^2/|b|^2 ; delta = Mhat^dagger q / (|b|^2 n)
+            void *pe = ws_get(c, "tr_e", spinor_field_bytes(F32, 1, Vh));
+            void *pq = ws_get(c, "tr_q", spinor_field_bytes(F32, 1, Vh));
+            if (!pe || !pq) return TMX_ENOMEM;
+            SpinorPtr E = make_spinor(pe, F32, 1, Vh), Q = make_spinor(pq, F32, 1, Vh);
+            OpPairResidual<F32> pr{};
+            pr.out = odd_view(c, acts[NN_L]);
+            pr.x = X;
+            pr.delta = E;
+            pr.scale = 1.0;
+            r = hip_err(c, run_blas(pr, Vh, 1, c->red, c->stream), "pair residual");
+            if (!r) r = op_mhat(c, Q, E, TMX_OP_PLUS, F32, 0, 1);
+            if (r) return r;
+            OpCopy<F32, F32> nq{};
+            nq.d = Q;
+            nq.s = Q;
+            nq.nf = 1;
+            r = hip_err(c, run_blas(nq, Vh, 1, c->red, c->stream), "residual norm");
+            double qq = 0;
+            if (!r) r = fetch(c, 1, &qq);
+            if (!r) r = op_mhat(c, E, Q, TMX_OP_PLUS, F32, 1, 1);
+            if (r) return r;
+            OpAxpby<F32, F32> sc{};
+            sc.y = odd_view(c, dl);
+            sc.x = E;
+            sc.nf = 1;
+            sc.a[0] = 1.0 / (xx * n);
+            sc.b[0] = 0.0;
+            r = hip_err(c, run_blas(sc, Vh, 1, c->red, c->stream), "delta");
+            if (r) return r;
+            L += qq / xx / n;
+        }
         // backward through the layers
         SpinorPtr delta = dl;
         for (int l = NN_L - 1; l >= 0; --l) {
@@ -1019,7 +1162,8 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
     return TMX_OK;
 }
 
-int tmx_pc_loss_grad(tmx_ctx *c, const double *b, const double *x, int npairs, double *loss, float *host_grad)
+int tmx_pc_loss_grad(tmx_ctx *c, const double *b, const double *x, int npairs, int loss_kind, double *loss,
+                     float *host_grad)
 {
     if (!c || !b || !x || npairs < 1 || !loss) return TMX_EINVAL;
     int r = nn_ensure(c);
@@ -1027,7 +1171,7 @@ int tmx_pc_loss_grad(tmx_ctx *c, const double *b, const double *x, int npairs, d
     if (!c->pc->have_weights) return set_err(c, TMX_ENOTLOADED, "preconditioner weights not set");
     r = ensure_ready(c, F32, false);
     if (!r) r = nn_build_weights(c);
-    if (!r) r = pc_loss_grad(c, b, x, nullptr, npairs, loss);
+    if (!r) r = pc_loss_grad(c, b, x, nullptr, npairs, loss_kind, loss);
     if (r) return r;
     if (host_grad) {
         hipError_t e = hipMemcpyAsync(host_grad, c->pc->grad, c->pc->nparam * sizeof(float), hipMemcpyDeviceToHost,
@@ -1072,7 +1216,7 @@ int tmx_pc_train(tmx_ctx *c, const double *b, const double *x, int npairs, const
             r = nn_build_weights(c);
             if (r) return r;
             double L;
-            r = pc_loss_grad(c, b, x, order.data() + i0, n, &L);
+            r = pc_loss_grad(c, b, x, order.data() + i0, n, cfg->loss_kind, &L);
             if (r) return r;
             if (!std::isfinite(L)) return set_err(c, TMX_ENOCONV, "training loss is not finite");
             eloss += L;

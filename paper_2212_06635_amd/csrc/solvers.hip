@@ -282,6 +282,143 @@ static int cg_solve(Sys &S, SpinorPtr x, SpinorPtr b, int cols, const double *si
     return rc;
 }
 
+// --------------------------------------------------------------------------
+// flexible preconditioned CG on N with the learned preconditioner P = K K^dagger
+// (Hermitian positive semi-definite by construction), low-precision inner
+// iterations and FP64 reliable updates; Polak-Ribiere beta because P is
+// applied in BF16 and therefore varies slightly from call to call.
+// --------------------------------------------------------------------------
+template <int P> struct OpPcgDots {
+    static constexpr int NRED = 2;
+    SpinorPtr r, z, q;
+    int nf;
+    __device__ void operator()(long t, int, double *acc) const
+    {
+        cd vr[12], vz[12], vq[12];
+        ld<P>(r, 0, t, vr);
+        ld<F32>(z, 0, t, vz);
+        ld<P>(q, 0, t, vq);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            acc[0] += vr[c].re * vz[c].re + vr[c].im * vz[c].im;
+            acc[1] += vz[c].re * vq[c].re + vz[c].im * vq[c].im;
+        }
+    }
+};
+
+template <int P>
+static int pcg_apply_pc(Sys &S, SpinorPtr z, SpinorPtr r, SpinorPtr tmp)
+{
+    int rc = pc_apply_internal(S.c, tmp, F32, r, P, 1, false, nullptr);  // K^dagger r
+    if (rc) return rc;
+    return pc_apply_internal(S.c, z, F32, tmp, F32, 0, false, nullptr);  // K K^dagger r
+}
+
+template <int P>
+static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const tmx_solver_cfg &cfg, bool x_is_guess, tmx_info *info)
+{
+    tmx_ctx *c = S.c;
+    const double tol = cfg.tol > 0 ? cfg.tol : 1e-10;
+    const int maxiter = cfg.maxiter > 0 ? cfg.maxiter : 10000;
+    const double delta = cfg.delta > 0 ? cfg.delta : 0.1;
+    SpinorPtr r = S.field("r", F64, 1), rl = S.field("rl", P, 1), p = S.field("p", P, 1), q = S.field("q", P, 1);
+    SpinorPtr xl = S.field("xl", F32, 1), z = S.field("z", F32, 1), tz = S.field("tz", F32, 1);
+    double bb, rr, rmax, rho, pq, dots[2];
+    TRY((copy_field<F64, F64>(S, r, b, 1, &bb)));
+    if (!x_is_guess) TRY(zero_field<F64>(S, x, 1));
+    if (bb == 0) {
+        TRY(zero_field<F64>(S, x, 1));
+        if (info) info->true_residual = 0;
+        return TMX_OK;
+    }
+    TRY(true_residual<P>(S, r, rl, true, b, x, nullptr, 1, &rr));
+    TRY(zero_field<F32>(S, xl, 1));
+    TRY(pcg_apply_pc<P>(S, z, rl, tz));
+    {
+        OpPcgDots<P> d{};
+        d.r = rl;
+        d.z = z;
+        d.q = rl;
+        d.nf = 1;
+        HTRY(run_blas(d, c->Vh, 1, c->red, c->stream), "pcg dots");
+        TRY(fetch(c, 2, dots));
+        rho = dots[0];
+    }
+    TRY((copy_field<P, F32>(S, p, z, 1, nullptr)));
+    rmax = rr;
+    int it = 0, nrel = 0, npc = 1;
+    bool after_reliable = false;
+    const double t0 = now_seconds();
+    while (std::sqrt(rr) > tol * std::sqrt(bb) && it < maxiter) {
+        TRY(apply_shifted<P>(S, q, p, nullptr, 1, &pq));
+        ++it;
+        if (!(pq > 0) || !(rho > 0)) return set_err(c, TMX_ENOCONV, "preconditioned CG breakdown");
+        const double alpha = rho / pq;
+        OpAxpyNorm<F32, P, P, P> up{};
+        up.x = xl;
+        up.p = p;
+        up.r = rl;
+        up.q = q;
+        up.nf = 1;
+        up.a[0] = alpha;
+        HTRY(run_blas(up, c->Vh, 1, c->red, c->stream), "pcg update");
+        TRY(fetch(c, 1, &rr));
+        if (!std::isfinite(rr)) return set_err(c, TMX_ENOCONV, "preconditioned CG: non-finite residual");
+        rmax = std::max(rmax, rr);
+        after_reliable = false;
+        if (std::sqrt(rr) < delta * std::sqrt(rmax) || std::sqrt(rr) <= tol * std::sqrt(bb)) {
+            OpAddTo<F64, F32> ad{};
+            ad.x = x;
+            ad.y = xl;
+            ad.nf = 1;
+            ad.zero_y = 1;
+            HTRY(run_blas(ad, c->Vh, 1, c->red, c->stream), "pcg reliable add");
+            TRY(true_residual<P>(S, r, rl, true, b, x, nullptr, 1, &rr));
+            rmax = rr;
+            nrel++;
+            after_reliable = true;
+            if (std::sqrt(rr) <= tol * std::sqrt(bb)) break;
+        }
+        TRY(pcg_apply_pc<P>(S, z, rl, tz));
+        ++npc;
+        OpPcgDots<P> d{};
+        d.r = rl;
+        d.z = z;
+        d.q = q;
+        d.nf = 1;
+        HTRY(run_blas(d, c->Vh, 1, c->red, c->stream), "pcg dots");
+        TRY(fetch(c, 2, dots));
+        double beta = after_reliable ? dots[0] / rho : -alpha * dots[1] / rho;
+        if (!(beta > 0)) beta = 0;  // restart the direction
+        OpAxpby<P, F32> px{};
+        px.y = p;
+        px.x = z;
+        px.nf = 1;
+        px.a[0] = 1.0;
+        px.b[0] = beta;
+        HTRY(run_blas(px, c->Vh, 1, c->red, c->stream), "pcg p update");
+        rho = dots[0];
+    }
+    OpAddTo<F64, F32> ad{};
+    ad.x = x;
+    ad.y = xl;
+    ad.nf = 1;
+    ad.zero_y = 1;
+    HTRY(run_blas(ad, c->Vh, 1, c->red, c->stream), "pcg final add");
+    double tr;
+    TRY(true_residual<P>(S, r, rl, false, b, x, nullptr, 1, &tr));
+    const double rel = std::sqrt(tr / bb);
+    if (info) {
+        info->iters += it;
+        info->reliable_updates += nrel;
+        info->restarts += npc;  // preconditioner applications (each K^dagger then K)
+        info->true_residual = rel;
+        info->seconds += now_seconds() - t0;
+        info->gbytes += S.gbytes;
+    }
+    return rel <= tol ? TMX_OK : TMX_ENOCONV;
+}
+
 static int dispatch_cg(Sys &S, int prec, SpinorPtr x, SpinorPtr b, int cols, const double *sigma,
                        const tmx_solver_cfg &cfg, bool guess, tmx_info *info)
 {
@@ -441,6 +578,21 @@ int tmx_solve(tmx_ctx *c, double *x, const double *b, int nrhs, const tmx_solver
         break;
     case TMX_SOLVER_MPCG_F16:
         rc = dispatch_cg(S, F16, X, B, nrhs, nullptr, *cfg, cfg->use_initial_guess != 0, info);
+        break;
+    case TMX_SOLVER_PCG_NN:
+        if (nrhs != 1) return set_err(c, TMX_EINVAL, "the preconditioned CG solves one right-hand side at a time");
+        if (cfg->op == TMX_OP_ND) return set_err(c, TMX_EINVAL, "the learned preconditioner is built for the degenerate operator");
+        TRY(ensure_ready(c, F32, false));
+        rc = (cfg->inner_prec == TMX_F16) ? pcg_nn_core<F16>(S, X, B, *cfg, cfg->use_initial_guess != 0, info)
+                                          : pcg_nn_core<F32>(S, X, B, *cfg, cfg->use_initial_guess != 0, info);
+        if (rc == TMX_ENOCONV && info && std::isfinite(info->true_residual)) {
+            // fall back to plain mixed-precision CG from the current x
+            tmx_info inf{};
+            rc = dispatch_cg(S, F32, X, B, 1, nullptr, *cfg, true, &inf);
+            info->fallback = 1;
+            info->iters += inf.iters;
+            info->true_residual = inf.true_residual;
+        }
         break;
     case TMX_SOLVER_FGCR_NN:
         if (nrhs != 1) return set_err(c, TMX_EINVAL, "FGCR solves one right-hand side at a time");

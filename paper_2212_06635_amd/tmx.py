@@ -23,7 +23,7 @@ TMX_OK, TMX_ENOCONV, TMX_EINVAL, TMX_ENOTLOADED, TMX_ENOMEM, TMX_EHIP = 0, 1, -1
 TMX_F64, TMX_F32, TMX_F16 = 0, 1, 2
 TMX_OP_PLUS, TMX_OP_MINUS, TMX_OP_ND = 1, -1, 2
 TMX_FIELD_ODD, TMX_FIELD_ODD_ND, TMX_FIELD_FULL, TMX_FIELD_FULL_ND = 0, 1, 2, 3
-TMX_SOLVER_CG, TMX_SOLVER_MPCG_F32, TMX_SOLVER_MPCG_F16, TMX_SOLVER_FGCR_NN = 0, 1, 2, 3
+TMX_SOLVER_CG, TMX_SOLVER_MPCG_F32, TMX_SOLVER_MPCG_F16, TMX_SOLVER_FGCR_NN, TMX_SOLVER_PCG_NN = 0, 1, 2, 3, 4
 
 PREC = {"f64": TMX_F64, "f32": TMX_F32, "f16": TMX_F16}
 
@@ -57,7 +57,7 @@ class tmx_info(ctypes.Structure):
 class tmx_train_cfg(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
-                ("seed", ctypes.c_int)]
+                ("seed", ctypes.c_int), ("loss_kind", ctypes.c_int)]
 
 
 def _load():
@@ -93,7 +93,7 @@ def _load():
         "tmx_pc_get_weights": ([P, P, Z], I),
         "tmx_pc_apply": ([P, P, P, I], I),
         "tmx_pc_train": ([P, P, P, I, ctypes.POINTER(tmx_train_cfg), P], I),
-        "tmx_pc_loss_grad": ([P, P, P, I, ctypes.POINTER(D), P], I),
+        "tmx_pc_loss_grad": ([P, P, P, I, I, ctypes.POINTER(D), P], I),
         "tmx_tune": ([P, I, I, I], I),
         "tmx_tuned_config": ([P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(I)], I),
         "tmx_kstats_enable": ([P, I], I),
@@ -277,8 +277,9 @@ class Context:
     def pc_apply(self, out, inp, dagger=0):
         return self.check(lib.tmx_pc_apply(self.h, _ptr(out), _ptr(inp), int(dagger)))
 
-    def pc_train(self, b, x, npairs, epochs=10, batch=8, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
-        cfg = tmx_train_cfg(epochs, batch, lr, beta1, beta2, eps, seed)
+    def pc_train(self, b, x, npairs, epochs=10, batch=8, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0,
+                 loss_kind=0):
+        cfg = tmx_train_cfg(epochs, batch, lr, beta1, beta2, eps, seed, loss_kind)
         loss = np.zeros(epochs, dtype=np.float32)
         self.check(lib.tmx_pc_train(self.h, _ptr(b), _ptr(x), npairs, ctypes.byref(cfg), loss.ctypes.data))
         return loss
@@ -310,10 +311,11 @@ class Context:
             i += 1
         return out
 
-    def pc_loss_grad(self, b, x, npairs):
+    def pc_loss_grad(self, b, x, npairs, loss_kind=0):
         loss = ctypes.c_double()
         g = np.zeros(self.pc_num_params(), dtype=np.float32)
-        self.check(lib.tmx_pc_loss_grad(self.h, _ptr(b), _ptr(x), npairs, ctypes.byref(loss), g.ctypes.data))
+        self.check(lib.tmx_pc_loss_grad(self.h, _ptr(b), _ptr(x), npairs, loss_kind, ctypes.byref(loss),
+                                        g.ctypes.data))
         return loss.value, g
 
     # -- tracing ----------------------------------------------------------------

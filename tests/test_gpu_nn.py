@@ -66,15 +66,22 @@ def test_random_network_matches_oracle(S, dagger):
     assert rel_l2(to_host(out, b.shape)[:, 0], ref) < 2e-2
 
 
-def test_gradient_matches_oracle(S):
-    tmx, ctx, lat, _ = S
+@pytest.mark.parametrize("loss_kind", [0, 1])
+def test_gradient_matches_oracle(S, loss_kind):
+    """GPU loss and weight gradient (residual and solution losses) against the oracle's."""
+    tmx, ctx, lat, U = S
     rng = np.random.default_rng(42)
     w = (nn.identity_init(rng, 0.1)).astype(np.float32)
     ctx.pc_set_weights(w)
     bs = np.stack([synth.gaussian_cb_spinor(DIMS, 42, k) for k in range(2)])
     xs = np.stack([synth.gaussian_cb_spinor(DIMS, 43, k) for k in range(2)])
-    loss, g = ctx.pc_loss_grad(to_dev(bs), to_dev(xs), 2)
-    L, gref = nn.loss_and_grad(lat, f32(w), [b[:, 0] for b in bs], [x[:, 0] for x in xs])
+    loss, g = ctx.pc_loss_grad(to_dev(bs), to_dev(xs), 2, loss_kind)
+    ops = ()
+    if loss_kind == 0:
+        o = Oracle(DIMS, U, KAPPA, CSW, mu=MU0)
+        ops = (lambda v: o.mhat(v.reshape(-1, 1, 4, 3)).reshape(-1, 4, 3),
+               lambda v: o.mhat(v.reshape(-1, 1, 4, 3), dagger=True).reshape(-1, 4, 3))
+    L, gref = nn.loss_and_grad(lat, f32(w), [b[:, 0] for b in bs], [x[:, 0] for x in xs], *ops)
     assert abs(loss - L) / L < 2e-2
     cos = float(np.dot(g, gref) / np.linalg.norm(g) / np.linalg.norm(gref))
     assert cos > 0.999, cos
@@ -96,13 +103,31 @@ def pairs(S):
     return bs, xd
 
 
-def test_training_reduces_loss(S, pairs):
+@pytest.mark.parametrize("loss_kind", [1, 0])
+def test_training_reduces_loss(S, pairs, loss_kind):
     tmx, ctx, lat, _ = S
     bs, xd = pairs
     ctx.pc_set_weights(nn.identity_init(np.random.default_rng(3), 1e-2))
-    losses = ctx.pc_train(to_dev(bs), xd, len(bs), epochs=12, batch=4, lr=3e-3, seed=1)
+    losses = ctx.pc_train(to_dev(bs), xd, len(bs), epochs=12, batch=4, lr=3e-3, seed=1, loss_kind=loss_kind)
     assert np.all(np.isfinite(losses))
     assert losses[-1] < 0.7 * losses[0], losses
+
+
+def test_trained_network_beats_untrained(S, pairs):
+    """What the trained network gains: preconditioned-CG iterations, trained vs identity network."""
+    tmx, ctx, lat, _ = S
+    bs, xd = pairs
+    b = to_dev(synth.gaussian_cb_spinor(DIMS, 62, 0))
+    ctx.pc_set_weights(nn.identity_init(None))
+    x = b * 0
+    rc0, info0 = ctx.solve(x, b, 1, kind=tmx.TMX_SOLVER_PCG_NN, op=1, tol=1e-10)
+    ctx.pc_set_weights(nn.identity_init(np.random.default_rng(3), 1e-2))
+    ctx.pc_train(to_dev(bs), xd, len(bs), epochs=30, batch=4, lr=3e-3, seed=2, loss_kind=0)
+    x = b * 0
+    rc1, info1 = ctx.solve(x, b, 1, kind=tmx.TMX_SOLVER_PCG_NN, op=1, tol=1e-10)
+    print("PCG iterations identity / trained:", info0[0]["iters"], info1[0]["iters"])
+    assert rc0 == tmx.TMX_OK and rc1 == tmx.TMX_OK
+    assert info1[0]["iters"] < info0[0]["iters"], (info0, info1)
 
 
 def test_fgcr_reaches_target(S, pairs):

@@ -102,3 +102,28 @@ def test_gradient_matches_finite_differences(lat):
         lm = nn.loss_and_grad(L, wm, bs, xs)[0]
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1e-3, abs(g[k])) + 1e-9, (k, fd, g[k])
+
+
+def test_residual_loss_gradient_matches_finite_differences(lat):
+    """Residual loss |Mhat (K b - x)|^2 / |b|^2 with the FP64 Schur operator of the C oracle."""
+    from oracle import Oracle
+
+    L, U = lat
+    o = Oracle(DIMS, U, 0.1394, 1.69, mu=0.01)
+    mh = lambda v: o.mhat(v.reshape(-1, 1, 4, 3)).reshape(-1, 4, 3)
+    mhd = lambda v: o.mhat(v.reshape(-1, 1, 4, 3), dagger=True).reshape(-1, 4, 3)
+    w = rand_params(5, 0.2)
+    bs = [synth.gaussian_cb_spinor(DIMS, 3, 30 + i)[:, 0] for i in range(2)]
+    xs = [synth.gaussian_cb_spinor(DIMS, 3, 40 + i)[:, 0] for i in range(2)]
+    loss, g = nn.loss_and_grad(L, w, bs, xs, mh, mhd)
+    # the loss itself: |Mhat K b - Mhat x|^2/|b|^2
+    direct = sum(np.linalg.norm(mh(nn.forward(L, w, b) - x)) ** 2 / np.linalg.norm(b) ** 2 for b, x in zip(bs, xs)) / 2
+    assert abs(loss - direct) / direct < 1e-13
+    rng = np.random.default_rng(8)
+    h = 1e-5
+    for k in rng.choice(w.size, 25, replace=False):
+        wp, wm = w.copy(), w.copy()
+        wp[k] += h
+        wm[k] -= h
+        fd = (nn.loss_and_grad(L, wp, bs, xs, mh, mhd)[0] - nn.loss_and_grad(L, wm, bs, xs, mh, mhd)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1e-3, abs(g[k])) + 1e-9, (k, fd, g[k])
