@@ -10,7 +10,14 @@ epsbar = 0.1315; links U = proj_SU3(exp(i 0.25 H)), seed 4):
     the two-flavour Mhat_h in FP32;
   * plain FP64 CG on N to a 1e-10 FP64 true residual;
   * mixed-precision CG (FP32 and FP16-storage inner iterations, FP64
-    reliable updates) to the same FP64 true residual.
+    reliable updates) to the same FP64 true residual;
+  * CG preconditioned by the learned network K K^dagger (FP16 inner, FP64
+    reliable updates; the network is trained once, before the timed region,
+    on 256 (source, solution) pairs from the plain solver on a 16^3x32 field);
+  * a 12-shift multishift solve of the two-flavour normal operator (FP32
+    multishift CG, then FP64-reliable refinement per shift; shifts
+    lambda_max * 10^(-5 + 5k/11)) and 12 Gaussian right-hand sides of the
+    two-flavour operator advanced together (FP32 inner, FP64 reliable updates).
 
 The headline value is the FP64 Schur-operator bandwidth: model bytes of one
 Mhat application (links, spinors and clover blocks each read once per
@@ -80,6 +87,60 @@ def cpu_baseline(dims, U, b, napply):
                          f"({dt:.3f} s each, same model bytes as the GPU figure)"}
 
 
+def train_network(tmx, synth, npairs, epochs):
+    """Train the preconditioner on a 16^3x32 field (seed 2) from (b, Mhat^{-1} b) pairs."""
+    import numpy as np
+    import torch
+
+    dims = (16, 16, 16, 32)
+    t0 = time.perf_counter()
+    U = synth.gauge_links(dims, 0.25, 2)
+    tc = tmx.Context(dims)
+    tc.set_params(tmx.Params(KAPPA, CSW, MU, 0.0, 0.0, -1))
+    tc.load_gauge(U, 2.0)
+    n1 = tc.Vh * 12
+    bs = torch.from_numpy(np.stack([synth.gaussian_cb_spinor(dims, 2, k) for k in range(npairs)]).reshape(-1)).cuda()
+    xs = torch.zeros_like(bs)
+    for k in range(npairs):
+        xk = torch.zeros(n1, dtype=torch.complex128, device="cuda")
+        tc.solve_mhat(xk, bs[k * n1:(k + 1) * n1], dagger=0, op=1, tol=1e-10)
+        xs[k * n1:(k + 1) * n1] = xk
+    t1 = time.perf_counter()
+    rng = np.random.default_rng(3)
+    w0 = np.zeros(tc.pc_num_params(), dtype=np.float32)
+    # identity on the d = 0 path of every layer, N(0, 1e-2) elsewhere
+    from_oracle_free_init(w0, rng)
+    tc.pc_set_weights(w0)
+    losses = tc.pc_train(bs, xs, npairs, epochs=epochs, batch=8, lr=3e-3, seed=1, loss_kind=0)
+    w = tc.pc_get_weights()
+    tc.close()
+    t2 = time.perf_counter()
+    return w, {"pairs": npairs, "lattice": list(dims), "pair_seconds": round(t1 - t0, 1),
+               "train_seconds": round(t2 - t1, 1), "epochs": epochs,
+               "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+
+
+def from_oracle_free_init(w, rng):
+    """Identity initialisation of the network weights (layout of tmx_pc_set_weights)."""
+    chans = [(1, 8), (8, 8), (8, 8), (8, 1)]
+    k = 0
+    for ci, co in chans:
+        for d in range(9):
+            n = 2 * (co * ci + 16)
+            w[k:k + n] = rng.standard_normal(n) * 1e-2
+            if d == 0:
+                C = w[k:k + 2 * co * ci].reshape(co, ci, 2)
+                C[:] = 0
+                for i in range(min(co, ci)):
+                    C[i, i, 0] = 1.0
+                G = w[k + 2 * co * ci:k + n].reshape(4, 4, 2)
+                G[:] = 0
+                for i in range(4):
+                    G[i, i, 0] = 1.0
+            k += n
+    assert k == w.size
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,9 +149,12 @@ def main():
     ap.add_argument("--dims", default="32,32,32,64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-applies", type=int, default=3)
-    ap.add_argument("--mode", default="full", choices=["full", "kernels"],
-                    help="kernels: only Mhat applies per precision and a copy of known size (for counters)")
+    ap.add_argument("--mode", default="full", choices=["full", "kernels", "nn"],
+                    help="kernels: only Mhat applies per precision and a copy of known size (for counters); "
+                         "nn: only applications of the learned preconditioner (for counters)")
     ap.add_argument("--tune", action="store_true", help="autotune the stencil launch shapes first")
+    ap.add_argument("--train-pairs", type=int, default=256)
+    ap.add_argument("--train-epochs", type=int, default=20)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -128,6 +192,17 @@ def main():
         ctx.tune(1, 2, 1)
         log("tuned: " + str({k: ctx.tuned_config(k) for k in ("K1_f64", "K2_f64", "K1_f32", "K2_f32", "K1_f16", "K2_f16")}))
     log("setup done")
+    if args.mode == "nn":
+        w0 = np.zeros(ctx.pc_num_params(), dtype=np.float32)
+        from_oracle_free_init(w0, np.random.default_rng(3))
+        ctx.pc_set_weights(w0)
+        o = torch.zeros_like(bd)
+        for _ in range(5):
+            ctx.pc_apply(o, bd, 0)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "nn", "lattice": list(dims), "applies": 5}), flush=True)
+        ctx.close()
+        return
     if args.mode == "kernels":
         # a fixed number of applies per precision, then a device copy of
         # 2 GiB whose FETCH_SIZE / WRITE_SIZE calibrate the counters
@@ -148,6 +223,25 @@ def main():
         ctx.close()
         return
 
+    weights, train_info = train_network(tmx, synth, args.train_pairs, args.train_epochs)
+    ctx.pc_set_weights(weights)
+    # largest eigenvalue of N_h by power iteration (FP32), for the shifts
+    v = ctx.pack(b2d, tmx.TMX_FIELD_ODD_ND, 1)
+    w2 = ctx.empty(tmx.TMX_FIELD_ODD_ND, 1)
+    lam = 0.0
+    for _ in range(30):
+        ctx.apply_mdagm(w2, v, 2, 1)
+        wc = ctx.unpack(w2, tmx.TMX_FIELD_ODD_ND, 1)
+        vc = ctx.unpack(v, tmx.TMX_FIELD_ODD_ND, 1)
+        lam = float(torch.vdot(vc, wc).real / torch.vdot(vc, vc).real)
+        v = ctx.pack(wc / wc.norm(), tmx.TMX_FIELD_ODD_ND, 1)
+    lam_max = 1.05 * lam
+    shifts = lam_max * 10.0 ** (-5.0 + 5.0 * np.arange(12) / 11.0)
+    xs_ms = torch.zeros(12 * b2d.numel(), dtype=torch.complex128, device="cuda")
+    b12 = torch.from_numpy(np.stack([synth.gaussian_cb_spinor(dims, 4, 100 + k, 2) for k in range(12)]).reshape(-1)).cuda()
+    x12 = torch.zeros_like(b12)
+    log(f"lambda_max(N_h) ~ {lam:.4f}; network trained ({train_info})")
+
     def timed(fn):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -162,14 +256,26 @@ def main():
         ev["N_f64"] = timed(lambda: [ctx.apply_mdagm(dst[0], src[0], 1, 0) for _ in range(NAPPLY)])
         ev["nd_f32"] = timed(lambda: [ctx.apply_mhat(dst_nd, src_nd, 2, 1) for _ in range(NAPPLY)])
         solves = {}
-        for kind, nm in ((tmx.TMX_SOLVER_CG, "cg_f64"), (tmx.TMX_SOLVER_MPCG_F32, "mpcg_f32"),
-                         (tmx.TMX_SOLVER_MPCG_F16, "mpcg_f16")):
+        for kind, nm, ip in ((tmx.TMX_SOLVER_CG, "cg_f64", 1), (tmx.TMX_SOLVER_MPCG_F32, "mpcg_f32", 1),
+                             (tmx.TMX_SOLVER_MPCG_F16, "mpcg_f16", 1), (tmx.TMX_SOLVER_PCG_NN, "pcg_nn_f16", 2)):
             x.zero_()
             t = time.perf_counter()
-            rc, info = ctx.solve(x, bd, 1, kind=kind, op=1, tol=1e-10)
+            rc, info = ctx.solve(x, bd, 1, kind=kind, op=1, tol=1e-10, inner_prec=ip)
             solves[nm] = {"seconds": time.perf_counter() - t, "iters": info[0]["iters"],
                           "reliable_updates": info[0]["reliable_updates"],
-                          "true_residual": info[0]["true_residual"], "rc": rc}
+                          "true_residual": info[0]["true_residual"], "fallback": info[0]["fallback"], "rc": rc}
+        xs_ms.zero_()
+        t = time.perf_counter()
+        rc, info = ctx.multishift_solve(xs_ms, b2d, shifts, op=2, tol=1e-10, inner_prec=1)
+        solves["multishift_nd_12"] = {"seconds": time.perf_counter() - t, "rc": rc,
+                                      "iters": [i["iters"] for i in info],
+                                      "max_true_residual": max(i["true_residual"] for i in info)}
+        x12.zero_()
+        t = time.perf_counter()
+        rc, info = ctx.solve(x12, b12, 12, kind=tmx.TMX_SOLVER_MPCG_F32, op=2, tol=1e-10)
+        solves["mrhs_nd_12_mpcg_f32"] = {"seconds": time.perf_counter() - t, "rc": rc,
+                                         "iters": max(i["iters"] for i in info),
+                                         "max_true_residual": max(i["true_residual"] for i in info)}
         return ev, solves
 
     for w in range(args.warmup):
@@ -201,8 +307,10 @@ def main():
     g, ms = gbs("nd_f32", mhat_bytes_per_site("f32", 2))
     dslash["nd_f32"] = {"GBps": round(g, 1), "pct_hbm_peak": round(100 * g / HBM_PEAK_GBS, 1), "ms": round(ms, 4)}
 
-    # dominant stencil kernel of the timed region (largest summed time)
-    dom = max(ks.items(), key=lambda kv: kv[1][1])
+    # dominant kernel of the Schur dslash in the timed region: the stencil
+    # kernel (K1/K2, degenerate, one right-hand side) with the largest summed time
+    stencil = {k: v for k, v in ks.items() if k[:2] in ("K1", "K2") and "_nd" not in k and "_r" not in k}
+    dom = max(stencil.items(), key=lambda kv: kv[1][1])
     dname, (dcount, dms) = dom
     per_launch_bytes = kernel_bytes_per_site(dname) * Vh
     avg_ms = dms / dcount
@@ -211,6 +319,15 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dname,
                 "avg_launch_ms": round(avg_ms, 4), "launches": dcount,
                 "bytes_per_launch": per_launch_bytes}
+
+    # the learned preconditioner's 8->8 layer against the BF16 matrix-core peak
+    nn_roof = None
+    if "NN_8x8" in ks:
+        n, ms_tot = ks["NN_8x8"]
+        flops = 2 * 64 * 64 * 27 * 2 * Vh  # (8 ch x 4 spin x re/im)^2 x 9 paths x 3 colours, all sites
+        tf = flops / (ms_tot / n * 1e-3) / 1e12
+        nn_roof = {"bound": "mfma", "achieved": round(tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                   "frac": round(tf / 2500.0, 5), "kernel": "NN_8x8", "avg_launch_ms": round(ms_tot / n, 4)}
 
     out = {
         "metric": METRIC,
@@ -234,6 +351,7 @@ def main():
         "solves": last,
         "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in ks.items()},
         "roofline": roofline,
+        "roofline_nn_layer": nn_roof,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")

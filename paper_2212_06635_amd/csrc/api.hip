@@ -516,6 +516,18 @@ int tmx_create(const int dims[4], void *hip_stream, tmx_ctx **out)
     c->Vh = V / 2;
     c->g.Lxh = dims[0] / 2;
     c->g.Vh = (int)c->Vh;
+    // (z, t) plane tiling of the internal site order (see Geom); the
+    // defaults come from measurement, TMX_SITE_ZB / TMX_SITE_TB override
+    auto pick = [](const char *env, int dflt, int extent) {
+        int v = dflt;
+        if (const char *e = std::getenv(env)) v = std::atoi(e);
+        int sh = 0;
+        while ((2 << sh) <= v) ++sh;
+        while (sh > 0 && extent % (1 << sh)) --sh;
+        return sh;
+    };
+    c->g.zbs = pick("TMX_SITE_ZB", 2, dims[2]);
+    c->g.tbs = pick("TMX_SITE_TB", 8, dims[3]);
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->red.max_blocks = 1024;
     if (hipMalloc(&c->red.partials, sizeof(double) * c->red.max_blocks * MAXR * 4) != hipSuccess ||

@@ -22,8 +22,20 @@ __global__ void pack_kernel(const double *canon, SpinorPtr dst, int nf, int full
     const long r = t / nsite;
     const long i = t - r * nsite;
     int parity = 1;
-    long s = i;
-    if (full) {
+    long s;
+    if (!full) {
+        // canonical odd site i is the lexicographic site 2i or 2i + 1 that is odd
+        int x[4];
+        long q = 2 * i;
+        x[0] = (int)(q % g.L[0]);
+        q /= g.L[0];
+        x[1] = (int)(q % g.L[1]);
+        q /= g.L[1];
+        x[2] = (int)(q % g.L[2]);
+        x[3] = (int)(q / g.L[2]);
+        if (((x[0] + x[1] + x[2] + x[3]) & 1) == 0) x[0] += 1;
+        s = cb_index(g, x);
+    } else {
         int x[4];
         long q = i;
         x[0] = (int)(q % g.L[0]);

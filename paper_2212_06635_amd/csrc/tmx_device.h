@@ -69,28 +69,47 @@ template <typename R> __device__ __forceinline__ void reg_fence(cx<R> *v, int n)
 // -------------------------------------------------------------------------
 // lattice geometry of one parity
 // -------------------------------------------------------------------------
+// Internal site order of one parity.  x/2 and y run fastest (a wavefront
+// covers whole x rows of consecutive y, so each of its loads is one
+// contiguous 1 KiB segment and every neighbour load a uniformly shifted
+// one).  The (z, t) planes are then visited in tiles of zb x tb planes,
+// z fastest inside a tile, tiles z-major:
+//     plane = ((t / tb) * (Lz / zb) + z / zb) * (zb * tb) + (t % tb) * zb + z % zb
+//     s     = (plane * Ly + y) * Lx/2 + x/2
+// so the z and t neighbours of a site are at most one tile of planes away
+// except for the t hops that leave a tile (1 in tb of them).  zb = tb = 1
+// is plain checkerboard order.  zb and tb are powers of two.
 struct Geom {
     int L[4];    // Lx, Ly, Lz, Lt
     int Lxh;     // Lx / 2
     int Vh;      // sites per parity
+    int zbs;     // log2(zb)
+    int tbs;     // log2(tb)
 };
 
-// coordinates of checkerboard site s of parity p
+// coordinates of internal site s of parity p
 __device__ __forceinline__ void cb_coords(const Geom &g, int s, int p, int x[4])
 {
-    int xh = s % g.Lxh;
+    const int xh = s % g.Lxh;
     int r = s / g.Lxh;
     x[1] = r % g.L[1];
-    r /= g.L[1];
-    x[2] = r % g.L[2];
-    x[3] = r / g.L[2];
+    r /= g.L[1];  // plane
+    const int zl = r & ((1 << g.zbs) - 1);
+    r >>= g.zbs;
+    const int tl = r & ((1 << g.tbs) - 1);
+    r >>= g.tbs;
+    const int nzt = g.L[2] >> g.zbs;
+    x[2] = ((r % nzt) << g.zbs) + zl;
+    x[3] = ((r / nzt) << g.tbs) + tl;
     x[0] = 2 * xh + ((x[1] + x[2] + x[3] + p) & 1);
 }
 
-// checkerboard index of the site with coordinates x (any parity)
+// internal index of the site with coordinates x (any parity)
 __device__ __forceinline__ int cb_index(const Geom &g, const int x[4])
 {
-    return (x[0] >> 1) + g.Lxh * (x[1] + g.L[1] * (x[2] + g.L[2] * x[3]));
+    const int nzt = g.L[2] >> g.zbs;
+    const int plane = ((((x[3] >> g.tbs) * nzt + (x[2] >> g.zbs)) << g.tbs) + (x[3] & ((1 << g.tbs) - 1))) << g.zbs;
+    return ((plane + (x[2] & ((1 << g.zbs) - 1))) * g.L[1] + x[1]) * g.Lxh + (x[0] >> 1);
 }
 
 // -------------------------------------------------------------------------
