@@ -46,12 +46,12 @@ __host__ __device__ constexpr int pad16(int x) { return (x + 15) / 16 * 16; }
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f)
+// FP32 -> BF16, round to nearest even (gfx950 converts pairs in one
+// v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ uint32_t f2bf2(float a, float b)
 {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)a) | ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)b) << 16);
 }
 
 static size_t layer_param_offset(int l)
@@ -127,6 +127,43 @@ struct Nbr {
     bool dag;   // U^dagger (backward path)
     bool ident; // d = 0
 };
+
+// neighbour along path d of the site (coordinates x, parity p, index cb)
+__device__ __forceinline__ Nbr path_neighbour_at(const Geom &g, const int x[4], int p, int cb, int d, int t_bc)
+{
+    Nbr r;
+    const long Vh = g.Vh;
+    r.bc = 1.f;
+    if (d == 0) {
+        r.idx = (long)p * Vh + cb;
+        r.ident = true;
+        r.dag = false;
+        r.lp = 0;
+        r.lcb = 0;
+        return r;
+    }
+    r.ident = false;
+    const int mu = (d - 1) / 2;
+    const bool back = ((d - 1) % 2) == 1;
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    if (!back) {
+        if (++y[mu] == g.L[mu]) {
+            y[mu] = 0;
+            if (mu == 3) r.bc = (float)t_bc;
+        }
+    } else {
+        if (--y[mu] < 0) {
+            y[mu] = g.L[mu] - 1;
+            if (mu == 3) r.bc = (float)t_bc;
+        }
+    }
+    const int ncb = cb_index(g, y);
+    r.idx = (long)(1 - p) * Vh + ncb;
+    r.dag = back;
+    r.lp = back ? 1 - p : p;
+    r.lcb = back ? ncb : cb;
+    return r;
+}
 
 __device__ __forceinline__ Nbr path_neighbour(const Geom &g, long gs, int d, int t_bc)
 {
@@ -220,8 +257,9 @@ __device__ __forceinline__ void stage_z(const Geom &g, const SpinorPtr &x, const
             uint16_t v[8];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                v[2 * s] = f2bf(z[3 * s + col].re);
-                v[2 * s + 1] = f2bf(z[3 * s + col].im);
+                const uint32_t w = f2bf2(z[3 * s + col].re, z[3 * s + col].im);
+                v[2 * s] = (uint16_t)(w & 0xffff);
+                v[2 * s + 1] = (uint16_t)(w >> 16);
             }
             const int n = sl * 3 + col;
             if (!transposed) {
@@ -245,17 +283,27 @@ template <int CIN> struct Staged {
     float4 lk[3];
     Nbr nb;
     bool valid;
+    int xs[4], p, cb;  // the thread's site, decoded once per tile
 };
+
+template <int CIN>
+__device__ __forceinline__ void stage_site(const Geom &g, long site0, long V, Staged<CIN> &st)
+{
+    const long gs = site0 + threadIdx.x / 4;
+    st.valid = gs < V;
+    if (!st.valid) return;
+    st.p = gs >= g.Vh ? 1 : 0;
+    st.cb = (int)(gs - (long)st.p * g.Vh);
+    cb_coords(g, st.cb, st.p, st.xs);
+}
 
 template <int CIN>
 __device__ __forceinline__ void stage_load(const Geom &g, const SpinorPtr &x, const LinkPtr &U, int t_bc, long site0,
                                            long V, int d, Staged<CIN> &st)
 {
-    const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
-    const long gs = site0 + sl;
-    st.valid = gs < V;
+    const int q = threadIdx.x % 4;
     if (!st.valid) return;
-    st.nb = path_neighbour(g, gs, d, t_bc);
+    st.nb = path_neighbour_at(g, st.xs, st.p, st.cb, d, t_bc);
     if (!st.nb.ident) {
         const int mu = (d - 1) / 2;
         const float4 *b = static_cast<const float4 *>(U.d) + (long)(st.nb.lp * 4 + mu) * 3 * U.Vh;
@@ -312,13 +360,12 @@ __device__ __forceinline__ void stage_store(const Staged<CIN> &st, uint16_t (*Zs
         }
 #pragma unroll
         for (int col = 0; col < 3; ++col) {
-            uint16_t v[8];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                v[2 * s] = f2bf(z[3 * s + col].re);
-                v[2 * s + 1] = f2bf(z[3 * s + col].im);
-            }
-            *reinterpret_cast<uint4 *>(&Zs[sl * 3 + col][c * 8]) = *reinterpret_cast<const uint4 *>(v);
+            uint4 v;
+            v.x = f2bf2(z[col].re, z[col].im);
+            v.y = f2bf2(z[3 + col].re, z[3 + col].im);
+            v.z = f2bf2(z[6 + col].re, z[6 + col].im);
+            v.w = f2bf2(z[9 + col].re, z[9 + col].im);
+            *reinterpret_cast<uint4 *>(&Zs[sl * 3 + col][c * 8]) = v;
         }
     }
 }
@@ -347,6 +394,7 @@ __global__ void __launch_bounds__(256) nn_layer_kernel(Geom g, SpinorPtr x, Spin
         for (int j = 0; j < 3; ++j) acc[mt][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     Staged<CIN> st;
+    stage_site<CIN>(g, site0, V, st);
     stage_load<CIN>(g, x, U, t_bc, site0, V, 0, st);
     stage_store<CIN, KS>(st, Zs[0]);
     __syncthreads();
@@ -471,6 +519,16 @@ __global__ void __launch_bounds__(256) nn_wgrad_kernel(Geom g, SpinorPtr x, Spin
             out[m * KD + k] += acc[j][i];
         }
     }
+}
+
+// sum of the per-block partials: P[i] = sum_b partial[b][i]
+__global__ void nn_reduce_partials_kernel(const float *partial, int nblocks, int n, float *P)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * n + i];
+    P[i] = s;
 }
 
 // P[l] = sum over blocks of the partials, then the complex weight gradient
@@ -1152,9 +1210,13 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
     for (int l = 0; l < NN_L; ++l) {
         const int per = NN_CIN[l] * NN_COUT[l] + 16;
         const int nthr = NN_P * per;
-        hipLaunchKernelGGL(nn_grad_combine_kernel, dim3((nthr + 127) / 128), dim3(128), 0, c->stream, partial[l],
-                           WG_BLOCKS, s.params + layer_param_offset(l), s.grad + layer_param_offset(l), NN_CIN[l],
-                           NN_COUT[l]);
+        const int np = NN_P * pad16(8 * NN_COUT[l]) * pad16(8 * NN_CIN[l]);
+        float *P = static_cast<float *>(ws_get(c, "nn_P" + std::to_string(l), (size_t)np * sizeof(float)));
+        if (!P) return TMX_ENOMEM;
+        hipLaunchKernelGGL(nn_reduce_partials_kernel, dim3((np + 255) / 256), dim3(256), 0, c->stream, partial[l],
+                           WG_BLOCKS, np, P);
+        hipLaunchKernelGGL(nn_grad_combine_kernel, dim3((nthr + 127) / 128), dim3(128), 0, c->stream, P, 1,
+                           s.params + layer_param_offset(l), s.grad + layer_param_offset(l), NN_CIN[l], NN_COUT[l]);
     }
     int r = hip_err(c, hipGetLastError(), "grad combine");
     if (r) return r;
