@@ -275,21 +275,27 @@ __device__ __forceinline__ void stage_z(const Geom &g, const SpinorPtr &x, const
 // ---------------------------------------------------------------------------
 // layer kernel: Y = sum_d W_d Z_d   (forward or adjoint, by the weights given)
 // ---------------------------------------------------------------------------
-// Staged data of one thread for one path: the neighbour spinors of its
-// channels and the raw link rows, held in registers while the matrix cores
-// work on the previous path (software pipelining across the nine paths).
-template <int CIN> struct Staged {
-    cx<float> psi[(CIN + 3) / 4][12];
+// Tile of 32 sites (96 GEMM columns), 256 threads: for staging, 8 threads
+// per site, one input channel each; for the contraction, wave w owns the
+// 16-row block m = 16 w .. 16 w + 15 of the output (all six column blocks),
+// so it needs only KT weight fragments per path.  Staged data for the next
+// path is loaded into registers while the matrix cores work on the current
+// one (double-buffered LDS, one barrier per path).  ~80 VGPRs and 28 KB of
+// LDS give five workgroups per CU to hide the neighbour-load latency.
+constexpr int NL_S = 32;
+constexpr int NL_N = 3 * NL_S;
+
+struct Staged1 {
+    cx<float> psi[12];
     float4 lk[3];
     Nbr nb;
     bool valid;
-    int xs[4], p, cb;  // the thread's site, decoded once per tile
+    int xs[4], p, cb;
 };
 
-template <int CIN>
-__device__ __forceinline__ void stage_site(const Geom &g, long site0, long V, Staged<CIN> &st)
+__device__ __forceinline__ void stage1_site(const Geom &g, long site0, long V, Staged1 &st)
 {
-    const long gs = site0 + threadIdx.x / 4;
+    const long gs = site0 + threadIdx.x / 8;
     st.valid = gs < V;
     if (!st.valid) return;
     st.p = gs >= g.Vh ? 1 : 0;
@@ -298,11 +304,11 @@ __device__ __forceinline__ void stage_site(const Geom &g, long site0, long V, St
 }
 
 template <int CIN>
-__device__ __forceinline__ void stage_load(const Geom &g, const SpinorPtr &x, const LinkPtr &U, int t_bc, long site0,
-                                           long V, int d, Staged<CIN> &st)
+__device__ __forceinline__ void stage1_load(const Geom &g, const SpinorPtr &x, const LinkPtr &U, int t_bc, int d,
+                                            Staged1 &st)
 {
-    const int q = threadIdx.x % 4;
-    if (!st.valid) return;
+    const int c = threadIdx.x % 8;
+    if (!st.valid || c >= CIN) return;
     st.nb = path_neighbour_at(g, st.xs, st.p, st.cb, d, t_bc);
     if (!st.nb.ident) {
         const int mu = (d - 1) / 2;
@@ -310,19 +316,23 @@ __device__ __forceinline__ void stage_load(const Geom &g, const SpinorPtr &x, co
 #pragma unroll
         for (int k = 0; k < 3; ++k) st.lk[k] = ldv<true>(b + k * U.Vh + st.nb.lcb);
     }
-#pragma unroll
-    for (int i = 0; i < (CIN + 3) / 4; ++i) {
-        const int c = q + 4 * i;
-        if (c < CIN) load_spinor<F32>(x, c, st.nb.idx, st.psi[i]);
-    }
+    load_spinor<F32>(x, c, st.nb.idx, st.psi);
 }
 
 template <int CIN, int KS>
-__device__ __forceinline__ void stage_store(const Staged<CIN> &st, uint16_t (*Zs)[KS])
+__device__ __forceinline__ void stage1_store(const Staged1 &st, uint16_t (*Zs)[KS])
 {
-    const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
-    cx<float> u[9];
-    if (st.valid && !st.nb.ident) {
+    const int sl = threadIdx.x / 8, c = threadIdx.x % 8;
+    if (c >= CIN) return;
+    cx<float> z[12];
+    if (!st.valid) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) z[k] = cx<float>{0.f, 0.f};
+    } else if (st.nb.ident) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) z[k] = st.psi[k];
+    } else {
+        cx<float> u[9];
         const float t[12] = {st.lk[0].x, st.lk[0].y, st.lk[0].z, st.lk[0].w, st.lk[1].x, st.lk[1].y,
                              st.lk[1].z, st.lk[1].w, st.lk[2].x, st.lk[2].y, st.lk[2].z, st.lk[2].w};
 #pragma unroll
@@ -330,43 +340,29 @@ __device__ __forceinline__ void stage_store(const Staged<CIN> &st, uint16_t (*Zs
         u[6] = conj(u[1] * u[5] - u[2] * u[4]);
         u[7] = conj(u[2] * u[3] - u[0] * u[5]);
         u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                cx<float> acc{0.f, 0.f};
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    if (st.nb.dag)
+                        cmac_conj(acc, u[3 * b + a], st.psi[3 * s + b]);
+                    else
+                        cmac(acc, u[3 * a + b], st.psi[3 * s + b]);
+                }
+                z[3 * s + a] = st.nb.bc * acc;
+            }
     }
 #pragma unroll
-    for (int i = 0; i < (CIN + 3) / 4; ++i) {
-        const int c = q + 4 * i;
-        if (c >= CIN) continue;
-        cx<float> z[12];
-        if (!st.valid) {
-#pragma unroll
-            for (int k = 0; k < 12; ++k) z[k] = cx<float>{0.f, 0.f};
-        } else if (st.nb.ident) {
-#pragma unroll
-            for (int k = 0; k < 12; ++k) z[k] = st.psi[i][k];
-        } else {
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    cx<float> acc{0.f, 0.f};
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        if (st.nb.dag)
-                            cmac_conj(acc, u[3 * b + a], st.psi[i][3 * s + b]);
-                        else
-                            cmac(acc, u[3 * a + b], st.psi[i][3 * s + b]);
-                    }
-                    z[3 * s + a] = st.nb.bc * acc;
-                }
-        }
-#pragma unroll
-        for (int col = 0; col < 3; ++col) {
-            uint4 v;
-            v.x = f2bf2(z[col].re, z[col].im);
-            v.y = f2bf2(z[3 + col].re, z[3 + col].im);
-            v.z = f2bf2(z[6 + col].re, z[6 + col].im);
-            v.w = f2bf2(z[9 + col].re, z[9 + col].im);
-            *reinterpret_cast<uint4 *>(&Zs[sl * 3 + col][c * 8]) = v;
-        }
+    for (int col = 0; col < 3; ++col) {
+        uint4 v;
+        v.x = f2bf2(z[col].re, z[col].im);
+        v.y = f2bf2(z[3 + col].re, z[3 + col].im);
+        v.z = f2bf2(z[6 + col].re, z[6 + col].im);
+        v.w = f2bf2(z[9 + col].re, z[9 + col].im);
+        *reinterpret_cast<uint4 *>(&Zs[sl * 3 + col][c * 8]) = v;
     }
 }
 
@@ -376,74 +372,70 @@ __global__ void __launch_bounds__(256) nn_layer_kernel(Geom g, SpinorPtr x, Spin
 {
     constexpr int KD = pad16(8 * CIN), MD = pad16(8 * COUT);
     constexpr int KS = KD + NN_PAD;
-    constexpr int MT = MD / 16, KT = KD / 16;
-    __shared__ __attribute__((aligned(16))) uint16_t Zs[2][NN_N][KS];
+    constexpr int MT = MD / 16, KT = KD / 16, NT = NL_N / 16;
+    // (mt, nt) blocks of this wave: one mt and all NT column blocks when MT
+    // covers the four waves, else column blocks shared out over the waves
+    constexpr int PER = MT >= 4 ? NT : (NT + 3) / 4;
+    __shared__ __attribute__((aligned(16))) uint16_t Zs[2][NL_N][KS];
     const long V = 2L * g.Vh;
-    const long site0 = (long)blockIdx.x * NN_S;
+    const long site0 = (long)blockIdx.x * NL_S;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int my_mt = MT >= 4 ? wave : 0;
 
-    // padded k columns stay zero for the whole kernel
     if (8 * CIN < KD) {
-        for (int i = threadIdx.x; i < 2 * NN_N; i += blockDim.x)
-            for (int k = 8 * CIN; k < KD; ++k) Zs[i / NN_N][i % NN_N][k] = 0;
+        for (int i = threadIdx.x; i < 2 * NL_N; i += blockDim.x)
+            for (int k = 8 * CIN; k < KD; ++k) Zs[i / NL_N][i % NL_N][k] = 0;
     }
-    f32x4 acc[MT][3];
+    f32x4 acc[PER];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) acc[mt][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < PER; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    Staged<CIN> st;
-    stage_site<CIN>(g, site0, V, st);
-    stage_load<CIN>(g, x, U, t_bc, site0, V, 0, st);
-    stage_store<CIN, KS>(st, Zs[0]);
+    Staged1 st;
+    stage1_site(g, site0, V, st);
+    stage1_load<CIN>(g, x, U, t_bc, 0, st);
+    stage1_store<CIN, KS>(st, Zs[0]);
     __syncthreads();
     for (int d = 0; d < NN_P; ++d) {
-        // weight fragments of path d straight from L2 (shared by every tile)
-        bf16x4 wa[MT][KT];
+        bf16x4 wa[KT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int kk = 0; kk < KT; ++kk)
-                wa[mt][kk] = *reinterpret_cast<const bf16x4 *>(
-                    W + ((size_t)d * MD + mt * 16 + lane % 16) * KD + kk * 16 + 4 * (lane / 16));
-        // the next path's neighbour data is in flight while the matrix cores run
-        if (d + 1 < NN_P) stage_load<CIN>(g, x, U, t_bc, site0, V, d + 1, st);
+        for (int kk = 0; kk < KT; ++kk)
+            wa[kk] = *reinterpret_cast<const bf16x4 *>(
+                W + ((size_t)d * MD + my_mt * 16 + lane % 16) * KD + kk * 16 + 4 * (lane / 16));
+        if (d + 1 < NN_P) stage1_load<CIN>(g, x, U, t_bc, d + 1, st);
         const int cur = d & 1;
 #pragma unroll
-        for (int kk = 0; kk < KT; ++kk) {
-            const int kb = kk * 16 + 4 * (lane / 16);
+        for (int j = 0; j < PER; ++j) {
+            const int nt = MT >= 4 ? j : wave + 4 * j;
+            if (nt >= NT) break;
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const int nt = wave * 3 + j;
-                const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&Zs[cur][nt * 16 + lane % 16][kb]);
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-                    acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[mt][kk], b, acc[mt][j], 0, 0, 0);
+            for (int kk = 0; kk < KT; ++kk) {
+                const bf16x4 b =
+                    *reinterpret_cast<const bf16x4 *>(&Zs[cur][nt * 16 + lane % 16][kk * 16 + 4 * (lane / 16)]);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[kk], b, acc[j], 0, 0, 0);
             }
         }
-        if (d + 1 < NN_P) stage_store<CIN, KS>(st, Zs[cur ^ 1]);
+        if (d + 1 < NN_P) stage1_store<CIN, KS>(st, Zs[cur ^ 1]);
         __syncthreads();
     }
     // D[m][n]: lane holds rows m = 16 mt + 4 (lane/16) + i, column n = 16 nt + lane%16
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int j = 0; j < PER; ++j) {
+        const int nt = MT >= 4 ? j : wave + 4 * j;
+        if (nt >= NT) break;
+        const int m0 = my_mt * 16 + 4 * (lane / 16);
+        const int n = nt * 16 + lane % 16;
+        const long gs = site0 + n / 3;
+        const int col = n % 3;
+        if (m0 >= 8 * COUT || gs >= V) continue;
+        const int c = m0 / 8, s0 = (m0 % 8) / 2;
+        float *base = static_cast<float *>(y.d);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int m0 = mt * 16 + 4 * (lane / 16);
-            const int n = (wave * 3 + j) * 16 + lane % 16;
-            const long gs = site0 + n / 3;
-            const int col = n % 3;
-            if (m0 >= 8 * COUT || gs >= V) continue;
-            const int c = m0 / 8, s0 = (m0 % 8) / 2;
-            float *base = static_cast<float *>(y.d);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int k = (s0 + h) * 3 + col;  // spinor component
-                float *dst = base + (((long)c * 6 + k / 2) * y.stride + gs) * 4 + (k % 2) * 2;
-                *reinterpret_cast<float2 *>(dst) = make_float2(acc[mt][j][2 * h], acc[mt][j][2 * h + 1]);
-            }
+        for (int h = 0; h < 2; ++h) {
+            const int k = (s0 + h) * 3 + col;  // spinor component
+            float *dst = base + (((long)c * 6 + k / 2) * y.stride + gs) * 4 + (k % 2) * 2;
+            *reinterpret_cast<float2 *>(dst) = make_float2(acc[j][2 * h], acc[j][2 * h + 1]);
         }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -645,7 +637,7 @@ int nn_build_weights(tmx_ctx *c)
 hipError_t launch_layer(tmx_ctx *c, int cin, int cout, SpinorPtr x, SpinorPtr y, const uint16_t *W)
 {
     const long V = 2 * c->Vh;
-    const dim3 grid((unsigned)((V + NN_S - 1) / NN_S)), block(256);
+    const dim3 grid((unsigned)((V + NL_S - 1) / NL_S)), block(256);
     LinkPtr U{c->links[F32], c->Vh};
     const int tb = c->par.t_bc;
     kstat_begin(c, "NN_" + std::to_string(cin) + "x" + std::to_string(cout));
