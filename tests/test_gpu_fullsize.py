@@ -1,0 +1,69 @@
+"""Parity at the benchmark's full size, in the launch configuration bench.py times.
+
+32^3x64, eps 0.25, seed 4, kappa 0.1394, csw 1.69, mu 0.00072 (and the
+two-flavour mubar 0.1246, epsbar 0.1315): the whole Schur operator in every
+precision against the FP64 oracle, and MP-CG / multishift solutions accepted
+by the oracle's FP64 residual.  (The oracle runs a full 32^3x64 application in
+well under a second on the host cores.)
+"""
+import numpy as np
+import pytest
+
+from helpers import CSW, EPSBAR, KAPPA, MUBAR, rel_l2, to_dev, to_host
+from oracle import Oracle
+from paper_2212_06635_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (32, 32, 32, 64)
+MU = 0.00072
+TOL = {0: 1e-13, 1: 1e-6, 2: 5e-3}
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_2212_06635_amd.tmx as tmx
+
+    print("\n[gpu full size] 32^3x64 eps=0.25 seed=4", flush=True)
+    U = synth.gauge_links(DIMS, 0.25, 4)
+    o = Oracle(DIMS, U, KAPPA, CSW, mu=MU, mubar=MUBAR, epsbar=EPSBAR)
+    ctx = tmx.Context(DIMS)
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU, MUBAR, EPSBAR, -1))
+    ctx.load_gauge(U, 4.0)
+    yield tmx, o, ctx
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("op,nf", [(1, 1), (2, 2)])
+def test_fullsize_mhat(F, op, nf, prec):
+    tmx, o, ctx = F
+    kind = tmx.TMX_FIELD_ODD if nf == 1 else tmx.TMX_FIELD_ODD_ND
+    v = synth.gaussian_cb_spinor(DIMS, 4, 0, nf)
+    ref = o.mhat(v, nf=nf, sgn=1)
+    out = ctx.empty(kind, prec)
+    ctx.apply_mhat(out, ctx.pack(to_dev(v), kind, prec), op, prec)
+    got = to_host(ctx.unpack(out, kind, prec), v.shape)
+    assert rel_l2(got, ref) < TOL[prec]
+
+
+def test_fullsize_mpcg_f16(F):
+    tmx, o, ctx = F
+    b = synth.gaussian_cb_spinor(DIMS, 4, 0)
+    x = to_dev(np.zeros_like(b))
+    rc, info = ctx.solve(x, to_dev(b), 1, kind=tmx.TMX_SOLVER_MPCG_F16, op=1, tol=1e-10)
+    assert rc == tmx.TMX_OK
+    assert o.residual(b, to_host(x, b.shape)) <= 1e-10
+
+
+def test_fullsize_multishift_nd(F):
+    """Twelve shifts spanning 1e-5..1 of the spectrum, FP32 multishift then FP64-reliable refinement."""
+    tmx, o, ctx = F
+    shifts = 2.08 * 10.0 ** (-5.0 + 5.0 * np.arange(12) / 11.0)
+    b = synth.gaussian_cb_spinor(DIMS, 4, 1, 2)
+    x = to_dev(np.zeros((12,) + b.shape))
+    rc, info = ctx.multishift_solve(x, to_dev(b), shifts, op=2, tol=1e-10, inner_prec=1)
+    assert rc == tmx.TMX_OK
+    xs = to_host(x, (12,) + b.shape)
+    for k in (0, 5, 11):
+        assert o.residual(b, xs[k], nf=2, shift=shifts[k]) <= 1e-10
