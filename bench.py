@@ -40,22 +40,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 KAPPA, CSW, MU, MUBAR, EPSBAR = 0.1394, 1.69, 0.00072, 0.1246, 0.1315
 NAPPLY = 20
 
-# algorithmic bytes per output site of one stencil launch (each input read
-# once): bytes per real b; F16 adds a 4-byte scale per spinor read/write
-def kernel_bytes_per_site(kernel: str) -> float:
-    prec = "f64" if "f64" in kernel else ("f32" if "f32" in kernel else "f16")
-    b = {"f64": 8, "f32": 4, "f16": 2}[prec]
-    nd = "_nd" in kernel
-    nrhs = int(kernel.split("_r")[-1]) if "_r" in kernel else 1
-    nf = 2 if nd else 1
-    norm = 4 if prec == "f16" else 0
-    if kernel.startswith("K1"):
-        fixed = 96 * b + (144 * b)  # 8 links x 12 reals; inverse blocks (deg: 2 full 6x6; nd: A + B Hermitian)
-        spin = nf * (48 * b + 2 * norm)  # read in, write out
-    else:
-        fixed = 96 * b + 72 * b  # links; Hermitian A_oo
-        spin = nf * (72 * b + 3 * norm)  # read hop input and x, write out
-    return fixed + nrhs * spin
+# algorithmic bytes per output site of one stencil launch (links, blocks and
+# spinors each read once)
+from paper_2212_06635_amd.counters import kernel_bytes_per_site, read_traffic  # noqa: E402
+
+PROFILE = os.path.join(ROOT, "profiles", "dslash_schur_32x32x32x64_kernels.txt")
 
 
 def mhat_bytes_per_site(prec: str, nf: int = 1) -> float:
@@ -315,8 +304,11 @@ def main():
     per_launch_bytes = kernel_bytes_per_site(dname) * Vh
     avg_ms = dms / dcount
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary
+    # (null unless it was taken at this size from the current kernel sources)
+    traffic = read_traffic(PROFILE, dname) if dims == (32, 32, 32, 64) else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dname,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dname,
                 "avg_launch_ms": round(avg_ms, 4), "launches": dcount,
                 "bytes_per_launch": per_launch_bytes}
 

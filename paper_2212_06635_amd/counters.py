@@ -1,0 +1,152 @@
+"""Summaries of rocprofv3 runs for the stencil kernels, and the per-launch HBM
+traffic they record.
+
+A summary is made from three runs of the same program (``bench.py --mode
+kernels``, which ends with device copies of a 2 GiB buffer):
+
+    rocprofv3 --kernel-trace --stats --output-format csv -d D/p_k -o k -- python3 bench.py --mode kernels
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d D/p_f -o f -- python3 bench.py --mode kernels
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d D/p_w -o w -- python3 bench.py --mode kernels
+    python3 -m paper_2212_06635_amd.counters D out.txt
+
+FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what they read for
+the plain copy of known size.  The summary carries a digest of the kernel
+sources, so that a reader (bench.py) uses its traffic figures only while the
+kernels are the ones that were measured.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import hashlib
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+STENCIL_SOURCES = ("csrc/dslash.hip", "csrc/tmx_device.h", "csrc/tmx_kernels.h")
+COPY_BYTES = 2 ** 31
+
+# rocprof kernel name -> bench label; dslash_kernel<P, NF, MODE>
+LABELS = {f"void tmx::dslash_kernel<{p}, 1, {m}>(tmx::DslashArgs)": f"K{m + 1}_{n}"
+          for p, n in ((0, "f64"), (1, "f32"), (2, "f16")) for m in (0, 1)}
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in STENCIL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_bytes_per_site(kernel: str) -> float:
+    """Algorithmic bytes per output site of one stencil launch (each input read
+    once): links (2 rows), blocks, spinors; FP16 adds a 4-byte scale per
+    spinor read or written."""
+    prec = "f64" if "f64" in kernel else ("f32" if "f32" in kernel else "f16")
+    b = {"f64": 8, "f32": 4, "f16": 2}[prec]
+    nd = "_nd" in kernel
+    nrhs = int(kernel.split("_r")[-1]) if "_r" in kernel else 1
+    nf = 2 if nd else 1
+    norm = 4 if prec == "f16" else 0
+    if kernel.startswith("K1"):
+        fixed = 96 * b + (144 * b)  # 8 links x 12 reals; inverse blocks (deg: 2 full 6x6; nd: A + B Hermitian)
+        spin = nf * (48 * b + 2 * norm)  # read in, write out
+    else:
+        fixed = 96 * b + 72 * b  # links; Hermitian A_oo
+        spin = nf * (72 * b + 3 * norm)  # read hop input and x, write out
+    return fixed + nrhs * spin
+
+
+def _stats(path):
+    out = {}
+    for r in csv.DictReader(open(path)):
+        out[r["Name"]] = (int(r["Calls"]), float(r["AverageNs"]))
+    return out
+
+
+def _pmc(path, counter):
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in agg.items()}
+
+
+def _find(d, suffix):
+    for root, _, files in os.walk(d):
+        for f in files:
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError(f"no *{suffix} under {d}")
+
+
+def summarize(d: str, vh: int) -> str:
+    st = _stats(_find(os.path.join(d, "p_k"), "kernel_stats.csv"))
+    f = _pmc(_find(os.path.join(d, "p_f"), "counter_collection.csv"), "FETCH_SIZE")
+    w = _pmc(_find(os.path.join(d, "p_w"), "counter_collection.csv"), "WRITE_SIZE")
+    copy_f = next(v for k, v in f.items() if "copyBuffer" in k)
+    copy_w = next(v for k, v in w.items() if "copyBuffer" in k)
+    sf, sw = COPY_BYTES / 1024 / copy_f, COPY_BYTES / 1024 / copy_w
+    copy_ns = next(v for k, v in st.items() if "copyBuffer" in k)[1]
+    lines = [
+        f"# Schur-operator stencil kernels, V/2 = {vh} sites per launch, MI355X",
+        "# commands (from /tmp, TMPDIR=/tmp; <repo> = repository root):",
+        "#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/p_k -o k -- python3 <repo>/bench.py --mode kernels",
+        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/p_f -o f -- python3 <repo>/bench.py --mode kernels",
+        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/p_w -o w -- python3 <repo>/bench.py --mode kernels",
+        "#   python3 -m paper_2212_06635_amd.counters <dir> <this file>",
+        "# bench.py --mode kernels: 10 Mhat applications per precision on the 32^3x64 field (eps 0.25, seed 4),",
+        "#   then 3 device copies of a 2 GiB buffer",
+        f"# counter calibration on the 2 GiB copy: FETCH_SIZE {copy_f:.1f} KiB, WRITE_SIZE {copy_w:.1f} KiB per dispatch",
+        f"#   -> FETCH scale {sf:.3f}, WRITE scale {sw:.3f} (applied below)",
+        f"# stencil sources digest: {source_digest()}",
+        "",
+        f"{'kernel':8s} {'calls':>5s} {'avg_us':>8s} {'alg_MB':>8s} {'alg_GB/s':>9s} {'%8TB/s':>7s} "
+        f"{'fetch_MB':>9s} {'write_MB':>9s} {'fetch/alg':>9s} {'traffic_GB/s':>12s}",
+    ]
+    for kname, lab in LABELS.items():
+        if kname not in st:
+            continue
+        calls, avg = st[kname]
+        alg = kernel_bytes_per_site(lab) * vh
+        fe = f[kname] * 1024 * sf
+        wr = w[kname] * 1024 * sw
+        rd = alg - (24 * {"f64": 8, "f32": 4, "f16": 2}[lab[3:]] + (4 if "f16" in lab else 0)) * vh
+        lines.append(f"{lab:8s} {calls:5d} {avg / 1e3:8.1f} {alg / 1e6:8.1f} {alg / (avg * 1e-9) / 1e9:9.1f} "
+                     f"{100 * alg / (avg * 1e-9) / 8e12:7.1f} {fe / 1e6:9.1f} {wr / 1e6:9.1f} {fe / rd:9.3f} "
+                     f"{(fe + wr) / (avg * 1e-9) / 1e9:12.1f}")
+    lines.append("")
+    lines.append(f"copy 2 GiB: {copy_ns / 1e3:.1f} us avg -> {2 * COPY_BYTES / (copy_ns * 1e-9) / 1e9:.1f} GB/s read+write")
+    return "\n".join(lines) + "\n"
+
+
+def read_traffic(path: str, label: str):
+    """HBM bytes per launch of kernel `label` (FETCH + WRITE, scaled) from a
+    summary, or None when the file is absent, lacks the kernel, or was taken
+    from other kernel sources than the current ones."""
+    try:
+        text = open(path).read().splitlines()
+    except OSError:
+        return None
+    digest = None
+    for ln in text:
+        if ln.startswith("# stencil sources digest:"):
+            digest = ln.split(":", 1)[1].strip()
+    if digest != source_digest():
+        return None
+    for ln in text:
+        p = ln.split()
+        if p and p[0] == label and len(p) >= 8:
+            return (float(p[6]) + float(p[7])) * 1e6
+    return None
+
+
+if __name__ == "__main__":
+    if len(sys.argv) != 3:
+        print("usage: python3 -m paper_2212_06635_amd.counters <rocprof output dir> <summary file>", file=sys.stderr)
+        sys.exit(2)
+    txt = summarize(sys.argv[1], 1048576)
+    with open(sys.argv[2], "w") as fh:
+        fh.write(txt)
+    print(txt, end="")

@@ -31,20 +31,6 @@ namespace tmx {
 
 enum { MODE_INV = 0, MODE_DIAG = 1 };
 
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-// L2.  With xcd != 0 the launch index is remapped so that XCD k works on one
-// contiguous 1/8 of the sites: neighbours in y, z and t then mostly hit the
-// L2 that already holds them.  (The map is a permutation of the blocks for
-// any grid, so the result never depends on the dispatch order.)
-__device__ __forceinline__ int xcd_block(int xcd)
-{
-    const int b = blockIdx.x;
-    if (!xcd) return b;
-    const int nb = gridDim.x, q = nb / 8, r = nb % 8;
-    const int k = b % 8, i = b / 8;
-    return k * q + (k < r ? k : r) + i;
-}
-
 // acc += (1 + sgn gamma_mu) * bc * W psi,  W = U (fwd) or U^dagger (bwd)
 template <int MU, int SGN, bool DAG, typename R>
 __device__ __forceinline__ void hop_term(const cx<R> u[9], R bc, const cx<R> psi[12], cx<R> acc[12])

@@ -14,13 +14,16 @@
 //     Y[m][n] = sum_d W_d[m][k] Z_d[k][n]
 // m = (out channel, spin, re/im), k = (in channel, spin, re/im),
 // n = (site, colour); W_d = C_d (x) Gamma_d written as a real matrix, Z_d the
-// transported input.  The transport runs on the vector ALUs in FP32 and is
-// staged in LDS as BF16; the contraction runs on the matrix cores
-// (v_mfma_f32_16x16x16bf16, FP32 accumulation).  The adjoint layer is the
-// same kernel with W'_d = W_{-d}^H (transport and weights commute).
+// transported input.  Activations and links are BF16, the transports run on
+// the vector ALUs as BF16 dot2 steps with FP32 accumulation, the contraction
+// on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  The
+// adjoint layer is the same kernel with W'_d = W_{-d}^H (transport and
+// weights commute).
 //
-// Activations are FP32 fields of `channels` flavours over all V sites
-// (site index parity * V/2 + checkerboard index) in the site-major layout.
+// The input is supported on odd sites and only the odd sites of the output
+// are kept, so the first layer skips zero inputs and the last layer computes
+// odd sites only, writing an FP32 odd field.
+
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -72,6 +75,9 @@ struct PcState {
     bool w_ok = false;
     bool have_weights = false;
     int adam_t = 0;
+    uint4 *la = nullptr, *lb = nullptr;  // BF16 network links (see NnLinks)
+    uint32_t *lc = nullptr;
+    int links_upload = -1;               // gauge upload the links were made from
 };
 
 // ---------------------------------------------------------------------------
@@ -117,10 +123,62 @@ __global__ void nn_build_w_kernel(const float *p, uint16_t *W, int cin, int cout
 }
 
 // ---------------------------------------------------------------------------
-// transport T_d of one spinor (FP32)
+// BF16 operands: activations, links, transports
 // ---------------------------------------------------------------------------
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// c + a.lo b.lo + a.hi b.hi over BF16 pairs with FP32 accumulation (v_dot2_f32_bf16)
+__device__ __forceinline__ float dot2bf(uint32_t a, uint32_t b, float c)
+{
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, a), __builtin_bit_cast(bf16x2v, b), c, false);
+}
+
+// Activation field (BF16, full lattice): colour a of channel c at site gs
+// (= parity * V/2 + checkerboard index) is the 16-byte vector
+// d[(c * 3 + a) * stride + gs], holding spins 0..3 as (re, im) BF16 pairs;
+// this is the operand format of the transports below and of the staging rows
+// of the contraction.
+struct Act {
+    uint4 *d;
+    long stride;
+};
+
+// BF16 links of the network: all nine entries of U_mu(x), x of parity p and
+// checkerboard index s, as (re, im) pairs; entries 0-3 at a[(p*4 + mu) * Vh + s],
+// 4-7 at b[...] and 8 at c[...] (36 bytes per link, no reconstruction).
+struct NnLinks {
+    const uint4 *a, *b;
+    const uint32_t *c;
+    long Vh;
+};
+
+// thread per (p, mu, s): from the FP64 two-row master copy (6 complex per link)
+__global__ void nn_links_kernel(const double2 *l64, uint4 *a, uint4 *b, uint32_t *c, long Vh)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 8 * Vh) return;
+    const long pm = i / Vh, s = i - pm * Vh;
+    cx<double> u[9];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double2 v = l64[(pm * 6 + k) * Vh + s];
+        u[k] = cx<double>{v.x, v.y};
+    }
+    u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+    u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+    u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+    uint32_t w[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) w[e] = f2bf2((float)u[e].re, (float)u[e].im);
+    a[i] = make_uint4(w[0], w[1], w[2], w[3]);
+    b[i] = make_uint4(w[4], w[5], w[6], w[7]);
+    c[i] = w[8];
+}
+
+// neighbour along path d of the site (coordinates x, parity p, index cb)
 struct Nbr {
-    long idx;   // neighbour site index in the activation layout
+    long idx;   // neighbour site in the activation layout
     int lp;     // link parity
     long lcb;   // link checkerboard index
     float bc;   // boundary factor
@@ -128,7 +186,6 @@ struct Nbr {
     bool ident; // d = 0
 };
 
-// neighbour along path d of the site (coordinates x, parity p, index cb)
 __device__ __forceinline__ Nbr path_neighbour_at(const Geom &g, const int x[4], int p, int cb, int d, int t_bc)
 {
     Nbr r;
@@ -165,259 +222,255 @@ __device__ __forceinline__ Nbr path_neighbour_at(const Geom &g, const int x[4], 
     return r;
 }
 
-__device__ __forceinline__ Nbr path_neighbour(const Geom &g, long gs, int d, int t_bc)
+// z_a = bc sum_b W_ab psi_b for NCH channels and NS spins (per colour, BF16
+// pairs), W = U_mu(x) (forward path) or U_mu(x - mu)^dagger (backward path).
+// Each complex product is two dot2 steps with coefficient pairs
+//   forward:  re (U.re, -U.im), im (U.im, U.re)   of U_ab
+//   backward: re (U.re,  U.im), im (-U.im, U.re)  of U_ba
+// made from the stored pair by a half swap and sign flips; sgn flips both
+// halves (bc = -1).
+template <bool DAG, int NCH, int NS>
+__device__ __forceinline__ void transport_bf(const uint32_t u[9], uint32_t sgn, const uint32_t (&psi)[NCH][3][NS],
+                                             uint32_t (&z)[NCH][3][NS])
 {
-    Nbr r;
-    const long Vh = g.Vh;
-    const int p = gs >= Vh ? 1 : 0;
-    const int cb = (int)(gs - p * Vh);
-    r.bc = 1.f;
-    if (d == 0) {
-        r.idx = gs;
-        r.ident = true;
-        r.dag = false;
-        r.lp = 0;
-        r.lcb = 0;
-        return r;
-    }
-    r.ident = false;
-    int x[4];
-    cb_coords(g, cb, p, x);
-    const int mu = (d - 1) / 2;
-    const bool back = ((d - 1) % 2) == 1;
-    int y[4] = {x[0], x[1], x[2], x[3]};
-    if (!back) {
-        if (++y[mu] == g.L[mu]) {
-            y[mu] = 0;
-            if (mu == 3) r.bc = (float)t_bc;
-        }
-    } else {
-        if (--y[mu] < 0) {
-            y[mu] = g.L[mu] - 1;
-            if (mu == 3) r.bc = (float)t_bc;
-        }
-    }
-    const int ncb = cb_index(g, y);
-    r.idx = (long)(1 - p) * Vh + ncb;
-    r.dag = back;
-    r.lp = back ? 1 - p : p;
-    r.lcb = back ? ncb : cb;
-    return r;
-}
-
-__device__ __forceinline__ void transport(const LinkPtr &U, const Nbr &nb, int mu, const cx<float> *psi, cx<float> *z)
-{
-    if (nb.ident) {
+    uint32_t pr[9], pi[9];
 #pragma unroll
-        for (int k = 0; k < 12; ++k) z[k] = psi[k];
-        return;
+    for (int e = 0; e < 9; ++e) {
+        const uint32_t sw = (u[e] >> 16) | (u[e] << 16);
+        pr[e] = (DAG ? u[e] : (u[e] ^ 0x80000000u)) ^ sgn;
+        pi[e] = (DAG ? (sw ^ 0x00008000u) : sw) ^ sgn;
     }
-    cx<float> u[9];
-    load_link<F32>(U, nb.lp, mu, nb.lcb, u);
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int j = 0; j < NCH; ++j)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            cx<float> acc{0.f, 0.f};
+            float re[NS], im[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) re[s] = im[s] = 0.f;
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                if (nb.dag)
-                    cmac_conj(acc, u[3 * b + a], psi[3 * s + b]);
-                else
-                    cmac(acc, u[3 * a + b], psi[3 * s + b]);
+                const int e = DAG ? 3 * b + a : 3 * a + b;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    re[s] = dot2bf(pr[e], psi[j][b][s], re[s]);
+                    im[s] = dot2bf(pi[e], psi[j][b][s], im[s]);
+                }
             }
-            z[3 * s + a] = nb.bc * acc;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) z[j][a][s] = f2bf2(re[s], im[s]);
         }
 }
 
-// Stage the transported input of a tile into LDS, rows n = (site, colour),
-// 8 bf16 per (channel c, colour): k = c * 8 + spin * 2 + re/im.
-template <int CIN, int KS>
-__device__ __forceinline__ void stage_z(const Geom &g, const SpinorPtr &x, const LinkPtr &U, int t_bc, long site0,
-                                        long V, int d, uint16_t (*Zs)[KS], bool transposed, uint16_t *Zt, int ztstride)
+// site of a staging thread: coordinates decoded once per tile
+struct SiteCtx {
+    int xs[4], p, cb;
+    bool valid;
+};
+
+__device__ __forceinline__ void site_ctx(const Geom &g, long gs, long s_end, SiteCtx &sc)
 {
-    const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
-    const long gs = site0 + sl;
-    const bool valid = gs < V;
-    Nbr nb{};
-    if (valid) nb = path_neighbour(g, gs, d, t_bc);
-    const int mu = d == 0 ? 0 : (d - 1) / 2;
-    for (int c = q; c < CIN; c += 4) {
-        cx<float> z[12];
-        if (valid) {
-            cx<float> psi[12];
-            load_spinor<F32>(x, c, nb.idx, psi);
-            transport(U, nb, mu, psi, z);
-        } else {
+    sc.valid = gs < s_end;
+    if (!sc.valid) return;
+    sc.p = gs >= g.Vh ? 1 : 0;
+    sc.cb = (int)(gs - (long)sc.p * g.Vh);
+    cb_coords(g, sc.cb, sc.p, sc.xs);
+}
+
+// register staging of one path for one thread: NCH channels from c0, NS
+// spins from s0 (NS = 4: whole channels; NS = 1: one spin of one channel)
+template <int NCH, int NS> struct Stg {
+    uint32_t psi[NCH][3][NS];
+    uint32_t u[9];
+    uint32_t sgn;
+    bool zero, ident, dag;
+};
+
+// in_odd: the input field is zero on even sites (and never read there)
+template <int NCH, int NS>
+__device__ __forceinline__ void stg_load(const Geom &g, const Act &x, const NnLinks &L, int t_bc, int d, bool in_odd,
+                                         const SiteCtx &sc, int c0, int s0, Stg<NCH, NS> &st)
+{
+    st.zero = !sc.valid;
+    if (st.zero) return;
+    const Nbr nb = path_neighbour_at(g, sc.xs, sc.p, sc.cb, d, t_bc);
+    const int np = d == 0 ? sc.p : 1 - sc.p;
+    if (in_odd && np == 0) {
+        st.zero = true;
+        return;
+    }
+    st.ident = nb.ident;
+    st.dag = nb.dag;
+    st.sgn = nb.bc < 0.f ? 0x80008000u : 0u;
+    if (!nb.ident) {
+        const int mu = (d - 1) / 2;
+        const long i = (long)(nb.lp * 4 + mu) * L.Vh + nb.lcb;
+        const uint4 a = ldv<true>(L.a + i), b = ldv<true>(L.b + i);
+        st.u[0] = a.x;
+        st.u[1] = a.y;
+        st.u[2] = a.z;
+        st.u[3] = a.w;
+        st.u[4] = b.x;
+        st.u[5] = b.y;
+        st.u[6] = b.z;
+        st.u[7] = b.w;
+        st.u[8] = __builtin_nontemporal_load(L.c + i);
+    }
 #pragma unroll
-            for (int k = 0; k < 12; ++k) z[k] = cx<float>{0.f, 0.f};
-        }
+    for (int j = 0; j < NCH; ++j)
 #pragma unroll
-        for (int col = 0; col < 3; ++col) {
-            uint16_t v[8];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const uint32_t w = f2bf2(z[3 * s + col].re, z[3 * s + col].im);
-                v[2 * s] = (uint16_t)(w & 0xffff);
-                v[2 * s + 1] = (uint16_t)(w >> 16);
-            }
-            const int n = sl * 3 + col;
-            if (!transposed) {
-                *reinterpret_cast<uint4 *>(&Zs[n][c * 8]) = *reinterpret_cast<const uint4 *>(v);
+        for (int a = 0; a < 3; ++a) {
+            const uint4 *p = x.d + ((long)(c0 + j) * 3 + a) * x.stride + nb.idx;
+            if constexpr (NS == 4) {
+                const uint4 v = *p;
+                st.psi[j][a][0] = v.x;
+                st.psi[j][a][1] = v.y;
+                st.psi[j][a][2] = v.z;
+                st.psi[j][a][3] = v.w;
             } else {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) Zt[(c * 8 + j) * ztstride + n] = v[j];
+                st.psi[j][a][0] = reinterpret_cast<const uint32_t *>(p)[s0];
             }
         }
+}
+
+// transported values of a staging thread: z[j][a][s]
+template <int NCH, int NS>
+__device__ __forceinline__ void stg_transport(const Stg<NCH, NS> &st, uint32_t (&z)[NCH][3][NS])
+{
+    if (st.zero) {
+#pragma unroll
+        for (int j = 0; j < NCH; ++j)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) z[j][a][s] = 0u;
+    } else if (st.ident) {
+#pragma unroll
+        for (int j = 0; j < NCH; ++j)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) z[j][a][s] = st.psi[j][a][s];
+    } else if (st.dag) {
+        transport_bf<true, NCH, NS>(st.u, st.sgn, st.psi, z);
+    } else {
+        transport_bf<false, NCH, NS>(st.u, st.sgn, st.psi, z);
     }
 }
 
 // ---------------------------------------------------------------------------
 // layer kernel: Y = sum_d W_d Z_d   (forward or adjoint, by the weights given)
 // ---------------------------------------------------------------------------
-// Tile of 32 sites (96 GEMM columns), 256 threads: for staging, 8 threads
-// per site, one input channel each; for the contraction, wave w owns the
-// 16-row block m = 16 w .. 16 w + 15 of the output (all six column blocks),
-// so it needs only KT weight fragments per path.  Staged data for the next
-// path is loaded into registers while the matrix cores work on the current
-// one (double-buffered LDS, one barrier per path).  ~80 VGPRs and 28 KB of
-// LDS give five workgroups per CU to hide the neighbour-load latency.
-constexpr int NL_S = 32;
+// Tile of 64 sites (192 GEMM columns), 256 threads.  Staging: four threads
+// per site, each transporting two input channels (or, with one input
+// channel, one spin) on the vector ALUs with BF16 dot2 steps, and writing
+// the BF16 rows Z_d[n = (site, colour)][k = (channel, spin, re/im)] to LDS.
+// Contraction: wave w owns the 16-row block m = 16 w .. 16 w + 15 of the
+// output (all twelve column blocks) on v_mfma_f32_16x16x32_bf16 (16x16x16
+// for a one-channel input).  The next path's neighbours and links are
+// loaded into registers while the matrix cores work on the current one.
+// One input channel means an input supported on odd sites (the embedded
+// source): tiles of one parity then skip the paths that only see zeros.  One
+// output channel means the last layer: only odd sites are computed and the
+// result is written in FP32 as an odd spinor field.
+constexpr int NL_S = 64;
 constexpr int NL_N = 3 * NL_S;
 
-struct Staged1 {
-    cx<float> psi[12];
-    float4 lk[3];
-    Nbr nb;
-    bool valid;
-    int xs[4], p, cb;
-};
-
-__device__ __forceinline__ void stage1_site(const Geom &g, long site0, long V, Staged1 &st)
-{
-    const long gs = site0 + threadIdx.x / 8;
-    st.valid = gs < V;
-    if (!st.valid) return;
-    st.p = gs >= g.Vh ? 1 : 0;
-    st.cb = (int)(gs - (long)st.p * g.Vh);
-    cb_coords(g, st.cb, st.p, st.xs);
-}
-
-template <int CIN>
-__device__ __forceinline__ void stage1_load(const Geom &g, const SpinorPtr &x, const LinkPtr &U, int t_bc, int d,
-                                            Staged1 &st)
-{
-    const int c = threadIdx.x % 8;
-    if (!st.valid || c >= CIN) return;
-    st.nb = path_neighbour_at(g, st.xs, st.p, st.cb, d, t_bc);
-    if (!st.nb.ident) {
-        const int mu = (d - 1) / 2;
-        const float4 *b = static_cast<const float4 *>(U.d) + (long)(st.nb.lp * 4 + mu) * 3 * U.Vh;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) st.lk[k] = ldv<true>(b + k * U.Vh + st.nb.lcb);
-    }
-    load_spinor<F32>(x, c, st.nb.idx, st.psi);
-}
-
-template <int CIN, int KS>
-__device__ __forceinline__ void stage1_store(const Staged1 &st, uint16_t (*Zs)[KS])
-{
-    const int sl = threadIdx.x / 8, c = threadIdx.x % 8;
-    if (c >= CIN) return;
-    cx<float> z[12];
-    if (!st.valid) {
-#pragma unroll
-        for (int k = 0; k < 12; ++k) z[k] = cx<float>{0.f, 0.f};
-    } else if (st.nb.ident) {
-#pragma unroll
-        for (int k = 0; k < 12; ++k) z[k] = st.psi[k];
-    } else {
-        cx<float> u[9];
-        const float t[12] = {st.lk[0].x, st.lk[0].y, st.lk[0].z, st.lk[0].w, st.lk[1].x, st.lk[1].y,
-                             st.lk[1].z, st.lk[1].w, st.lk[2].x, st.lk[2].y, st.lk[2].z, st.lk[2].w};
-#pragma unroll
-        for (int k = 0; k < 6; ++k) u[k] = cx<float>{t[2 * k], t[2 * k + 1]};
-        u[6] = conj(u[1] * u[5] - u[2] * u[4]);
-        u[7] = conj(u[2] * u[3] - u[0] * u[5]);
-        u[8] = conj(u[0] * u[4] - u[1] * u[3]);
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                cx<float> acc{0.f, 0.f};
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    if (st.nb.dag)
-                        cmac_conj(acc, u[3 * b + a], st.psi[3 * s + b]);
-                    else
-                        cmac(acc, u[3 * a + b], st.psi[3 * s + b]);
-                }
-                z[3 * s + a] = st.nb.bc * acc;
-            }
-    }
-#pragma unroll
-    for (int col = 0; col < 3; ++col) {
-        uint4 v;
-        v.x = f2bf2(z[col].re, z[col].im);
-        v.y = f2bf2(z[3 + col].re, z[3 + col].im);
-        v.z = f2bf2(z[6 + col].re, z[6 + col].im);
-        v.w = f2bf2(z[9 + col].re, z[9 + col].im);
-        *reinterpret_cast<uint4 *>(&Zs[sl * 3 + col][c * 8]) = v;
-    }
-}
-
 template <int CIN, int COUT>
-__global__ void __launch_bounds__(256) nn_layer_kernel(Geom g, SpinorPtr x, SpinorPtr y, LinkPtr U,
-                                                       const uint16_t *W, int t_bc)
+__global__ void __launch_bounds__(256) nn_layer_kernel(Geom g, Act x, Act y, SpinorPtr yo, NnLinks L,
+                                                       const uint16_t *W, int t_bc, long s_begin, long s_end, int xcd)
 {
     constexpr int KD = pad16(8 * CIN), MD = pad16(8 * COUT);
     constexpr int KS = KD + NN_PAD;
-    constexpr int MT = MD / 16, KT = KD / 16, NT = NL_N / 16;
-    // (mt, nt) blocks of this wave: one mt and all NT column blocks when MT
-    // covers the four waves, else column blocks shared out over the waves
+    constexpr int MT = MD / 16, NT = NL_N / 16;
+    constexpr bool K32 = KD % 32 == 0;
+    constexpr int KK = K32 ? KD / 32 : KD / 16;
     constexpr int PER = MT >= 4 ? NT : (NT + 3) / 4;
-    __shared__ __attribute__((aligned(16))) uint16_t Zs[2][NL_N][KS];
-    const long V = 2L * g.Vh;
-    const long site0 = (long)blockIdx.x * NL_S;
+    constexpr int NCH = CIN >= 4 ? CIN / 4 : 1;
+    constexpr int NS = CIN >= 4 ? 4 : 1;
+    constexpr bool IN_ODD = CIN == 1;
+    static_assert(MT == 4 || MT == 1, "output rows: 8 or 1 channels");
+    __shared__ __attribute__((aligned(16))) uint16_t Zs[NL_N][KS];
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int my_mt = MT >= 4 ? wave : 0;
+    const long site0 = s_begin + (long)xcd_block(xcd) * NL_S;
+    const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
+    const int c0 = CIN >= 4 ? q * NCH : 0, s0 = CIN >= 4 ? 0 : q;
 
     if (8 * CIN < KD) {
-        for (int i = threadIdx.x; i < 2 * NL_N; i += blockDim.x)
-            for (int k = 8 * CIN; k < KD; ++k) Zs[i / NL_N][i % NL_N][k] = 0;
+        for (int i = threadIdx.x; i < NL_N; i += blockDim.x)
+            for (int k = 8 * CIN; k < KD; ++k) Zs[i][k] = 0;
+    }
+    SiteCtx sc;
+    site_ctx(g, site0 + sl, s_end, sc);
+    // paths that can contribute to this tile
+    int npath = NN_P, dfirst = 0;
+    if (IN_ODD) {
+        const long last = (site0 + NL_S < s_end ? site0 + NL_S : s_end) - 1;
+        const int pf = site0 >= g.Vh, pl = last >= g.Vh;
+        if (pf == pl) {
+            npath = pf ? 1 : NN_P - 1;
+            dfirst = pf ? 0 : 1;
+        }
     }
     f32x4 acc[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    Staged1 st;
-    stage1_site(g, site0, V, st);
-    stage1_load<CIN>(g, x, U, t_bc, 0, st);
-    stage1_store<CIN, KS>(st, Zs[0]);
-    __syncthreads();
-    for (int d = 0; d < NN_P; ++d) {
-        bf16x4 wa[KT];
+    Stg<NCH, NS> st;
+    stg_load<NCH, NS>(g, x, L, t_bc, dfirst, IN_ODD, sc, c0, s0, st);
+    for (int i = 0; i < npath; ++i) {
+        const int d = dfirst + i;
+        {
+            uint32_t z[NCH][3][NS];
+            stg_transport<NCH, NS>(st, z);
 #pragma unroll
-        for (int kk = 0; kk < KT; ++kk)
-            wa[kk] = *reinterpret_cast<const bf16x4 *>(
-                W + ((size_t)d * MD + my_mt * 16 + lane % 16) * KD + kk * 16 + 4 * (lane / 16));
-        if (d + 1 < NN_P) stage1_load<CIN>(g, x, U, t_bc, d + 1, st);
-        const int cur = d & 1;
+            for (int j = 0; j < NCH; ++j)
 #pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int nt = MT >= 4 ? j : wave + 4 * j;
-            if (nt >= NT) break;
+                for (int a = 0; a < 3; ++a) {
+                    if constexpr (NS == 4)
+                        *reinterpret_cast<uint4 *>(&Zs[sl * 3 + a][(c0 + j) * 8]) =
+                            make_uint4(z[j][a][0], z[j][a][1], z[j][a][2], z[j][a][3]);
+                    else
+                        *reinterpret_cast<uint32_t *>(&Zs[sl * 3 + a][(c0 + j) * 8 + 2 * s0]) = z[j][a][0];
+                }
+        }
+        __syncthreads();
+        if (i + 1 < npath) stg_load<NCH, NS>(g, x, L, t_bc, d + 1, IN_ODD, sc, c0, s0, st);
+        const uint16_t *Wd = W + ((size_t)d * MD + my_mt * 16 + lane % 16) * KD;
+        if constexpr (K32) {
+            bf16x8 wa[KK];
 #pragma unroll
-            for (int kk = 0; kk < KT; ++kk) {
-                const bf16x4 b =
-                    *reinterpret_cast<const bf16x4 *>(&Zs[cur][nt * 16 + lane % 16][kk * 16 + 4 * (lane / 16)]);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[kk], b, acc[j], 0, 0, 0);
+            for (int kk = 0; kk < KK; ++kk) wa[kk] = *reinterpret_cast<const bf16x8 *>(Wd + kk * 32 + 8 * (lane / 16));
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int nt = MT >= 4 ? j : wave + 4 * j;
+                if (nt >= NT) break;
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) {
+                    const bf16x8 b =
+                        *reinterpret_cast<const bf16x8 *>(&Zs[nt * 16 + lane % 16][kk * 32 + 8 * (lane / 16)]);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kk], b, acc[j], 0, 0, 0);
+                }
+            }
+        } else {
+            bf16x4 wa[KK];
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) wa[kk] = *reinterpret_cast<const bf16x4 *>(Wd + kk * 16 + 4 * (lane / 16));
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int nt = MT >= 4 ? j : wave + 4 * j;
+                if (nt >= NT) break;
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) {
+                    const bf16x4 b =
+                        *reinterpret_cast<const bf16x4 *>(&Zs[nt * 16 + lane % 16][kk * 16 + 4 * (lane / 16)]);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[kk], b, acc[j], 0, 0, 0);
+                }
             }
         }
-        if (d + 1 < NN_P) stage1_store<CIN, KS>(st, Zs[cur ^ 1]);
         __syncthreads();
     }
-    // D[m][n]: lane holds rows m = 16 mt + 4 (lane/16) + i, column n = 16 nt + lane%16
+    // D[m][n]: lane holds rows m = 16 mt + 4 (lane/16) + i of column n = 16 nt + lane%16
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int nt = MT >= 4 ? j : wave + 4 * j;
@@ -426,14 +479,21 @@ __global__ void __launch_bounds__(256) nn_layer_kernel(Geom g, SpinorPtr x, Spin
         const int n = nt * 16 + lane % 16;
         const long gs = site0 + n / 3;
         const int col = n % 3;
-        if (m0 >= 8 * COUT || gs >= V) continue;
-        const int c = m0 / 8, s0 = (m0 % 8) / 2;
-        float *base = static_cast<float *>(y.d);
+        if (m0 >= 8 * COUT || gs >= s_end) continue;
+        const int c = m0 / 8, sp = (m0 % 8) / 2;  // channel, first of two spins
+        if constexpr (COUT == 1) {
+            // FP32 odd spinor: component k = spin * 3 + colour in vector k / 2, half k % 2
+            float *base = static_cast<float *>(yo.d);
+            const long cb = gs - g.Vh;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int k = (s0 + h) * 3 + col;  // spinor component
-            float *dst = base + (((long)c * 6 + k / 2) * y.stride + gs) * 4 + (k % 2) * 2;
-            *reinterpret_cast<float2 *>(dst) = make_float2(acc[j][2 * h], acc[j][2 * h + 1]);
+            for (int h = 0; h < 2; ++h) {
+                const int k = (sp + h) * 3 + col;
+                float *dst = base + ((long)(k / 2) * yo.stride + cb) * 4 + (k % 2) * 2;
+                *reinterpret_cast<float2 *>(dst) = make_float2(acc[j][2 * h], acc[j][2 * h + 1]);
+            }
+        } else {
+            uint32_t *dst = reinterpret_cast<uint32_t *>(y.d + ((long)(c * 3 + col) * y.stride + gs)) + sp;
+            *reinterpret_cast<uint2 *>(dst) = make_uint2(f2bf2(acc[j][0], acc[j][1]), f2bf2(acc[j][2], acc[j][3]));
         }
     }
 }
@@ -441,49 +501,89 @@ __global__ void __launch_bounds__(256) nn_layer_kernel(Geom g, SpinorPtr x, Spin
 // ---------------------------------------------------------------------------
 // weight gradient: P_d[m][k] += sum_n Dl[m][n] Z_d[k][n]   (grid.y = path)
 // ---------------------------------------------------------------------------
+// Tiles of 64 sites; the transported input (staged as in the layer kernel)
+// and the output adjoint are written to LDS with n innermost, the
+// contraction over n runs on v_mfma_f32_16x16x32_bf16.  Sites where one of
+// the two factors vanishes identically (odd-supported input, odd-only output
+// adjoint) are skipped as whole ranges.
 template <int CIN, int COUT>
-__global__ void __launch_bounds__(256) nn_wgrad_kernel(Geom g, SpinorPtr x, SpinorPtr dy, LinkPtr U, int t_bc,
-                                                       float *partial, long ntiles)
+__global__ void __launch_bounds__(256) nn_wgrad_kernel(Geom g, Act x, Act dy, NnLinks L, int t_bc, float *partial)
 {
     constexpr int KD = pad16(8 * CIN), MD = pad16(8 * COUT);
-    constexpr int NS = NN_N + NN_PAD;
+    constexpr int NSTR = NN_N + NN_PAD;
     constexpr int MT = MD / 16, KT = KD / 16, NTILE = MT * KT;
     constexpr int PER_WAVE = (NTILE + 3) / 4;
-    __shared__ __attribute__((aligned(16))) uint16_t Dl[MD][NS];
-    __shared__ __attribute__((aligned(16))) uint16_t Zt[KD][NS];
+    constexpr int NCH = CIN >= 4 ? CIN / 4 : 1, NS = CIN >= 4 ? 4 : 1;
+    constexpr int DCH = COUT >= 4 ? COUT / 4 : 1, DS = COUT >= 4 ? 4 : 1;
+    static_assert(NN_S == NL_S, "one tile size");
+    __shared__ __attribute__((aligned(16))) uint16_t Dl[MD][NSTR];
+    __shared__ __attribute__((aligned(16))) uint16_t Zt[KD][NSTR];
     const long V = 2L * g.Vh;
     const int d = blockIdx.y;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int i = threadIdx.x; i < MD * NS; i += blockDim.x) Dl[i / NS][i % NS] = 0;
-    for (int i = threadIdx.x; i < KD * NS; i += blockDim.x) Zt[i / NS][i % NS] = 0;
+    const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
+    const int c0 = CIN >= 4 ? q * NCH : 0, s0 = CIN >= 4 ? 0 : q;
+    const int e0 = COUT >= 4 ? q * DCH : 0, t0 = COUT >= 4 ? 0 : q;
+    long sb = 0, se = V;
+    if (COUT == 1) sb = g.Vh;  // the output adjoint lives on odd sites
+    if (CIN == 1) {            // odd-supported input: d = 0 feeds odd sites, hops even ones
+        if (d == 0)
+            sb = g.Vh;
+        else
+            se = g.Vh;
+    }
+    const long ntiles = (se - sb + NN_S - 1) / NN_S;
+    for (int i = threadIdx.x; i < MD * NSTR; i += blockDim.x) Dl[i / NSTR][i % NSTR] = 0;
+    for (int i = threadIdx.x; i < KD * NSTR; i += blockDim.x) Zt[i / NSTR][i % NSTR] = 0;
     f32x4 acc[PER_WAVE];
 #pragma unroll
     for (int j = 0; j < PER_WAVE; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const long site0 = tile * NN_S;
+        const long site0 = sb + tile * NN_S;
         __syncthreads();
-        stage_z<CIN, 1>(g, x, U, t_bc, site0, V, d, nullptr, true, &Zt[0][0], NS);
-        // output adjoint at the sites themselves (no transport)
+        SiteCtx sc;
+        site_ctx(g, site0 + sl, se, sc);
+        Stg<NCH, NS> st;
+        stg_load<NCH, NS>(g, x, L, t_bc, d, CIN == 1, sc, c0, s0, st);
+        // output adjoint at the site itself
         {
-            const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
             const long gs = site0 + sl;
-            for (int c = q; c < COUT; c += 4) {
-                cx<float> v[12];
-                if (gs < V) {
-                    load_spinor<F32>(dy, c, gs, v);
-                } else {
 #pragma unroll
-                    for (int k = 0; k < 12; ++k) v[k] = cx<float>{0.f, 0.f};
-                }
+            for (int j = 0; j < DCH; ++j)
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
+                for (int a = 0; a < 3; ++a) {
+                    const int n = sl * 3 + a;
+                    if constexpr (DS == 4) {
+                        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                        if (sc.valid) v = dy.d[((long)(e0 + j) * 3 + a) * dy.stride + gs];
+                        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-                    for (int col = 0; col < 3; ++col) {
-                        Dl[c * 8 + s * 2][sl * 3 + col] = f2bf(v[3 * s + col].re);
-                        Dl[c * 8 + s * 2 + 1][sl * 3 + col] = f2bf(v[3 * s + col].im);
+                        for (int s = 0; s < 4; ++s) {
+                            Dl[(e0 + j) * 8 + 2 * s][n] = (uint16_t)(w[s] & 0xffffu);
+                            Dl[(e0 + j) * 8 + 2 * s + 1][n] = (uint16_t)(w[s] >> 16);
+                        }
+                    } else {
+                        uint32_t w = 0u;
+                        if (sc.valid) w = reinterpret_cast<const uint32_t *>(dy.d + (long)a * dy.stride + gs)[t0];
+                        Dl[2 * t0][n] = (uint16_t)(w & 0xffffu);
+                        Dl[2 * t0 + 1][n] = (uint16_t)(w >> 16);
                     }
-            }
+                }
+        }
+        {
+            uint32_t z[NCH][3][NS];
+            stg_transport<NCH, NS>(st, z);
+#pragma unroll
+            for (int j = 0; j < NCH; ++j)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        const int k = (c0 + j) * 8 + 2 * (s0 + s);
+                        Zt[k][sl * 3 + a] = (uint16_t)(z[j][a][s] & 0xffffu);
+                        Zt[k + 1][sl * 3 + a] = (uint16_t)(z[j][a][s] >> 16);
+                    }
         }
         __syncthreads();
 #pragma unroll
@@ -491,11 +591,12 @@ __global__ void __launch_bounds__(256) nn_wgrad_kernel(Geom g, SpinorPtr x, Spin
             const int t = wave + 4 * j;
             if (t >= NTILE) break;
             const int mt = t / KT, kt = t % KT;
-            for (int nk = 0; nk < NN_N / 16; ++nk) {
-                const int nb = nk * 16 + 4 * (lane / 16);
-                const bf16x4 a = *reinterpret_cast<const bf16x4 *>(&Dl[mt * 16 + lane % 16][nb]);
-                const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&Zt[kt * 16 + lane % 16][nb]);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+#pragma unroll
+            for (int nk = 0; nk < NN_N / 32; ++nk) {
+                const int nb = nk * 32 + 8 * (lane / 16);
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&Dl[mt * 16 + lane % 16][nb]);
+                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Zt[kt * 16 + lane % 16][nb]);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
             }
         }
     }
@@ -511,6 +612,19 @@ __global__ void __launch_bounds__(256) nn_wgrad_kernel(Geom g, SpinorPtr x, Spin
             out[m * KD + k] += acc[j][i];
         }
     }
+}
+
+// odd source r (precision P) -> one-channel BF16 activation (odd half only)
+template <int P> __global__ void nn_embed_kernel(SpinorPtr r, Act a, long Vh)
+{
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= Vh) return;
+    cx<float> v[12];
+    load_spinor<P>(r, 0, s, v);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        a.d[(long)c * a.stride + Vh + s] = make_uint4(f2bf2(v[c].re, v[c].im), f2bf2(v[3 + c].re, v[3 + c].im),
+                                                     f2bf2(v[6 + c].re, v[6 + c].im), f2bf2(v[9 + c].re, v[9 + c].im));
 }
 
 // sum of the per-block partials: P[i] = sum_b partial[b][i]
@@ -634,135 +748,150 @@ int nn_build_weights(tmx_ctx *c)
     return r;
 }
 
-hipError_t launch_layer(tmx_ctx *c, int cin, int cout, SpinorPtr x, SpinorPtr y, const uint16_t *W)
+// BF16 network links, rebuilt from the FP64 master copy after every gauge upload
+int nn_links(tmx_ctx *c, NnLinks &L)
 {
+    PcState &s = *c->pc;
+    const long Vh = c->Vh;
+    if (!s.la) {
+        if (hipMalloc(&s.la, 8 * Vh * sizeof(uint4)) != hipSuccess ||
+            hipMalloc(&s.lb, 8 * Vh * sizeof(uint4)) != hipSuccess ||
+            hipMalloc(&s.lc, 8 * Vh * sizeof(uint32_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_err(c, TMX_ENOMEM, "network links");
+        }
+    }
+    if (s.links_upload != c->uploads) {
+        if (!c->gauge_loaded) return set_err(c, TMX_ENOTLOADED, "no gauge field loaded");
+        const long n = 8 * Vh;
+        hipLaunchKernelGGL(nn_links_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                           static_cast<const double2 *>(c->links[F64]), s.la, s.lb, s.lc, Vh);
+        int r = hip_err(c, hipGetLastError(), "network links");
+        if (r) return r;
+        s.links_upload = c->uploads;
+    }
+    L = NnLinks{s.la, s.lb, s.lc, Vh};
+    return TMX_OK;
+}
+
+// one layer: bf16 output y, or (cout == 1) FP32 odd spinor yo
+int launch_layer(tmx_ctx *c, int cin, int cout, Act x, Act y, SpinorPtr yo, const uint16_t *W)
+{
+    NnLinks L;
+    int r = nn_links(c, L);
+    if (r) return r;
     const long V = 2 * c->Vh;
-    const dim3 grid((unsigned)((V + NL_S - 1) / NL_S)), block(256);
-    LinkPtr U{c->links[F32], c->Vh};
-    const int tb = c->par.t_bc;
+    const long s_begin = cout == 1 ? c->Vh : 0;
+    const long ntiles = (V - s_begin + NL_S - 1) / NL_S;
+    const dim3 grid((unsigned)ntiles), block(256);
+    const int tb = c->par.t_bc, xcd = c->xcd_remap;
     kstat_begin(c, "NN_" + std::to_string(cin) + "x" + std::to_string(cout));
     if (cin == 1 && cout == 8)
-        hipLaunchKernelGGL((nn_layer_kernel<1, 8>), grid, block, 0, c->stream, c->g, x, y, U, W, tb);
+        hipLaunchKernelGGL((nn_layer_kernel<1, 8>), grid, block, 0, c->stream, c->g, x, y, yo, L, W, tb, s_begin, V,
+                           xcd);
     else if (cin == 8 && cout == 8)
-        hipLaunchKernelGGL((nn_layer_kernel<8, 8>), grid, block, 0, c->stream, c->g, x, y, U, W, tb);
+        hipLaunchKernelGGL((nn_layer_kernel<8, 8>), grid, block, 0, c->stream, c->g, x, y, yo, L, W, tb, s_begin, V,
+                           xcd);
     else if (cin == 8 && cout == 1)
-        hipLaunchKernelGGL((nn_layer_kernel<8, 1>), grid, block, 0, c->stream, c->g, x, y, U, W, tb);
+        hipLaunchKernelGGL((nn_layer_kernel<8, 1>), grid, block, 0, c->stream, c->g, x, y, yo, L, W, tb, s_begin, V,
+                           xcd);
     else
-        return hipErrorInvalidValue;
+        return set_err(c, TMX_EINVAL, "network layer shape");
     kstat_end(c);
-    return hipGetLastError();
+    return hip_err(c, hipGetLastError(), "network layer");
 }
 
 constexpr int WG_BLOCKS = 64;
 
-hipError_t launch_wgrad(tmx_ctx *c, int cin, int cout, SpinorPtr x, SpinorPtr dy, float *partial)
+int launch_wgrad(tmx_ctx *c, int cin, int cout, Act x, Act dy, float *partial)
 {
-    const long V = 2 * c->Vh;
-    const long ntiles = (V + NN_S - 1) / NN_S;
+    NnLinks L;
+    int r = nn_links(c, L);
+    if (r) return r;
     const dim3 grid(WG_BLOCKS, NN_P), block(256);
-    LinkPtr U{c->links[F32], c->Vh};
     const int tb = c->par.t_bc;
     if (cin == 1 && cout == 8)
-        hipLaunchKernelGGL((nn_wgrad_kernel<1, 8>), grid, block, 0, c->stream, c->g, x, dy, U, tb, partial, ntiles);
+        hipLaunchKernelGGL((nn_wgrad_kernel<1, 8>), grid, block, 0, c->stream, c->g, x, dy, L, tb, partial);
     else if (cin == 8 && cout == 8)
-        hipLaunchKernelGGL((nn_wgrad_kernel<8, 8>), grid, block, 0, c->stream, c->g, x, dy, U, tb, partial, ntiles);
+        hipLaunchKernelGGL((nn_wgrad_kernel<8, 8>), grid, block, 0, c->stream, c->g, x, dy, L, tb, partial);
     else if (cin == 8 && cout == 1)
-        hipLaunchKernelGGL((nn_wgrad_kernel<8, 1>), grid, block, 0, c->stream, c->g, x, dy, U, tb, partial, ntiles);
+        hipLaunchKernelGGL((nn_wgrad_kernel<8, 1>), grid, block, 0, c->stream, c->g, x, dy, L, tb, partial);
     else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+        return set_err(c, TMX_EINVAL, "network layer shape");
+    return hip_err(c, hipGetLastError(), "weight gradient");
 }
 
-// activation buffer l (channels ch) of the full lattice, FP32
-SpinorPtr act(tmx_ctx *c, const std::string &name, int ch)
+// activation buffer (channels ch) of the full lattice, BF16
+Act act(tmx_ctx *c, const std::string &name, int ch)
 {
     const long V = 2 * c->Vh;
-    void *d = ws_get(c, "nn_" + name, spinor_field_bytes(F32, ch, V));
-    return make_spinor(d, F32, ch, V);
+    void *d = ws_get(c, "nn_" + name, (size_t)3 * ch * V * sizeof(uint4));
+    return Act{static_cast<uint4 *>(d), V};
 }
 
-// the odd half of a one-channel activation, addressed by checkerboard index
-SpinorPtr odd_view(tmx_ctx *c, SpinorPtr f)
+// odd field r (precision pr) -> one-channel activation supported on odd sites
+int embed(tmx_ctx *c, SpinorPtr r, int pr, Act a)
 {
-    SpinorPtr o = f;
-    o.d = static_cast<char *>(f.d) + (size_t)c->Vh * 16;
-    return o;
+    const long Vh = c->Vh;
+    const dim3 grid((unsigned)((Vh + 255) / 256)), block(256);
+    if (pr == F64)
+        hipLaunchKernelGGL(nn_embed_kernel<F64>, grid, block, 0, c->stream, r, a, Vh);
+    else if (pr == F32)
+        hipLaunchKernelGGL(nn_embed_kernel<F32>, grid, block, 0, c->stream, r, a, Vh);
+    else
+        hipLaunchKernelGGL(nn_embed_kernel<F16>, grid, block, 0, c->stream, r, a, Vh);
+    return hip_err(c, hipGetLastError(), "embed");
 }
-SpinorPtr even_view(SpinorPtr f) { return f; }
 
-}  // namespace
-
-// z = K r (dagger = 0) or K^dagger r (dagger = 1): odd fields r (precision
-// pr, stride Vh) and z (precision pz); all layers in FP32/BF16.
-int pc_apply_internal(tmx_ctx *c, SpinorPtr z, int pz, SpinorPtr r, int pr, int dagger, bool keep,
-                      std::vector<SpinorPtr> *acts_out)
+// The network on the odd field r: out = K r (dagger = 0) or K^dagger r, an
+// FP32 odd field.  With acts, the layer inputs are kept (for the gradient).
+int nn_forward(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, int dagger, std::vector<Act> *acts)
 {
     int rc = nn_ensure(c);
     if (rc) return rc;
     if (!c->pc->have_weights) return set_err(c, TMX_ENOTLOADED, "preconditioner weights not set");
     rc = ensure_ready(c, F32, false);
+    if (!rc) rc = nn_build_weights(c);
     if (rc) return rc;
-    rc = nn_build_weights(c);
-    if (rc) return rc;
-    const long Vh = c->Vh;
-    // layer order and channel counts
-    int order[NN_L];
-    for (int i = 0; i < NN_L; ++i) order[i] = dagger ? NN_L - 1 - i : i;
-    SpinorPtr a = act(c, keep ? "a0" : "p0", 1);
+    const bool keep = acts != nullptr;
+    Act a = act(c, keep ? "a0" : "p0", 1);
     if (!a.d) return TMX_ENOMEM;
-    // embed: even half zero, odd half = r
-    {
-        OpZero<F32> oz{};
-        oz.d = even_view(a);
-        oz.nf = 1;
-        HIP_CHECK_RET(c, run_blas(oz, Vh, 1, c->red, c->stream), "embed zero");
-        SpinorPtr ov = odd_view(c, a);
-        if (pr == F64) {
-            OpCopy<F32, F64> cp{};
-            cp.d = ov;
-            cp.s = r;
-            cp.nf = 1;
-            HIP_CHECK_RET(c, run_blas(cp, Vh, 1, c->red, c->stream), "embed");
-        } else if (pr == F16) {
-            OpCopy<F32, F16> cp{};
-            cp.d = ov;
-            cp.s = r;
-            cp.nf = 1;
-            HIP_CHECK_RET(c, run_blas(cp, Vh, 1, c->red, c->stream), "embed");
-        } else {
-            OpCopy<F32, F32> cp{};
-            cp.d = ov;
-            cp.s = r;
-            cp.nf = 1;
-            HIP_CHECK_RET(c, run_blas(cp, Vh, 1, c->red, c->stream), "embed");
-        }
-    }
-    if (acts_out) acts_out->push_back(a);
+    rc = embed(c, r, pr, a);
+    if (rc) return rc;
     for (int i = 0; i < NN_L; ++i) {
-        const int l = order[i];
+        const int l = dagger ? NN_L - 1 - i : i;
         const int cin = dagger ? NN_COUT[l] : NN_CIN[l];
         const int cout = dagger ? NN_CIN[l] : NN_COUT[l];
-        const std::string nm = (keep ? "a" : "p") + std::to_string(i + 1);
-        SpinorPtr b = act(c, nm, cout);
+        const uint16_t *W = dagger ? c->pc->Wa[l] : c->pc->Wf[l];
+        if (acts) acts->push_back(a);
+        if (cout == 1) return launch_layer(c, cin, cout, a, Act{}, out, W);
+        Act b = act(c, (keep ? "a" : "p") + std::to_string(i + 1), cout);
         if (!b.d) return TMX_ENOMEM;
-        HIP_CHECK_RET(c, launch_layer(c, cin, cout, a, b, dagger ? c->pc->Wa[l] : c->pc->Wf[l]), "nn layer");
-        if (acts_out) acts_out->push_back(b);
+        rc = launch_layer(c, cin, cout, a, b, SpinorPtr{}, W);
+        if (rc) return rc;
         a = b;
     }
-    SpinorPtr ov = odd_view(c, a);
-    if (pz == F64) {
-        OpCopy<F64, F32> cp{};
-        cp.d = z;
-        cp.s = ov;
-        cp.nf = 1;
-        HIP_CHECK_RET(c, run_blas(cp, Vh, 1, c->red, c->stream), "restrict");
-    } else {
-        OpCopy<F32, F32> cp{};
-        cp.d = z;
-        cp.s = ov;
-        cp.nf = 1;
-        HIP_CHECK_RET(c, run_blas(cp, Vh, 1, c->red, c->stream), "restrict");
-    }
+    return set_err(c, TMX_EINVAL, "network without an output layer");
+}
+
+}  // namespace
+
+// z = K r (dagger = 0) or K^dagger r (dagger = 1): odd fields r (precision
+// pr, stride Vh) and z (precision pz: F64 or F32)
+int pc_apply_internal(tmx_ctx *c, SpinorPtr z, int pz, SpinorPtr r, int pr, int dagger)
+{
+    if (pz != F32 && pz != F64) return set_err(c, TMX_EINVAL, "preconditioner output precision");
+    if (pz == F32) return nn_forward(c, z, r, pr, dagger, nullptr);
+    void *po = ws_get(c, "nn_pout", spinor_field_bytes(F32, 1, c->Vh));
+    if (!po) return TMX_ENOMEM;
+    SpinorPtr o = make_spinor(po, F32, 1, c->Vh);
+    int rc = nn_forward(c, o, r, pr, dagger, nullptr);
+    if (rc) return rc;
+    OpCopy<F64, F32> cp{};
+    cp.d = z;
+    cp.s = o;
+    cp.nf = 1;
+    HIP_CHECK_RET(c, run_blas(cp, c->Vh, 1, c->red, c->stream), "restrict");
     return TMX_OK;
 }
 
@@ -870,7 +999,7 @@ int fgcr_stage(tmx_ctx *c, int op, int dagger, SpinorPtr x, SpinorPtr b, double 
         double rlo = rr;
         for (int j = 0; j < m && it < maxiter; ++j) {
             // z_j = K r ; w = A z_j   (low precision)
-            rc = pc_apply_internal(c, zs[j], F32, rl, F32, dagger, false, nullptr);
+            rc = pc_apply_internal(c, zs[j], F32, rl, F32, dagger);
             if (rc) return rc;
             rc = op_mhat(c, w, zs[j], op, inner_prec == F64 ? F32 : F32, dagger, 1);
             if (rc) return rc;
@@ -1037,6 +1166,9 @@ void tmx_pc_free(tmx_ctx *c)
         dev_free(s.Wf[l]);
         dev_free(s.Wa[l]);
     }
+    dev_free(s.la);
+    dev_free(s.lb);
+    dev_free(s.lc);
     delete c->pc;
     c->pc = nullptr;
 }
@@ -1086,7 +1218,7 @@ int tmx_pc_apply(tmx_ctx *c, double *out, const double *in, int dagger)
     SpinorPtr I = make_spinor(pi, F32, 1, Vh), O = make_spinor(po, F32, 1, Vh);
     int r = hip_err(c, launch_pack_spinor(in, I, F32, TMX_FIELD_ODD, c->g, 1, c->stream), "pack");
     if (r) return r;
-    r = pc_apply_internal(c, O, F32, I, F32, dagger ? 1 : 0, false, nullptr);
+    r = pc_apply_internal(c, O, F32, I, F32, dagger ? 1 : 0);
     if (r) return r;
     r = hip_err(c, launch_unpack_spinor(out, O, F32, TMX_FIELD_ODD, c->g, 1, c->stream), "unpack");
     if (r) return r;
@@ -1128,25 +1260,20 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
         if (!r) r = fetch(c, 1, &xx);
         if (r) return r;
         if (!(xx > 0)) return set_err(c, TMX_EINVAL, "training pair with zero norm");
-        std::vector<SpinorPtr> acts;
+        std::vector<Act> acts;
         void *pz = ws_get(c, "tr_z", spinor_field_bytes(F32, 1, Vh));
-        if (!pz) return TMX_ENOMEM;
-        r = pc_apply_internal(c, make_spinor(pz, F32, 1, Vh), F32, B, F32, 0, true, &acts);
+        void *pd = ws_get(c, "tr_dl", spinor_field_bytes(F32, 1, Vh));
+        if (!pz || !pd) return TMX_ENOMEM;
+        const SpinorPtr Z = make_spinor(pz, F32, 1, Vh), DL = make_spinor(pd, F32, 1, Vh);
+        r = nn_forward(c, Z, B, F32, 0, &acts);
         if (r) return r;
-        // delta = embed(K b - x) / (|x|^2 n)
-        SpinorPtr dl = act(c, "d4", 1);
-        {
-            OpZero<F32> oz{};
-            oz.d = dl;
-            oz.nf = 1;
-            r = hip_err(c, run_blas(oz, Vh, 1, c->red, c->stream), "zero delta");
-            if (r) return r;
-        }
+        // DL = dLoss / d(K b) (odd field), then as the one-channel output adjoint
         if (loss_kind == TMX_LOSS_SOLUTION) {
+            // (K b - x) / (|x|^2 n)
             OpPairResidual<F32> pr{};
-            pr.out = odd_view(c, acts[NN_L]);
+            pr.out = Z;
             pr.x = X;
-            pr.delta = odd_view(c, dl);
+            pr.delta = DL;
             pr.scale = 1.0 / (xx * n);
             r = hip_err(c, run_blas(pr, Vh, 1, c->red, c->stream), "pair residual");
             double red[2];
@@ -1154,13 +1281,13 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
             if (r) return r;
             L += red[0] / xx / n;
         } else {
-            // e = K b - x ; q = Mhat e ; loss |q|^2/|b|^2 ; delta = Mhat^dagger q / (|b|^2 n)
+            // e = K b - x ; q = Mhat e ; loss |q|^2/|b|^2 ; DL = Mhat^dagger q / (|b|^2 n)
             void *pe = ws_get(c, "tr_e", spinor_field_bytes(F32, 1, Vh));
             void *pq = ws_get(c, "tr_q", spinor_field_bytes(F32, 1, Vh));
             if (!pe || !pq) return TMX_ENOMEM;
             SpinorPtr E = make_spinor(pe, F32, 1, Vh), Q = make_spinor(pq, F32, 1, Vh);
             OpPairResidual<F32> pr{};
-            pr.out = odd_view(c, acts[NN_L]);
+            pr.out = Z;
             pr.x = X;
             pr.delta = E;
             pr.scale = 1.0;
@@ -1177,7 +1304,7 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
             if (!r) r = op_mhat(c, E, Q, TMX_OP_PLUS, F32, 1, 1);
             if (r) return r;
             OpAxpby<F32, F32> sc{};
-            sc.y = odd_view(c, dl);
+            sc.y = DL;
             sc.x = E;
             sc.nf = 1;
             sc.a[0] = 1.0 / (xx * n);
@@ -1186,14 +1313,18 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
             if (r) return r;
             L += qq / xx / n;
         }
+        Act delta = act(c, "d4", 1);
+        if (!delta.d) return TMX_ENOMEM;
+        r = embed(c, DL, F32, delta);
+        if (r) return r;
         // backward through the layers
-        SpinorPtr delta = dl;
         for (int l = NN_L - 1; l >= 0; --l) {
-            r = hip_err(c, launch_wgrad(c, NN_CIN[l], NN_COUT[l], acts[l], delta, partial[l]), "wgrad");
+            r = launch_wgrad(c, NN_CIN[l], NN_COUT[l], acts[l], delta, partial[l]);
             if (r) return r;
             if (l > 0) {
-                SpinorPtr nd = act(c, "d" + std::to_string(l), NN_CIN[l]);
-                r = hip_err(c, launch_layer(c, NN_COUT[l], NN_CIN[l], delta, nd, s.Wa[l]), "adjoint layer");
+                Act nd = act(c, "d" + std::to_string(l), NN_CIN[l]);
+                if (!nd.d) return TMX_ENOMEM;
+                r = launch_layer(c, NN_COUT[l], NN_CIN[l], delta, nd, SpinorPtr{}, s.Wa[l]);
                 if (r) return r;
                 delta = nd;
             }

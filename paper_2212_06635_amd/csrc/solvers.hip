@@ -309,9 +309,9 @@ template <int P> struct OpPcgDots {
 template <int P>
 static int pcg_apply_pc(Sys &S, SpinorPtr z, SpinorPtr r, SpinorPtr tmp)
 {
-    int rc = pc_apply_internal(S.c, tmp, F32, r, P, 1, false, nullptr);  // K^dagger r
+    int rc = pc_apply_internal(S.c, tmp, F32, r, P, 1);  // K^dagger r
     if (rc) return rc;
-    return pc_apply_internal(S.c, z, F32, tmp, F32, 0, false, nullptr);  // K K^dagger r
+    return pc_apply_internal(S.c, z, F32, tmp, F32, 0);  // K K^dagger r
 }
 
 template <int P>

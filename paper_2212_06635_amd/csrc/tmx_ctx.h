@@ -141,8 +141,7 @@ double mhat_bytes_per_site(int prec, int nf, int nrhs);
 double now_seconds();
 
 // learned preconditioner: z = K r (dagger = 0) or K^dagger r on odd fields
-int pc_apply_internal(tmx_ctx *c, SpinorPtr z, int pz, SpinorPtr r, int pr, int dagger, bool keep,
-                      std::vector<SpinorPtr> *acts_out);
+int pc_apply_internal(tmx_ctx *c, SpinorPtr z, int pz, SpinorPtr r, int pr, int dagger);
 // plain / mixed CG on N used as the fallback of the flexible GCR solver
 int cg_fallback(tmx_ctx *c, int op, SpinorPtr x, SpinorPtr b, double tol, int maxiter, tmx_info *info);
 

@@ -152,6 +152,20 @@ __device__ __forceinline__ uint2 f_to_h4(const float *o)
     return v;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  With xcd != 0 the launch index is remapped so that XCD k works on one
+// contiguous 1/8 of the sites: neighbours in y, z and t then mostly hit the
+// L2 that already holds them.  (The map is a permutation of the blocks for
+// any grid, so the result never depends on the dispatch order.)
+__device__ __forceinline__ int xcd_block(int xcd)
+{
+    const int b = blockIdx.x;
+    if (!xcd) return b;
+    const int nb = gridDim.x, q = nb / 8, r = nb % 8;
+    const int k = b % 8, i = b / 8;
+    return k * q + (k < r ? k : r) + i;
+}
+
 // 16-byte load; NT = non-temporal (streamed operands such as links and
 // clover blocks are read once per sweep: keeping them out of the way in L2
 // leaves room for the neighbour spinors, which are read eight times)
