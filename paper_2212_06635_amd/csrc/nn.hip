@@ -30,6 +30,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "tmx_ctx.h"
@@ -52,9 +53,11 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // FP32 -> BF16, round to nearest even (gfx950 converts pairs in one
 // v_cvt_pk_bf16_f32)
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t f2bf2(float a, float b)
 {
-    return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)a) | ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)b) << 16);
+    const bf16x2v r = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, r);
 }
 
 static size_t layer_param_offset(int l)
@@ -75,9 +78,8 @@ struct PcState {
     bool w_ok = false;
     bool have_weights = false;
     int adam_t = 0;
-    uint4 *la = nullptr, *lb = nullptr;  // BF16 network links (see NnLinks)
-    uint32_t *lc = nullptr;
-    int links_upload = -1;               // gauge upload the links were made from
+    uint32_t *lrow = nullptr, *lcol = nullptr;  // BF16 network links (see NnLinks)
+    int links_upload = -1;  // gauge upload the links were made from
 };
 
 // ---------------------------------------------------------------------------
@@ -125,36 +127,40 @@ __global__ void nn_build_w_kernel(const float *p, uint16_t *W, int cin, int cout
 // ---------------------------------------------------------------------------
 // BF16 operands: activations, links, transports
 // ---------------------------------------------------------------------------
-typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// c + a.lo b.lo + a.hi b.hi over BF16 pairs with FP32 accumulation (v_dot2_f32_bf16)
-__device__ __forceinline__ float dot2bf(uint32_t a, uint32_t b, float c)
-{
-    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, a), __builtin_bit_cast(bf16x2v, b), c, false);
-}
-
-// Activation field (BF16, full lattice): colour a of channel c at site gs
-// (= parity * V/2 + checkerboard index) is the 16-byte vector
-// d[(c * 3 + a) * stride + gs], holding spins 0..3 as (re, im) BF16 pairs;
-// this is the operand format of the transports below and of the staging rows
-// of the contraction.
+// Activation field (BF16, full lattice): channel c at site gs (= parity * V/2
+// + checkerboard index) is 12 words at d[(c * stride + gs) * 12], spin s
+// in words 3 s .. 3 s + 2 (colours 0..2 as (re, im) BF16 pairs).  Lane q of
+// a site reads the three words of spin q: the four lanes of a site read 48
+// contiguous bytes and consecutive sites follow each other.
 struct Act {
-    uint4 *d;
+    uint32_t *d;
     long stride;
 };
 
-// BF16 links of the network: all nine entries of U_mu(x), x of parity p and
-// checkerboard index s, as (re, im) pairs; entries 0-3 at a[(p*4 + mu) * Vh + s],
-// 4-7 at b[...] and 8 at c[...] (36 bytes per link, no reconstruction).
+struct W3 {
+    uint32_t x, y, z;
+};
+__device__ __forceinline__ W3 ld3(const uint32_t *p)
+{
+    W3 r;
+    r.x = p[0];
+    r.y = p[1];
+    r.z = p[2];
+    return r;
+}
+
+// BF16 links of the network: U_mu(x), x of parity p and checkerboard index s,
+// as nine (re, im) pairs at row[((p*4 + mu) * Vh + s) * 9 + 3 r + k] = U[r][k]
+// and, transposed, col[... + 3 r + k] = U[k][r].
 struct NnLinks {
-    const uint4 *a, *b;
-    const uint32_t *c;
+    const uint32_t *row, *col;
     long Vh;
 };
 
 // thread per (p, mu, s): from the FP64 two-row master copy (6 complex per link)
-__global__ void nn_links_kernel(const double2 *l64, uint4 *a, uint4 *b, uint32_t *c, long Vh)
+__global__ void nn_links_kernel(const double2 *l64, uint32_t *row, uint32_t *col, long Vh)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 8 * Vh) return;
@@ -168,12 +174,13 @@ __global__ void nn_links_kernel(const double2 *l64, uint4 *a, uint4 *b, uint32_t
     u[6] = conj(u[1] * u[5] - u[2] * u[4]);
     u[7] = conj(u[2] * u[3] - u[0] * u[5]);
     u[8] = conj(u[0] * u[4] - u[1] * u[3]);
-    uint32_t w[9];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) w[e] = f2bf2((float)u[e].re, (float)u[e].im);
-    a[i] = make_uint4(w[0], w[1], w[2], w[3]);
-    b[i] = make_uint4(w[4], w[5], w[6], w[7]);
-    c[i] = w[8];
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            row[i * 9 + 3 * r + k] = f2bf2((float)u[3 * r + k].re, (float)u[3 * r + k].im);
+            col[i * 9 + 3 * r + k] = f2bf2((float)u[3 * k + r].re, (float)u[3 * k + r].im);
+        }
 }
 
 // neighbour along path d of the site (coordinates x, parity p, index cb)
@@ -222,45 +229,6 @@ __device__ __forceinline__ Nbr path_neighbour_at(const Geom &g, const int x[4], 
     return r;
 }
 
-// z_a = bc sum_b W_ab psi_b for NCH channels and NS spins (per colour, BF16
-// pairs), W = U_mu(x) (forward path) or U_mu(x - mu)^dagger (backward path).
-// Each complex product is two dot2 steps with coefficient pairs
-//   forward:  re (U.re, -U.im), im (U.im, U.re)   of U_ab
-//   backward: re (U.re,  U.im), im (-U.im, U.re)  of U_ba
-// made from the stored pair by a half swap and sign flips; sgn flips both
-// halves (bc = -1).
-template <bool DAG, int NCH, int NS>
-__device__ __forceinline__ void transport_bf(const uint32_t u[9], uint32_t sgn, const uint32_t (&psi)[NCH][3][NS],
-                                             uint32_t (&z)[NCH][3][NS])
-{
-    uint32_t pr[9], pi[9];
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        const uint32_t sw = (u[e] >> 16) | (u[e] << 16);
-        pr[e] = (DAG ? u[e] : (u[e] ^ 0x80000000u)) ^ sgn;
-        pi[e] = (DAG ? (sw ^ 0x00008000u) : sw) ^ sgn;
-    }
-#pragma unroll
-    for (int j = 0; j < NCH; ++j)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            float re[NS], im[NS];
-#pragma unroll
-            for (int s = 0; s < NS; ++s) re[s] = im[s] = 0.f;
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const int e = DAG ? 3 * b + a : 3 * a + b;
-#pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    re[s] = dot2bf(pr[e], psi[j][b][s], re[s]);
-                    im[s] = dot2bf(pi[e], psi[j][b][s], im[s]);
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < NS; ++s) z[j][a][s] = f2bf2(re[s], im[s]);
-        }
-}
-
 // site of a staging thread: coordinates decoded once per tile
 struct SiteCtx {
     int xs[4], p, cb;
@@ -276,102 +244,122 @@ __device__ __forceinline__ void site_ctx(const Geom &g, long gs, long s_end, Sit
     cb_coords(g, sc.cb, sc.p, sc.xs);
 }
 
-// register staging of one path for one thread: NCH channels from c0, NS
-// spins from s0 (NS = 4: whole channels; NS = 1: one spin of one channel)
-template <int NCH, int NS> struct Stg {
-    uint32_t psi[NCH][3][NS];
-    uint32_t u[9];
-    uint32_t sgn;
-    bool zero, ident, dag;
+// Transport on the matrix cores.  The four lanes of a site (q = lane % 4) are
+// one block of v_mfma_f32_4x4x4_16b_bf16 (A[i][k] in lane 4b + i, B[k][j] in
+// lane 4b + j, D[i][j] in lane 4b + j, register i).  With the input channel
+// as Psi[colour k][spin i] and W = U or U^dagger,
+//     D = Psi^T W^T,   D[i][j] = (W Psi)[colour j][spin i],
+// so lane q supplies spin q of the input (A row q: colours 0..2, zero) and
+// row q of W (B column q), and receives colour q of the result, all four
+// spins: exactly one staging row of the contraction.  Complex products take
+// four real steps: D_re = A_re B_re - A_im B_im, D_im = A_re B_im + A_im B_re.
+struct Wop {
+    bf16x4 re, im, nim;  // B column of this lane: re, im and -im of W[q][k]
+};
+
+// (re, im) pairs of three complex numbers -> BF16 vectors of the real and
+// imaginary parts, fourth entry zero
+__device__ __forceinline__ void split3(uint32_t d0, uint32_t d1, uint32_t d2, bf16x4 &re, bf16x4 &im)
+{
+    re = __builtin_bit_cast(bf16x4, make_uint2(__builtin_amdgcn_perm(d1, d0, 0x05040100u), d2 & 0xffffu));
+    im = __builtin_bit_cast(bf16x4, make_uint2(__builtin_amdgcn_perm(d1, d0, 0x07060302u), d2 >> 16));
+}
+
+// W operand of lane q for path data: ident -> unit matrix; otherwise row q of
+// U (forward) or the conjugate of column q of U (backward), times bc
+__device__ __forceinline__ Wop make_wop(bool ident, bool dag, float bc, W3 w, int q)
+{
+    Wop o;
+    if (ident) {
+        const uint32_t one = 0x3f80u;  // BF16 1.0
+        const uint2 v = make_uint2(q == 0 ? one : (q == 1 ? one << 16 : 0u), q == 2 ? one : 0u);
+        o.re = __builtin_bit_cast(bf16x4, v);
+        o.im = o.nim = __builtin_bit_cast(bf16x4, make_uint2(0u, 0u));
+        return o;
+    }
+    split3(w.x, w.y, w.z, o.re, o.im);
+    const uint32_t neg = 0x80008000u;
+    uint2 r = __builtin_bit_cast(uint2, o.re), i = __builtin_bit_cast(uint2, o.im);
+    if (dag) i = make_uint2(i.x ^ neg, i.y ^ (neg & 0xffffu));
+    if (bc < 0.f) {
+        r = make_uint2(r.x ^ neg, r.y ^ (neg & 0xffffu));
+        i = make_uint2(i.x ^ neg, i.y ^ (neg & 0xffffu));
+    }
+    o.re = __builtin_bit_cast(bf16x4, r);
+    o.im = __builtin_bit_cast(bf16x4, i);
+    o.nim = __builtin_bit_cast(bf16x4, make_uint2(i.x ^ neg, i.y ^ (neg & 0xffffu)));
+    return o;
+}
+
+// one channel: spin q of the input (colours in x, y, z) -> colour q of the
+// transported field, spins 0..3, as BF16 (re, im) pairs
+__device__ __forceinline__ void transport4(const Wop &w, W3 psi, uint32_t out[4])
+{
+    bf16x4 are, aim;
+    split3(psi.x, psi.y, psi.z, are, aim);
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    f32x4 dre = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(are, w.re, z, 0, 0, 0);
+    dre = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(aim, w.nim, dre, 0, 0, 0);
+    f32x4 dim = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(are, w.im, z, 0, 0, 0);
+    dim = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(aim, w.re, dim, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[i] = f2bf2(dre[i], dim[i]);
+}
+
+// register staging of one path for lane q of a site: spin q of all CIN
+// input channels, and this lane's row / column of the link
+template <int CIN> struct Stg {
+    W3 psi[CIN];
+    W3 w;
+    float bc;
+    bool ident, dag;
 };
 
 // in_odd: the input field is zero on even sites (and never read there)
-template <int NCH, int NS>
+template <int CIN>
 __device__ __forceinline__ void stg_load(const Geom &g, const Act &x, const NnLinks &L, int t_bc, int d, bool in_odd,
-                                         const SiteCtx &sc, int c0, int s0, Stg<NCH, NS> &st)
+                                         const SiteCtx &sc, int q, Stg<CIN> &st)
 {
-    st.zero = !sc.valid;
-    if (st.zero) return;
-    const Nbr nb = path_neighbour_at(g, sc.xs, sc.p, sc.cb, d, t_bc);
-    const int np = d == 0 ? sc.p : 1 - sc.p;
-    if (in_odd && np == 0) {
-        st.zero = true;
-        return;
+    // zero operands where the input vanishes: the transport still runs on
+    // every lane (matrix-core steps are never placed under a divergent branch)
+    bool zero = !sc.valid;
+    Nbr nb{};
+    if (!zero) {
+        nb = path_neighbour_at(g, sc.xs, sc.p, sc.cb, d, t_bc);
+        const int np = d == 0 ? sc.p : 1 - sc.p;
+        zero = in_odd && np == 0;
     }
-    st.ident = nb.ident;
-    st.dag = nb.dag;
-    st.sgn = nb.bc < 0.f ? 0x80008000u : 0u;
-    if (!nb.ident) {
+    const W3 z0 = {0u, 0u, 0u};
+    st.ident = !zero && nb.ident;
+    st.dag = !zero && nb.dag;
+    st.bc = zero ? 1.f : nb.bc;
+    st.w = z0;
+    if (!zero && !nb.ident && q < 3) {
         const int mu = (d - 1) / 2;
-        const long i = (long)(nb.lp * 4 + mu) * L.Vh + nb.lcb;
-        const uint4 a = ldv<true>(L.a + i), b = ldv<true>(L.b + i);
-        st.u[0] = a.x;
-        st.u[1] = a.y;
-        st.u[2] = a.z;
-        st.u[3] = a.w;
-        st.u[4] = b.x;
-        st.u[5] = b.y;
-        st.u[6] = b.z;
-        st.u[7] = b.w;
-        st.u[8] = __builtin_nontemporal_load(L.c + i);
+        const long li = ((long)(nb.lp * 4 + mu) * L.Vh + nb.lcb) * 9 + 3 * q;
+        st.w = ld3((nb.dag ? L.col : L.row) + li);
     }
 #pragma unroll
-    for (int j = 0; j < NCH; ++j)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const uint4 *p = x.d + ((long)(c0 + j) * 3 + a) * x.stride + nb.idx;
-            if constexpr (NS == 4) {
-                const uint4 v = *p;
-                st.psi[j][a][0] = v.x;
-                st.psi[j][a][1] = v.y;
-                st.psi[j][a][2] = v.z;
-                st.psi[j][a][3] = v.w;
-            } else {
-                st.psi[j][a][0] = reinterpret_cast<const uint32_t *>(p)[s0];
-            }
-        }
-}
-
-// transported values of a staging thread: z[j][a][s]
-template <int NCH, int NS>
-__device__ __forceinline__ void stg_transport(const Stg<NCH, NS> &st, uint32_t (&z)[NCH][3][NS])
-{
-    if (st.zero) {
-#pragma unroll
-        for (int j = 0; j < NCH; ++j)
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int s = 0; s < NS; ++s) z[j][a][s] = 0u;
-    } else if (st.ident) {
-#pragma unroll
-        for (int j = 0; j < NCH; ++j)
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int s = 0; s < NS; ++s) z[j][a][s] = st.psi[j][a][s];
-    } else if (st.dag) {
-        transport_bf<true, NCH, NS>(st.u, st.sgn, st.psi, z);
-    } else {
-        transport_bf<false, NCH, NS>(st.u, st.sgn, st.psi, z);
-    }
+    for (int c = 0; c < CIN; ++c) st.psi[c] = zero ? z0 : ld3(x.d + ((long)c * x.stride + nb.idx) * 12 + 3 * q);
 }
 
 // ---------------------------------------------------------------------------
 // layer kernel: Y = sum_d W_d Z_d   (forward or adjoint, by the weights given)
 // ---------------------------------------------------------------------------
-// Tile of 64 sites (192 GEMM columns), 256 threads.  Staging: four threads
-// per site, each transporting two input channels (or, with one input
-// channel, one spin) on the vector ALUs with BF16 dot2 steps, and writing
-// the BF16 rows Z_d[n = (site, colour)][k = (channel, spin, re/im)] to LDS.
+// Tile of 64 sites (192 GEMM columns), 256 threads.  Staging: four lanes per
+// site, lane q loading spin q of every input channel at the neighbour and
+// transporting it on the matrix cores (above); lanes q < 3 write the BF16
+// rows Z_d[n = (site, colour q)][k = (channel, spin, re/im)] to LDS.
 // Contraction: wave w owns the 16-row block m = 16 w .. 16 w + 15 of the
 // output (all twelve column blocks) on v_mfma_f32_16x16x32_bf16 (16x16x16
-// for a one-channel input).  The next path's neighbours and links are
-// loaded into registers while the matrix cores work on the current one.
-// One input channel means an input supported on odd sites (the embedded
-// source): tiles of one parity then skip the paths that only see zeros.  One
-// output channel means the last layer: only odd sites are computed and the
-// result is written in FP32 as an odd spinor field.
+// for a one-channel input).  The paths are unrolled; the weights of path
+// i + 2 and the neighbours and links of path i + 2 (i + 1 in the 8 -> 8
+// layer) are requested while path i is contracted, so memory latency
+// overlaps the steps in between.  One input channel means an input supported on odd
+// sites (the embedded source): tiles then hold one parity, and odd tiles
+// run the d = 0 path only, even tiles the eight hops only.  One output
+// channel means the last layer: only odd sites are computed and the result
+// is written in FP32 as an odd spinor field.
 constexpr int NL_S = 64;
 constexpr int NL_N = 3 * NL_S;
 
@@ -385,16 +373,29 @@ __global__ void __launch_bounds__(256) nn_layer_kernel(Geom g, Act x, Act y, Spi
     constexpr bool K32 = KD % 32 == 0;
     constexpr int KK = K32 ? KD / 32 : KD / 16;
     constexpr int PER = MT >= 4 ? NT : (NT + 3) / 4;
-    constexpr int NCH = CIN >= 4 ? CIN / 4 : 1;
-    constexpr int NS = CIN >= 4 ? 4 : 1;
     constexpr bool IN_ODD = CIN == 1;
     static_assert(MT == 4 || MT == 1, "output rows: 8 or 1 channels");
-    __shared__ __attribute__((aligned(16))) uint16_t Zs[NL_N][KS];
+    // LDS: the staging rows, then (after the last path) the output tile
+    constexpr int ZS_BYTES = NL_N * KS * 2;
+    constexpr int YS_BYTES = COUT == 1 ? NL_S * 24 * 4 : NL_S * COUT * 48;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[ZS_BYTES > YS_BYTES ? ZS_BYTES : YS_BYTES];
+    uint16_t(*Zs)[KS] = reinterpret_cast<uint16_t(*)[KS]>(smem);
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int my_mt = MT >= 4 ? wave : 0;
-    const long site0 = s_begin + (long)xcd_block(xcd) * NL_S;
+    // tile -> sites.  With an odd-supported input, tiles alternate between
+    // the parities (tile 2i + p: sites p V/2 + 64 i ...), so that every tile
+    // has one parity and every XCD gets as many 8-path (even) tiles as
+    // 1-path (odd) ones.
+    const long tile = xcd_block(xcd);
+    long site0;
+    if (IN_ODD) {
+        const long par = tile & 1;
+        site0 = par * g.Vh + (tile >> 1) * NL_S;
+        s_end = (par + 1) * (long)g.Vh;
+    } else {
+        site0 = s_begin + tile * NL_S;
+    }
     const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
-    const int c0 = CIN >= 4 ? q * NCH : 0, s0 = CIN >= 4 ? 0 : q;
 
     if (8 * CIN < KD) {
         for (int i = threadIdx.x; i < NL_N; i += blockDim.x)
@@ -402,98 +403,126 @@ __global__ void __launch_bounds__(256) nn_layer_kernel(Geom g, Act x, Act y, Spi
     }
     SiteCtx sc;
     site_ctx(g, site0 + sl, s_end, sc);
-    // paths that can contribute to this tile
-    int npath = NN_P, dfirst = 0;
-    if (IN_ODD) {
-        const long last = (site0 + NL_S < s_end ? site0 + NL_S : s_end) - 1;
-        const int pf = site0 >= g.Vh, pl = last >= g.Vh;
-        if (pf == pl) {
-            npath = pf ? 1 : NN_P - 1;
-            dfirst = pf ? 0 : 1;
-        }
-    }
     f32x4 acc[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    Stg<NCH, NS> st;
-    stg_load<NCH, NS>(g, x, L, t_bc, dfirst, IN_ODD, sc, c0, s0, st);
-    for (int i = 0; i < npath; ++i) {
-        const int d = dfirst + i;
-        {
-            uint32_t z[NCH][3][NS];
-            stg_transport<NCH, NS>(st, z);
-#pragma unroll
-            for (int j = 0; j < NCH; ++j)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    if constexpr (NS == 4)
-                        *reinterpret_cast<uint4 *>(&Zs[sl * 3 + a][(c0 + j) * 8]) =
-                            make_uint4(z[j][a][0], z[j][a][1], z[j][a][2], z[j][a][3]);
-                    else
-                        *reinterpret_cast<uint32_t *>(&Zs[sl * 3 + a][(c0 + j) * 8 + 2 * s0]) = z[j][a][0];
-                }
-        }
-        __syncthreads();
-        if (i + 1 < npath) stg_load<NCH, NS>(g, x, L, t_bc, d + 1, IN_ODD, sc, c0, s0, st);
+    using WFrag = typename std::conditional<K32, bf16x8, bf16x4>::type;
+    // weight fragments of path d for this wave's output rows
+    auto load_w = [&](int d, WFrag (&wa)[KK]) {
         const uint16_t *Wd = W + ((size_t)d * MD + my_mt * 16 + lane % 16) * KD;
-        if constexpr (K32) {
-            bf16x8 wa[KK];
 #pragma unroll
-            for (int kk = 0; kk < KK; ++kk) wa[kk] = *reinterpret_cast<const bf16x8 *>(Wd + kk * 32 + 8 * (lane / 16));
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                const int nt = MT >= 4 ? j : wave + 4 * j;
-                if (nt >= NT) break;
-#pragma unroll
-                for (int kk = 0; kk < KK; ++kk) {
-                    const bf16x8 b =
-                        *reinterpret_cast<const bf16x8 *>(&Zs[nt * 16 + lane % 16][kk * 32 + 8 * (lane / 16)]);
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[kk], b, acc[j], 0, 0, 0);
-                }
-            }
-        } else {
-            bf16x4 wa[KK];
-#pragma unroll
-            for (int kk = 0; kk < KK; ++kk) wa[kk] = *reinterpret_cast<const bf16x4 *>(Wd + kk * 16 + 4 * (lane / 16));
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                const int nt = MT >= 4 ? j : wave + 4 * j;
-                if (nt >= NT) break;
-#pragma unroll
-                for (int kk = 0; kk < KK; ++kk) {
-                    const bf16x4 b =
-                        *reinterpret_cast<const bf16x4 *>(&Zs[nt * 16 + lane % 16][kk * 16 + 4 * (lane / 16)]);
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[kk], b, acc[j], 0, 0, 0);
-                }
-            }
+        for (int kk = 0; kk < KK; ++kk)
+            wa[kk] = K32 ? *reinterpret_cast<const WFrag *>(Wd + kk * 32 + 8 * (lane / 16))
+                         : *reinterpret_cast<const WFrag *>(Wd + kk * 16 + 4 * (lane / 16));
+    };
+    // Neighbour slots: the 8 -> 8 layer keeps one path ahead (two would
+    // halve its occupancy), the others two.
+    constexpr int NSLOT = (CIN == 8 && COUT == 8) ? 1 : 2;
+    // paths D0 .. D0 + NP - 1
+    auto run = [&](auto d0c, auto npc) {
+        constexpr int D0 = decltype(d0c)::value, NP = decltype(npc)::value;
+        Stg<CIN> st[NSLOT];
+        WFrag wa[2][KK];
+        stg_load<CIN>(g, x, L, t_bc, D0, IN_ODD, sc, q, st[0]);
+        load_w(D0, wa[0]);
+        if constexpr (NP > 1) {
+            if constexpr (NSLOT > 1) stg_load<CIN>(g, x, L, t_bc, D0 + 1, IN_ODD, sc, q, st[1]);
+            load_w(D0 + 1, wa[1]);
         }
-        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int b = i & 1, sb = i % NSLOT;
+            {
+                const Wop w = make_wop(st[sb].ident, st[sb].dag, st[sb].bc, st[sb].w, q);
+#pragma unroll
+                for (int c = 0; c < CIN; ++c) {
+                    uint32_t z[4];
+                    transport4(w, st[sb].psi[c], z);
+                    if (q < 3)
+                        *reinterpret_cast<uint4 *>(&Zs[sl * 3 + q][c * 8]) = make_uint4(z[0], z[1], z[2], z[3]);
+                }
+            }
+            __syncthreads();
+            if (i + NSLOT < NP) stg_load<CIN>(g, x, L, t_bc, D0 + i + NSLOT, IN_ODD, sc, q, st[sb]);
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int nt = MT >= 4 ? j : wave + 4 * j;
+                if (nt >= NT) break;
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) {
+                    if constexpr (K32) {
+                        const bf16x8 bz =
+                            *reinterpret_cast<const bf16x8 *>(&Zs[nt * 16 + lane % 16][kk * 32 + 8 * (lane / 16)]);
+                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[b][kk], bz, acc[j], 0, 0, 0);
+                    } else {
+                        const bf16x4 bz =
+                            *reinterpret_cast<const bf16x4 *>(&Zs[nt * 16 + lane % 16][kk * 16 + 4 * (lane / 16)]);
+                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[b][kk], bz, acc[j], 0, 0, 0);
+                    }
+                }
+            }
+            if (i + 2 < NP) load_w(D0 + i + 2, wa[b]);
+            __syncthreads();
+        }
+    };
+    if constexpr (IN_ODD) {
+        // odd tiles: their own (odd) input; even tiles: the odd neighbours
+        if (site0 >= g.Vh)
+            run(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{});
+        else
+            run(std::integral_constant<int, 1>{}, std::integral_constant<int, NN_P - 1>{});
+    } else {
+        run(std::integral_constant<int, 0>{}, std::integral_constant<int, NN_P>{});
     }
-    // D[m][n]: lane holds rows m = 16 mt + 4 (lane/16) + i of column n = 16 nt + lane%16
+
+    // D[m][n]: lane holds rows m = 16 mt + 4 (lane/16) + i of column n = 16 nt + lane%16.
+    // The tile goes through LDS so that every global store is a whole
+    // 16-byte vector and a wave's stores are contiguous.
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int nt = MT >= 4 ? j : wave + 4 * j;
         if (nt >= NT) break;
         const int m0 = my_mt * 16 + 4 * (lane / 16);
         const int n = nt * 16 + lane % 16;
-        const long gs = site0 + n / 3;
-        const int col = n % 3;
-        if (m0 >= 8 * COUT || gs >= s_end) continue;
+        const int sn = n / 3, col = n % 3;
+        if (m0 >= 8 * COUT) continue;
         const int c = m0 / 8, sp = (m0 % 8) / 2;  // channel, first of two spins
         if constexpr (COUT == 1) {
-            // FP32 odd spinor: component k = spin * 3 + colour in vector k / 2, half k % 2
-            float *base = static_cast<float *>(yo.d);
-            const long cb = gs - g.Vh;
+            // [site][k = spin * 3 + colour][re, im] in FP32
+            float *Yf = reinterpret_cast<float *>(smem);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int k = (sp + h) * 3 + col;
-                float *dst = base + ((long)(k / 2) * yo.stride + cb) * 4 + (k % 2) * 2;
-                *reinterpret_cast<float2 *>(dst) = make_float2(acc[j][2 * h], acc[j][2 * h + 1]);
+                *reinterpret_cast<float2 *>(&Yf[(sn * 12 + k) * 2]) = make_float2(acc[j][2 * h], acc[j][2 * h + 1]);
             }
         } else {
-            uint32_t *dst = reinterpret_cast<uint32_t *>(y.d + ((long)(c * 3 + col) * y.stride + gs)) + sp;
-            *reinterpret_cast<uint2 *>(dst) = make_uint2(f2bf2(acc[j][0], acc[j][1]), f2bf2(acc[j][2], acc[j][3]));
+            // [channel][site][12 words], as in the activation layout
+            uint32_t *Ys = reinterpret_cast<uint32_t *>(smem);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                Ys[(c * NL_S + sn) * 12 + (sp + h) * 3 + col] = f2bf2(acc[j][2 * h], acc[j][2 * h + 1]);
+        }
+    }
+    __syncthreads();
+    if constexpr (COUT == 1) {
+        // FP32 odd spinor: vector kv of site cb holds components 2 kv and 2 kv + 1
+        const float *Yf = reinterpret_cast<const float *>(smem);
+        for (int v = threadIdx.x; v < 6 * NL_S; v += blockDim.x) {
+            const int kv = v / NL_S, sn = v % NL_S;
+            const long gs = site0 + sn;
+            if (gs >= s_end) continue;
+            reinterpret_cast<float4 *>(yo.d)[(long)kv * yo.stride + (gs - g.Vh)] =
+                *reinterpret_cast<const float4 *>(&Yf[(sn * 12 + 2 * kv) * 2]);
+        }
+    } else {
+        // per channel, the tile's 64 sites are 192 contiguous 16-byte vectors
+        const uint4 *Yv = reinterpret_cast<const uint4 *>(smem);
+        for (int v = threadIdx.x; v < COUT * NL_S * 3; v += blockDim.x) {
+            const int c = v / (NL_S * 3), o = v % (NL_S * 3);
+            const long gs = site0 + o / 3;
+            if (gs >= s_end) continue;
+            reinterpret_cast<uint4 *>(y.d + ((long)c * y.stride + site0) * 12)[o] = Yv[v];
         }
     }
 }
@@ -513,8 +542,6 @@ __global__ void __launch_bounds__(256) nn_wgrad_kernel(Geom g, Act x, Act dy, Nn
     constexpr int NSTR = NN_N + NN_PAD;
     constexpr int MT = MD / 16, KT = KD / 16, NTILE = MT * KT;
     constexpr int PER_WAVE = (NTILE + 3) / 4;
-    constexpr int NCH = CIN >= 4 ? CIN / 4 : 1, NS = CIN >= 4 ? 4 : 1;
-    constexpr int DCH = COUT >= 4 ? COUT / 4 : 1, DS = COUT >= 4 ? 4 : 1;
     static_assert(NN_S == NL_S, "one tile size");
     __shared__ __attribute__((aligned(16))) uint16_t Dl[MD][NSTR];
     __shared__ __attribute__((aligned(16))) uint16_t Zt[KD][NSTR];
@@ -522,8 +549,6 @@ __global__ void __launch_bounds__(256) nn_wgrad_kernel(Geom g, Act x, Act dy, Nn
     const int d = blockIdx.y;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
-    const int c0 = CIN >= 4 ? q * NCH : 0, s0 = CIN >= 4 ? 0 : q;
-    const int e0 = COUT >= 4 ? q * DCH : 0, t0 = COUT >= 4 ? 0 : q;
     long sb = 0, se = V;
     if (COUT == 1) sb = g.Vh;  // the output adjoint lives on odd sites
     if (CIN == 1) {            // odd-supported input: d = 0 feeds odd sites, hops even ones
@@ -544,46 +569,37 @@ __global__ void __launch_bounds__(256) nn_wgrad_kernel(Geom g, Act x, Act dy, Nn
         __syncthreads();
         SiteCtx sc;
         site_ctx(g, site0 + sl, se, sc);
-        Stg<NCH, NS> st;
-        stg_load<NCH, NS>(g, x, L, t_bc, d, CIN == 1, sc, c0, s0, st);
-        // output adjoint at the site itself
+        Stg<CIN> st;
+        stg_load<CIN>(g, x, L, t_bc, d, CIN == 1, sc, q, st);
+        // output adjoint at the site itself: lane q holds spin q of every channel
         {
             const long gs = site0 + sl;
 #pragma unroll
-            for (int j = 0; j < DCH; ++j)
+            for (int c = 0; c < COUT; ++c) {
+                W3 v = {0u, 0u, 0u};
+                if (sc.valid) v = ld3(dy.d + ((long)c * dy.stride + gs) * 12 + 3 * q);
+                const uint32_t w[3] = {v.x, v.y, v.z};
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const int n = sl * 3 + a;
-                    if constexpr (DS == 4) {
-                        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                        if (sc.valid) v = dy.d[((long)(e0 + j) * 3 + a) * dy.stride + gs];
-                        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) {
-                            Dl[(e0 + j) * 8 + 2 * s][n] = (uint16_t)(w[s] & 0xffffu);
-                            Dl[(e0 + j) * 8 + 2 * s + 1][n] = (uint16_t)(w[s] >> 16);
-                        }
-                    } else {
-                        uint32_t w = 0u;
-                        if (sc.valid) w = reinterpret_cast<const uint32_t *>(dy.d + (long)a * dy.stride + gs)[t0];
-                        Dl[2 * t0][n] = (uint16_t)(w & 0xffffu);
-                        Dl[2 * t0 + 1][n] = (uint16_t)(w >> 16);
-                    }
+                    Dl[c * 8 + 2 * q][sl * 3 + a] = (uint16_t)(w[a] & 0xffffu);
+                    Dl[c * 8 + 2 * q + 1][sl * 3 + a] = (uint16_t)(w[a] >> 16);
                 }
+            }
         }
         {
-            uint32_t z[NCH][3][NS];
-            stg_transport<NCH, NS>(st, z);
+            const Wop w = make_wop(st.ident, st.dag, st.bc, st.w, q);
 #pragma unroll
-            for (int j = 0; j < NCH; ++j)
+            for (int c = 0; c < CIN; ++c) {
+                uint32_t z[4];
+                transport4(w, st.psi[c], z);
+                if (q < 3) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int s = 0; s < NS; ++s) {
-                        const int k = (c0 + j) * 8 + 2 * (s0 + s);
-                        Zt[k][sl * 3 + a] = (uint16_t)(z[j][a][s] & 0xffffu);
-                        Zt[k + 1][sl * 3 + a] = (uint16_t)(z[j][a][s] >> 16);
+                    for (int s = 0; s < 4; ++s) {
+                        Zt[c * 8 + 2 * s][sl * 3 + q] = (uint16_t)(z[s] & 0xffffu);
+                        Zt[c * 8 + 2 * s + 1][sl * 3 + q] = (uint16_t)(z[s] >> 16);
                     }
+                }
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -621,10 +637,13 @@ template <int P> __global__ void nn_embed_kernel(SpinorPtr r, Act a, long Vh)
     if (s >= Vh) return;
     cx<float> v[12];
     load_spinor<P>(r, 0, s, v);
+    uint32_t w[12];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-        a.d[(long)c * a.stride + Vh + s] = make_uint4(f2bf2(v[c].re, v[c].im), f2bf2(v[3 + c].re, v[3 + c].im),
-                                                     f2bf2(v[6 + c].re, v[6 + c].im), f2bf2(v[9 + c].re, v[9 + c].im));
+    for (int k = 0; k < 12; ++k) w[k] = f2bf2(v[k].re, v[k].im);  // spin-major: word 3 s + colour
+    uint4 *dst = reinterpret_cast<uint4 *>(a.d + (Vh + s) * 12);
+    dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    dst[2] = make_uint4(w[8], w[9], w[10], w[11]);
 }
 
 // sum of the per-block partials: P[i] = sum_b partial[b][i]
@@ -753,10 +772,9 @@ int nn_links(tmx_ctx *c, NnLinks &L)
 {
     PcState &s = *c->pc;
     const long Vh = c->Vh;
-    if (!s.la) {
-        if (hipMalloc(&s.la, 8 * Vh * sizeof(uint4)) != hipSuccess ||
-            hipMalloc(&s.lb, 8 * Vh * sizeof(uint4)) != hipSuccess ||
-            hipMalloc(&s.lc, 8 * Vh * sizeof(uint32_t)) != hipSuccess) {
+    if (!s.lrow) {
+        if (hipMalloc(&s.lrow, 72 * Vh * sizeof(uint32_t)) != hipSuccess ||
+            hipMalloc(&s.lcol, 72 * Vh * sizeof(uint32_t)) != hipSuccess) {
             (void)hipGetLastError();
             return set_err(c, TMX_ENOMEM, "network links");
         }
@@ -765,12 +783,12 @@ int nn_links(tmx_ctx *c, NnLinks &L)
         if (!c->gauge_loaded) return set_err(c, TMX_ENOTLOADED, "no gauge field loaded");
         const long n = 8 * Vh;
         hipLaunchKernelGGL(nn_links_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
-                           static_cast<const double2 *>(c->links[F64]), s.la, s.lb, s.lc, Vh);
+                           static_cast<const double2 *>(c->links[F64]), s.lrow, s.lcol, Vh);
         int r = hip_err(c, hipGetLastError(), "network links");
         if (r) return r;
         s.links_upload = c->uploads;
     }
-    L = NnLinks{s.la, s.lb, s.lc, Vh};
+    L = NnLinks{s.lrow, s.lcol, Vh};
     return TMX_OK;
 }
 
@@ -782,7 +800,8 @@ int launch_layer(tmx_ctx *c, int cin, int cout, Act x, Act y, SpinorPtr yo, cons
     if (r) return r;
     const long V = 2 * c->Vh;
     const long s_begin = cout == 1 ? c->Vh : 0;
-    const long ntiles = (V - s_begin + NL_S - 1) / NL_S;
+    // one-channel input: tiles of the two parities interleaved (see the kernel)
+    const long ntiles = cin == 1 ? 2 * ((c->Vh + NL_S - 1) / NL_S) : (V - s_begin + NL_S - 1) / NL_S;
     const dim3 grid((unsigned)ntiles), block(256);
     const int tb = c->par.t_bc, xcd = c->xcd_remap;
     kstat_begin(c, "NN_" + std::to_string(cin) + "x" + std::to_string(cout));
@@ -825,8 +844,8 @@ int launch_wgrad(tmx_ctx *c, int cin, int cout, Act x, Act dy, float *partial)
 Act act(tmx_ctx *c, const std::string &name, int ch)
 {
     const long V = 2 * c->Vh;
-    void *d = ws_get(c, "nn_" + name, (size_t)3 * ch * V * sizeof(uint4));
-    return Act{static_cast<uint4 *>(d), V};
+    void *d = ws_get(c, "nn_" + name, (size_t)ch * V * 48);
+    return Act{static_cast<uint32_t *>(d), V};
 }
 
 // odd field r (precision pr) -> one-channel activation supported on odd sites
@@ -1166,9 +1185,8 @@ void tmx_pc_free(tmx_ctx *c)
         dev_free(s.Wf[l]);
         dev_free(s.Wa[l]);
     }
-    dev_free(s.la);
-    dev_free(s.lb);
-    dev_free(s.lc);
+    dev_free(s.lrow);
+    dev_free(s.lcol);
     delete c->pc;
     c->pc = nullptr;
 }
