@@ -12,8 +12,10 @@ epsbar = 0.1315; links U = proj_SU3(exp(i 0.25 H)), seed 4):
   * mixed-precision CG (FP32 and FP16-storage inner iterations, FP64
     reliable updates) to the same FP64 true residual;
   * CG preconditioned by the learned network K K^dagger (FP16 inner, FP64
-    reliable updates; the network is trained once, before the timed region,
-    on 256 (source, solution) pairs from the plain solver on a 16^3x32 field);
+    reliable updates; the network is trained before the timed region on 256
+    (source, solution) pairs from the plain solver on a 16^3x32 field, the
+    best of three initialisations by preconditioned-CG iterations on a
+    held-out source of that field);
   * a 12-shift multishift solve of the two-flavour normal operator (FP32
     multishift CG, then FP64-reliable refinement per shift; shifts
     lambda_max * 10^(-5 + 5k/11)) and 12 Gaussian right-hand sides of the
@@ -76,8 +78,16 @@ def cpu_baseline(dims, U, b, napply):
                          f"({dt:.3f} s each, same model bytes as the GPU figure)"}
 
 
-def train_network(tmx, synth, npairs, epochs):
-    """Train the preconditioner on a 16^3x32 field (seed 2) from (b, Mhat^{-1} b) pairs."""
+def train_network(tmx, synth, npairs, epochs, inits=3):
+    """Train the preconditioner on a 16^3x32 field (seed 2) from (b, Mhat^{-1} b) pairs.
+
+    The residual loss is an average over Gaussian sources and does not see
+    how the network treats the lowest modes, which set the iteration count
+    of preconditioned CG; training runs from `inits` random initialisations
+    are therefore compared by that count on a held-out source of the same
+    training field, and the best is kept.  Nothing of the benchmark field
+    enters the choice.
+    """
     import numpy as np
     import torch
 
@@ -94,19 +104,28 @@ def train_network(tmx, synth, npairs, epochs):
         xk = torch.zeros(n1, dtype=torch.complex128, device="cuda")
         tc.solve_mhat(xk, bs[k * n1:(k + 1) * n1], dagger=0, op=1, tol=1e-10)
         xs[k * n1:(k + 1) * n1] = xk
+    bval = torch.from_numpy(synth.gaussian_cb_spinor(dims, 2, 10 ** 6).reshape(-1)).cuda()
     t1 = time.perf_counter()
-    rng = np.random.default_rng(3)
-    w0 = np.zeros(tc.pc_num_params(), dtype=np.float32)
-    # identity on the d = 0 path of every layer, N(0, 1e-2) elsewhere
-    from_oracle_free_init(w0, rng)
-    tc.pc_set_weights(w0)
-    losses = tc.pc_train(bs, xs, npairs, epochs=epochs, batch=8, lr=3e-3, seed=1, loss_kind=0)
-    w = tc.pc_get_weights()
+    runs, best = [], None
+    for init in range(inits):
+        w0 = np.zeros(tc.pc_num_params(), dtype=np.float32)
+        # identity on the d = 0 path of every layer, N(0, 1e-2) elsewhere
+        from_oracle_free_init(w0, np.random.default_rng(3 + init))
+        tc.pc_set_weights(w0)
+        losses = tc.pc_train(bs, xs, npairs, epochs=epochs, batch=8, lr=3e-3, seed=1, loss_kind=0)
+        x = torch.zeros_like(bval)
+        rc, info = tc.solve(x, bval, 1, kind=tmx.TMX_SOLVER_PCG_NN, op=1, tol=1e-10, inner_prec=2)
+        it = info[0]["iters"] if rc == tmx.TMX_OK else 10 ** 9
+        runs.append({"init": init, "loss_first": float(losses[0]), "loss_last": float(losses[-1]), "val_pcg_iters": it})
+        if best is None or it < best[0]:
+            best = (it, tc.pc_get_weights())
+    x = torch.zeros_like(bval)
+    rc, info = tc.solve(x, bval, 1, kind=tmx.TMX_SOLVER_MPCG_F16, op=1, tol=1e-10)
     tc.close()
     t2 = time.perf_counter()
-    return w, {"pairs": npairs, "lattice": list(dims), "pair_seconds": round(t1 - t0, 1),
-               "train_seconds": round(t2 - t1, 1), "epochs": epochs,
-               "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+    return best[1], {"pairs": npairs, "lattice": list(dims), "pair_seconds": round(t1 - t0, 1),
+                     "train_seconds": round(t2 - t1, 1), "epochs": epochs, "runs": runs,
+                     "val_cg_iters": info[0]["iters"]}
 
 
 def from_oracle_free_init(w, rng):
@@ -188,6 +207,12 @@ def main():
         o = torch.zeros_like(bd)
         for _ in range(5):
             ctx.pc_apply(o, bd, 0)
+        # a device copy of 2 GiB, whose FETCH_SIZE / WRITE_SIZE calibrate the counters
+        a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")
+        a.fill_(1.0)
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "nn", "lattice": list(dims), "applies": 5}), flush=True)
         ctx.close()
@@ -344,6 +369,7 @@ def main():
         "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in ks.items()},
         "roofline": roofline,
         "roofline_nn_layer": nn_roof,
+        "learned_pc_training": train_info,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")

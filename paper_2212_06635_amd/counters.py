@@ -7,7 +7,7 @@ kernels``, which ends with device copies of a 2 GiB buffer):
     rocprofv3 --kernel-trace --stats --output-format csv -d D/p_k -o k -- python3 bench.py --mode kernels
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d D/p_f -o f -- python3 bench.py --mode kernels
     rocprofv3 --pmc WRITE_SIZE --output-format csv -d D/p_w -o w -- python3 bench.py --mode kernels
-    python3 -m paper_2212_06635_amd.counters D out.txt
+    python3 -m paper_2212_06635_amd.counters stencil D out.txt
 
 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what they read for
 the plain copy of known size.  The summary carries a digest of the kernel
@@ -73,6 +73,16 @@ def _pmc(path, counter):
     return {k: sum(v) / len(v) for k, v in agg.items()}
 
 
+def _copy_kib(path, counter):
+    """Counter value (KiB) of the 2 GiB calibration copies: the median of the
+    three largest copy dispatches (smaller copies in the same run are not
+    the calibration)."""
+    vals = sorted(float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+                  if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"])
+    top = vals[-3:]
+    return top[len(top) // 2]
+
+
 def _find(d, suffix):
     for root, _, files in os.walk(d):
         for f in files:
@@ -83,10 +93,10 @@ def _find(d, suffix):
 
 def summarize(d: str, vh: int) -> str:
     st = _stats(_find(os.path.join(d, "p_k"), "kernel_stats.csv"))
-    f = _pmc(_find(os.path.join(d, "p_f"), "counter_collection.csv"), "FETCH_SIZE")
-    w = _pmc(_find(os.path.join(d, "p_w"), "counter_collection.csv"), "WRITE_SIZE")
-    copy_f = next(v for k, v in f.items() if "copyBuffer" in k)
-    copy_w = next(v for k, v in w.items() if "copyBuffer" in k)
+    pf = _find(os.path.join(d, "p_f"), "counter_collection.csv")
+    pw = _find(os.path.join(d, "p_w"), "counter_collection.csv")
+    f, w = _pmc(pf, "FETCH_SIZE"), _pmc(pw, "WRITE_SIZE")
+    copy_f, copy_w = _copy_kib(pf, "FETCH_SIZE"), _copy_kib(pw, "WRITE_SIZE")
     sf, sw = COPY_BYTES / 1024 / copy_f, COPY_BYTES / 1024 / copy_w
     copy_ns = next(v for k, v in st.items() if "copyBuffer" in k)[1]
     lines = [
@@ -95,7 +105,7 @@ def summarize(d: str, vh: int) -> str:
         "#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/p_k -o k -- python3 <repo>/bench.py --mode kernels",
         "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/p_f -o f -- python3 <repo>/bench.py --mode kernels",
         "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/p_w -o w -- python3 <repo>/bench.py --mode kernels",
-        "#   python3 -m paper_2212_06635_amd.counters <dir> <this file>",
+        "#   python3 -m paper_2212_06635_amd.counters stencil <dir> <this file>",
         "# bench.py --mode kernels: 10 Mhat applications per precision on the 32^3x64 field (eps 0.25, seed 4),",
         "#   then 3 device copies of a 2 GiB buffer",
         f"# counter calibration on the 2 GiB copy: FETCH_SIZE {copy_f:.1f} KiB, WRITE_SIZE {copy_w:.1f} KiB per dispatch",
@@ -142,11 +152,69 @@ def read_traffic(path: str, label: str):
     return None
 
 
+def kernel_table(stats_csv: str, title: str, command: str) -> str:
+    """Per-kernel time table of one rocprofv3 --kernel-trace --stats run."""
+    rows = []
+    for r in csv.DictReader(open(stats_csv)):
+        rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]), float(r["TotalDurationNs"]),
+                     float(r["Percentage"])))
+    rows.sort(key=lambda t: -t[3])
+    lines = [f"# {title}", f"# command: {command}", "",
+             f"{'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'%':>6s}  kernel"]
+    for name, calls, avg, tot, pct in rows:
+        short = name.split("(")[0].replace("void ", "")
+        lines.append(f"{calls:6d} {avg / 1e3:10.1f} {tot / 1e6:10.2f} {pct:6.2f}  {short}")
+    return "\n".join(lines) + "\n"
+
+
+def network(d: str, v: int) -> str:
+    """Network layer kernels: time, counter traffic and matrix-core rate."""
+    st = _stats(_find(os.path.join(d, "p_k"), "kernel_stats.csv"))
+    pf = _find(os.path.join(d, "p_f"), "counter_collection.csv")
+    pw = _find(os.path.join(d, "p_w"), "counter_collection.csv")
+    f, w = _pmc(pf, "FETCH_SIZE"), _pmc(pw, "WRITE_SIZE")
+    copy_f, copy_w = _copy_kib(pf, "FETCH_SIZE"), _copy_kib(pw, "WRITE_SIZE")
+    sf, sw = COPY_BYTES / 1024 / copy_f, COPY_BYTES / 1024 / copy_w
+    lines = [
+        f"# learned-preconditioner layer kernels, V = {v} sites, MI355X",
+        "# commands (from /tmp, TMPDIR=/tmp; <repo> = repository root):",
+        "#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/p_k -o k -- python3 <repo>/bench.py --mode nn",
+        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/p_f -o f -- python3 <repo>/bench.py --mode nn",
+        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/p_w -o w -- python3 <repo>/bench.py --mode nn",
+        "#   python3 -m paper_2212_06635_amd.counters network <dir> <this file>",
+        "# bench.py --mode nn: 5 applications of K (layers 1->8, 8->8, 8->8, 8->1) on the 32^3x64 field,",
+        "#   then 3 device copies of a 2 GiB buffer (counter calibration)",
+        f"# FETCH scale {sf:.3f}, WRITE scale {sw:.3f}; matrix-core work: 2 x 64 x 64 x 27 flops per site",
+        "#   for the 8->8 layer (9 paths x 3 colours of a real 64 x 64 product)",
+        "",
+        f"{'kernel':10s} {'calls':>5s} {'avg_us':>8s} {'fetch_MB':>9s} {'write_MB':>9s} {'GB/s':>7s} {'TFLOP/s':>8s}",
+    ]
+    for name, (calls, avg) in sorted(st.items()):
+        if "nn_layer_kernel" not in name:
+            continue
+        tag = name[name.index("<") + 1:name.index(">")].replace(", ", "x")
+        fe = f.get(name, 0.0) * 1024 * sf
+        wr = w.get(name, 0.0) * 1024 * sw
+        tf = 2 * 64 * 64 * 27 * v / (avg * 1e-9) / 1e12 if tag == "8x8" else float("nan")
+        lines.append(f"NN_{tag:7s} {calls:5d} {avg / 1e3:8.1f} {fe / 1e6:9.1f} {wr / 1e6:9.1f} "
+                     f"{(fe + wr) / (avg * 1e-9) / 1e9:7.1f} {tf:8.1f}")
+    return "\n".join(lines) + "\n"
+
+
 if __name__ == "__main__":
-    if len(sys.argv) != 3:
-        print("usage: python3 -m paper_2212_06635_amd.counters <rocprof output dir> <summary file>", file=sys.stderr)
+    usage = ("usage: python3 -m paper_2212_06635_amd.counters stencil <rocprof dir> <summary>\n"
+             "       python3 -m paper_2212_06635_amd.counters network <rocprof dir> <summary>\n"
+             "       python3 -m paper_2212_06635_amd.counters stats <kernel_stats.csv> <summary> <title> <command>")
+    a = sys.argv[1:]
+    if len(a) >= 3 and a[0] == "stencil":
+        txt = summarize(a[1], 1048576)
+    elif len(a) >= 3 and a[0] == "network":
+        txt = network(a[1], 2097152)
+    elif len(a) == 5 and a[0] == "stats":
+        txt = kernel_table(a[1], a[3], a[4])
+    else:
+        print(usage, file=sys.stderr)
         sys.exit(2)
-    txt = summarize(sys.argv[1], 1048576)
-    with open(sys.argv[2], "w") as fh:
+    with open(a[2], "w") as fh:
         fh.write(txt)
     print(txt, end="")
