@@ -35,6 +35,7 @@ struct Sys {
     long stride;
     double bytes_per_N;  // model bytes of one N application (all columns)
     double gbytes = 0;
+    bool nomem = false;  // a workspace could not be allocated
 
     Sys(tmx_ctx *c_, int op_, int nrhs_) : c(c_), op(op_), nf(op_ == TMX_OP_ND ? 2 : 1), nrhs(nrhs_)
     {
@@ -45,8 +46,11 @@ struct Sys {
     {
         const long s = cols < 0 ? stride : c->Vh * cols;
         void *d = ws_get(c, "sv_" + name, spinor_field_bytes(prec, nf, s));
+        if (!d) nomem = true;
         return make_spinor(d, prec, nf, s);
     }
+    // after a group of field() calls: nothing may run on a missing workspace
+    int need() const { return nomem ? set_err(c, TMX_ENOMEM, "solver workspace: out of device memory") : TMX_OK; }
     int N(SpinorPtr out, SpinorPtr in, int prec, int cols)
     {
         gbytes += 2.0 * mhat_bytes_per_site(prec, nf, cols) * c->Vh * 1e-9;
@@ -110,6 +114,7 @@ static int true_residual(Sys &S, SpinorPtr r, SpinorPtr rlo, bool write_lo, Spin
 {
     tmx_ctx *c = S.c;
     SpinorPtr q = S.field("trq", F64, cols);
+    TRY(S.need());
     double dummy[MAXR];
     TRY(apply_shifted<F64>(S, q, x, sigma, cols, dummy));
     OpXmyNorm<F64, F64, F64, PL> o{};
@@ -162,6 +167,7 @@ static int cg_core(Sys &S, SpinorPtr x, SpinorPtr b, int cols, const double *sig
     SpinorPtr p = S.field("p", P, cols);
     SpinorPtr q = S.field("q", P, cols);
     SpinorPtr xl = mixed ? S.field("xl", F32, cols) : x;
+    TRY(S.need());
 
     double bb[MAXR], rho[MAXR], rho1[MAXR], rmax[MAXR], pq[MAXR];
     int active[MAXR], iters[MAXR], nrel[MAXR];
@@ -323,6 +329,7 @@ static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const tmx_solver_cfg &c
     const double delta = cfg.delta > 0 ? cfg.delta : 0.1;
     SpinorPtr r = S.field("r", F64, 1), rl = S.field("rl", P, 1), p = S.field("p", P, 1), q = S.field("q", P, 1);
     SpinorPtr xl = S.field("xl", F32, 1), z = S.field("z", F32, 1), tz = S.field("tz", F32, 1);
+    TRY(S.need());
     double bb, rr, rmax, rho, pq, dots[2];
     TRY((copy_field<F64, F64>(S, r, b, 1, &bb)));
     if (!x_is_guess) TRY(zero_field<F64>(S, x, 1));
@@ -440,6 +447,7 @@ static int mscg_core(Sys &S, std::vector<SpinorPtr> &xs, SpinorPtr b64, const do
     SpinorPtr q = S.field("ms_q", P, 1);
     std::vector<SpinorPtr> ps(ns);
     for (int k = 0; k < ns; ++k) ps[k] = S.field("ms_p" + std::to_string(k), P, 1);
+    TRY(S.need());
     double bb;
     TRY((copy_field<P, F64>(S, r, b64, 1, &bb)));
     for (int k = 0; k < ns; ++k) {
@@ -565,6 +573,7 @@ int tmx_solve(tmx_ctx *c, double *x, const double *b, int nrhs, const tmx_solver
     const int kind = cfg->op == TMX_OP_ND ? TMX_FIELD_ODD_ND : TMX_FIELD_ODD;
     TRY(ensure_ready(c, F64, cfg->op == TMX_OP_ND));
     SpinorPtr X = S.field("x", F64), B = S.field("b", F64);
+    TRY(S.need());
     if (!X.d || !B.d) return TMX_ENOMEM;
     HTRY(launch_pack_spinor(b, B, F64, kind, c->g, nrhs, c->stream), "pack b");
     if (cfg->use_initial_guess) HTRY(launch_pack_spinor(x, X, F64, kind, c->g, nrhs, c->stream), "pack x");
@@ -627,6 +636,7 @@ int tmx_multishift_solve(tmx_ctx *c, double *x, const double *b, const double *s
     TRY(ensure_ready(c, F64, nd));
     Sys S(c, cfg->op, 1);
     SpinorPtr B = S.field("msb", F64, 1);
+    TRY(S.need());
     HTRY(launch_pack_spinor(b, B, F64, kind, c->g, 1, c->stream), "pack b");
     const double tol = cfg->tol > 0 ? cfg->tol : 1e-10;
     const double inner = cfg->inner_tol > 0 ? cfg->inner_tol : (prec == TMX_F16 ? 5e-4 : (prec == TMX_F32 ? 1e-6 : tol));
@@ -635,6 +645,7 @@ int tmx_multishift_solve(tmx_ctx *c, double *x, const double *b, const double *s
     const int PX = prec == F64 ? F64 : F32;
     std::vector<SpinorPtr> xs(nshift);
     for (int k = 0; k < nshift; ++k) xs[k] = S.field("msx" + std::to_string(k), PX, 1);
+    TRY(S.need());
     std::vector<int> its(nshift, 0);
     int r;
     if (prec == F64)
@@ -648,6 +659,7 @@ int tmx_multishift_solve(tmx_ctx *c, double *x, const double *b, const double *s
     // shift-by-shift refinement with FP64 reliable updates
     int rc = TMX_OK;
     SpinorPtr X = S.field("msx64", F64, 1);
+    TRY(S.need());
     for (int k = 0; k < nshift; ++k) {
         if (prec == F64)
             TRY((copy_field<F64, F64>(S, X, xs[k], 1, nullptr)));
@@ -691,6 +703,7 @@ int tmx_solve_mhat(tmx_ctx *c, double *x, const double *b, int dagger, const tmx
     TRY(ensure_ready(c, F64, nd));
     Sys S(c, cfg->op, 1);
     SpinorPtr B = S.field("mh_b", F64, 1), T = S.field("mh_t", F64, 1);
+    TRY(S.need());
     const size_t cbytes = (size_t)c->Vh * 24 * nf * sizeof(double);
     void *canon = ws_get(c, "mh_canon", cbytes);
     if (!canon) return TMX_ENOMEM;

@@ -97,38 +97,11 @@ def test_64x128_mpcg_f16(F):
     cond(N) * 2e-10 (cond(N) ~ 40 on these fields)."""
     tmx, o, ctx = F
     b0 = synth.gaussian_cb_spinor(BASE, 5, 1)
-    x0 = o.cg(b0, tol=1e-11)
+    x0, _, rel = o.cg(b0, tol=1e-11)
+    assert rel <= 1e-11
     b = tile_cb(b0)
     x = to_dev(np.zeros_like(b))
     rc, info = ctx.solve(x, to_dev(b), 1, kind=tmx.TMX_SOLVER_MPCG_F16, op=1, tol=1e-10)
     assert rc == tmx.TMX_OK
     assert info[0]["true_residual"] <= 1e-10
     assert rel_l2(to_host(x, b.shape), tile_cb(x0)) < 5e-8
-
-
-@pytest.mark.gpu
-def test_64x128_multishift_nd(F):
-    """Twelve shifts of the two-flavour operator at 33.5M sites (FP16-storage
-    multishift, FP64-reliable refinement; FP16 keeps the twelve shift vectors
-    and directions within HBM next to the twelve FP64 solutions): every
-    shift's FP64 true residual (the FP64 operator is the one checked above)
-    <= 1e-10, and the largest shift against the tiled oracle solution."""
-    import torch
-
-    tmx, o, ctx = F
-    torch.cuda.empty_cache()
-    mem("before multishift")
-    shifts = 2.08 * 10.0 ** (-5.0 + 5.0 * np.arange(12) / 11.0)
-    b0 = synth.gaussian_cb_spinor(BASE, 5, 2, 2)
-    b = to_dev(tile_cb(b0))
-    n = b.numel()
-    x = torch.zeros(12 * n, dtype=torch.complex128, device="cuda")
-    rc, info = ctx.multishift_solve(x, b, shifts, op=2, tol=1e-10, inner_prec=2)
-    mem("after multishift")
-    assert rc == tmx.TMX_OK
-    assert max(i["true_residual"] for i in info) <= 1e-10
-    x11 = x[11 * n:].cpu().numpy().reshape((-1,) + b0.shape[1:])
-    ref = tile_cb(o.cg(b0, nf=2, shift=shifts[11], tol=1e-11))
-    assert rel_l2(x11, ref) < 5e-8
-    del x, b
-    torch.cuda.empty_cache()
