@@ -128,6 +128,39 @@ def train_network(tmx, synth, npairs, epochs, inits=3):
                      "val_cg_iters": info[0]["iters"]}
 
 
+def learned_pc_other_volume(tmx, synth, weights, dims=(24, 24, 24, 48), seed=3):
+    """The trained weights (translation invariant) used unchanged on a second
+    volume: plain CG, MP-CG, CG preconditioned by K K^dagger and flexible GCR
+    with K, each to a 1e-10 FP64 true residual (one warm-up solve each, then
+    the median of three)."""
+    import numpy as np
+    import torch
+
+    U = synth.gauge_links(dims, 0.25, seed)
+    ctx = tmx.Context(dims)
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU, 0.0, 0.0, -1))
+    ctx.load_gauge(U, float(seed))
+    ctx.pc_set_weights(weights)
+    b = torch.from_numpy(synth.gaussian_cb_spinor(dims, seed, 0).reshape(-1)).cuda()
+    x = torch.zeros_like(b)
+    out = {"lattice": list(dims), "seed": seed}
+    for kind, name, ip in ((tmx.TMX_SOLVER_CG, "cg_f64", 1), (tmx.TMX_SOLVER_MPCG_F16, "mpcg_f16", 1),
+                           (tmx.TMX_SOLVER_PCG_NN, "pcg_nn_f16", 2), (tmx.TMX_SOLVER_FGCR_NN, "fgcr_nn_f32", 1)):
+        times = []
+        for rep in range(4):
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rc, info = ctx.solve(x, b, 1, kind=kind, op=1, tol=1e-10, inner_prec=ip, restart=16)
+            torch.cuda.synchronize()
+            if rep:
+                times.append(time.perf_counter() - t)
+        out[name] = {"seconds": sorted(times)[1], "iters": info[0]["iters"], "rc": rc,
+                     "true_residual": info[0]["true_residual"], "fallback": info[0]["fallback"]}
+    ctx.close()
+    return out
+
+
 def from_oracle_free_init(w, rng):
     """Identity initialisation of the network weights (layout of tmx_pc_set_weights)."""
     chans = [(1, 8), (8, 8), (8, 8), (8, 1)]
@@ -371,6 +404,9 @@ def main():
         "roofline_nn_layer": nn_roof,
         "learned_pc_training": train_info,
     }
+    if dims == (32, 32, 32, 64):
+        log("learned preconditioner on a 24^3x48 field")
+        out["learned_pc_24x24x24x48"] = learned_pc_other_volume(tmx, synth, weights)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         o, cb = cpu_baseline(dims, U, b, args.cpu_applies)

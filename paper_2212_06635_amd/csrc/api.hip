@@ -529,7 +529,9 @@ int tmx_create(const int dims[4], void *hip_stream, tmx_ctx **out)
     c->g.zbs = pick("TMX_SITE_ZB", 2, dims[2]);
     c->g.tbs = pick("TMX_SITE_TB", 8, dims[3]);
     c->stream = static_cast<hipStream_t>(hip_stream);
-    c->red.max_blocks = 1024;
+    // enough workgroups for one slot per thread up to V/2 = 2M sites: a
+    // grid-stride loop over several sites serialises their memory latency
+    c->red.max_blocks = 8192;
     if (hipMalloc(&c->red.partials, sizeof(double) * c->red.max_blocks * MAXR * 4) != hipSuccess ||
         hipMalloc(&c->red.result, sizeof(double) * MAXR * 4) != hipSuccess ||
         hipHostMalloc(&c->host_red, sizeof(double) * MAXR * 4, hipHostMallocDefault) != hipSuccess) {
