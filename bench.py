@@ -307,12 +307,14 @@ def main():
         for kind, nm, ip in ((tmx.TMX_SOLVER_CG, "cg_f64", 1), (tmx.TMX_SOLVER_MPCG_F32, "mpcg_f32", 1),
                              (tmx.TMX_SOLVER_MPCG_F16, "mpcg_f16", 1), (tmx.TMX_SOLVER_PCG_NN, "pcg_nn_f16", 2)):
             x.zero_()
+            torch.cuda.synchronize()
             t = time.perf_counter()
             rc, info = ctx.solve(x, bd, 1, kind=kind, op=1, tol=1e-10, inner_prec=ip)
             solves[nm] = {"seconds": time.perf_counter() - t, "iters": info[0]["iters"],
                           "reliable_updates": info[0]["reliable_updates"],
                           "true_residual": info[0]["true_residual"], "fallback": info[0]["fallback"], "rc": rc}
         xs_ms.zero_()
+        torch.cuda.synchronize()
         t = time.perf_counter()
         rc, info = ctx.multishift_solve(xs_ms, b2d, shifts, op=2, tol=1e-10, inner_prec=1)
         solves["multishift_nd_12"] = {"seconds": time.perf_counter() - t, "rc": rc,
@@ -320,12 +322,14 @@ def main():
                                       "max_true_residual": max(i["true_residual"] for i in info)}
         for kind, nm in ((tmx.TMX_SOLVER_MPCG_F32, "mrhs_nd_12_mpcg_f32"), (tmx.TMX_SOLVER_MPCG_F16, "mrhs_nd_12_mpcg_f16")):
             x12.zero_()
+            torch.cuda.synchronize()
             t = time.perf_counter()
             rc, info = ctx.solve(x12, b12, 12, kind=kind, op=2, tol=1e-10)
             solves[nm] = {"seconds": time.perf_counter() - t, "rc": rc, "iters": max(i["iters"] for i in info),
                           "max_true_residual": max(i["true_residual"] for i in info)}
         # the same multishift with FP16-storage shift vectors
         xs_ms.zero_()
+        torch.cuda.synchronize()
         t = time.perf_counter()
         rc, info = ctx.multishift_solve(xs_ms, b2d, shifts, op=2, tol=1e-10, inner_prec=2)
         solves["multishift_nd_12_f16"] = {"seconds": time.perf_counter() - t, "rc": rc,
