@@ -245,18 +245,33 @@ __device__ __forceinline__ void load_seq(const void *base, long stride, long s, 
     }
 }
 
-template <int P, int N, typename R>
+// Store N reals of site s; NT marks the stores non-temporal (data written once
+// and not read again by the same kernel).
+template <int P, int N, typename R, bool NT = false>
 __device__ __forceinline__ void store_seq(void *base, long stride, long s, const R *o)
 {
     if constexpr (P == F64) {
-        double2 *b = static_cast<double2 *>(base);
+        ev_d2 *b = static_cast<ev_d2 *>(base);
 #pragma unroll
-        for (int k = 0; k < N / 2; ++k) b[k * stride + s] = make_double2(o[2 * k], o[2 * k + 1]);
+        for (int k = 0; k < N / 2; ++k) {
+            const ev_d2 v = {(double)o[2 * k], (double)o[2 * k + 1]};
+            if constexpr (NT)
+                __builtin_nontemporal_store(v, b + k * stride + s);
+            else
+                b[k * stride + s] = v;
+        }
     } else if constexpr (P == F32) {
-        float4 *b = static_cast<float4 *>(base);
+        ev_f4 *b = static_cast<ev_f4 *>(base);
 #pragma unroll
-        for (int k = 0; k < N / 4; ++k) b[k * stride + s] = make_float4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
+        for (int k = 0; k < N / 4; ++k) {
+            const ev_f4 v = {(float)o[4 * k], (float)o[4 * k + 1], (float)o[4 * k + 2], (float)o[4 * k + 3]};
+            if constexpr (NT)
+                __builtin_nontemporal_store(v, b + k * stride + s);
+            else
+                b[k * stride + s] = v;
+        }
     } else {
+        static_assert(!NT, "half-precision stores are not marked non-temporal");
         uint4 *b = static_cast<uint4 *>(base);
 #pragma unroll
         for (int k = 0; k < N / 8; ++k) {
@@ -323,7 +338,7 @@ __device__ __forceinline__ void load_spinor(const SpinorPtr &f, int flav, long s
     for (int k = 0; k < 12; ++k) v[k] = cx<R>{tmp[2 * k], tmp[2 * k + 1]};
 }
 
-template <int P, typename R>
+template <int P, bool NT = false, typename R>
 __device__ __forceinline__ void store_spinor(const SpinorPtr &f, int flav, long s, const cx<R> *v)
 {
     R tmp[24];
@@ -342,7 +357,7 @@ __device__ __forceinline__ void store_spinor(const SpinorPtr &f, int flav, long 
         for (int k = 0; k < 24; ++k) tmp[k] = (R)((float)tmp[k] * inv);
         f.nrm[flav * f.stride + s] = m;
     }
-    store_seq<P, 24>(base, f.stride, s, tmp);
+    store_seq<P, 24, R, NT>(base, f.stride, s, tmp);
 }
 
 // -------------------------------------------------------------------------
@@ -425,20 +440,21 @@ __device__ __forceinline__ void herm_apply(const void *base, long stride, long s
 }
 
 // Load the 6 components (2 spins x 3 colours) of chirality block chir of a
-// spinor: components 6 chir .. 6 chir + 5.
+// spinor: components 6 chir .. 6 chir + 5.  Used for the diagonal input of a
+// stencil, read once per launch: the loads are non-temporal.
 template <int P, typename R>
 __device__ __forceinline__ void load_chiral(const SpinorPtr &f, int flav, long s, int chir, cx<R> *v)
 {
     const char *base = static_cast<const char *>(f.d) + (size_t)flav * spinor_vecs<P>() * f.stride * 16;
     R t[12];
     if constexpr (P == F64) {
-        load_seq<P, 12>(base + (size_t)6 * chir * f.stride * 16, f.stride, s, t);
+        load_seq<P, 12, R, true>(base + (size_t)6 * chir * f.stride * 16, f.stride, s, t);
     } else if constexpr (P == F32) {
-        load_seq<P, 12>(base + (size_t)3 * chir * f.stride * 16, f.stride, s, t);
+        load_seq<P, 12, R, true>(base + (size_t)3 * chir * f.stride * 16, f.stride, s, t);
     } else {
         // halves 12 chir .. 12 chir + 11 live in 16-byte vectors chir and chir + 1
         R w[16];
-        load_seq<P, 16>(base + (size_t)chir * f.stride * 16, f.stride, s, w);
+        load_seq<P, 16, R, true>(base + (size_t)chir * f.stride * 16, f.stride, s, w);
         const float sc = f.nrm[flav * f.stride + s];
 #pragma unroll
         for (int k = 0; k < 12; ++k) t[k] = (chir ? w[k + 4] : w[k]) * sc;
