@@ -99,7 +99,7 @@ typedef struct {
     int op;             /* TMX_OP_PLUS / TMX_OP_MINUS / TMX_OP_ND */
     double tol;         /* relative 2-norm of the FP64 true residual, e.g. 1e-10 */
     int maxiter;        /* iteration cap (per stage) */
-    double delta;       /* reliable-update trigger (0 => 0.1) */
+    double delta;       /* reliable-update trigger (0 => 0.01 FP32, 0.03 FP16 iterations) */
     int restart;        /* FGCR restart length m (0 => 16) */
     int use_initial_guess; /* 1: x holds the start vector on entry */
     double inner_tol;   /* multishift: low-precision stage tolerance (0 => 1e-6 / 5e-4) */

@@ -152,6 +152,14 @@ template <int PD> static int zero_field(Sys &S, SpinorPtr d, int cols)
 // --------------------------------------------------------------------------
 // CG / MP-CG on N + sigma_k for `cols` columns (x, b FP64 internal)
 // --------------------------------------------------------------------------
+// Default reliable-update trigger for iterations in precision P.  Between
+// updates the iterated residual is trusted down to a drop of delta; its
+// relative error then is about u / delta, u the storage rounding unit (6e-8
+// FP32; 5e-4 FP16 with one scale per site), so delta = 0.01 (FP32) and 0.03
+// (FP16) keep that error at 2 % or less while needing fewer FP64 residual
+// recomputations than delta = 0.1 (one per decade of residual).
+template <int P> constexpr double default_delta() { return P == F16 ? 0.03 : 0.01; }
+
 template <int P>
 static int cg_core(Sys &S, SpinorPtr x, SpinorPtr b, int cols, const double *sigma, const tmx_solver_cfg &cfg,
                    bool x_is_guess, tmx_info *info)
@@ -159,7 +167,7 @@ static int cg_core(Sys &S, SpinorPtr x, SpinorPtr b, int cols, const double *sig
     tmx_ctx *c = S.c;
     const double tol = cfg.tol > 0 ? cfg.tol : 1e-10;
     const int maxiter = cfg.maxiter > 0 ? cfg.maxiter : 10000;
-    const double delta = cfg.delta > 0 ? cfg.delta : 0.1;
+    const double delta = cfg.delta > 0 ? cfg.delta : default_delta<P>();
     constexpr bool mixed = P != F64;
 
     SpinorPtr r = S.field("r", F64, cols);
@@ -326,7 +334,7 @@ static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const tmx_solver_cfg &c
     tmx_ctx *c = S.c;
     const double tol = cfg.tol > 0 ? cfg.tol : 1e-10;
     const int maxiter = cfg.maxiter > 0 ? cfg.maxiter : 10000;
-    const double delta = cfg.delta > 0 ? cfg.delta : 0.1;
+    const double delta = cfg.delta > 0 ? cfg.delta : default_delta<P>();
     SpinorPtr r = S.field("r", F64, 1), rl = S.field("rl", P, 1), p = S.field("p", P, 1), q = S.field("q", P, 1);
     SpinorPtr xl = S.field("xl", F32, 1), z = S.field("z", F32, 1), tz = S.field("tz", F32, 1);
     TRY(S.need());

@@ -234,7 +234,7 @@ class Context:
 
     # -- solvers (canonical complex128 device tensors) -----------------------
     @staticmethod
-    def cfg(kind=TMX_SOLVER_CG, op=TMX_OP_PLUS, tol=1e-10, maxiter=10000, delta=0.1, restart=16,
+    def cfg(kind=TMX_SOLVER_CG, op=TMX_OP_PLUS, tol=1e-10, maxiter=10000, delta=0.0, restart=16,
             use_initial_guess=0, inner_tol=0.0, inner_prec=TMX_F32):
         return tmx_solver_cfg(kind, op, tol, maxiter, delta, restart, use_initial_guess, inner_tol, inner_prec)
 
