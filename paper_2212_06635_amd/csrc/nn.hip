@@ -374,6 +374,7 @@ __global__ void __launch_bounds__(256) nn_layer_kernel(Geom g, Act x, Act y, Spi
     constexpr int KK = K32 ? KD / 32 : KD / 16;
     constexpr int PER = MT >= 4 ? NT : (NT + 3) / 4;
     constexpr bool IN_ODD = CIN == 1;
+    constexpr bool ILV = IN_ODD || (CIN == 8 && COUT == 8);  // parity-interleaved tiles
     static_assert(MT == 4 || MT == 1, "output rows: 8 or 1 channels");
     // LDS: the staging rows, then (after the last path) the output tile
     constexpr int ZS_BYTES = NL_N * KS * 2;
@@ -382,13 +383,15 @@ __global__ void __launch_bounds__(256) nn_layer_kernel(Geom g, Act x, Act y, Spi
     uint16_t(*Zs)[KS] = reinterpret_cast<uint16_t(*)[KS]>(smem);
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int my_mt = MT >= 4 ? wave : 0;
-    // tile -> sites.  With an odd-supported input, tiles alternate between
-    // the parities (tile 2i + p: sites p V/2 + 64 i ...), so that every tile
-    // has one parity and every XCD gets as many 8-path (even) tiles as
-    // 1-path (odd) ones.
+    // tile -> sites.  When both parities are computed, tiles alternate
+    // between them (tile 2i + p: sites p V/2 + 64 i ...): every tile has one
+    // parity, and the contiguous tile range of an XCD covers both parities of
+    // one region, so the hop neighbours of its sites are its own sites (read
+    // through its own L2).  With an odd-supported input this also gives every
+    // XCD as many 8-path (even) tiles as 1-path (odd) ones.
     const long tile = xcd_block(xcd);
     long site0;
-    if (IN_ODD) {
+    if (ILV) {
         const long par = tile & 1;
         site0 = par * g.Vh + (tile >> 1) * NL_S;
         s_end = (par + 1) * (long)g.Vh;
@@ -800,8 +803,9 @@ int launch_layer(tmx_ctx *c, int cin, int cout, Act x, Act y, SpinorPtr yo, cons
     if (r) return r;
     const long V = 2 * c->Vh;
     const long s_begin = cout == 1 ? c->Vh : 0;
-    // one-channel input: tiles of the two parities interleaved (see the kernel)
-    const long ntiles = cin == 1 ? 2 * ((c->Vh + NL_S - 1) / NL_S) : (V - s_begin + NL_S - 1) / NL_S;
+    // one-channel input or 8 -> 8: tiles of the two parities interleaved (see the kernel)
+    const bool ilv = cin == 1 || (cin == 8 && cout == 8);
+    const long ntiles = ilv ? 2 * ((c->Vh + NL_S - 1) / NL_S) : (V - s_begin + NL_S - 1) / NL_S;
     const dim3 grid((unsigned)ntiles), block(256);
     const int tb = c->par.t_bc, xcd = c->xcd_remap;
     kstat_begin(c, "NN_" + std::to_string(cin) + "x" + std::to_string(cout));
