@@ -83,7 +83,9 @@ double mhat_bytes_per_site(int prec, int nf, int nrhs)
 
 int fetch(tmx_ctx *c, int n, double *host)
 {
-    hipError_t e = hipMemcpyAsync(c->host_red, c->red.result, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream);
+    hipError_t e = hipSuccess;
+    if (!c->red.host)
+        e = hipMemcpyAsync(c->host_red, c->red.result, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_err(c, e, "reduction readback");
     std::memcpy(host, c->host_red, sizeof(double) * n);
@@ -534,12 +536,19 @@ int tmx_create(const int dims[4], void *hip_stream, tmx_ctx **out)
     c->red.max_blocks = 8192;
     if (hipMalloc(&c->red.partials, sizeof(double) * c->red.max_blocks * MAXR * 4) != hipSuccess ||
         hipMalloc(&c->red.result, sizeof(double) * MAXR * 4) != hipSuccess ||
-        hipHostMalloc(&c->host_red, sizeof(double) * MAXR * 4, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&c->host_red, sizeof(double) * MAXR * 4, hipHostMallocCoherent) != hipSuccess) {
         (void)hipGetLastError();
         dev_free(c->red.partials);
         dev_free(c->red.result);
         delete c;
         return TMX_ENOMEM;
+    }
+    // reductions also land in the coherent pinned buffer, so a readback is a
+    // stream synchronisation without a copy launch (if the mapping is not
+    // available the readback copies instead)
+    if (hipHostGetDevicePointer(reinterpret_cast<void **>(&c->red.host), c->host_red, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        c->red.host = nullptr;
     }
     const char *tr = std::getenv("TMX_TRACE");
     c->trace = tr && tr[0] == '1';

@@ -47,8 +47,10 @@ template <int PX, int PP, int PR, int PQ> struct OpAxpyNorm {
     SpinorPtr x, p, r, q;
     int nf;
     double a[MAXR];
+    const double *ad;  // if set: the coefficients in device memory instead of a
     __device__ void operator()(long t, int k, double *acc) const
     {
+        const double ak = ad ? ad[k] : a[k];
         for (int f = 0; f < nf; ++f) {
             cd vx[12], vp[12], vr[12], vq[12];
             ld<PX>(x, f, t, vx);
@@ -57,8 +59,8 @@ template <int PX, int PP, int PR, int PQ> struct OpAxpyNorm {
             ld<PQ>(q, f, t, vq);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                vx[c] = vx[c] + a[k] * vp[c];
-                vr[c] = vr[c] - a[k] * vq[c];
+                vx[c] = vx[c] + ak * vp[c];
+                vr[c] = vr[c] - ak * vq[c];
             }
             st<PX>(x, f, t, vx);
             st<PR>(r, f, t, vr);
@@ -314,7 +316,8 @@ __global__ void __launch_bounds__(256) blas_kernel(Op op, long nslot, int nrhs, 
 }
 
 // result[o] = sum_b partials[b * nout + o], fixed order (one block per output)
-static __global__ void __launch_bounds__(256) blas_finish_kernel(const double *partials, int nblocks, int nout, double *result)
+static __global__ void __launch_bounds__(256) blas_finish_kernel(const double *partials, int nblocks, int nout, double *result,
+                                                                 double *host)
 {
     __shared__ double sh[256];
     const int o = blockIdx.x;
@@ -326,12 +329,16 @@ static __global__ void __launch_bounds__(256) blas_finish_kernel(const double *p
         if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) result[o] = sh[0];
+    if (threadIdx.x == 0) {
+        result[o] = sh[0];
+        if (host) host[o] = sh[0];  // also straight into the host's readback buffer
+    }
 }
 
 struct RedWork {
     double *partials;  // >= max_blocks * MAXR * 4 doubles
     double *result;    // >= MAXR * 4 doubles (device)
+    double *host;      // device view of a coherent pinned host copy of result, or null
     int max_blocks;
 };
 
@@ -352,7 +359,8 @@ hipError_t run_blas(const Op &op, long nslot, int nrhs, const RedWork &w, hipStr
     if (e != hipSuccess) return e;
     if constexpr (Op::NRED > 0) {
         const int nout = nrhs * Op::NRED;
-        hipLaunchKernelGGL(blas_finish_kernel, dim3(nout), dim3(256), 0, st, w.partials, (int)nb, nout, w.result);
+        hipLaunchKernelGGL(blas_finish_kernel, dim3(nout), dim3(256), 0, st, w.partials, (int)nb, nout, w.result,
+                           w.host);
         e = hipGetLastError();
     }
     return e;

@@ -104,7 +104,21 @@ static int apply_shifted(Sys &S, SpinorPtr q, SpinorPtr p, const double *sigma, 
     o.nf = S.nf;
     for (int k = 0; k < cols; ++k) o.sigma[k] = sigma ? sigma[k] : 0.0;
     HTRY(run_blas(o, c->Vh * cols, cols, c->red, c->stream), "shifted dot");
-    return fetch(c, cols, pq);
+    return pq ? fetch(c, cols, pq) : TMX_OK;  // else the dots stay on the device
+}
+
+// CG step length alpha_k = rho_k / <p, q>_k from the reduction just taken,
+// computed on the device so that the update needs no host round trip;
+// inactive columns (and a vanishing <p, q>) get 0, as on the host before
+struct AlphaArgs {
+    double rho[MAXR];
+    int active[MAXR];
+    int cols;
+};
+static __global__ void cg_alpha_kernel(const double *pq, AlphaArgs a, double *alpha)
+{
+    const int k = threadIdx.x;
+    if (k < a.cols) alpha[k] = (a.active[k] && pq[k] != 0.0) ? a.rho[k] / pq[k] : 0.0;
 }
 
 // true residual r = b - (N + sigma) x (FP64); writes rlo if PL given; returns |r|^2 per column
@@ -115,8 +129,7 @@ static int true_residual(Sys &S, SpinorPtr r, SpinorPtr rlo, bool write_lo, Spin
     tmx_ctx *c = S.c;
     SpinorPtr q = S.field("trq", F64, cols);
     TRY(S.need());
-    double dummy[MAXR];
-    TRY(apply_shifted<F64>(S, q, x, sigma, cols, dummy));
+    TRY(apply_shifted<F64>(S, q, x, sigma, cols, nullptr));
     OpXmyNorm<F64, F64, F64, PL> o{};
     o.r = r;
     o.b = b;
@@ -176,8 +189,10 @@ static int cg_core(Sys &S, SpinorPtr x, SpinorPtr b, int cols, const double *sig
     SpinorPtr q = S.field("q", P, cols);
     SpinorPtr xl = mixed ? S.field("xl", F32, cols) : x;
     TRY(S.need());
+    double *alpha = static_cast<double *>(ws_get(c, "cg_alpha", sizeof(double) * MAXR));
+    if (!alpha) return set_err(c, TMX_ENOMEM, "solver workspace: out of device memory");
 
-    double bb[MAXR], rho[MAXR], rho1[MAXR], rmax[MAXR], pq[MAXR];
+    double bb[MAXR], rho[MAXR], rho1[MAXR], rmax[MAXR];
     int active[MAXR], iters[MAXR], nrel[MAXR];
     TRY((copy_field<F64, F64>(S, r, b, cols, bb)));
     if (!x_is_guess) TRY(zero_field<F64>(S, x, cols));
@@ -201,15 +216,23 @@ static int cg_core(Sys &S, SpinorPtr x, SpinorPtr b, int cols, const double *sig
     const double t0 = now_seconds();
     int it = 0;
     while (nactive > 0 && it < maxiter) {
-        TRY(apply_shifted<P>(S, q, p, sigma, cols, pq));
+        TRY(apply_shifted<P>(S, q, p, sigma, cols, nullptr));
         ++it;
+        AlphaArgs aa{};
+        aa.cols = cols;
+        for (int k = 0; k < cols; ++k) {
+            aa.rho[k] = rho[k];
+            aa.active[k] = active[k];
+        }
+        hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(64), 0, c->stream, c->red.result, aa, alpha);
+        HTRY(hipGetLastError(), "cg step length");
         OpAxpyNorm<mixed ? F32 : F64, P, P, P> up{};
         up.x = xl;
         up.p = p;
         up.r = rl;
         up.q = q;
         up.nf = S.nf;
-        for (int k = 0; k < cols; ++k) up.a[k] = (active[k] && pq[k] != 0.0) ? rho[k] / pq[k] : 0.0;
+        up.ad = alpha;
         HTRY(run_blas(up, c->Vh * cols, cols, c->red, c->stream), "cg update");
         TRY(fetch(c, cols, rho1));
         bool reliable = false;
