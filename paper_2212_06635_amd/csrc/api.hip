@@ -313,7 +313,7 @@ static DslashArgs base_args(tmx_ctx *c, int prec, bool nd, int nrhs)
 
 // K1: u = B_ee(sgn)^{-1} H_eo in ; K2: out = B_oo(sgn) x - kappa^2 H_oe u
 static int schur_pair(tmx_ctx *c, SpinorPtr out, SpinorPtr in, SpinorPtr u, int prec, bool nd, int nrhs, int sgn,
-                      int g5in, int g5out)
+                      int g5in, int g5out, double *nrm = nullptr)
 {
     const int nf = nd ? 2 : 1;
     DslashArgs a = base_args(c, prec, nd, nrhs);
@@ -341,6 +341,7 @@ static int schur_pair(tmx_ctx *c, SpinorPtr out, SpinorPtr in, SpinorPtr u, int 
     b.kfac = c->par.kappa * c->par.kappa;
     b.g5x = g5in;
     b.g5out = g5out;
+    b.nrm = nrm;
     const std::string k2 = kname("K2", prec, nd, nrhs);
     const LaunchCfg l2 = launch_cfg(c, k2);
     b.xcd = l2.xcd;
@@ -374,7 +375,7 @@ int op_mhat(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int dagge
     return schur_pair(c, out, in, u, prec, nd, nrhs, dagger ? -sgn : sgn, dagger, dagger);
 }
 
-int op_mdagm(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int nrhs)
+int op_mdagm(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int nrhs, double *nrm)
 {
     int r = check_op(c, op);
     if (r) return r;
@@ -388,8 +389,9 @@ int op_mdagm(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int nrhs
     if (!ud || !vd) return TMX_ENOMEM;
     SpinorPtr u = make_spinor(ud, prec, nf, stride), v = make_spinor(vd, prec, nf, stride);
     const int sgn = nd ? 1 : op;
-    // v = g5 Mhat(sgn) in ; out = g5 Mhat(-sgn) v
-    r = schur_pair(c, v, in, u, prec, nd, nrhs, sgn, 0, 1);
+    // v = g5 Mhat(sgn) in ; out = g5 Mhat(-sgn) v = N in (g5 Mhat(-sgn) g5 is the
+    // adjoint of Mhat(sgn)), so <in, N in> = |v|^2 per slot if nrm is given
+    r = schur_pair(c, v, in, u, prec, nd, nrhs, sgn, 0, 1, nrm);
     if (r) return r;
     return schur_pair(c, out, v, u, prec, nd, nrhs, -sgn, 0, 1);
 }

@@ -69,6 +69,13 @@ template <int PX, int PP, int PR, int PQ> struct OpAxpyNorm {
     }
 };
 
+// sum of a per-slot FP64 array (per right-hand side)
+struct OpSlotSum {
+    static constexpr int NRED = 1;
+    const double *v;
+    __device__ void operator()(long t, int, double *acc) const { acc[0] += v[t]; }
+};
+
 // r -= a q ; |r|^2
 template <int PR, int PQ> struct OpRupdNorm {
     static constexpr int NRED = 1;

@@ -271,6 +271,14 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 #pragma unroll
             for (int k = 6; k < 12; ++k) out[f][k] = -out[f][k];
     }
+    if (MODE == MODE_DIAG && a.nrm) {
+        double n2 = 0.0;
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int k = 0; k < 12; ++k) n2 += (double)out[f][k].re * out[f][k].re + (double)out[f][k].im * out[f][k].im;
+        a.nrm[t] = n2;
+    }
     // the output is written once per sweep: non-temporal stores keep it from
     // displacing the neighbour spinors in L2 (FP16 outputs, 52 bytes a site,
     // measured no faster that way)

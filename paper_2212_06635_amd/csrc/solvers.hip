@@ -51,10 +51,10 @@ struct Sys {
     }
     // after a group of field() calls: nothing may run on a missing workspace
     int need() const { return nomem ? set_err(c, TMX_ENOMEM, "solver workspace: out of device memory") : TMX_OK; }
-    int N(SpinorPtr out, SpinorPtr in, int prec, int cols)
+    int N(SpinorPtr out, SpinorPtr in, int prec, int cols, double *nrm = nullptr)
     {
         gbytes += 2.0 * mhat_bytes_per_site(prec, nf, cols) * c->Vh * 1e-9;
-        return op_mdagm(c, out, in, op, prec, cols);
+        return op_mdagm(c, out, in, op, prec, cols, nrm);
     }
 };
 
@@ -190,7 +190,12 @@ static int cg_core(Sys &S, SpinorPtr x, SpinorPtr b, int cols, const double *sig
     SpinorPtr xl = mixed ? S.field("xl", F32, cols) : x;
     TRY(S.need());
     double *alpha = static_cast<double *>(ws_get(c, "cg_alpha", sizeof(double) * MAXR));
-    if (!alpha) return set_err(c, TMX_ENOMEM, "solver workspace: out of device memory");
+    // unshifted: <p, N p> = |Mhat p|^2, summed from the per-slot norms the
+    // operator's first half writes (no separate pass over p and q)
+    bool shifted = false;
+    for (int k = 0; k < cols; ++k) shifted = shifted || (sigma && sigma[k] != 0.0);
+    double *pnrm = shifted ? nullptr : static_cast<double *>(ws_get(c, "cg_pnrm", sizeof(double) * c->Vh * cols));
+    if (!alpha || (!shifted && !pnrm)) return set_err(c, TMX_ENOMEM, "solver workspace: out of device memory");
 
     double bb[MAXR], rho[MAXR], rho1[MAXR], rmax[MAXR];
     int active[MAXR], iters[MAXR], nrel[MAXR];
@@ -216,7 +221,14 @@ static int cg_core(Sys &S, SpinorPtr x, SpinorPtr b, int cols, const double *sig
     const double t0 = now_seconds();
     int it = 0;
     while (nactive > 0 && it < maxiter) {
-        TRY(apply_shifted<P>(S, q, p, sigma, cols, nullptr));
+        if (shifted) {
+            TRY(apply_shifted<P>(S, q, p, sigma, cols, nullptr));
+        } else {
+            TRY(S.N(q, p, P, cols, pnrm));
+            OpSlotSum sum{};
+            sum.v = pnrm;
+            HTRY(run_blas(sum, c->Vh * cols, cols, c->red, c->stream), "<p, N p>");
+        }
         ++it;
         AlphaArgs aa{};
         aa.cols = cols;

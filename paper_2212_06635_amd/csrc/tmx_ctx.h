@@ -126,7 +126,9 @@ int ensure_ready(tmx_ctx *c, int prec, bool nd);
 
 // operators on internal fields (asynchronous)
 int op_mhat(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int dagger, int nrhs);
-int op_mdagm(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int nrhs);
+// out = N in = Mhat^dagger Mhat in; if nrm is given it receives <in, N in> = |Mhat in|^2
+// of every slot (FP64, Vh * nrhs values)
+int op_mdagm(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int nrhs, double *nrm = nullptr);
 int op_D(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec);
 
 // launch shape for a kernel key ("K1_f64", "K2_f32_nd_r12", ...)
