@@ -105,3 +105,30 @@ def test_64x128_mpcg_f16(F):
     assert rc == tmx.TMX_OK
     assert info[0]["true_residual"] <= 1e-10
     assert rel_l2(to_host(x, b.shape), tile_cb(x0)) < 5e-8
+
+
+@pytest.mark.gpu
+def test_64x128_pcg_learned_preconditioner(F):
+    """CG on N preconditioned by K K^dagger (the learned network, FP16 inner
+    iterations) at 33.5M sites: every network layer indexes activations of
+    67M sites x 8 channels (offsets beyond 2^32 bytes).  The network is the
+    seeded identity-plus-noise initialisation (K K^dagger is Hermitian
+    positive definite whatever the weights); the solution is checked against
+    the tiled oracle CG solution as for MP-CG."""
+    from oracle import nn_oracle as nn
+
+    tmx, o, ctx = F
+    ctx.pc_set_weights(nn.identity_init(np.random.default_rng(3), 1e-2))
+    b0 = synth.gaussian_cb_spinor(BASE, 5, 2)
+    x0, _, rel = o.cg(b0, tol=1e-11)
+    assert rel <= 1e-11
+    b = tile_cb(b0)
+    x = to_dev(np.zeros_like(b))
+    mem("before the preconditioned solve")
+    rc, info = ctx.solve(x, to_dev(b), 1, kind=tmx.TMX_SOLVER_PCG_NN, op=1, tol=1e-10, inner_prec=2)
+    mem("after the preconditioned solve")
+    print("[gpu 64^3x128] PCG-NN iterations", info[0]["iters"], "fallback", info[0]["fallback"], flush=True)
+    assert rc == tmx.TMX_OK
+    assert info[0]["fallback"] == 0  # converged on the preconditioned path itself
+    assert info[0]["true_residual"] <= 1e-10
+    assert rel_l2(to_host(x, b.shape), tile_cb(x0)) < 5e-8
