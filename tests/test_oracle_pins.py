@@ -328,3 +328,54 @@ def test_cg_against_dense_solve(nf, shift):
     cond = np.linalg.cond(N)
     assert np.linalg.norm(x.reshape(-1) - xd) / np.linalg.norm(xd) < 10 * cond * 1e-12
     assert o.residual(b, x, nf=nf, shift=shift) == pytest.approx(relres, rel=1e-6)
+
+
+# --------------------------------------------------------------------------
+# mass preconditioning: W^pm(rho) = Q^pm pm i rho (Section 2, eq. for W^pm)
+# --------------------------------------------------------------------------
+
+RHO = 0.07  # in the normalisation of mu: the operator gets rho~ = 2 kappa rho
+
+
+def test_mass_preconditioned_identity_unpreconditioned(rough):
+    """W+ W- = Q+ Q- + 2 nu rho~ + rho~^2, the paper's identity, which is exact
+    for the unpreconditioned Q^pm = gamma5 D(pm mu): pins the sign of the
+    i rho term and the place of gamma5 in the oracle's W."""
+    U, o = rough
+    g, _ = Oracle.gammas()
+    g5 = lambda w: np.einsum("st,xftc->xfsc", g[4], w)
+    psi = synth.gaussian_spinor(o.V, 5, 0, 1)
+    lhs = o.w_full(o.w_full(psi, -1, RHO), +1, RHO)
+    qq = g5(o.D(g5(o.D(psi, sgn=-1)), sgn=1))
+    nu, rt = 2 * KAPPA * o.mu, 2 * KAPPA * RHO
+    assert rel(lhs, qq + (2 * nu * rt + rt * rt) * psi) < 1e-14
+    # a wrong sign of the i rho term would give -2 nu rho~ instead
+    assert rel(lhs, qq + (-2 * nu * rt + rt * rt) * psi) > 1e-6
+
+
+def test_mass_preconditioned_schur(rough):
+    """What^pm(rho) = g5 Mhat^pm pm i rho~: rho = 0 is Qhat; its adjoint is
+    What^-+ (also through the oracle's separate Mhat^dagger); the product
+    What^+ What^- carries the cross term i rho~ (Qhat^- - Qhat^+), which is
+    not 2 nu rho~ for the Schur operator (the paper's identity holds only
+    unpreconditioned); W^dagger W is Hermitian positive."""
+    U, o = rough
+    g, _ = Oracle.gammas()
+    g5 = lambda w: np.einsum("st,xftc->xfsc", g[4], w)
+    u = synth.gaussian_cb_spinor(SYM_DIMS, 6, 0)
+    v = synth.gaussian_cb_spinor(SYM_DIMS, 6, 1)
+    nu, rt = 2 * KAPPA * o.mu, 2 * KAPPA * RHO
+    assert np.array_equal(o.w_hat(v, 1, 0.0), g5(o.mhat(v, sgn=1)))
+    for s in (1, -1):
+        lhs = inner(u, o.w_hat(v, s, RHO))
+        assert abs(lhs - inner(o.w_hat(u, -s, RHO), v)) / abs(lhs) < 1e-14
+        assert abs(lhs - inner(o.w_hat(u, s, RHO, dagger=True), v)) / abs(lhs) < 1e-14
+    qp = lambda w: g5(o.mhat(w, sgn=1))
+    qm = lambda w: g5(o.mhat(w, sgn=-1))
+    wpwm = o.w_hat(o.w_hat(v, -1, RHO), 1, RHO)
+    assert rel(wpwm, qp(qm(v)) + 1j * rt * (qm(v) - qp(v)) + rt * rt * v) < 1e-14
+    assert rel(wpwm, qp(qm(v)) + (2 * nu * rt + rt * rt) * v) > 1e-8
+    a = inner(u, o.w_normal(v, 1, RHO))
+    b = inner(o.w_normal(u, 1, RHO), v)
+    assert abs(a - b) / abs(a) < 1e-14
+    assert inner(v, o.w_normal(v, 1, RHO)).real > 0
