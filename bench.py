@@ -41,6 +41,9 @@ if ROOT not in sys.path:
 METRIC = "Schur dslash GB/s (% HBM peak); CG time-to-1e-10, plain vs mixed+learned PC"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 KAPPA, CSW, MU, MUBAR, EPSBAR = 0.1394, 1.69, 0.00072, 0.1246, 0.1315
+# mass-preconditioning mass of What^pm(rho): about 28 x mu, within the 20-30 x
+# range of the light-sector determinant ratios the paper discusses (Section 4.1)
+RHO = 0.02
 NAPPLY = 20
 
 # algorithmic bytes per output site of one stencil launch (links, blocks and
@@ -217,7 +220,7 @@ def main():
     b = synth.gaussian_cb_spinor(dims, 4, 0)
     b2 = synth.gaussian_cb_spinor(dims, 4, 1, 2)
     ctx = tmx.Context(dims)
-    ctx.set_params(tmx.Params(KAPPA, CSW, MU, MUBAR, EPSBAR, -1))
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU, MUBAR, EPSBAR, -1, rho=RHO))
     ctx.load_gauge(U, 4.0)
     Vh = ctx.Vh
     bd = torch.from_numpy(b.reshape(-1)).cuda()
@@ -304,12 +307,15 @@ def main():
         ev["N_f64"] = timed(lambda: [ctx.apply_mdagm(dst[0], src[0], 1, 0) for _ in range(NAPPLY)])
         ev["nd_f32"] = timed(lambda: [ctx.apply_mhat(dst_nd, src_nd, 2, 1) for _ in range(NAPPLY)])
         solves = {}
-        for kind, nm, ip in ((tmx.TMX_SOLVER_CG, "cg_f64", 1), (tmx.TMX_SOLVER_MPCG_F32, "mpcg_f32", 1),
-                             (tmx.TMX_SOLVER_MPCG_F16, "mpcg_f16", 1), (tmx.TMX_SOLVER_PCG_NN, "pcg_nn_f16", 2)):
+        for kind, nm, ip, op in ((tmx.TMX_SOLVER_CG, "cg_f64", 1, 1), (tmx.TMX_SOLVER_MPCG_F32, "mpcg_f32", 1, 1),
+                                 (tmx.TMX_SOLVER_MPCG_F16, "mpcg_f16", 1, 1), (tmx.TMX_SOLVER_PCG_NN, "pcg_nn_f16", 2, 1),
+                                 # the mass-preconditioned normal operator What^dagger What
+                                 (tmx.TMX_SOLVER_CG, "cg_w_f64", 1, tmx.TMX_OP_WPLUS),
+                                 (tmx.TMX_SOLVER_MPCG_F16, "mpcg_w_f16", 1, tmx.TMX_OP_WPLUS)):
             x.zero_()
             torch.cuda.synchronize()
             t = time.perf_counter()
-            rc, info = ctx.solve(x, bd, 1, kind=kind, op=1, tol=1e-10, inner_prec=ip)
+            rc, info = ctx.solve(x, bd, 1, kind=kind, op=op, tol=1e-10, inner_prec=ip)
             solves[nm] = {"seconds": time.perf_counter() - t, "iters": info[0]["iters"],
                           "reliable_updates": info[0]["reliable_updates"],
                           "true_residual": info[0]["true_residual"], "fallback": info[0]["fallback"], "rc": rc}
@@ -407,7 +413,7 @@ def main():
         "config": {"workload": "32^3x64 Wilson twisted-mass clover: Schur Mhat apply + CG / MP-CG to 1e-10"
                    if dims == (32, 32, 32, 64) else f"{'x'.join(map(str, dims))} twisted-mass clover",
                    "lattice": list(dims), "kappa": KAPPA, "csw": CSW, "mu": MU, "mubar": MUBAR,
-                   "epsbar": EPSBAR, "link_eps": 0.25, "seed": 4, "t_bc": "antiperiodic"},
+                   "epsbar": EPSBAR, "rho": RHO, "link_eps": 0.25, "seed": 4, "t_bc": "antiperiodic"},
         "pct_hbm_peak": dslash["f64"]["pct_hbm_peak"],
         "dslash": dslash,
         "solves": last,

@@ -63,8 +63,16 @@ enum {
  * with one FP32 scale per site and computes in FP32. */
 enum { TMX_F64 = 0, TMX_F32 = 1, TMX_F16 = 2 };
 
-/* operator selector: degenerate with +mu / -mu, or the two-flavour operator */
-enum { TMX_OP_PLUS = 1, TMX_OP_MINUS = -1, TMX_OP_ND = 2 };
+/* operator selector: degenerate with +mu / -mu, the two-flavour operator, or
+ * the mass-preconditioned What^pm(rho) = Qhat^pm pm i rho~ of Section 2 (eq.
+ * for W^pm), Qhat^pm = gamma5 Mhat(pm mu), rho~ = 2 kappa rho with rho from
+ * tmx_params.  For the W operators tmx_apply_mhat applies What^pm (its adjoint
+ * What^-+ with dagger = 1), tmx_apply_mdagm and the CG solvers use
+ * (What^pm)^dagger What^pm = What^-+ What^pm; the product is applied as such
+ * (the paper's identity What^+ What^- = Qhat^+ Qhat^- + 2 mu rho + rho^2 holds
+ * only for the unpreconditioned operator).  Not defined for tmx_apply_D, the
+ * learned preconditioner or the autotuner. */
+enum { TMX_OP_PLUS = 1, TMX_OP_MINUS = -1, TMX_OP_ND = 2, TMX_OP_WPLUS = 3, TMX_OP_WMINUS = -3 };
 
 /* field kinds for tmx_field_bytes / tmx_pack / tmx_unpack */
 enum {
@@ -81,6 +89,9 @@ typedef struct {
     double mubar;  /* two-flavour twisted mass (nubar = 2 kappa mubar) */
     double epsbar; /* two-flavour mass splitting (epst = 2 kappa epsbar) */
     int t_bc;      /* +1 periodic, -1 antiperiodic fermion time boundary */
+    double rho;    /* mass-preconditioning mass of TMX_OP_WPLUS / WMINUS, in the
+                      normalisation of mu (the operator gets rho~ = 2 kappa rho);
+                      the site-block inverses do not depend on it */
 } tmx_params;
 
 /* solver kinds */
@@ -96,7 +107,7 @@ enum {
 
 typedef struct {
     int kind;           /* TMX_SOLVER_* */
-    int op;             /* TMX_OP_PLUS / TMX_OP_MINUS / TMX_OP_ND */
+    int op;             /* TMX_OP_PLUS / TMX_OP_MINUS / TMX_OP_ND / TMX_OP_WPLUS / TMX_OP_WMINUS */
     double tol;         /* relative 2-norm of the FP64 true residual, e.g. 1e-10 */
     int maxiter;        /* iteration cap (per stage) */
     double delta;       /* reliable-update trigger (0 => 0.01 FP32, 0.03 FP16 iterations) */

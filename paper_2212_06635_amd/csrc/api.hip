@@ -313,7 +313,7 @@ static DslashArgs base_args(tmx_ctx *c, int prec, bool nd, int nrhs)
 
 // K1: u = B_ee(sgn)^{-1} H_eo in ; K2: out = B_oo(sgn) x - kappa^2 H_oe u
 static int schur_pair(tmx_ctx *c, SpinorPtr out, SpinorPtr in, SpinorPtr u, int prec, bool nd, int nrhs, int sgn,
-                      int g5in, int g5out, double *nrm = nullptr)
+                      int g5in, int g5out, double *nrm = nullptr, double rho = 0.0)
 {
     const int nf = nd ? 2 : 1;
     DslashArgs a = base_args(c, prec, nd, nrhs);
@@ -342,6 +342,7 @@ static int schur_pair(tmx_ctx *c, SpinorPtr out, SpinorPtr in, SpinorPtr u, int 
     b.g5x = g5in;
     b.g5out = g5out;
     b.nrm = nrm;
+    b.rho = rho;
     const std::string k2 = kname("K2", prec, nd, nrhs);
     const LaunchCfg l2 = launch_cfg(c, k2);
     b.xcd = l2.xcd;
@@ -354,9 +355,17 @@ static int schur_pair(tmx_ctx *c, SpinorPtr out, SpinorPtr in, SpinorPtr u, int 
 
 static int check_op(tmx_ctx *c, int op)
 {
-    if (op != TMX_OP_PLUS && op != TMX_OP_MINUS && op != TMX_OP_ND) return set_err(c, TMX_EINVAL, "bad op");
+    if (op != TMX_OP_PLUS && op != TMX_OP_MINUS && op != TMX_OP_ND && op != TMX_OP_WPLUS && op != TMX_OP_WMINUS)
+        return set_err(c, TMX_EINVAL, "bad op");
     return TMX_OK;
 }
+
+// the mass-preconditioned What^pm(rho) = g5 Mhat(pm) pm i rho~ (eq. for W^pm)
+static bool op_is_w(int op) { return op == TMX_OP_WPLUS || op == TMX_OP_WMINUS; }
+// twist sign of the Schur operator behind op
+static int op_sign(int op) { return op == TMX_OP_ND ? 1 : (op > 0 ? 1 : -1); }
+// i rho~ coefficient of What^s: s rho~, rho~ = 2 kappa rho
+static double w_rho(const tmx_ctx *c, int s) { return s * 2.0 * c->par.kappa * c->par.rho; }
 
 int op_mhat(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int dagger, int nrhs)
 {
@@ -370,7 +379,12 @@ int op_mhat(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int dagge
     void *ud = ws_get(c, "op_u" + std::to_string(prec), spinor_field_bytes(prec, nf, stride));
     if (!ud) return TMX_ENOMEM;
     SpinorPtr u = make_spinor(ud, prec, nf, stride);
-    const int sgn = nd ? 1 : op;
+    const int sgn = op_sign(op);
+    if (op_is_w(op)) {
+        // What^s = g5 Mhat(s) + i s rho~ ; its adjoint is What^-s
+        const int s = dagger ? -sgn : sgn;
+        return schur_pair(c, out, in, u, prec, false, nrhs, s, 0, 1, nullptr, w_rho(c, s));
+    }
     // Mhat^dagger = g5 Mhat(-sgn) g5
     return schur_pair(c, out, in, u, prec, nd, nrhs, dagger ? -sgn : sgn, dagger, dagger);
 }
@@ -388,18 +402,21 @@ int op_mdagm(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int nrhs
     void *vd = ws_get(c, "op_v" + std::to_string(prec), spinor_field_bytes(prec, nf, stride));
     if (!ud || !vd) return TMX_ENOMEM;
     SpinorPtr u = make_spinor(ud, prec, nf, stride), v = make_spinor(vd, prec, nf, stride);
-    const int sgn = nd ? 1 : op;
+    const int sgn = op_sign(op);
     // v = g5 Mhat(sgn) in ; out = g5 Mhat(-sgn) v = N in (g5 Mhat(-sgn) g5 is the
-    // adjoint of Mhat(sgn)), so <in, N in> = |v|^2 per slot if nrm is given
-    r = schur_pair(c, v, in, u, prec, nd, nrhs, sgn, 0, 1, nrm);
+    // adjoint of Mhat(sgn)), so <in, N in> = |v|^2 per slot if nrm is given.
+    // For What: v = What^sgn in, out = What^-sgn v = (What^sgn)^dagger What^sgn in.
+    const bool w = op_is_w(op);
+    r = schur_pair(c, v, in, u, prec, nd, nrhs, sgn, 0, 1, nrm, w ? w_rho(c, sgn) : 0.0);
     if (r) return r;
-    return schur_pair(c, out, v, u, prec, nd, nrhs, -sgn, 0, 1);
+    return schur_pair(c, out, v, u, prec, nd, nrhs, -sgn, 0, 1, nullptr, w ? w_rho(c, -sgn) : 0.0);
 }
 
 int op_D(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec)
 {
     int r = check_op(c, op);
     if (r) return r;
+    if (op_is_w(op)) return set_err(c, TMX_EINVAL, "What^pm is defined for the Schur operator only");
     const bool nd = op == TMX_OP_ND;
     r = ensure_links(c, prec);
     if (!r) r = ensure_clover(c, prec);
@@ -601,7 +618,7 @@ int tmx_set_params(tmx_ctx *c, const tmx_params *p)
 {
     if (!c || !p) return TMX_EINVAL;
     if (!(p->kappa > 0) || !std::isfinite(p->kappa) || !std::isfinite(p->csw) || !std::isfinite(p->mu) ||
-        !std::isfinite(p->mubar) || !std::isfinite(p->epsbar) || (p->t_bc != 1 && p->t_bc != -1))
+        !std::isfinite(p->mubar) || !std::isfinite(p->epsbar) || !std::isfinite(p->rho) || (p->t_bc != 1 && p->t_bc != -1))
         return set_err(c, TMX_EINVAL, "invalid parameters");
     if (c->have_params && !c->clover_from_host && (p->kappa != c->par.kappa || p->csw != c->par.csw))
         c->clov_ok[0] = c->clov_ok[1] = c->clov_ok[2] = false;

@@ -12,7 +12,9 @@
 //     factor stored.
 //   MODE_DIAG (second half, "K2", or one parity of the full operator D):
 //       out = (A_p + X(sgn)) x(s) - kfac (H in)(s)
-//     with X = i sgn nu g5 (degenerate) or the two-flavour X above.
+//     with X = i sgn nu g5 (degenerate) or the two-flavour X above; for the
+//     mass-preconditioned operator (one flavour) i rho x is added to the
+//     final output.
 //
 // H is the Wilson hopping term with the spin projectors (1 -+ gamma_mu) of
 // the chiral basis written out per direction: the projected half spinor
@@ -239,6 +241,13 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 #pragma unroll
                 for (int k = 0; k < 6; ++k) xv[k] = gx * xv[k];
                 herm_apply_c<P>(a.clov, cs, s, c, tw, xv, out[0] + 6 * c);
+                if (a.rho != 0.0) {
+                    // + i rho x on the final output: before the output gamma5,
+                    // the lower chirality takes the opposite sign
+                    const R rs = (c == 1 && a.g5out) ? R(-a.rho) : R(a.rho);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) out[0][6 * c + k] = out[0][6 * c + k] + rs * imul(gx * xv[k]);
+                }
             } else {
                 const R ep = R(a.epst);
                 cx<R> x0[6], x1[6];

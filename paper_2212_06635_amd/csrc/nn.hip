@@ -1133,7 +1133,8 @@ int fgcr_stage(tmx_ctx *c, int op, int dagger, SpinorPtr x, SpinorPtr b, double 
 // network fails to deliver (stagnation, non-finite values or the target missed).
 extern "C" int tmx_fgcr_solve_internal(tmx_ctx *c, SpinorPtr x, SpinorPtr b, const tmx_solver_cfg *cfg, tmx_info *info)
 {
-    if (cfg->op == TMX_OP_ND) return set_err(c, TMX_EINVAL, "FGCR is built for the degenerate operator");
+    if (cfg->op != TMX_OP_PLUS && cfg->op != TMX_OP_MINUS)
+        return set_err(c, TMX_EINVAL, "FGCR is built for the degenerate Schur operator");
     tmx_info local{};
     if (!info) info = &local;
     const double tol = cfg->tol > 0 ? cfg->tol : 1e-10;

@@ -598,7 +598,8 @@ extern "C" {
 static int check_cfg(tmx_ctx *c, const tmx_solver_cfg *cfg)
 {
     if (!cfg) return set_err(c, TMX_EINVAL, "null solver config");
-    if (cfg->op != TMX_OP_PLUS && cfg->op != TMX_OP_MINUS && cfg->op != TMX_OP_ND)
+    if (cfg->op != TMX_OP_PLUS && cfg->op != TMX_OP_MINUS && cfg->op != TMX_OP_ND && cfg->op != TMX_OP_WPLUS &&
+        cfg->op != TMX_OP_WMINUS)
         return set_err(c, TMX_EINVAL, "bad op in solver config");
     if (!(cfg->tol > 0) && cfg->tol != 0) return set_err(c, TMX_EINVAL, "bad tolerance");
     return TMX_OK;
@@ -633,7 +634,8 @@ int tmx_solve(tmx_ctx *c, double *x, const double *b, int nrhs, const tmx_solver
         break;
     case TMX_SOLVER_PCG_NN:
         if (nrhs != 1) return set_err(c, TMX_EINVAL, "the preconditioned CG solves one right-hand side at a time");
-        if (cfg->op == TMX_OP_ND) return set_err(c, TMX_EINVAL, "the learned preconditioner is built for the degenerate operator");
+        if (cfg->op != TMX_OP_PLUS && cfg->op != TMX_OP_MINUS)
+            return set_err(c, TMX_EINVAL, "the learned preconditioner is built for the degenerate Schur operator");
         TRY(ensure_ready(c, F32, false));
         rc = (cfg->inner_prec == TMX_F16) ? pcg_nn_core<F16>(S, X, B, *cfg, cfg->use_initial_guess != 0, info)
                                           : pcg_nn_core<F32>(S, X, B, *cfg, cfg->use_initial_guess != 0, info);

@@ -26,6 +26,7 @@ struct DslashArgs {
     int g5in, g5x, g5out;
     int xcd;           // XCD-aware block order
     double *nrm;       // MODE_DIAG, if set: |out|^2 of every slot (FP64), for <p, N p> = |Mhat p|^2
+    double rho;        // MODE_DIAG, one flavour: adds i rho x to the final output (after g5out)
 };
 
 hipError_t launch_dslash(int prec, int nf, int mode, const DslashArgs &a, hipStream_t st, int block);

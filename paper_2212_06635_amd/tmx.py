@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libtmx.so")
 
 TMX_OK, TMX_ENOCONV, TMX_EINVAL, TMX_ENOTLOADED, TMX_ENOMEM, TMX_EHIP = 0, 1, -1, -2, -3, -4
 TMX_F64, TMX_F32, TMX_F16 = 0, 1, 2
-TMX_OP_PLUS, TMX_OP_MINUS, TMX_OP_ND = 1, -1, 2
+TMX_OP_PLUS, TMX_OP_MINUS, TMX_OP_ND, TMX_OP_WPLUS, TMX_OP_WMINUS = 1, -1, 2, 3, -3
 TMX_FIELD_ODD, TMX_FIELD_ODD_ND, TMX_FIELD_FULL, TMX_FIELD_FULL_ND = 0, 1, 2, 3
 TMX_SOLVER_CG, TMX_SOLVER_MPCG_F32, TMX_SOLVER_MPCG_F16, TMX_SOLVER_FGCR_NN, TMX_SOLVER_PCG_NN = 0, 1, 2, 3, 4
 
@@ -36,7 +36,8 @@ class TmxError(RuntimeError):
 
 class tmx_params(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_double), ("csw", ctypes.c_double), ("mu", ctypes.c_double),
-                ("mubar", ctypes.c_double), ("epsbar", ctypes.c_double), ("t_bc", ctypes.c_int)]
+                ("mubar", ctypes.c_double), ("epsbar", ctypes.c_double), ("t_bc", ctypes.c_int),
+                ("rho", ctypes.c_double)]
 
 
 class tmx_solver_cfg(ctypes.Structure):
@@ -137,6 +138,7 @@ class Params:
     mubar: float = 0.0
     epsbar: float = 0.0
     t_bc: int = -1
+    rho: float = 0.0
 
 
 class Context:
@@ -179,7 +181,7 @@ class Context:
 
     # -- state ---------------------------------------------------------------
     def set_params(self, p: Params):
-        cp = tmx_params(p.kappa, p.csw, p.mu, p.mubar, p.epsbar, p.t_bc)
+        cp = tmx_params(p.kappa, p.csw, p.mu, p.mubar, p.epsbar, p.t_bc, p.rho)
         return self.check(lib.tmx_set_params(self.h, ctypes.byref(cp)))
 
     def load_gauge(self, U: np.ndarray, gauge_id: float):

@@ -1,0 +1,118 @@
+"""The mass-preconditioned operator What^pm(rho) = g5 Mhat(pm mu) pm i rho~
+(Section 2, eq. for W^pm; rho~ = 2 kappa rho) on the GPU against the oracle:
+applies of What^pm and of its adjoint in three precisions, the normal
+operator (What^pm)^dagger What^pm, and CG / MP-CG solves of it accepted by the
+oracle's FP64 residual."""
+import numpy as np
+import pytest
+
+from helpers import CSW, KAPPA, rel_l2, to_dev, to_host
+from oracle import Oracle
+from paper_2212_06635_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+MU0, RHO = 0.01, 0.05
+TOL = {0: 1e-13, 1: 1e-6, 2: 5e-3}
+CASES = [((8, 8, 8, 8), 0.3, 1), ((6, 4, 2, 10), 0.3, 3)]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=lambda c: "x".join(map(str, c[0])))
+def S(request):
+    import paper_2212_06635_amd.tmx as tmx
+
+    dims, eps, seed = request.param
+    print(f"\n[gpu mass preconditioning] lattice {dims} eps={eps} seed={seed} rho={RHO}", flush=True)
+    U = synth.gauge_links(dims, eps, seed)
+    o = Oracle(dims, U, KAPPA, CSW, mu=MU0)
+    ctx = tmx.Context(dims)
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU0, 0.0, 0.0, -1, rho=RHO))
+    ctx.load_gauge(U, float(seed))
+    yield tmx, o, ctx, dims
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("dagger", [0, 1])
+@pytest.mark.parametrize("sgn", [1, -1])
+def test_apply_w(S, sgn, dagger, prec):
+    tmx, o, ctx, dims = S
+    op = tmx.TMX_OP_WPLUS if sgn > 0 else tmx.TMX_OP_WMINUS
+    v = synth.gaussian_cb_spinor(dims, 21, 0)
+    ref = o.w_hat(v, sgn, RHO, dagger=bool(dagger))
+    out = ctx.empty(tmx.TMX_FIELD_ODD, prec)
+    ctx.apply_mhat(out, ctx.pack(to_dev(v), tmx.TMX_FIELD_ODD, prec), op, prec, dagger)
+    got = to_host(ctx.unpack(out, tmx.TMX_FIELD_ODD, prec), v.shape)
+    assert rel_l2(got, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("sgn", [1, -1])
+def test_apply_w_normal(S, sgn, prec):
+    tmx, o, ctx, dims = S
+    op = tmx.TMX_OP_WPLUS if sgn > 0 else tmx.TMX_OP_WMINUS
+    v = synth.gaussian_cb_spinor(dims, 22, 0)
+    ref = o.w_normal(v, sgn, RHO)
+    out = ctx.empty(tmx.TMX_FIELD_ODD, prec)
+    ctx.apply_mdagm(out, ctx.pack(to_dev(v), tmx.TMX_FIELD_ODD, prec), op, prec)
+    got = to_host(ctx.unpack(out, tmx.TMX_FIELD_ODD, prec), v.shape)
+    assert rel_l2(got, ref) < TOL[prec]
+
+
+def test_rho_zero_is_gamma5_mhat(S):
+    """rho = 0: What^+ is g5 Mhat(+) bit for bit (same kernels, no i rho term)."""
+    tmx, o, ctx, dims = S
+    v = synth.gaussian_cb_spinor(dims, 23, 0)
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU0, 0.0, 0.0, -1, rho=0.0))
+    try:
+        a = ctx.empty(tmx.TMX_FIELD_ODD, 0)
+        ctx.apply_mhat(a, ctx.pack(to_dev(v), tmx.TMX_FIELD_ODD, 0), tmx.TMX_OP_WPLUS, 0)
+        w0 = to_host(ctx.unpack(a, tmx.TMX_FIELD_ODD, 0), v.shape)
+        ctx.apply_mhat(a, ctx.pack(to_dev(v), tmx.TMX_FIELD_ODD, 0), tmx.TMX_OP_PLUS, 0)
+        m = to_host(ctx.unpack(a, tmx.TMX_FIELD_ODD, 0), v.shape)
+    finally:
+        ctx.set_params(tmx.Params(KAPPA, CSW, MU0, 0.0, 0.0, -1, rho=RHO))
+    assert np.array_equal(w0, o.g5(m))
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("sgn", [1, -1])
+def test_solve_w_normal(S, sgn, kind):
+    """CG (FP64) and MP-CG (FP32 / FP16 inner) on (What)^dagger What, accepted
+    by the oracle's FP64 residual; the added rho~^2 makes it no harder than
+    Mhat^dagger Mhat (iterations printed; at most rounding-level extra)."""
+    tmx, o, ctx, dims = S
+    op = tmx.TMX_OP_WPLUS if sgn > 0 else tmx.TMX_OP_WMINUS
+    b = synth.gaussian_cb_spinor(dims, 24, 0)
+    x = to_dev(np.zeros_like(b))
+    rc, info = ctx.solve(x, to_dev(b), 1, kind=kind, op=op, tol=1e-10)
+    assert rc == tmx.TMX_OK
+    assert o.residual_w(b, to_host(x, b.shape), sgn, RHO) <= 1e-10
+    x2 = to_dev(np.zeros_like(b))
+    rc2, info2 = ctx.solve(x2, to_dev(b), 1, kind=kind, op=sgn, tol=1e-10)
+    assert rc2 == tmx.TMX_OK
+    print(f"iterations W / Mhat ({'+' if sgn > 0 else '-'}, kind {kind}):", info[0]["iters"], info2[0]["iters"])
+    assert info[0]["iters"] <= info2[0]["iters"] + 2
+
+
+def test_solve_what(S):
+    """What^+ x = b through the normal equations (tmx_solve_mhat)."""
+    tmx, o, ctx, dims = S
+    b = synth.gaussian_cb_spinor(dims, 25, 0)
+    x = to_dev(np.zeros_like(b))
+    rc, info = ctx.solve_mhat(x, to_dev(b), 0, kind=tmx.TMX_SOLVER_MPCG_F32, op=tmx.TMX_OP_WPLUS, tol=1e-10)
+    assert rc == tmx.TMX_OK
+    xh = to_host(x, b.shape)
+    assert rel_l2(o.w_hat(xh, 1, RHO), b) <= 1e-9
+
+
+def test_w_rejected_where_undefined(S):
+    tmx, o, ctx, dims = S
+    b = to_dev(synth.gaussian_cb_spinor(dims, 26, 0))
+    x = b * 0
+    for kind in (tmx.TMX_SOLVER_PCG_NN, tmx.TMX_SOLVER_FGCR_NN):
+        with pytest.raises(tmx.TmxError):
+            ctx.solve(x, b, 1, kind=kind, op=tmx.TMX_OP_WPLUS, tol=1e-10)
+    full = to_dev(synth.gaussian_spinor(int(np.prod(dims)), 27, 0))
+    with pytest.raises(tmx.TmxError):
+        ctx.apply_D(full * 0, full, tmx.TMX_OP_WPLUS, 0)
