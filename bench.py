@@ -16,11 +16,15 @@ epsbar = 0.1315; links U = proj_SU3(exp(i 0.25 H)), seed 4):
     (source, solution) pairs from the plain solver on a 16^3x32 field, the
     best of three initialisations by preconditioned-CG iterations on a
     held-out source of that field);
+  * CG and FP16 MP-CG on the mass-preconditioned What^dagger What (rho = 0.02);
   * a 12-shift multishift solve of the two-flavour normal operator (FP32
-    multishift CG, then FP64-reliable refinement per shift; shifts
-    lambda_max * 10^(-5 + 5k/11)) and 12 Gaussian right-hand sides of the
-    two-flavour operator advanced together (FP32 inner, FP64 reliable updates),
-    each also with FP16-storage inner iterations.
+    multishift CG, then FP64-reliable refinement per shift) at the poles of
+    Zolotarev's 12-pole approximation of N_h^(-1/2) on [1e-5, 1] lambda_max,
+    and 12 Gaussian right-hand sides of the two-flavour operator advanced
+    together (FP32 inner, FP64 reliable updates), each also with FP16-storage
+    inner iterations.
+After the timed steps, once: the rational approximation applied as a whole
+(R(N_h) b with the same poles) and its accuracy N_h R(N_h)^2 b = b.
 
 The headline value is the FP64 Schur-operator bandwidth: model bytes of one
 Mhat application (links, spinors and clover blocks each read once per
@@ -211,7 +215,7 @@ def main():
     import torch
 
     import paper_2212_06635_amd.tmx as tmx
-    from paper_2212_06635_amd import synth
+    from paper_2212_06635_amd import synth, zolotarev
 
     dims = tuple(int(x) for x in args.dims.split(","))
     torch.cuda.set_device(0)
@@ -287,7 +291,9 @@ def main():
         lam = float(torch.vdot(vc, wc).real / torch.vdot(vc, vc).real)
         v = ctx.pack(wc / wc.norm(), tmx.TMX_FIELD_ODD_ND, 1)
     lam_max = 1.05 * lam
-    shifts = lam_max * 10.0 ** (-5.0 + 5.0 * np.arange(12) / 11.0)
+    # poles of Zolotarev's approximation of N_h^(-1/2) on [1e-5, 1] lambda_max
+    zolo = zolotarev.for_spectrum(12, 1e-5 * lam_max, lam_max)
+    shifts = zolo.shifts
     xs_ms = torch.zeros(12 * b2d.numel(), dtype=torch.complex128, device="cuda")
     b12 = torch.from_numpy(np.stack([synth.gaussian_cb_spinor(dims, 4, 100 + k, 2) for k in range(12)]).reshape(-1)).cuda()
     x12 = torch.zeros_like(b12)
@@ -422,6 +428,24 @@ def main():
         "roofline_nn_layer": nn_roof,
         "learned_pc_training": train_info,
     }
+    # the rational approximation as a whole: R(N_h) b, then N_h R(N_h)^2 b = b
+    log("rational approximation R(N_h) b (FP16 inner) and its accuracy")
+    rb = torch.zeros_like(b2d)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rc, rinfo = ctx.rational_apply(rb, b2d, zolo.a0, zolo.a, zolo.shifts, op=2, tol=1e-10, inner_prec=2)
+    torch.cuda.synchronize()
+    t_rat = time.perf_counter() - t
+    rrb = torch.zeros_like(b2d)
+    ctx.rational_apply(rrb, rb, zolo.a0, zolo.a, zolo.shifts, op=2, tol=1e-10, inner_prec=2)
+    v_in = ctx.pack(rrb, tmx.TMX_FIELD_ODD_ND, 0)
+    v_out = ctx.empty(tmx.TMX_FIELD_ODD_ND, 0)
+    ctx.apply_mdagm(v_out, v_in, 2, 0)
+    back = ctx.unpack(v_out, tmx.TMX_FIELD_ODD_ND, 0)
+    out["rational_nd_12_f16"] = {"seconds": round(t_rat, 4), "rc": rc, "poles": 12,
+                                 "interval": [1e-5 * lam_max, lam_max], "delta": zolo.delta,
+                                 "iters": [i["iters"] for i in rinfo],
+                                 "check_N_R2_b": float((back - b2d).norm() / b2d.norm())}
     if dims == (32, 32, 32, 64):
         log("learned preconditioner on a 24^3x48 field")
         out["learned_pc_24x24x24x48"] = learned_pc_other_volume(tmx, synth, weights)

@@ -198,6 +198,18 @@ int tmx_solve_mhat(tmx_ctx *ctx, double *x, const double *b, int dagger, const t
  * plain FP64 multishift CG). */
 int tmx_multishift_solve(tmx_ctx *ctx, double *x, const double *b, const double *shifts, int nshift,
                          const tmx_solver_cfg *cfg, tmx_info *info);
+/* Rational function of the normal operator, the partial-fraction form of the
+ * rational approximation (Section 4.2):
+ *     out = a0 b + sum_{k < nshift} coeffs[k] (N + shifts[k])^{-1} b,
+ * N of cfg->op (TMX_OP_ND for the heavy sector).  The solves are those of
+ * tmx_multishift_solve (same cfg fields, shifts ascending, nshift <= 32,
+ * per-shift accuracy cfg->tol) and the sum is accumulated on the device as
+ * each shift's solution is refined; b and out are one odd field each (host
+ * arrays coeffs / shifts of nshift doubles, copied).  info has nshift entries
+ * (may be NULL).  With the Zolotarev coefficients of x^(-1/2) this applies
+ * N^(-1/2) to the relative accuracy of the approximation. */
+int tmx_rational_apply(tmx_ctx *ctx, double *out, const double *b, double a0, const double *coeffs,
+                       const double *shifts, int nshift, const tmx_solver_cfg *cfg, tmx_info *info);
 
 /* ---- learned preconditioner ------------------------------------------- */
 

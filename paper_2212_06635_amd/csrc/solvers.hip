@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -664,25 +665,23 @@ int tmx_solve(tmx_ctx *c, double *x, const double *b, int nrhs, const tmx_solver
     return rc;
 }
 
-int tmx_multishift_solve(tmx_ctx *c, double *x, const double *b, const double *shifts, int nshift,
-                         const tmx_solver_cfg *cfg, tmx_info *info)
+static int check_shifts(tmx_ctx *c, const double *shifts, int nshift)
 {
-    if (!c || !x || !b || !shifts || nshift < 1 || nshift > MAXR)
-        return c ? set_err(c, TMX_EINVAL, "tmx_multishift_solve: bad argument") : TMX_EINVAL;
-    TRY(check_cfg(c, cfg));
     for (int k = 0; k < nshift; ++k)
         if (!(shifts[k] >= 0) || shifts[k] < shifts[0] || !std::isfinite(shifts[k]))
             return set_err(c, TMX_EINVAL, "shifts must be finite, >= 0 and shifts[0] the smallest");
-    const double t0 = now_seconds();
-    if (info) std::memset(info, 0, sizeof(tmx_info) * nshift);
+    return TMX_OK;
+}
+
+// The batched multishift solve of B (packed FP64) for every shift: one
+// low-precision multishift CG, then shift-by-shift refinement with FP64
+// reliable updates.  Each refined FP64 solution is handed to consume(k, X_k)
+// in shift order (X_k is reused for the next shift).
+static int multishift_run(tmx_ctx *c, Sys &S, SpinorPtr B, const double *shifts, int nshift,
+                          const tmx_solver_cfg *cfg, tmx_info *info,
+                          const std::function<int(int, SpinorPtr)> &consume)
+{
     const int prec = (cfg->inner_prec == TMX_F16 || cfg->inner_prec == TMX_F64) ? cfg->inner_prec : TMX_F32;
-    const bool nd = cfg->op == TMX_OP_ND;
-    const int kind = nd ? TMX_FIELD_ODD_ND : TMX_FIELD_ODD;
-    TRY(ensure_ready(c, F64, nd));
-    Sys S(c, cfg->op, 1);
-    SpinorPtr B = S.field("msb", F64, 1);
-    TRY(S.need());
-    HTRY(launch_pack_spinor(b, B, F64, kind, c->g, 1, c->stream), "pack b");
     const double tol = cfg->tol > 0 ? cfg->tol : 1e-10;
     const double inner = cfg->inner_tol > 0 ? cfg->inner_tol : (prec == TMX_F16 ? 5e-4 : (prec == TMX_F32 ? 1e-6 : tol));
     const int maxiter = cfg->maxiter > 0 ? cfg->maxiter : 10000;
@@ -719,9 +718,7 @@ int tmx_multishift_solve(tmx_ctx *c, double *x, const double *b, const double *s
         int rk = dispatch_cg(S, prec, X, B, 1, &sk, rc_cfg, true, &inf);
         if (rk < 0) return rk;
         if (rk == TMX_ENOCONV) rc = TMX_ENOCONV;
-        HTRY(launch_unpack_spinor(x + (size_t)k * c->Vh * 24 * S.nf, X, F64, kind, c->g, 1,
-                                  c->stream),
-             "unpack x_k");
+        TRY(consume(k, X));
         if (info) {
             info[k].iters = its[k] + inf.iters;
             info[k].reliable_updates = inf.reliable_updates;
@@ -729,7 +726,75 @@ int tmx_multishift_solve(tmx_ctx *c, double *x, const double *b, const double *s
             info[k].gbytes = inf.gbytes + (k == 0 ? ms_gb : 0.0);
         }
     }
+    return rc;
+}
+
+int tmx_multishift_solve(tmx_ctx *c, double *x, const double *b, const double *shifts, int nshift,
+                         const tmx_solver_cfg *cfg, tmx_info *info)
+{
+    if (!c || !x || !b || !shifts || nshift < 1 || nshift > MAXR)
+        return c ? set_err(c, TMX_EINVAL, "tmx_multishift_solve: bad argument") : TMX_EINVAL;
+    TRY(check_cfg(c, cfg));
+    TRY(check_shifts(c, shifts, nshift));
+    const double t0 = now_seconds();
+    if (info) std::memset(info, 0, sizeof(tmx_info) * nshift);
+    const bool nd = cfg->op == TMX_OP_ND;
+    const int kind = nd ? TMX_FIELD_ODD_ND : TMX_FIELD_ODD;
+    TRY(ensure_ready(c, F64, nd));
+    Sys S(c, cfg->op, 1);
+    SpinorPtr B = S.field("msb", F64, 1);
+    TRY(S.need());
+    HTRY(launch_pack_spinor(b, B, F64, kind, c->g, 1, c->stream), "pack b");
+    const int rc = multishift_run(c, S, B, shifts, nshift, cfg, info, [&](int k, SpinorPtr X) {
+        return hip_err(c, launch_unpack_spinor(x + (size_t)k * c->Vh * 24 * S.nf, X, F64, kind, c->g, 1, c->stream),
+                       "unpack x_k");
+    });
+    if (rc < 0) return rc;
     HTRY(hipStreamSynchronize(c->stream), "multishift sync");
+    if (info)
+        for (int k = 0; k < nshift; ++k) info[k].seconds = now_seconds() - t0;
+    return rc;
+}
+
+int tmx_rational_apply(tmx_ctx *c, double *out, const double *b, double a0, const double *coeffs,
+                       const double *shifts, int nshift, const tmx_solver_cfg *cfg, tmx_info *info)
+{
+    if (!c || !out || !b || !coeffs || !shifts || nshift < 1 || nshift > MAXR || !std::isfinite(a0))
+        return c ? set_err(c, TMX_EINVAL, "tmx_rational_apply: bad argument") : TMX_EINVAL;
+    TRY(check_cfg(c, cfg));
+    TRY(check_shifts(c, shifts, nshift));
+    for (int k = 0; k < nshift; ++k)
+        if (!std::isfinite(coeffs[k])) return set_err(c, TMX_EINVAL, "coefficients must be finite");
+    const double t0 = now_seconds();
+    if (info) std::memset(info, 0, sizeof(tmx_info) * nshift);
+    const bool nd = cfg->op == TMX_OP_ND;
+    const int kind = nd ? TMX_FIELD_ODD_ND : TMX_FIELD_ODD;
+    TRY(ensure_ready(c, F64, nd));
+    Sys S(c, cfg->op, 1);
+    SpinorPtr B = S.field("msb", F64, 1), A = S.field("ra_acc", F64, 1);
+    TRY(S.need());
+    HTRY(launch_pack_spinor(b, B, F64, kind, c->g, 1, c->stream), "pack b");
+    // A = a0 b, then A += a_k x_k as each shift's solution is refined
+    TRY(zero_field<F64>(S, A, 1));
+    OpAxpby<F64, F64> ax{};
+    ax.y = A;
+    ax.x = B;
+    ax.nf = S.nf;
+    ax.a[0] = a0;
+    ax.b[0] = 1.0;
+    HTRY(run_blas(ax, c->Vh, 1, c->red, c->stream), "rational a0 b");
+    const int rc = multishift_run(c, S, B, shifts, nshift, cfg, info, [&](int k, SpinorPtr X) {
+        OpAxpby<F64, F64> o{};
+        o.y = A;
+        o.x = X;
+        o.nf = S.nf;
+        o.a[0] = coeffs[k];
+        o.b[0] = 1.0;
+        return hip_err(c, run_blas(o, c->Vh, 1, c->red, c->stream), "rational accumulate");
+    });
+    if (rc < 0) return rc;
+    HTRY(launch_unpack_spinor(out, A, F64, kind, c->g, 1, c->stream), "unpack out");
+    HTRY(hipStreamSynchronize(c->stream), "rational sync");
     if (info)
         for (int k = 0; k < nshift; ++k) info[k].seconds = now_seconds() - t0;
     return rc;

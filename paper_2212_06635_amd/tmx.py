@@ -89,6 +89,7 @@ def _load():
         "tmx_solve": ([P, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
         "tmx_solve_mhat": ([P, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
         "tmx_multishift_solve": ([P, P, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
+        "tmx_rational_apply": ([P, P, P, D, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
         "tmx_pc_num_params": ([P, ctypes.POINTER(Z)], I),
         "tmx_pc_set_weights": ([P, P, Z], I),
         "tmx_pc_get_weights": ([P, P, Z], I),
@@ -259,6 +260,18 @@ class Context:
         info = (tmx_info * len(sh))()
         rc = self.check(lib.tmx_multishift_solve(self.h, _ptr(x), _ptr(b), sh.ctypes.data, len(sh),
                                                  ctypes.byref(cfg), info), allow_noconv=True)
+        return rc, [i.as_dict() for i in info]
+
+    def rational_apply(self, out, b, a0, coeffs, shifts, **kw):
+        """out = a0 b + sum_k coeffs[k] (N + shifts[k])^{-1} b (device odd fields)."""
+        cfg = self.cfg(**kw)
+        a = np.ascontiguousarray(coeffs, dtype=np.float64)
+        sh = np.ascontiguousarray(shifts, dtype=np.float64)
+        if a.shape != sh.shape:
+            raise ValueError("coeffs and shifts differ in length")
+        info = (tmx_info * len(sh))()
+        rc = self.check(lib.tmx_rational_apply(self.h, _ptr(out), _ptr(b), float(a0), a.ctypes.data, sh.ctypes.data,
+                                               len(sh), ctypes.byref(cfg), info), allow_noconv=True)
         return rc, [i.as_dict() for i in info]
 
     # -- learned preconditioner ---------------------------------------------

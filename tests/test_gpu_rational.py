@@ -1,0 +1,77 @@
+"""Rational functions of the normal operator on the GPU (the partial fractions
+of the heavy-sector rational approximation, Section 4.2) against the oracle:
+out = a0 b + sum_k a_k (N + sigma_k)^{-1} b with Zolotarev's coefficients of
+x^(-1/2), checked term by term against the oracle's CG solutions and, as a
+whole, by N R(N)^2 b = b to the approximation's accuracy."""
+import numpy as np
+import pytest
+
+from helpers import CSW, EPSBAR, KAPPA, MUBAR, rel_l2, to_dev, to_host
+from oracle import Oracle
+from paper_2212_06635_amd import synth, zolotarev
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (8, 8, 8, 8)
+MU0 = 0.01
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_2212_06635_amd.tmx as tmx
+
+    print("\n[gpu rational] 8^4 eps=0.3 seed=1", flush=True)
+    U = synth.gauge_links(DIMS, 0.3, 1)
+    o = Oracle(DIMS, U, KAPPA, CSW, mu=MU0, mubar=MUBAR, epsbar=EPSBAR)
+    ctx = tmx.Context(DIMS)
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU0, MUBAR, EPSBAR, -1))
+    ctx.load_gauge(U, 1.0)
+    yield tmx, o, ctx
+    ctx.close()
+
+
+def lambda_max(o, nf, sgn):
+    v = synth.gaussian_cb_spinor(DIMS, 31, 0, nf)
+    lam = 0.0
+    for _ in range(40):
+        w = o.mdagm(v, nf=nf, sgn=sgn)
+        lam = float(np.vdot(v.reshape(-1), w.reshape(-1)).real / np.vdot(v.reshape(-1), v.reshape(-1)).real)
+        v = w / np.linalg.norm(w)
+    return lam
+
+
+@pytest.mark.parametrize("op,nf,sgn,inner", [(2, 2, 1, 1), (2, 2, 1, 2), (1, 1, 1, 1)])
+def test_inverse_sqrt_of_normal_operator(S, op, nf, sgn, inner):
+    tmx, o, ctx = S
+    hi = 1.05 * lambda_max(o, nf, sgn)
+    r = zolotarev.for_spectrum(12, 1e-7 * hi, hi)
+    b = synth.gaussian_cb_spinor(DIMS, 32, 0, nf)
+    out = to_dev(np.zeros_like(b))
+    rc, info = ctx.rational_apply(out, to_dev(b), r.a0, r.a, r.shifts, op=op, tol=1e-10, inner_prec=inner)
+    assert rc == tmx.TMX_OK and len(info) == 12
+    got = to_host(out, b.shape)
+    ref = r.a0 * b
+    for a, s in zip(r.a, r.shifts):
+        x, _, rel = o.cg(b, nf=nf, sgn=sgn, shift=s, tol=1e-12)
+        assert rel <= 1e-12
+        ref = ref + a * x
+    assert rel_l2(got, ref) < 1e-8
+    # the whole: N R(N)^2 b = b up to the approximation error (|2 delta| + delta^2)
+    out2 = to_dev(np.zeros_like(b))
+    ctx.rational_apply(out2, out, r.a0, r.a, r.shifts, op=op, tol=1e-10, inner_prec=inner)
+    back = o.mdagm(to_host(out2, b.shape), nf=nf, sgn=sgn)
+    err = rel_l2(back, b)
+    print(f"|N R(N)^2 b - b| / |b| = {err:.2e} (delta = {r.delta:.2e})")
+    assert err <= 2.5 * r.delta + 1e-8
+
+
+def test_rational_apply_validates(S):
+    tmx, o, ctx = S
+    b = to_dev(synth.gaussian_cb_spinor(DIMS, 33, 0))
+    out = b * 0
+    with pytest.raises(tmx.TmxError):
+        ctx.rational_apply(out, b, 1.0, [1.0, 1.0], [0.5, 0.1], op=1)  # shifts not ascending
+    with pytest.raises(tmx.TmxError):
+        ctx.rational_apply(out, b, 1.0, [np.nan], [0.5], op=1)
+    with pytest.raises(ValueError):
+        ctx.rational_apply(out, b, 1.0, [1.0], [0.5, 0.6], op=1)
