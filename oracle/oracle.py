@@ -203,6 +203,29 @@ class Oracle:
         b = _c(b)
         return float(np.linalg.norm(b - self.w_normal(x, sgn, rho)) / np.linalg.norm(b))
 
+    # -- rational approximation (Section 4.2) --------------------------------
+    def rational(self, b, a0, coeffs, shifts, nf=1, sgn=1, tol=1e-13):
+        """a0 b + sum_k coeffs[k] (N + shifts[k])^{-1} b, each solve by the oracle's CG."""
+        out = a0 * _c(b)
+        for a, s in zip(coeffs, shifts):
+            x, _, _ = self.cg(b, nf=nf, sgn=sgn, shift=float(s), tol=tol)
+            out = out + a * x
+        return out
+
+    def rational_correction(self, eta, a0, coeffs, shifts, nf=1, sgn=1, terms=6):
+        """Partial sums of sum_k binom(-1/2, k) <eta, Z^k eta>, Z = N R(N)^2 - 1,
+        for k = 1 .. terms (the exponent of the correction factor
+        det(1 + Z)^(1/2) = < exp(-eta^dagger [(1 + Z)^(-1/2) - 1] eta) >)."""
+        eta = _c(eta)
+        v, e, coef, sums = eta, 0.0, 1.0, []
+        for k in range(1, terms + 1):
+            r2 = self.rational(self.rational(v, a0, coeffs, shifts, nf, sgn), a0, coeffs, shifts, nf, sgn)
+            v = self.mdagm(r2, nf=nf, sgn=sgn) - v
+            coef *= (-0.5 - (k - 1)) / k
+            e += coef * float(np.vdot(eta.reshape(-1), v.reshape(-1)).real)
+            sums.append(e)
+        return sums
+
     def residual_mhat(self, b, x, nf=1, sgn=1, dagger=False):
         b, x = _c(b), _c(x)
         return self.lib.orc_residual_mhat(_ptr(self.L), self.t_bc, _ptr(self.U), _ptr(self.T), self.kappa,

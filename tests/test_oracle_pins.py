@@ -379,3 +379,34 @@ def test_mass_preconditioned_schur(rough):
     b = inner(o.w_normal(u, 1, RHO), v)
     assert abs(a - b) / abs(a) < 1e-14
     assert inner(v, o.w_normal(v, 1, RHO)).real > 0
+
+
+# --------------------------------------------------------------------------
+# rational approximation and its correction term (Section 4.2)
+# --------------------------------------------------------------------------
+
+def test_rational_correction_against_spectral_form(rough):
+    """N and R(N) commute, so Z = N R(N)^2 - 1 = f(N) with f(x) = x R(x)^2 - 1
+    and eta^dagger [(1 + Z)^(-1/2) - 1] eta = sum_i |<u_i, eta>|^2 ((1 + f(l_i))^(-1/2) - 1)
+    over the eigenpairs of N from a dense eigendecomposition.  The oracle's
+    series (shifted CG solves, binomial coefficients) must reach it."""
+    from paper_2212_06635_amd import zolotarev
+
+    U, o = rough
+    n = o.Vh * 12
+    cols = []
+    for j in range(n):
+        e = np.zeros(n, dtype=np.complex128)
+        e[j] = 1.0
+        cols.append(o.mdagm(e.reshape(o.Vh, 1, 4, 3)).reshape(-1))
+    Nd = np.stack(cols, axis=1)
+    lam, u = np.linalg.eigh(0.5 * (Nd + Nd.conj().T))
+    assert lam[0] > 0
+    r = zolotarev.for_spectrum(3, 0.5 * lam[0], 1.1 * lam[-1])   # coarse: |Z| ~ 1e-3, several terms matter
+    f = lam * r(lam) ** 2 - 1.0
+    eta = synth.gaussian_cb_spinor(SYM_DIMS, 7, 0)
+    c = u.conj().T @ eta.reshape(-1)
+    exact = float(np.sum(np.abs(c) ** 2 * ((1.0 + f) ** -0.5 - 1.0)))
+    sums = o.rational_correction(eta, r.a0, r.a, r.shifts, terms=5)
+    assert abs(sums[0] - exact) / abs(exact) > 1e-6        # one term is not enough here
+    assert abs(sums[-1] - exact) / abs(exact) < 1e-8
