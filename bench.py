@@ -24,7 +24,8 @@ epsbar = 0.1315; links U = proj_SU3(exp(i 0.25 H)), seed 4):
     together (FP32 inner, FP64 reliable updates), each also with FP16-storage
     inner iterations.
 After the timed steps, once: the rational approximation applied as a whole
-(R(N_h) b with the same poles) and its accuracy N_h R(N_h)^2 b = b.
+(R(N_h) b with the same poles), its accuracy N_h R(N_h)^2 b = b, and the
+exponent of its correction factor for one Gaussian eta.
 
 The headline value is the FP64 Schur-operator bandwidth: model bytes of one
 Mhat application (links, spinors and clover blocks each read once per
@@ -446,6 +447,16 @@ def main():
                                  "interval": [1e-5 * lam_max, lam_max], "delta": zolo.delta,
                                  "iters": [i["iters"] for i in rinfo],
                                  "check_N_R2_b": float((back - b2d).norm() / b2d.norm())}
+    # the correction term of the approximation for one Gaussian eta (density exp(-|eta|^2))
+    eta = torch.from_numpy(synth.gaussian_cb_spinor(dims, 4, 200, 2).reshape(-1) / np.sqrt(2.0)).cuda()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rc, e_corr, nterms = ctx.rational_correction(eta, zolo.a0, zolo.a, zolo.shifts, series_tol=1e-6, maxterms=6,
+                                                 op=2, tol=1e-10, inner_prec=2)
+    torch.cuda.synchronize()
+    out["rational_correction_nd_12_f16"] = {"seconds": round(time.perf_counter() - t, 4), "rc": rc,
+                                            "exponent": e_corr, "terms": nterms,
+                                            "eta_norm2": float(eta.norm() ** 2)}
     if dims == (32, 32, 32, 64):
         log("learned preconditioner on a 24^3x48 field")
         out["learned_pc_24x24x24x48"] = learned_pc_other_volume(tmx, synth, weights)

@@ -210,6 +210,21 @@ int tmx_multishift_solve(tmx_ctx *ctx, double *x, const double *b, const double 
  * N^(-1/2) to the relative accuracy of the approximation. */
 int tmx_rational_apply(tmx_ctx *ctx, double *out, const double *b, double a0, const double *coeffs,
                        const double *shifts, int nshift, const tmx_solver_cfg *cfg, tmx_info *info);
+/* Correction term of a rational approximation R(N) ~ N^(-1/2) (Section 4.2;
+ * the error of the approximation enters the acceptance step): with
+ * Z = N R(N)^2 - 1, det(N)^(1/2) = det(R)^(-1) det(1 + Z)^(1/2), and for a
+ * Gaussian eta (density exp(-eta^dagger eta)) det(1 + Z)^(1/2) is the mean of
+ * exp(-E) with
+ *     E = eta^dagger [(1 + Z)^(-1/2) - 1] eta = sum_{k>=1} binom(-1/2, k) <eta, Z^k eta>.
+ * Sums the series until a term is below tol * |E| or maxterms terms; each
+ * term applies R twice (as tmx_rational_apply) and N once, all on the device.
+ * eta: one odd field (device, canonical); *exponent receives E (real part),
+ * *terms (may be NULL) the number of terms.  Returns TMX_ENOCONV (with the
+ * partial sum in *exponent) if a solve missed cfg->tol or the series had not
+ * reached tol after maxterms terms. */
+int tmx_rational_correction(tmx_ctx *ctx, const double *eta, double a0, const double *coeffs, const double *shifts,
+                            int nshift, double tol, int maxterms, const tmx_solver_cfg *cfg, double *exponent,
+                            int *terms);
 
 /* ---- learned preconditioner ------------------------------------------- */
 

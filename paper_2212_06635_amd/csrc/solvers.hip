@@ -756,15 +756,48 @@ int tmx_multishift_solve(tmx_ctx *c, double *x, const double *b, const double *s
     return rc;
 }
 
-int tmx_rational_apply(tmx_ctx *c, double *out, const double *b, double a0, const double *coeffs,
-                       const double *shifts, int nshift, const tmx_solver_cfg *cfg, tmx_info *info)
+static int check_rational(tmx_ctx *c, double a0, const double *coeffs, const double *shifts, int nshift,
+                          const tmx_solver_cfg *cfg)
 {
-    if (!c || !out || !b || !coeffs || !shifts || nshift < 1 || nshift > MAXR || !std::isfinite(a0))
-        return c ? set_err(c, TMX_EINVAL, "tmx_rational_apply: bad argument") : TMX_EINVAL;
+    if (!coeffs || !shifts || nshift < 1 || nshift > MAXR || !std::isfinite(a0))
+        return set_err(c, TMX_EINVAL, "rational function: bad argument");
     TRY(check_cfg(c, cfg));
     TRY(check_shifts(c, shifts, nshift));
     for (int k = 0; k < nshift; ++k)
         if (!std::isfinite(coeffs[k])) return set_err(c, TMX_EINVAL, "coefficients must be finite");
+    return TMX_OK;
+}
+
+// out = a0 in + sum_k coeffs[k] (N + shifts[k])^{-1} in on internal FP64
+// fields (out != in): out = a0 in, then out += a_k x_k as each shift's
+// solution is refined
+static int rational_internal(tmx_ctx *c, Sys &S, SpinorPtr out, SpinorPtr in, double a0, const double *coeffs,
+                             const double *shifts, int nshift, const tmx_solver_cfg *cfg, tmx_info *info)
+{
+    TRY(zero_field<F64>(S, out, 1));
+    OpAxpby<F64, F64> ax{};
+    ax.y = out;
+    ax.x = in;
+    ax.nf = S.nf;
+    ax.a[0] = a0;
+    ax.b[0] = 1.0;
+    HTRY(run_blas(ax, c->Vh, 1, c->red, c->stream), "rational a0 b");
+    return multishift_run(c, S, in, shifts, nshift, cfg, info, [&](int k, SpinorPtr X) {
+        OpAxpby<F64, F64> o{};
+        o.y = out;
+        o.x = X;
+        o.nf = S.nf;
+        o.a[0] = coeffs[k];
+        o.b[0] = 1.0;
+        return hip_err(c, run_blas(o, c->Vh, 1, c->red, c->stream), "rational accumulate");
+    });
+}
+
+int tmx_rational_apply(tmx_ctx *c, double *out, const double *b, double a0, const double *coeffs,
+                       const double *shifts, int nshift, const tmx_solver_cfg *cfg, tmx_info *info)
+{
+    if (!c || !out || !b) return c ? set_err(c, TMX_EINVAL, "tmx_rational_apply: bad argument") : TMX_EINVAL;
+    TRY(check_rational(c, a0, coeffs, shifts, nshift, cfg));
     const double t0 = now_seconds();
     if (info) std::memset(info, 0, sizeof(tmx_info) * nshift);
     const bool nd = cfg->op == TMX_OP_ND;
@@ -774,29 +807,72 @@ int tmx_rational_apply(tmx_ctx *c, double *out, const double *b, double a0, cons
     SpinorPtr B = S.field("msb", F64, 1), A = S.field("ra_acc", F64, 1);
     TRY(S.need());
     HTRY(launch_pack_spinor(b, B, F64, kind, c->g, 1, c->stream), "pack b");
-    // A = a0 b, then A += a_k x_k as each shift's solution is refined
-    TRY(zero_field<F64>(S, A, 1));
-    OpAxpby<F64, F64> ax{};
-    ax.y = A;
-    ax.x = B;
-    ax.nf = S.nf;
-    ax.a[0] = a0;
-    ax.b[0] = 1.0;
-    HTRY(run_blas(ax, c->Vh, 1, c->red, c->stream), "rational a0 b");
-    const int rc = multishift_run(c, S, B, shifts, nshift, cfg, info, [&](int k, SpinorPtr X) {
-        OpAxpby<F64, F64> o{};
-        o.y = A;
-        o.x = X;
-        o.nf = S.nf;
-        o.a[0] = coeffs[k];
-        o.b[0] = 1.0;
-        return hip_err(c, run_blas(o, c->Vh, 1, c->red, c->stream), "rational accumulate");
-    });
+    const int rc = rational_internal(c, S, A, B, a0, coeffs, shifts, nshift, cfg, info);
     if (rc < 0) return rc;
     HTRY(launch_unpack_spinor(out, A, F64, kind, c->g, 1, c->stream), "unpack out");
     HTRY(hipStreamSynchronize(c->stream), "rational sync");
     if (info)
         for (int k = 0; k < nshift; ++k) info[k].seconds = now_seconds() - t0;
+    return rc;
+}
+
+int tmx_rational_correction(tmx_ctx *c, const double *eta, double a0, const double *coeffs, const double *shifts,
+                            int nshift, double tol, int maxterms, const tmx_solver_cfg *cfg, double *exponent,
+                            int *terms)
+{
+    if (!c || !eta || !exponent || maxterms < 1 || !(tol > 0))
+        return c ? set_err(c, TMX_EINVAL, "tmx_rational_correction: bad argument") : TMX_EINVAL;
+    TRY(check_rational(c, a0, coeffs, shifts, nshift, cfg));
+    const bool nd = cfg->op == TMX_OP_ND;
+    const int kind = nd ? TMX_FIELD_ODD_ND : TMX_FIELD_ODD;
+    TRY(ensure_ready(c, F64, nd));
+    Sys S(c, cfg->op, 1);
+    SpinorPtr E = S.field("rc_eta", F64, 1), V = S.field("rc_v", F64, 1), T1 = S.field("rc_t1", F64, 1),
+              T2 = S.field("rc_t2", F64, 1), W = S.field("rc_w", F64, 1);
+    TRY(S.need());
+    HTRY(launch_pack_spinor(eta, E, F64, kind, c->g, 1, c->stream), "pack eta");
+    TRY((copy_field<F64, F64>(S, V, E, 1, nullptr)));
+    // E = sum_k binom(-1/2, k) <eta, Z^k eta>,  Z = N R(N)^2 - 1
+    double sum = 0.0, coef = 1.0, dots[2];
+    int k = 0, rc = TMX_OK;
+    bool converged = false;
+    while (k < maxterms) {
+        ++k;
+        int r = rational_internal(c, S, T1, V, a0, coeffs, shifts, nshift, cfg, nullptr);
+        if (r < 0) return r;
+        if (r == TMX_ENOCONV) rc = r;
+        r = rational_internal(c, S, T2, T1, a0, coeffs, shifts, nshift, cfg, nullptr);
+        if (r < 0) return r;
+        if (r == TMX_ENOCONV) rc = r;
+        TRY(op_mdagm(c, W, T2, cfg->op, F64, 1));
+        OpAxpby<F64, F64> z{};  // V = W - V = Z V
+        z.y = V;
+        z.x = W;
+        z.nf = S.nf;
+        z.a[0] = 1.0;
+        z.b[0] = -1.0;
+        HTRY(run_blas(z, c->Vh, 1, c->red, c->stream), "Z v");
+        OpCdot<F64, F64> d{};
+        d.a = E;
+        d.b = V;
+        d.nf = S.nf;
+        HTRY(run_blas(d, c->Vh, 1, c->red, c->stream), "<eta, Z^k eta>");
+        TRY(fetch(c, 2, dots));
+        coef *= (-0.5 - (k - 1)) / k;
+        const double term = coef * dots[0];
+        sum += term;
+        if (!std::isfinite(sum)) return set_err(c, TMX_ENOCONV, "rational correction: non-finite series");
+        if (std::fabs(term) <= tol * std::fabs(sum)) {
+            converged = true;
+            break;
+        }
+    }
+    *exponent = sum;
+    if (terms) *terms = k;
+    if (!converged && rc == TMX_OK) {
+        set_err(c, TMX_ENOCONV, "rational correction: series not converged within maxterms");
+        rc = TMX_ENOCONV;
+    }
     return rc;
 }
 

@@ -90,6 +90,8 @@ def _load():
         "tmx_solve_mhat": ([P, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
         "tmx_multishift_solve": ([P, P, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
         "tmx_rational_apply": ([P, P, P, D, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
+        "tmx_rational_correction": ([P, P, D, P, P, I, D, I, ctypes.POINTER(tmx_solver_cfg), ctypes.POINTER(D),
+                                     ctypes.POINTER(I)], I),
         "tmx_pc_num_params": ([P, ctypes.POINTER(Z)], I),
         "tmx_pc_set_weights": ([P, P, Z], I),
         "tmx_pc_get_weights": ([P, P, Z], I),
@@ -273,6 +275,20 @@ class Context:
         rc = self.check(lib.tmx_rational_apply(self.h, _ptr(out), _ptr(b), float(a0), a.ctypes.data, sh.ctypes.data,
                                                len(sh), ctypes.byref(cfg), info), allow_noconv=True)
         return rc, [i.as_dict() for i in info]
+
+    def rational_correction(self, eta, a0, coeffs, shifts, series_tol=1e-12, maxterms=8, **kw):
+        """E = sum_k binom(-1/2, k) <eta, Z^k eta>, Z = N R(N)^2 - 1; returns (rc, E, terms).
+        series_tol stops the series; kw are the solver settings (tol, inner_prec, op, ...)."""
+        cfg = self.cfg(**kw)
+        a = np.ascontiguousarray(coeffs, dtype=np.float64)
+        sh = np.ascontiguousarray(shifts, dtype=np.float64)
+        if a.shape != sh.shape:
+            raise ValueError("coeffs and shifts differ in length")
+        e, n = ctypes.c_double(), ctypes.c_int()
+        rc = self.check(lib.tmx_rational_correction(self.h, _ptr(eta), float(a0), a.ctypes.data, sh.ctypes.data,
+                                                    len(sh), float(series_tol), int(maxterms), ctypes.byref(cfg),
+                                                    ctypes.byref(e), ctypes.byref(n)), allow_noconv=True)
+        return rc, e.value, n.value
 
     # -- learned preconditioner ---------------------------------------------
     def pc_num_params(self):

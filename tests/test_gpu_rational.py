@@ -75,3 +75,45 @@ def test_rational_apply_validates(S):
         ctx.rational_apply(out, b, 1.0, [np.nan], [0.5], op=1)
     with pytest.raises(ValueError):
         ctx.rational_apply(out, b, 1.0, [1.0], [0.5, 0.6], op=1)
+
+
+SMALL = (4, 4, 4, 8)
+
+
+@pytest.fixture(scope="module")
+def T():
+    import paper_2212_06635_amd.tmx as tmx
+
+    print("\n[gpu rational correction] 4x4x4x8 eps=0.3 seed=9", flush=True)
+    U = synth.gauge_links(SMALL, 0.3, 9)
+    o = Oracle(SMALL, U, KAPPA, CSW, mu=MU0, mubar=MUBAR, epsbar=EPSBAR)
+    ctx = tmx.Context(SMALL)
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU0, MUBAR, EPSBAR, -1))
+    ctx.load_gauge(U, 9.0)
+    yield tmx, o, ctx
+    ctx.close()
+
+
+@pytest.mark.parametrize("op,nf", [(1, 1), (2, 2)])
+def test_rational_correction(T, op, nf):
+    """The correction-term series E = sum_k binom(-1/2, k) <eta, Z^k eta>,
+    Z = N R(N)^2 - 1, on the GPU against the oracle's partial sum of the same
+    length, for a coarse 4-pole approximation (several terms contribute)."""
+    tmx, o, ctx = T
+    v = synth.gaussian_cb_spinor(SMALL, 34, 0, nf)
+    lam = 0.0
+    for _ in range(60):
+        w = o.mdagm(v, nf=nf)
+        lam = float(np.vdot(v.reshape(-1), w.reshape(-1)).real / np.vdot(v.reshape(-1), v.reshape(-1)).real)
+        v = w / np.linalg.norm(w)
+    r = zolotarev.for_spectrum(4, 1e-6 * lam, 1.1 * lam)
+    eta = synth.gaussian_cb_spinor(SMALL, 35, 0, nf)
+    rc, e, nterms = ctx.rational_correction(to_dev(eta), r.a0, r.a, r.shifts, series_tol=1e-8, maxterms=12,
+                                            op=op, tol=1e-11)
+    assert rc == tmx.TMX_OK and 2 <= nterms < 12
+    ref = o.rational_correction(eta, r.a0, r.a, r.shifts, nf=nf, terms=nterms)[-1]
+    print(f"E = {e:.6e} (oracle {ref:.6e}), {nterms} terms, delta = {r.delta:.1e}")
+    assert abs(e - ref) <= 1e-6 * abs(ref)
+    # too few terms: reported, with the partial sum
+    rc2, e2, n2 = ctx.rational_correction(to_dev(eta), r.a0, r.a, r.shifts, series_tol=1e-14, maxterms=2, op=op)
+    assert rc2 == tmx.TMX_ENOCONV and n2 == 2
