@@ -203,6 +203,60 @@ class Oracle:
         b = _c(b)
         return float(np.linalg.norm(b - self.w_normal(x, sgn, rho)) / np.linalg.norm(b))
 
+    # -- hopping-term force ---------------------------------------------------
+    def hop_force(self, X, Y, sgn=1):
+        """Link derivative of S = Re<Y, Mhat(sgn) X> through the hopping terms
+        (clover and twist blocks held fixed), for U_mu(x) -> exp(i eps T) U_mu(x):
+        dS/d eps = Re Tr[i T F_mu(x)], F = TA(Q) the traceless anti-Hermitian
+        part of Q_mu(x) = -kappa^2 bc U_mu(x) [sum_s ((1 - g_mu) b(x+mu))_s a(x)_s^dagger
+        + sum_s ((1 + g_mu) a(x+mu))_s b(x)_s^dagger], with full-lattice fields
+        b = X (odd) | u = B_ee(sgn)^-1 H_eo X (even) and
+        a = Y (odd) | w = B_ee(-sgn)^-1 g5 H_eo g5 Y (even).  Shape (V, 4, 3, 3)."""
+        g, _ = self.gammas()
+        lx, ly, lz, lt = self.dims
+        V = self.V
+        lex = np.arange(V)
+        co = np.stack([lex % lx, (lex // lx) % ly, (lex // (lx * ly)) % lz, lex // (lx * ly * lz)], axis=1)
+        par = co.sum(axis=1) % 2
+        odd, even = np.nonzero(par == 1)[0], np.nonzero(par == 0)[0]
+
+        def full(v_odd):
+            f = np.zeros((V, 4, 3), dtype=np.complex128)
+            f[odd] = _c(v_odd).reshape(-1, 4, 3)
+            return f
+
+        def g5(f):
+            return np.einsum("st,xtc->xsc", g[4], f)
+
+        def hop_to_even(f):
+            return self.hop(f.reshape(V, 1, 4, 3), out_parity=0).reshape(V, 4, 3)
+
+        def block_solve(f, s):
+            out = np.zeros_like(f)
+            for x in even:
+                out[x] = np.linalg.solve(self.site_block(int(x), 1, s), f[x].reshape(12)).reshape(4, 3)
+            return out
+
+        b = full(X)
+        a = full(Y)
+        b[even] = block_solve(hop_to_even(b), sgn)[even]
+        a[even] = block_solve(g5(hop_to_even(g5(a))), -sgn)[even]
+        F = np.zeros((V, 4, 3, 3), dtype=np.complex128)
+        eye4 = np.eye(4)
+        L = (lx, ly, lz, lt)
+        for mu in range(4):
+            c2 = co.copy()
+            c2[:, mu] = (c2[:, mu] + 1) % L[mu]
+            y = c2[:, 0] + lx * (c2[:, 1] + ly * (c2[:, 2] + lz * c2[:, 3]))
+            bc = np.where((mu == 3) & (co[:, 3] == lt - 1), float(self.t_bc), 1.0)
+            pb = np.einsum("st,xtc->xsc", eye4 - g[mu], b[y])
+            pa = np.einsum("st,xtc->xsc", eye4 + g[mu], a[y])
+            M = np.einsum("xsc,xsd->xcd", pb, a.conj()) + np.einsum("xsc,xsd->xcd", pa, b.conj())
+            Q = -(self.kappa ** 2) * bc[:, None, None] * np.einsum("xij,xjk->xik", self.U[:, mu], M)
+            A = 0.5 * (Q - np.conj(np.swapaxes(Q, 1, 2)))
+            F[:, mu] = A - (np.trace(A, axis1=1, axis2=2) / 3.0)[:, None, None] * np.eye(3)
+        return F
+
     # -- rational approximation (Section 4.2) --------------------------------
     def rational(self, b, a0, coeffs, shifts, nf=1, sgn=1, tol=1e-13):
         """a0 b + sum_k coeffs[k] (N + shifts[k])^{-1} b, each solve by the oracle's CG."""

@@ -410,3 +410,47 @@ def test_rational_correction_against_spectral_form(rough):
     sums = o.rational_correction(eta, r.a0, r.a, r.shifts, terms=5)
     assert abs(sums[0] - exact) / abs(exact) > 1e-6        # one term is not enough here
     assert abs(sums[-1] - exact) / abs(exact) < 1e-8
+
+
+# --------------------------------------------------------------------------
+# hopping-term force: the link derivative of Re<Y, Mhat X>
+# --------------------------------------------------------------------------
+
+def _random_su3_algebra(n, rng):
+    """n Hermitian traceless 3x3 matrices."""
+    h = rng.standard_normal((n, 3, 3)) + 1j * rng.standard_normal((n, 3, 3))
+    h = 0.5 * (h + np.conj(np.swapaxes(h, 1, 2)))
+    return h - (np.trace(h, axis1=1, axis2=2) / 3.0)[:, None, None] * np.eye(3)
+
+
+def _expi(h):
+    """exp(i h) for Hermitian h, by eigendecomposition."""
+    w, v = np.linalg.eigh(h)
+    return np.einsum("xij,xj,xkj->xik", v, np.exp(1j * w), np.conj(v))
+
+
+@pytest.mark.parametrize("sgn", [1, -1])
+def test_hop_force_against_finite_differences(rough, sgn):
+    """d/d eps Re<Y, Mhat[exp(i eps P) U] X> at eps = 0, with the clover term
+    held fixed, by central differences of the oracle's own operator, against
+    sum Re Tr[i P F] over all links (every direction and the time boundary)."""
+    U, o = rough
+    rng = np.random.default_rng(17)
+    X = synth.gaussian_cb_spinor(SYM_DIMS, 8, 0)
+    Y = synth.gaussian_cb_spinor(SYM_DIMS, 8, 1)
+    F = o.hop_force(X, Y, sgn)
+    assert np.abs(F + np.conj(np.swapaxes(F, 2, 3))).max() < 1e-13          # anti-Hermitian
+    assert np.abs(np.trace(F, axis1=2, axis2=3)).max() < 1e-13                # traceless
+    U4 = U.reshape(o.V, 4, 3, 3)
+    for trial in range(2):
+        P = _random_su3_algebra(o.V * 4, rng).reshape(o.V, 4, 3, 3)
+        analytic = float(np.sum(np.einsum("xmij,xmji->xm", 1j * P, F).real))
+
+        def S(eps):
+            Ue = np.einsum("xmij,xmjk->xmik", _expi(eps * P.reshape(-1, 3, 3)).reshape(o.V, 4, 3, 3), U4)
+            oe = Oracle(SYM_DIMS, Ue, KAPPA, CSW, mu=o.mu, T=o.T)
+            return float(np.vdot(Y.reshape(-1), oe.mhat(X, sgn=sgn).reshape(-1)).real)
+
+        h = 1e-5
+        numeric = (S(h) - S(-h)) / (2 * h)
+        assert abs(numeric - analytic) < 1e-7 * abs(analytic)
