@@ -25,7 +25,8 @@ epsbar = 0.1315; links U = proj_SU3(exp(i 0.25 H)), seed 4):
     inner iterations.
 After the timed steps, once: the rational approximation applied as a whole
 (R(N_h) b with the same poles), its accuracy N_h R(N_h)^2 b = b, and the
-exponent of its correction factor for one Gaussian eta.
+exponent of its correction factor for one Gaussian eta; the hopping-term
+force kernel (link outer products of one shift).
 
 The headline value is the FP64 Schur-operator bandwidth: model bytes of one
 Mhat application (links, spinors and clover blocks each read once per
@@ -457,6 +458,23 @@ def main():
     out["rational_correction_nd_12_f16"] = {"seconds": round(time.perf_counter() - t, 4), "rc": rc,
                                             "exponent": e_corr, "terms": nterms,
                                             "eta_norm2": float(eta.norm() ** 2)}
+    # hopping-term force: the link outer products of one shift (Section 4.3)
+    log("hopping-term force")
+    fbuf = torch.zeros(Vh * 2 * 36, dtype=torch.complex128, device="cuda")
+    ctx.hop_force(fbuf, x, bd, op=1)
+    torch.cuda.synchronize()
+    ctx.kstats_enable(True)
+    for _ in range(5):
+        ctx.hop_force(fbuf, x, bd, op=1)
+    torch.cuda.synchronize()
+    fks = ctx.kstats()
+    ctx.kstats_enable(False)
+    if "HOP_FORCE" in fks:
+        n, ms_tot = fks["HOP_FORCE"]
+        fbytes = 1344.0 * 2 * Vh  # a, b fields (2 x 192 B), 4 links (4 x 96 B), 4 outputs (4 x 144 B) per site
+        out["hop_force_f64"] = {"kernel_ms": round(ms_tot / n, 4), "GBps": round(fbytes / (ms_tot / n * 1e-3) / 1e9, 1),
+                                "bytes_per_site": 1344}
+    del fbuf
     if dims == (32, 32, 32, 64):
         log("learned preconditioner on a 24^3x48 field")
         out["learned_pc_24x24x24x48"] = learned_pc_other_volume(tmx, synth, weights)

@@ -182,6 +182,18 @@ int tmx_apply_mhat(tmx_ctx *ctx, void *out, const void *in, int op, int prec, in
 /* out = N in = Mhat^dagger Mhat in. */
 int tmx_apply_mdagm(tmx_ctx *ctx, void *out, const void *in, int op, int prec, int nrhs);
 
+/* Hopping-term force (the link derivative that the fermion force of the
+ * rational monomials sums over the shifts, Section 4.3): for odd fields x, y
+ * (device, canonical complex128) and S = Re<y, Mhat(op) x> with the clover
+ * and twist blocks held fixed, the derivative along U_mu(z) -> exp(i eps T)
+ * U_mu(z) (T Hermitian traceless) is Re Tr[i T F_mu(z)], F the traceless
+ * anti-Hermitian 3x3 matrix written to force[((lex * 4 + mu) * 3 + i) * 3 + j]
+ * (complex128, the canonical link layout of tmx_load_gauge).  force =
+ * coeff F, or force += coeff F with accumulate = 1 (summing over shifts).
+ * op: TMX_OP_PLUS or TMX_OP_MINUS.  Enqueued on the context stream. */
+int tmx_hop_force(tmx_ctx *ctx, double *force, const double *x, const double *y, int op, double coeff,
+                  int accumulate);
+
 /* ---- solvers (device buffers, canonical complex128 odd fields) -------- */
 
 /* Solve N x = b (cfg->op selects the operator) for nrhs right-hand sides

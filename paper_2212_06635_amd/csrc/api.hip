@@ -783,6 +783,60 @@ int tmx_apply_mdagm(tmx_ctx *c, void *out, const void *in, int op, int prec, int
                     prec, nrhs);
 }
 
+int tmx_hop_force(tmx_ctx *c, double *force, const double *x, const double *y, int op, double coeff, int accumulate)
+{
+    if (!c || !force || !x || !y || !std::isfinite(coeff))
+        return c ? set_err(c, TMX_EINVAL, "tmx_hop_force: bad argument") : TMX_EINVAL;
+    if (op != TMX_OP_PLUS && op != TMX_OP_MINUS)
+        return set_err(c, TMX_EINVAL, "the hopping force is built for the degenerate Schur operator");
+    int r = ensure_ready(c, F64, false);
+    if (r) return r;
+    const size_t fb = spinor_field_bytes(F64, 1, c->Vh);
+    void *px = ws_get(c, "hf_x", fb), *py = ws_get(c, "hf_y", fb), *pu = ws_get(c, "hf_u", fb),
+         *pw = ws_get(c, "hf_w", fb);
+    if (!px || !py || !pu || !pw) return set_err(c, TMX_ENOMEM, "hop force workspace: out of device memory");
+    SpinorPtr X = make_spinor(px, F64, 1, c->Vh), Y = make_spinor(py, F64, 1, c->Vh),
+              U = make_spinor(pu, F64, 1, c->Vh), W = make_spinor(pw, F64, 1, c->Vh);
+    r = hip_err(c, launch_pack_spinor(x, X, F64, TMX_FIELD_ODD, c->g, 1, c->stream), "pack x");
+    if (!r) r = hip_err(c, launch_pack_spinor(y, Y, F64, TMX_FIELD_ODD, c->g, 1, c->stream), "pack y");
+    if (r) return r;
+    // u = B_ee(s)^{-1} H_eo X ; w' = B_ee(-s)^{-1} H_eo g5 Y (the force kernel applies the outer g5)
+    const LaunchCfg l1 = launch_cfg(c, kname("K1", F64, false, 1));
+    DslashArgs a = base_args(c, F64, false, 1);
+    a.parity = 0;
+    a.clov = clov_parity(c, F64, 0);
+    a.inv = c->inv[F64];
+    a.xcd = l1.xcd;
+    a.sgn = op;
+    a.in = X;
+    a.out = U;
+    hipError_t e = launch_dslash(F64, 1, 0, a, c->stream, l1.block);
+    if (e != hipSuccess) return hip_err(c, e, "K1 launch");
+    a.sgn = -op;
+    a.g5in = 1;
+    a.in = Y;
+    a.out = W;
+    e = launch_dslash(F64, 1, 0, a, c->stream, l1.block);
+    if (e != hipSuccess) return hip_err(c, e, "K1 launch");
+    ForceArgs f{};
+    f.g = c->g;
+    f.U = LinkPtr{c->links[F64], c->Vh};
+    f.X = X;
+    f.Y = Y;
+    f.u = U;
+    f.w = W;
+    f.t_bc = c->par.t_bc;
+    f.kfac = c->par.kappa * c->par.kappa;
+    f.coeff = coeff;
+    f.accumulate = accumulate ? 1 : 0;
+    f.out = force;
+    f.xcd = c->xcd_remap;
+    kstat_begin(c, "HOP_FORCE");
+    e = launch_hop_force(f, c->stream);
+    kstat_end(c);
+    return hip_err(c, e, "hop force");
+}
+
 // ---- autotuner -----------------------------------------------------------------
 int tmx_tune(tmx_ctx *c, int prec, int op, int nrhs)
 {

@@ -31,6 +31,22 @@ struct DslashArgs {
 
 hipError_t launch_dslash(int prec, int nf, int mode, const DslashArgs &a, hipStream_t st, int block);
 
+// hopping-term force (force.hip): out[lex][mu] (3x3 complex, canonical link
+// layout) = coeff TA(Q_mu(x)) (+ out if accumulate); X, Y odd, u = K1(s) X,
+// w = K1(-s, g5 in) Y even, all FP64
+struct ForceArgs {
+    Geom g;
+    LinkPtr U;
+    SpinorPtr X, Y, u, w;
+    int t_bc;
+    double kfac;  // kappa^2
+    double coeff;
+    int accumulate;
+    double *out;
+    int xcd;
+};
+hipError_t launch_hop_force(const ForceArgs &f, hipStream_t st);
+
 // ---- gauge / clover set-up (gauge.hip) ----------------------------------
 // canonical host-order links (device, complex128) -> compressed FP64 links
 hipError_t launch_pack_links(const double *canon, double *links64, Geom g, hipStream_t st);

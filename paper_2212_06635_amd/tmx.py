@@ -90,6 +90,7 @@ def _load():
         "tmx_solve_mhat": ([P, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
         "tmx_multishift_solve": ([P, P, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
         "tmx_rational_apply": ([P, P, P, D, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
+        "tmx_hop_force": ([P, P, P, P, I, D, I], I),
         "tmx_rational_correction": ([P, P, D, P, P, I, D, I, ctypes.POINTER(tmx_solver_cfg), ctypes.POINTER(D),
                                      ctypes.POINTER(I)], I),
         "tmx_pc_num_params": ([P, ctypes.POINTER(Z)], I),
@@ -263,6 +264,11 @@ class Context:
         rc = self.check(lib.tmx_multishift_solve(self.h, _ptr(x), _ptr(b), sh.ctypes.data, len(sh),
                                                  ctypes.byref(cfg), info), allow_noconv=True)
         return rc, [i.as_dict() for i in info]
+
+    def hop_force(self, force, x, y, op=TMX_OP_PLUS, coeff=1.0, accumulate=0):
+        """force (= or +=) coeff * TA link derivative of Re<y, Mhat(op) x> (hopping terms)."""
+        return self.check(lib.tmx_hop_force(self.h, _ptr(force), _ptr(x), _ptr(y), int(op), float(coeff),
+                                            int(accumulate)))
 
     def rational_apply(self, out, b, a0, coeffs, shifts, **kw):
         """out = a0 b + sum_k coeffs[k] (N + shifts[k])^{-1} b (device odd fields)."""
