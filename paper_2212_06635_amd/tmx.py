@@ -267,6 +267,10 @@ class Context:
 
     def hop_force(self, force, x, y, op=TMX_OP_PLUS, coeff=1.0, accumulate=0):
         """force (= or +=) coeff * TA link derivative of Re<y, Mhat(op) x> (hopping terms)."""
+        # the library takes plain pointers: check the element counts here
+        for t, n, name in ((force, self.V * 36, "force"), (x, self.Vh * 12, "x"), (y, self.Vh * 12, "y")):
+            if hasattr(t, "numel") and t.numel() < n:
+                raise ValueError(f"{name} holds {t.numel()} complex values, needs {n}")
         return self.check(lib.tmx_hop_force(self.h, _ptr(force), _ptr(x), _ptr(y), int(op), float(coeff),
                                             int(accumulate)))
 

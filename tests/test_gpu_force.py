@@ -65,3 +65,5 @@ def test_hop_force_rejects_other_operators(S):
     for op in (tmx.TMX_OP_ND, tmx.TMX_OP_WPLUS):
         with pytest.raises(tmx.TmxError):
             ctx.hop_force(F, X, X, op=op)
+    with pytest.raises(ValueError):
+        ctx.hop_force(F[:10], X, X, op=1)  # too small an output: refused before any launch
