@@ -200,7 +200,7 @@ def main():
     ap.add_argument("--dims", default="32,32,32,64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-applies", type=int, default=3)
-    ap.add_argument("--mode", default="full", choices=["full", "kernels", "nn"],
+    ap.add_argument("--mode", default="full", choices=["full", "kernels", "nn", "force"],
                     help="kernels: only Mhat applies per precision and a copy of known size (for counters); "
                          "nn: only applications of the learned preconditioner (for counters)")
     ap.add_argument("--tune", action="store_true", help="autotune the stencil launch shapes first")
@@ -258,6 +258,22 @@ def main():
             c.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "nn", "lattice": list(dims), "applies": 5}), flush=True)
+        ctx.close()
+        return
+    if args.mode == "force":
+        # 10 hopping-term force calls (two K1 launches and the force kernel
+        # each), then the 2 GiB calibration copies
+        fy = torch.from_numpy(synth.gaussian_cb_spinor(dims, 4, 1).reshape(-1)).cuda()
+        fbuf = torch.zeros(Vh * 2 * 36, dtype=torch.complex128, device="cuda")
+        for _ in range(10):
+            ctx.hop_force(fbuf, bd, fy, op=1)
+        a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")
+        a.fill_(1.0)
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "force", "lattice": list(dims), "calls": 10, "Vh": Vh}), flush=True)
         ctx.close()
         return
     if args.mode == "kernels":

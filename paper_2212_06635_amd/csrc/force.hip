@@ -147,13 +147,17 @@ __device__ __forceinline__ void force_link(const ForceArgs &f, const int x[4], i
         }
 }
 
+// Workgroups alternate between the parities (workgroup 2i + p: sites
+// 256 i ... of parity p), so the contiguous workgroup range of an XCD holds
+// both parities of one region and the neighbours of its sites are read
+// through its own L2.
 __global__ void __launch_bounds__(256) hop_force_kernel(ForceArgs f)
 {
-    const long t = (long)xcd_block(f.xcd) * blockDim.x + threadIdx.x;
-    const long Vh = f.g.Vh;
-    if (t >= 2 * Vh) return;
-    const int p = t >= Vh ? 1 : 0;
-    const int s = (int)(t - p * Vh);
+    const long blk = xcd_block(f.xcd);
+    const int p = (int)(blk & 1);
+    const long st = (blk >> 1) * blockDim.x + threadIdx.x;
+    if (st >= f.g.Vh) return;
+    const int s = (int)st;
     int x[4];
     cb_coords(f.g, s, p, x);
     const long lex = x[0] + (long)f.g.L[0] * (x[1] + (long)f.g.L[1] * (x[2] + (long)f.g.L[2] * x[3]));
@@ -173,10 +177,11 @@ __global__ void __launch_bounds__(256) hop_force_kernel(ForceArgs f)
 
 hipError_t launch_hop_force(const ForceArgs &f, hipStream_t st)
 {
-    const long n = 2 * (long)f.g.Vh;
-    if (n == 0) return hipSuccess;
+    const long vh = f.g.Vh;
+    if (vh == 0) return hipSuccess;
     const int block = 256;
-    hipLaunchKernelGGL(hop_force_kernel, dim3((unsigned)((n + block - 1) / block)), dim3(block), 0, st, f);
+    const long nblk = 2 * ((vh + block - 1) / block);  // both parities, interleaved
+    hipLaunchKernelGGL(hop_force_kernel, dim3((unsigned)nblk), dim3(block), 0, st, f);
     return hipGetLastError();
 }
 
