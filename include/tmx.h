@@ -249,11 +249,12 @@ int tmx_pc_get_weights(tmx_ctx *ctx, float *host_w, size_t n);
  * complex128 device fields. */
 int tmx_pc_apply(tmx_ctx *ctx, double *out, const double *in, int dagger);
 
-/* Training loss (loss_kind as in tmx_train_cfg) over npairs canonical odd
- * device fields and its gradient with respect to the weights (host_grad may be
- * NULL), as used by one training step. */
-int tmx_pc_loss_grad(tmx_ctx *ctx, const double *b, const double *x, int npairs, int loss_kind, double *loss,
-                     float *host_grad);
+/* Training loss (loss_kind as in tmx_train_cfg, Mhat of op: TMX_OP_PLUS or
+ * TMX_OP_MINUS) over npairs canonical odd device fields and its gradient with
+ * respect to the weights (host_grad may be NULL), as used by one training
+ * step. */
+int tmx_pc_loss_grad(tmx_ctx *ctx, const double *b, const double *x, int npairs, int loss_kind, int op,
+                     double *loss, float *host_grad);
 
 typedef struct {
     int epochs;
@@ -262,6 +263,8 @@ typedef struct {
     float beta1, beta2, eps;
     int seed;
     int loss_kind; /* TMX_LOSS_RESIDUAL (default) or TMX_LOSS_SOLUTION */
+    int op;        /* operator the network is trained for: TMX_OP_PLUS (0 = default) or
+                      TMX_OP_MINUS (separately trained weights for the Mhat(-mu) solves) */
 } tmx_train_cfg;
 
 /* training losses over pairs (b_i, x_i = Mhat^{-1} b_i):

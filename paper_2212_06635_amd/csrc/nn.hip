@@ -1250,7 +1250,7 @@ int tmx_pc_apply(tmx_ctx *c, double *out, const double *in, int dagger)
 
 // gradient of the loss for a set of pairs (internal helper, also used by the
 // gradient check entry point): accumulates into the partial buffers, returns loss
-static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int *idx, int n, int loss_kind,
+static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int *idx, int n, int loss_kind, int op,
                         double *loss)
 {
     PcState &s = *c->pc;
@@ -1315,7 +1315,7 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
             pr.delta = E;
             pr.scale = 1.0;
             r = hip_err(c, run_blas(pr, Vh, 1, c->red, c->stream), "pair residual");
-            if (!r) r = op_mhat(c, Q, E, TMX_OP_PLUS, F32, 0, 1);
+            if (!r) r = op_mhat(c, Q, E, op, F32, 0, 1);
             if (r) return r;
             OpCopy<F32, F32> nq{};
             nq.d = Q;
@@ -1324,7 +1324,7 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
             r = hip_err(c, run_blas(nq, Vh, 1, c->red, c->stream), "residual norm");
             double qq = 0;
             if (!r) r = fetch(c, 1, &qq);
-            if (!r) r = op_mhat(c, E, Q, TMX_OP_PLUS, F32, 1, 1);
+            if (!r) r = op_mhat(c, E, Q, op, F32, 1, 1);
             if (r) return r;
             OpAxpby<F32, F32> sc{};
             sc.y = DL;
@@ -1370,16 +1370,18 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
     return TMX_OK;
 }
 
-int tmx_pc_loss_grad(tmx_ctx *c, const double *b, const double *x, int npairs, int loss_kind, double *loss,
+int tmx_pc_loss_grad(tmx_ctx *c, const double *b, const double *x, int npairs, int loss_kind, int op, double *loss,
                      float *host_grad)
 {
     if (!c || !b || !x || npairs < 1 || !loss) return TMX_EINVAL;
+    if (op != TMX_OP_PLUS && op != TMX_OP_MINUS)
+        return set_err(c, TMX_EINVAL, "the network is trained for Mhat(+mu) or Mhat(-mu)");
     int r = nn_ensure(c);
     if (r) return r;
     if (!c->pc->have_weights) return set_err(c, TMX_ENOTLOADED, "preconditioner weights not set");
     r = ensure_ready(c, F32, false);
     if (!r) r = nn_build_weights(c);
-    if (!r) r = pc_loss_grad(c, b, x, nullptr, npairs, loss_kind, loss);
+    if (!r) r = pc_loss_grad(c, b, x, nullptr, npairs, loss_kind, op, loss);
     if (r) return r;
     if (host_grad) {
         hipError_t e = hipMemcpyAsync(host_grad, c->pc->grad, c->pc->nparam * sizeof(float), hipMemcpyDeviceToHost,
@@ -1393,6 +1395,9 @@ int tmx_pc_loss_grad(tmx_ctx *c, const double *b, const double *x, int npairs, i
 int tmx_pc_train(tmx_ctx *c, const double *b, const double *x, int npairs, const tmx_train_cfg *cfg, float *loss_out)
 {
     if (!c || !b || !x || npairs < 1 || !cfg || cfg->epochs < 1 || cfg->batch < 1) return TMX_EINVAL;
+    const int op = cfg->op == 0 ? TMX_OP_PLUS : cfg->op;
+    if (op != TMX_OP_PLUS && op != TMX_OP_MINUS)
+        return set_err(c, TMX_EINVAL, "the network is trained for Mhat(+mu) or Mhat(-mu)");
     int r = nn_ensure(c);
     if (r) return r;
     if (!c->pc->have_weights) return set_err(c, TMX_ENOTLOADED, "preconditioner weights not set");
@@ -1424,7 +1429,7 @@ int tmx_pc_train(tmx_ctx *c, const double *b, const double *x, int npairs, const
             r = nn_build_weights(c);
             if (r) return r;
             double L;
-            r = pc_loss_grad(c, b, x, order.data() + i0, n, cfg->loss_kind, &L);
+            r = pc_loss_grad(c, b, x, order.data() + i0, n, cfg->loss_kind, op, &L);
             if (r) return r;
             if (!std::isfinite(L)) return set_err(c, TMX_ENOCONV, "training loss is not finite");
             eloss += L;

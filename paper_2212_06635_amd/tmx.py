@@ -58,7 +58,7 @@ class tmx_info(ctypes.Structure):
 class tmx_train_cfg(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
-                ("seed", ctypes.c_int), ("loss_kind", ctypes.c_int)]
+                ("seed", ctypes.c_int), ("loss_kind", ctypes.c_int), ("op", ctypes.c_int)]
 
 
 def _load():
@@ -98,7 +98,7 @@ def _load():
         "tmx_pc_get_weights": ([P, P, Z], I),
         "tmx_pc_apply": ([P, P, P, I], I),
         "tmx_pc_train": ([P, P, P, I, ctypes.POINTER(tmx_train_cfg), P], I),
-        "tmx_pc_loss_grad": ([P, P, P, I, I, ctypes.POINTER(D), P], I),
+        "tmx_pc_loss_grad": ([P, P, P, I, I, I, ctypes.POINTER(D), P], I),
         "tmx_tune": ([P, I, I, I], I),
         "tmx_tuned_config": ([P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(I)], I),
         "tmx_kstats_enable": ([P, I], I),
@@ -319,8 +319,8 @@ class Context:
         return self.check(lib.tmx_pc_apply(self.h, _ptr(out), _ptr(inp), int(dagger)))
 
     def pc_train(self, b, x, npairs, epochs=10, batch=8, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0,
-                 loss_kind=0):
-        cfg = tmx_train_cfg(epochs, batch, lr, beta1, beta2, eps, seed, loss_kind)
+                 loss_kind=0, op=TMX_OP_PLUS):
+        cfg = tmx_train_cfg(epochs, batch, lr, beta1, beta2, eps, seed, loss_kind, op)
         loss = np.zeros(epochs, dtype=np.float32)
         self.check(lib.tmx_pc_train(self.h, _ptr(b), _ptr(x), npairs, ctypes.byref(cfg), loss.ctypes.data))
         return loss
@@ -352,10 +352,10 @@ class Context:
             i += 1
         return out
 
-    def pc_loss_grad(self, b, x, npairs, loss_kind=0):
+    def pc_loss_grad(self, b, x, npairs, loss_kind=0, op=TMX_OP_PLUS):
         loss = ctypes.c_double()
         g = np.zeros(self.pc_num_params(), dtype=np.float32)
-        self.check(lib.tmx_pc_loss_grad(self.h, _ptr(b), _ptr(x), npairs, loss_kind, ctypes.byref(loss),
+        self.check(lib.tmx_pc_loss_grad(self.h, _ptr(b), _ptr(x), npairs, loss_kind, op, ctypes.byref(loss),
                                         g.ctypes.data))
         return loss.value, g
 

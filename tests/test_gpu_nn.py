@@ -66,21 +66,23 @@ def test_random_network_matches_oracle(S, dagger):
     assert rel_l2(to_host(out, b.shape)[:, 0], ref) < 2e-2
 
 
-@pytest.mark.parametrize("loss_kind", [0, 1])
-def test_gradient_matches_oracle(S, loss_kind):
-    """GPU loss and weight gradient (residual and solution losses) against the oracle's."""
+@pytest.mark.parametrize("loss_kind,op", [(0, 1), (1, 1), (0, -1)])
+def test_gradient_matches_oracle(S, loss_kind, op):
+    """GPU loss and weight gradient (residual and solution losses; the residual
+    loss also for Mhat(-mu), the operator of separately trained weights)
+    against the oracle's."""
     tmx, ctx, lat, U = S
     rng = np.random.default_rng(42)
     w = (nn.identity_init(rng, 0.1)).astype(np.float32)
     ctx.pc_set_weights(w)
     bs = np.stack([synth.gaussian_cb_spinor(DIMS, 42, k) for k in range(2)])
     xs = np.stack([synth.gaussian_cb_spinor(DIMS, 43, k) for k in range(2)])
-    loss, g = ctx.pc_loss_grad(to_dev(bs), to_dev(xs), 2, loss_kind)
+    loss, g = ctx.pc_loss_grad(to_dev(bs), to_dev(xs), 2, loss_kind, op)
     ops = ()
     if loss_kind == 0:
         o = Oracle(DIMS, U, KAPPA, CSW, mu=MU0)
-        ops = (lambda v: o.mhat(v.reshape(-1, 1, 4, 3)).reshape(-1, 4, 3),
-               lambda v: o.mhat(v.reshape(-1, 1, 4, 3), dagger=True).reshape(-1, 4, 3))
+        ops = (lambda v: o.mhat(v.reshape(-1, 1, 4, 3), sgn=op).reshape(-1, 4, 3),
+               lambda v: o.mhat(v.reshape(-1, 1, 4, 3), sgn=op, dagger=True).reshape(-1, 4, 3))
     L, gref = nn.loss_and_grad(lat, f32(w), [b[:, 0] for b in bs], [x[:, 0] for x in xs], *ops)
     assert abs(loss - L) / L < 2e-2
     cos = float(np.dot(g, gref) / np.linalg.norm(g) / np.linalg.norm(gref))
@@ -163,3 +165,34 @@ def test_weights_validation(S):
     bad[5] = np.nan
     with pytest.raises(tmx.TmxError):
         ctx.pc_set_weights(bad)
+
+
+def test_separately_trained_weights_for_minus_mu(S):
+    """Weights trained for Mhat(-mu) on (b, Mhat(-mu)^{-1} b) pairs (the
+    residual loss with Mhat(-mu)) precondition the Mhat(-mu) solve: fewer
+    iterations than the identity network, solution accepted by the oracle."""
+    tmx, ctx, lat, U = S
+    o = Oracle(DIMS, U, KAPPA, CSW, mu=MU0)
+    n = 16
+    bs = np.stack([synth.gaussian_cb_spinor(DIMS, 70, k) for k in range(n)])
+    xd = to_dev(np.zeros_like(bs))
+    for k in range(n):
+        xk = to_dev(np.zeros_like(bs[k]))
+        rc, info = ctx.solve_mhat(xk, to_dev(bs[k]), dagger=0, op=-1, tol=1e-10)
+        assert rc == tmx.TMX_OK
+        xd[k * bs[k].size:(k + 1) * bs[k].size] = xk
+    b = synth.gaussian_cb_spinor(DIMS, 71, 0)
+    ctx.pc_set_weights(nn.identity_init(None))
+    x = to_dev(np.zeros_like(b))
+    rc0, info0 = ctx.solve(x, to_dev(b), 1, kind=tmx.TMX_SOLVER_PCG_NN, op=-1, tol=1e-10)
+    ctx.pc_set_weights(nn.identity_init(np.random.default_rng(3), 1e-2))
+    losses = ctx.pc_train(to_dev(bs), xd, n, epochs=30, batch=4, lr=3e-3, seed=2, loss_kind=0, op=-1)
+    assert losses[-1] < 0.7 * losses[0], losses
+    x = to_dev(np.zeros_like(b))
+    rc1, info1 = ctx.solve(x, to_dev(b), 1, kind=tmx.TMX_SOLVER_PCG_NN, op=-1, tol=1e-10)
+    print("PCG(-mu) iterations identity / trained for -mu:", info0[0]["iters"], info1[0]["iters"])
+    assert rc0 == tmx.TMX_OK and rc1 == tmx.TMX_OK
+    assert info1[0]["iters"] < info0[0]["iters"], (info0, info1)
+    assert o.residual(b, to_host(x, b.shape), sgn=-1) <= 1e-10
+    with pytest.raises(tmx.TmxError):
+        ctx.pc_train(to_dev(bs), xd, n, epochs=1, op=2)
