@@ -116,3 +116,18 @@ def test_w_rejected_where_undefined(S):
     full = to_dev(synth.gaussian_spinor(int(np.prod(dims)), 27, 0))
     with pytest.raises(tmx.TmxError):
         ctx.apply_D(full * 0, full, tmx.TMX_OP_WPLUS, 0)
+
+
+def test_multishift_w_normal(S):
+    """Multishift solve of (What^+)^dagger What^+ + sigma_k (FP32 inner, FP64
+    refinement), each shift accepted by the oracle's FP64 residual."""
+    tmx, o, ctx, dims = S
+    b = synth.gaussian_cb_spinor(dims, 28, 0)
+    shifts = np.array([0.0, 1e-3, 1e-2, 1e-1])
+    xs = to_dev(np.zeros((len(shifts),) + b.shape))
+    rc, info = ctx.multishift_solve(xs, to_dev(b), shifts, op=tmx.TMX_OP_WPLUS, tol=1e-10, inner_prec=1)
+    assert rc == tmx.TMX_OK
+    xh = to_host(xs, (len(shifts),) + b.shape)
+    for k, s in enumerate(shifts):
+        r = b - (o.w_normal(xh[k], 1, RHO) + s * xh[k])
+        assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
