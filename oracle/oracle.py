@@ -257,6 +257,93 @@ class Oracle:
             F[:, mu] = A - (np.trace(A, axis1=1, axis2=2) / 3.0)[:, None, None] * np.eye(3)
         return F
 
+    def _force_fields(self, X, Y, sgn):
+        """Full-lattice a (Y | B_ee(-sgn)^-1 g5 H_eo g5 Y) and b (X | B_ee(sgn)^-1 H_eo X),
+        shape (V, 4, 3), the lexicographic coordinates and the parity of every site."""
+        g, _ = self.gammas()
+        lx, ly, lz, lt = self.dims
+        V = self.V
+        lex = np.arange(V)
+        co = np.stack([lex % lx, (lex // lx) % ly, (lex // (lx * ly)) % lz, lex // (lx * ly * lz)], axis=1)
+        par = co.sum(axis=1) % 2
+        odd, even = np.nonzero(par == 1)[0], np.nonzero(par == 0)[0]
+        g5 = lambda f: np.einsum("st,xtc->xsc", g[4], f)
+        hop_even = lambda f: self.hop(f.reshape(V, 1, 4, 3), out_parity=0).reshape(V, 4, 3)
+
+        def full(v_odd):
+            f = np.zeros((V, 4, 3), dtype=np.complex128)
+            f[odd] = _c(v_odd).reshape(-1, 4, 3)
+            return f
+
+        def block_solve(f, s):
+            out = np.zeros_like(f)
+            for x in even:
+                out[x] = np.linalg.solve(self.site_block(int(x), 1, s), f[x].reshape(12)).reshape(4, 3)
+            return out
+
+        b, a = full(X), full(Y)
+        b[even] = block_solve(hop_even(b), sgn)[even]
+        a[even] = block_solve(g5(hop_even(g5(a))), -sgn)[even]
+        return a, b, co, par
+
+    def clover_force(self, X, Y, sgn=1):
+        """Link derivative of S = Re<Y, Mhat(sgn) X> through the clover term
+        T = i kappa csw sum_{mu<nu} sigma_mu,nu F_mu,nu (F = (Q - Q^dagger)/8, Q the
+        four leaves), hopping matrices held fixed, in the convention of hop_force:
+        dS/d eps = Re Tr[i T F_rho(y)] for U_rho(y) -> exp(i eps T) U_rho(y).
+        With Lambda = c b a^dagger (c = 1 odd, kappa^2 even; a, b as in hop_force),
+        G_rn(z) = c sum_s (sigma_rn b)_s a_s^dagger, H = G + G^dagger, and for
+        every plane (rho, nu) the plaquettes through U_rho(y) oriented rho -> nu
+        with H inserted at each corner:
+        F = TA[(i kappa csw / 8) sum_nu (U C_up - E_low U^dagger)].  Shape (V, 4, 3, 3)."""
+        _, sig = self.gammas()
+        a, b, co, par = self._force_fields(X, Y, sgn)
+        V = self.V
+        L = self.dims
+        c = np.where(par == 1, 1.0, self.kappa ** 2)
+        U = self.U
+        dag = lambda m: np.conj(np.swapaxes(m, -1, -2))
+        mm = lambda *ms: ms[0] if len(ms) == 1 else np.einsum("xij,xjk->xik", ms[0], mm(*ms[1:]))
+
+        def sh(idx, mu, d):
+            cc = co[idx].copy()
+            cc[:, mu] = (cc[:, mu] + d) % L[mu]
+            return cc[:, 0] + L[0] * (cc[:, 1] + L[1] * (cc[:, 2] + L[2] * cc[:, 3]))
+
+        H = {}
+        for r in range(4):
+            for n in range(4):
+                if r != n:
+                    sb = np.einsum("st,xtc->xsc", sig[r, n], b)
+                    G = c[:, None, None] * np.einsum("xsi,xsj->xij", sb, np.conj(a))
+                    H[r, n] = G + dag(G)
+        F = np.zeros((V, 4, 3, 3), dtype=np.complex128)
+        y = np.arange(V)
+        for r in range(4):
+            Z = np.zeros((V, 3, 3), dtype=np.complex128)
+            Ur = U[:, r]
+            for n in range(4):
+                if n == r:
+                    continue
+                h = H[r, n]
+                yr, yn = sh(y, r, 1), sh(y, n, 1)
+                yrn = sh(yr, n, 1)
+                ymn = sh(y, n, -1)
+                ymnr = sh(ymn, r, 1)
+                # upper plaquette y -> y+r -> y+r+n -> y+n -> y
+                a1, a2, a3 = U[yr, n], dag(U[yn, r]), dag(U[y, n])
+                B = mm(a1, a2, a3)
+                Cup = (mm(B, h[y]) + mm(h[yr], B) + mm(a1, h[yrn], a2, a3) + mm(a1, a2, h[yn], a3))
+                # lower plaquette y-n -> y-n+r -> y+r -> y -> y-n, through U_r(y)^dagger
+                d1, d2, d3 = dag(U[ymn, n]), U[ymn, r], U[ymnr, n]
+                D = mm(d1, d2, d3)
+                Elow = (mm(D, h[yr]) + mm(h[y], D) + mm(d1, h[ymn], d2, d3) + mm(d1, d2, h[ymnr], d3))
+                Z += mm(Ur, Cup) - mm(Elow, dag(Ur))
+            Z *= 1j * self.kappa * self.csw / 8.0
+            A = 0.5 * (Z - dag(Z))
+            F[:, r] = A - (np.trace(A, axis1=1, axis2=2) / 3.0)[:, None, None] * np.eye(3)
+        return F
+
     # -- rational approximation (Section 4.2) --------------------------------
     def rational(self, b, a0, coeffs, shifts, nf=1, sgn=1, tol=1e-13):
         """a0 b + sum_k coeffs[k] (N + shifts[k])^{-1} b, each solve by the oracle's CG."""

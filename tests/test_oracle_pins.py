@@ -454,3 +454,31 @@ def test_hop_force_against_finite_differences(rough, sgn):
         h = 1e-5
         numeric = (S(h) - S(-h)) / (2 * h)
         assert abs(numeric - analytic) < 1e-7 * abs(analytic)
+
+
+@pytest.mark.parametrize("sgn", [1, -1])
+def test_full_force_against_finite_differences(rough, sgn):
+    """The whole link derivative of Re<Y, Mhat X> -- hopping terms and the clover
+    term rebuilt from the perturbed links -- by central differences, against
+    hop_force + clover_force along random su(3) directions on every link."""
+    U, o = rough
+    rng = np.random.default_rng(23)
+    X = synth.gaussian_cb_spinor(SYM_DIMS, 9, 0)
+    Y = synth.gaussian_cb_spinor(SYM_DIMS, 9, 1)
+    Fh, Fc = o.hop_force(X, Y, sgn), o.clover_force(X, Y, sgn)
+    assert np.abs(Fc + np.conj(np.swapaxes(Fc, 2, 3))).max() < 1e-13
+    assert np.abs(np.trace(Fc, axis1=2, axis2=3)).max() < 1e-13
+    U4 = U.reshape(o.V, 4, 3, 3)
+    P = _random_su3_algebra(o.V * 4, rng).reshape(o.V, 4, 3, 3)
+    lin = lambda F: float(np.sum(np.einsum("xmij,xmji->xm", 1j * P, F).real))
+
+    def S(eps):
+        Ue = np.einsum("xmij,xmjk->xmik", _expi(eps * P.reshape(-1, 3, 3)).reshape(o.V, 4, 3, 3), U4)
+        oe = Oracle(SYM_DIMS, Ue, KAPPA, CSW, mu=o.mu)   # clover term rebuilt from Ue
+        return float(np.vdot(Y.reshape(-1), oe.mhat(X, sgn=sgn).reshape(-1)).real)
+
+    h = 1e-5
+    numeric = (S(h) - S(-h)) / (2 * h)
+    total = lin(Fh) + lin(Fc)
+    assert abs(lin(Fc)) > 1e-3 * abs(total)          # the clover part matters here
+    assert abs(numeric - total) < 1e-7 * abs(total)
