@@ -267,6 +267,8 @@ def main():
         fbuf = torch.zeros(Vh * 2 * 36, dtype=torch.complex128, device="cuda")
         for _ in range(10):
             ctx.hop_force(fbuf, bd, fy, op=1)
+        for _ in range(10):
+            ctx.clover_force(fbuf, bd, fy, op=1)
         a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")
         a.fill_(1.0)
         c = torch.empty_like(a)
@@ -490,6 +492,19 @@ def main():
         fbytes = 1344.0 * 2 * Vh  # a, b fields (2 x 192 B), 4 links (4 x 96 B), 4 outputs (4 x 144 B) per site
         out["hop_force_f64"] = {"kernel_ms": round(ms_tot / n, 4), "GBps": round(fbytes / (ms_tot / n * 1e-3) / 1e9, 1),
                                 "bytes_per_site": 1344}
+    # clover-term force: six sigma-plane insertions per site, then the staple
+    # sums with the insertion at every plaquette corner
+    ctx.kstats_enable(True)
+    for _ in range(5):
+        ctx.clover_force(fbuf, x, bd, op=1)
+    torch.cuda.synchronize()
+    cks = ctx.kstats()
+    ctx.kstats_enable(False)
+    if "CLOVER_FORCE" in cks:
+        n, ms_tot = cks["CLOVER_FORCE"]
+        cbytes = 3072.0 * 2 * Vh  # a, b (384 B) + H written and read (2 x 864 B) + 4 links (384 B) + 4 outputs (576 B)
+        out["clover_force_f64"] = {"kernel_ms": round(ms_tot / n, 4),
+                                   "GBps": round(cbytes / (ms_tot / n * 1e-3) / 1e9, 1), "bytes_per_site": 3072}
     del fbuf
     if dims == (32, 32, 32, 64):
         log("learned preconditioner on a 24^3x48 field")

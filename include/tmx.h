@@ -193,6 +193,16 @@ int tmx_apply_mdagm(tmx_ctx *ctx, void *out, const void *in, int op, int prec, i
  * op: TMX_OP_PLUS or TMX_OP_MINUS.  Enqueued on the context stream. */
 int tmx_hop_force(tmx_ctx *ctx, double *force, const double *x, const double *y, int op, double coeff,
                   int accumulate);
+/* Clover-term force (Section 4.3, the clover term of Section 2): the same
+ * derivative of S = Re<y, Mhat(op) x> taken through the clover term
+ * T = i kappa csw sum_{mu<nu} sigma_mu,nu F_mu,nu (F the four-leaf field
+ * strength) of both parities, in A_oo and inside A_ee^{-1}, with the hopping
+ * matrices held fixed.  Same arguments, layout and accumulation as
+ * tmx_hop_force; the full link derivative of S is the sum of the two.
+ * TMX_EINVAL if the clover term was loaded with tmx_load_clover (the force
+ * needs it built from the links).  Uses a 1728 Vh-byte workspace. */
+int tmx_clover_force(tmx_ctx *ctx, double *force, const double *x, const double *y, int op, double coeff,
+                     int accumulate);
 
 /* ---- solvers (device buffers, canonical complex128 odd fields) -------- */
 

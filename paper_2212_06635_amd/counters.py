@@ -201,36 +201,47 @@ def network(d: str, v: int) -> str:
     return "\n".join(lines) + "\n"
 
 
+# force kernels: (kernel-name fragment, label, model bytes per site, read, write)
+FORCE_KERNELS = (
+    ("hop_force_kernel", "HOP_FORCE", 1344, 768, 576),          # a, b 2 x 192, 4 links x 96 | 4 outputs x 144
+    ("clover_insertion_kernel", "CLOV_INSERT", 1248, 384, 864),  # a, b | 6 planes x 144
+    ("clover_force_kernel", "CLOV_LINKS", 1824, 1248, 576),     # 6 planes x 144, 4 links x 96 | 4 outputs x 144
+)
+
+
 def force(d: str, v: int) -> str:
-    """Hopping-term force kernel: time, counter traffic against the model
-    (a and b fields 2 x 192 B, 4 links x 96 B, 4 outputs x 144 B per site)."""
+    """Force kernels: time, counter traffic against the byte model of each."""
     st = _stats(_find(os.path.join(d, "p_k"), "kernel_stats.csv"))
     pf = _find(os.path.join(d, "p_f"), "counter_collection.csv")
     pw = _find(os.path.join(d, "p_w"), "counter_collection.csv")
     f, w = _pmc(pf, "FETCH_SIZE"), _pmc(pw, "WRITE_SIZE")
     copy_f, copy_w = _copy_kib(pf, "FETCH_SIZE"), _copy_kib(pw, "WRITE_SIZE")
     sf, sw = COPY_BYTES / 1024 / copy_f, COPY_BYTES / 1024 / copy_w
-    model = 1344.0 * v
     lines = [
-        f"# hopping-term force kernel, V = {v} sites (all 4V links), MI355X",
+        f"# fermion-force kernels (hopping term; clover term = insertions + link sums), V = {v} sites "
+        "(all 4V links), MI355X",
         "# commands (from /tmp, TMPDIR=/tmp; <repo> = repository root):",
         "#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/p_k -o k -- python3 <repo>/bench.py --mode force",
         "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/p_f -o f -- python3 <repo>/bench.py --mode force",
         "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/p_w -o w -- python3 <repo>/bench.py --mode force",
         "#   python3 -m paper_2212_06635_amd.counters force <dir> <this file>",
-        "# bench.py --mode force: 10 force calls on the 32^3x64 field, then 3 device copies of 2 GiB",
-        f"# FETCH scale {sf:.3f}, WRITE scale {sw:.3f}; model bytes per site 1344 (read 768, write 576)",
+        "# bench.py --mode force: 10 hopping-force and 10 clover-force calls on the 32^3x64 field, "
+        "then 3 device copies of 2 GiB",
+        f"# FETCH scale {sf:.3f}, WRITE scale {sw:.3f}; model bytes per site: "
+        + ", ".join(f"{lab} {b} (read {r}, write {wr})" for _, lab, b, r, wr in FORCE_KERNELS),
         "",
         f"{'kernel':12s} {'calls':>5s} {'avg_us':>8s} {'model_MB':>9s} {'fetch_MB':>9s} {'write_MB':>9s} {'model_GB/s':>10s} {'%8TB/s':>7s}",
     ]
-    for name, (calls, avg) in sorted(st.items()):
-        if "hop_force_kernel" not in name:
-            continue
-        fe = f.get(name, 0.0) * 1024 * sf
-        wr = w.get(name, 0.0) * 1024 * sw
-        gbs = model / (avg * 1e-9) / 1e9
-        lines.append(f"{'HOP_FORCE':12s} {calls:5d} {avg / 1e3:8.1f} {model / 1e6:9.1f} {fe / 1e6:9.1f} {wr / 1e6:9.1f} "
-                     f"{gbs:10.1f} {gbs / 80:7.1f}")
+    for frag, label, bps, _, _ in FORCE_KERNELS:
+        for name, (calls, avg) in sorted(st.items()):
+            if frag not in name:
+                continue
+            model = float(bps) * v
+            fe = f.get(name, 0.0) * 1024 * sf
+            wr = w.get(name, 0.0) * 1024 * sw
+            gbs = model / (avg * 1e-9) / 1e9
+            lines.append(f"{label:12s} {calls:5d} {avg / 1e3:8.1f} {model / 1e6:9.1f} {fe / 1e6:9.1f} {wr / 1e6:9.1f} "
+                         f"{gbs:10.1f} {gbs / 80:7.1f}")
     return "\n".join(lines) + "\n"
 
 

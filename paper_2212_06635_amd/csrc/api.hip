@@ -15,6 +15,7 @@
 #include <string>
 
 #include "tmx_ctx.h"
+#include "force.h"
 
 using namespace tmx;
 
@@ -783,24 +784,28 @@ int tmx_apply_mdagm(tmx_ctx *c, void *out, const void *in, int op, int prec, int
                     prec, nrhs);
 }
 
-int tmx_hop_force(tmx_ctx *c, double *force, const double *x, const double *y, int op, double coeff, int accumulate)
+// Full-lattice fields of the force terms: X, Y odd (packed from x, y),
+// u = B_ee(s)^{-1} H_eo X and w' = B_ee(-s)^{-1} H_eo g5 Y even (the force
+// kernels apply the outer g5 of w).
+struct ForceFields {
+    SpinorPtr X, Y, u, w;
+};
+
+static int force_fields(tmx_ctx *c, const double *x, const double *y, int op, ForceFields &ff)
 {
-    if (!c || !force || !x || !y || !std::isfinite(coeff))
-        return c ? set_err(c, TMX_EINVAL, "tmx_hop_force: bad argument") : TMX_EINVAL;
-    if (op != TMX_OP_PLUS && op != TMX_OP_MINUS)
-        return set_err(c, TMX_EINVAL, "the hopping force is built for the degenerate Schur operator");
     int r = ensure_ready(c, F64, false);
     if (r) return r;
     const size_t fb = spinor_field_bytes(F64, 1, c->Vh);
     void *px = ws_get(c, "hf_x", fb), *py = ws_get(c, "hf_y", fb), *pu = ws_get(c, "hf_u", fb),
          *pw = ws_get(c, "hf_w", fb);
-    if (!px || !py || !pu || !pw) return set_err(c, TMX_ENOMEM, "hop force workspace: out of device memory");
-    SpinorPtr X = make_spinor(px, F64, 1, c->Vh), Y = make_spinor(py, F64, 1, c->Vh),
-              U = make_spinor(pu, F64, 1, c->Vh), W = make_spinor(pw, F64, 1, c->Vh);
-    r = hip_err(c, launch_pack_spinor(x, X, F64, TMX_FIELD_ODD, c->g, 1, c->stream), "pack x");
-    if (!r) r = hip_err(c, launch_pack_spinor(y, Y, F64, TMX_FIELD_ODD, c->g, 1, c->stream), "pack y");
+    if (!px || !py || !pu || !pw) return set_err(c, TMX_ENOMEM, "force workspace: out of device memory");
+    ff.X = make_spinor(px, F64, 1, c->Vh);
+    ff.Y = make_spinor(py, F64, 1, c->Vh);
+    ff.u = make_spinor(pu, F64, 1, c->Vh);
+    ff.w = make_spinor(pw, F64, 1, c->Vh);
+    r = hip_err(c, launch_pack_spinor(x, ff.X, F64, TMX_FIELD_ODD, c->g, 1, c->stream), "pack x");
+    if (!r) r = hip_err(c, launch_pack_spinor(y, ff.Y, F64, TMX_FIELD_ODD, c->g, 1, c->stream), "pack y");
     if (r) return r;
-    // u = B_ee(s)^{-1} H_eo X ; w' = B_ee(-s)^{-1} H_eo g5 Y (the force kernel applies the outer g5)
     const LaunchCfg l1 = launch_cfg(c, kname("K1", F64, false, 1));
     DslashArgs a = base_args(c, F64, false, 1);
     a.parity = 0;
@@ -808,23 +813,34 @@ int tmx_hop_force(tmx_ctx *c, double *force, const double *x, const double *y, i
     a.inv = c->inv[F64];
     a.xcd = l1.xcd;
     a.sgn = op;
-    a.in = X;
-    a.out = U;
+    a.in = ff.X;
+    a.out = ff.u;
     hipError_t e = launch_dslash(F64, 1, 0, a, c->stream, l1.block);
     if (e != hipSuccess) return hip_err(c, e, "K1 launch");
     a.sgn = -op;
     a.g5in = 1;
-    a.in = Y;
-    a.out = W;
+    a.in = ff.Y;
+    a.out = ff.w;
     e = launch_dslash(F64, 1, 0, a, c->stream, l1.block);
-    if (e != hipSuccess) return hip_err(c, e, "K1 launch");
+    return e != hipSuccess ? hip_err(c, e, "K1 launch") : TMX_OK;
+}
+
+int tmx_hop_force(tmx_ctx *c, double *force, const double *x, const double *y, int op, double coeff, int accumulate)
+{
+    if (!c || !force || !x || !y || !std::isfinite(coeff))
+        return c ? set_err(c, TMX_EINVAL, "tmx_hop_force: bad argument") : TMX_EINVAL;
+    if (op != TMX_OP_PLUS && op != TMX_OP_MINUS)
+        return set_err(c, TMX_EINVAL, "the hopping force is built for the degenerate Schur operator");
+    ForceFields ff;
+    int r = force_fields(c, x, y, op, ff);
+    if (r) return r;
     ForceArgs f{};
     f.g = c->g;
     f.U = LinkPtr{c->links[F64], c->Vh};
-    f.X = X;
-    f.Y = Y;
-    f.u = U;
-    f.w = W;
+    f.X = ff.X;
+    f.Y = ff.Y;
+    f.u = ff.u;
+    f.w = ff.w;
     f.t_bc = c->par.t_bc;
     f.kfac = c->par.kappa * c->par.kappa;
     f.coeff = coeff;
@@ -832,9 +848,42 @@ int tmx_hop_force(tmx_ctx *c, double *force, const double *x, const double *y, i
     f.out = force;
     f.xcd = c->xcd_remap;
     kstat_begin(c, "HOP_FORCE");
-    e = launch_hop_force(f, c->stream);
+    hipError_t e = launch_hop_force(f, c->stream);
     kstat_end(c);
     return hip_err(c, e, "hop force");
+}
+
+int tmx_clover_force(tmx_ctx *c, double *force, const double *x, const double *y, int op, double coeff,
+                     int accumulate)
+{
+    if (!c || !force || !x || !y || !std::isfinite(coeff))
+        return c ? set_err(c, TMX_EINVAL, "tmx_clover_force: bad argument") : TMX_EINVAL;
+    if (op != TMX_OP_PLUS && op != TMX_OP_MINUS)
+        return set_err(c, TMX_EINVAL, "the clover force is built for the degenerate Schur operator");
+    if (c->clover_from_host)
+        return set_err(c, TMX_EINVAL, "the clover force needs the clover term built from the links");
+    ForceFields ff;
+    int r = force_fields(c, x, y, op, ff);
+    if (r) return r;
+    void *ph = ws_get(c, "cf_h", (size_t)6 * 9 * 2 * c->Vh * sizeof(double2));
+    if (!ph) return set_err(c, TMX_ENOMEM, "clover force workspace: out of device memory");
+    CloverForceArgs f{};
+    f.g = c->g;
+    f.U = LinkPtr{c->links[F64], c->Vh};
+    f.X = ff.X;
+    f.Y = ff.Y;
+    f.u = ff.u;
+    f.w = ff.w;
+    f.kfac = c->par.kappa * c->par.kappa;
+    f.kc8 = c->par.kappa * c->par.csw / 8.0;
+    f.coeff = coeff;
+    f.accumulate = accumulate ? 1 : 0;
+    f.H = static_cast<double2 *>(ph);
+    f.out = force;
+    kstat_begin(c, "CLOVER_FORCE");
+    hipError_t e = launch_clover_force(f, c->stream);
+    kstat_end(c);
+    return hip_err(c, e, "clover force");
 }
 
 // ---- autotuner -----------------------------------------------------------------

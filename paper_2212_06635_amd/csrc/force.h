@@ -1,0 +1,26 @@
+// Clover-term force (force.hip): declarations shared by the kernels and the
+// library entry point.
+#pragma once
+#include "tmx_device.h"
+
+namespace tmx {
+
+// out[lex][rho] (3x3 complex, canonical link layout) = coeff TA(Z_rho(x))
+// (+ out if accumulate), the link derivative of Re<Y, Mhat X> through the
+// clover term of both parities (hopping matrices fixed).  X, Y odd,
+// u = K1(s) X, w = K1(-s, g5 in) Y even, all FP64.  H is the insertion
+// workspace: 6 planes x 9 entries x 2 Vh double2, site index p Vh + s.
+struct CloverForceArgs {
+    Geom g;
+    LinkPtr U;
+    SpinorPtr X, Y, u, w;
+    double kfac;  // kappa^2, the weight of the even-site term
+    double kc8;   // kappa csw / 8
+    double coeff;
+    int accumulate;
+    double2 *H;
+    double *out;
+};
+hipError_t launch_clover_force(const CloverForceArgs &f, hipStream_t st);
+
+}  // namespace tmx

@@ -91,6 +91,7 @@ def _load():
         "tmx_multishift_solve": ([P, P, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
         "tmx_rational_apply": ([P, P, P, D, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
         "tmx_hop_force": ([P, P, P, P, I, D, I], I),
+        "tmx_clover_force": ([P, P, P, P, I, D, I], I),
         "tmx_rational_correction": ([P, P, D, P, P, I, D, I, ctypes.POINTER(tmx_solver_cfg), ctypes.POINTER(D),
                                      ctypes.POINTER(I)], I),
         "tmx_pc_num_params": ([P, ctypes.POINTER(Z)], I),
@@ -267,12 +268,21 @@ class Context:
 
     def hop_force(self, force, x, y, op=TMX_OP_PLUS, coeff=1.0, accumulate=0):
         """force (= or +=) coeff * TA link derivative of Re<y, Mhat(op) x> (hopping terms)."""
+        self._check_force_sizes(force, x, y)
+        return self.check(lib.tmx_hop_force(self.h, _ptr(force), _ptr(x), _ptr(y), int(op), float(coeff),
+                                            int(accumulate)))
+
+    def clover_force(self, force, x, y, op=TMX_OP_PLUS, coeff=1.0, accumulate=0):
+        """force (= or +=) coeff * TA link derivative of Re<y, Mhat(op) x> (clover term)."""
+        self._check_force_sizes(force, x, y)
+        return self.check(lib.tmx_clover_force(self.h, _ptr(force), _ptr(x), _ptr(y), int(op), float(coeff),
+                                               int(accumulate)))
+
+    def _check_force_sizes(self, force, x, y):
         # the library takes plain pointers: check the element counts here
         for t, n, name in ((force, self.V * 36, "force"), (x, self.Vh * 12, "x"), (y, self.Vh * 12, "y")):
             if hasattr(t, "numel") and t.numel() < n:
                 raise ValueError(f"{name} holds {t.numel()} complex values, needs {n}")
-        return self.check(lib.tmx_hop_force(self.h, _ptr(force), _ptr(x), _ptr(y), int(op), float(coeff),
-                                            int(accumulate)))
 
     def rational_apply(self, out, b, a0, coeffs, shifts, **kw):
         """out = a0 b + sum_k coeffs[k] (N + shifts[k])^{-1} b (device odd fields)."""

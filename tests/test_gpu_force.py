@@ -1,6 +1,7 @@
-"""Hopping-term force on the GPU against the oracle: the link derivative of
-Re<Y, Mhat X> (site blocks fixed) as traceless anti-Hermitian 3x3 matrices in
-the canonical link layout; the oracle's form is pinned by finite differences."""
+"""Fermion-force building blocks on the GPU against the oracle: the link
+derivative of Re<Y, Mhat X> through the hopping terms and through the clover
+term, as traceless anti-Hermitian 3x3 matrices in the canonical link layout;
+the oracle's forms are pinned by finite differences."""
 import numpy as np
 import pytest
 
@@ -67,3 +68,53 @@ def test_hop_force_rejects_other_operators(S):
             ctx.hop_force(F, X, X, op=op)
     with pytest.raises(ValueError):
         ctx.hop_force(F[:10], X, X, op=1)  # too small an output: refused before any launch
+
+
+@pytest.mark.parametrize("sgn", [1, -1])
+def test_clover_force(S, sgn):
+    """The clover-term part of the link derivative (both parities' site blocks)."""
+    import torch
+
+    tmx, o, ctx, dims = S
+    X = synth.gaussian_cb_spinor(dims, 44, 0)
+    Y = synth.gaussian_cb_spinor(dims, 44, 1)
+    ref = o.clover_force(X, Y, sgn)
+    F = torch.zeros(ref.size, dtype=torch.complex128, device="cuda")
+    ctx.clover_force(F, to_dev(X), to_dev(Y), op=sgn)
+    assert rel_l2(to_host(F, ref.shape), ref) < 1e-13
+
+
+def test_full_force_accumulated(S):
+    """hop_force then clover_force accumulating: the whole derivative of
+    Re<Y, Mhat X>, the sum that the oracle's finite-difference pin checks."""
+    import torch
+
+    tmx, o, ctx, dims = S
+    X = synth.gaussian_cb_spinor(dims, 45, 0)
+    Y = synth.gaussian_cb_spinor(dims, 45, 1)
+    ref = 0.75 * (o.hop_force(X, Y, 1) + o.clover_force(X, Y, 1))
+    F = torch.full((ref.size,), complex(np.nan, np.nan), dtype=torch.complex128, device="cuda")
+    ctx.hop_force(F, to_dev(X), to_dev(Y), op=1, coeff=0.75)
+    ctx.clover_force(F, to_dev(X), to_dev(Y), op=1, coeff=0.75, accumulate=1)
+    assert rel_l2(to_host(F, ref.shape), ref) < 1e-13
+
+
+def test_clover_force_rejects_other_operators(S):
+    import torch
+
+    tmx, o, ctx, dims = S
+    X = to_dev(synth.gaussian_cb_spinor(dims, 46, 0))
+    F = torch.zeros(int(np.prod(dims)) * 36, dtype=torch.complex128, device="cuda")
+    for op in (tmx.TMX_OP_ND, tmx.TMX_OP_WPLUS):
+        with pytest.raises(tmx.TmxError):
+            ctx.clover_force(F, X, X, op=op)
+    with pytest.raises(ValueError):
+        ctx.clover_force(F, X[:10], X, op=1)
+    # a clover term loaded from the host has no links to differentiate
+    ctx.load_clover(ctx.get_clover())
+    try:
+        with pytest.raises(tmx.TmxError):
+            ctx.clover_force(F, X, X, op=1)
+    finally:
+        ctx.load_clover(None)  # back to the term built from the links
+    ctx.clover_force(F, X, X, op=1)
