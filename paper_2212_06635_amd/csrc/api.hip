@@ -880,6 +880,7 @@ int tmx_clover_force(tmx_ctx *c, double *force, const double *x, const double *y
     f.accumulate = accumulate ? 1 : 0;
     f.H = static_cast<double2 *>(ph);
     f.out = force;
+    f.xcd = c->xcd_remap;
     kstat_begin(c, "CLOVER_FORCE");
     hipError_t e = launch_clover_force(f, c->stream);
     kstat_end(c);

@@ -20,6 +20,7 @@ struct CloverForceArgs {
     int accumulate;
     double2 *H;
     double *out;
+    int xcd;  // XCD-contiguous workgroup order of the link sums
 };
 hipError_t launch_clover_force(const CloverForceArgs &f, hipStream_t st);
 

@@ -441,16 +441,22 @@ __device__ __forceinline__ void clover_link(const CloverForceArgs &f, const int 
         }
 }
 
-// one thread per link: blockIdx.y is the direction, sites of both parities
+// One thread per link.  Workgroup 8 i + 4 p + rho takes direction rho of
+// sites 256 i ... of parity p: the four directions and both parities of one
+// site block are neighbouring workgroups (with the XCD remap, on one XCD),
+// so the insertions and links of their common staples are read through one
+// L2 instead of once per direction.
 __global__ void __launch_bounds__(256) clover_force_kernel(CloverForceArgs f)
 {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 2L * f.g.Vh) return;
-    const int p = (int)(t / f.g.Vh);
+    const long blk = xcd_block(f.xcd);
+    const int r = (int)(blk & 3);
+    const int p = (int)((blk >> 2) & 1);
+    const long st = (blk >> 3) * blockDim.x + threadIdx.x;
+    if (st >= f.g.Vh) return;
     int x[4];
-    cb_coords(f.g, (int)(t - (long)p * f.g.Vh), p, x);
+    cb_coords(f.g, (int)st, p, x);
     const long lex = x[0] + (long)f.g.L[0] * (x[1] + (long)f.g.L[1] * (x[2] + (long)f.g.L[2] * x[3]));
-    switch (blockIdx.y) {
+    switch (r) {
     case 0: clover_link<0>(f, x, lex); break;
     case 1: clover_link<1>(f, x, lex); break;
     case 2: clover_link<2>(f, x, lex); break;
@@ -468,7 +474,8 @@ hipError_t launch_clover_force(const CloverForceArgs &f, hipStream_t st)
     hipLaunchKernelGGL(clover_insertion_kernel, dim3(nb), dim3(256), 0, st, f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(clover_force_kernel, dim3(nb, 4), dim3(256), 0, st, f);
+    const long nlink = 8 * ((f.g.Vh + 255) / 256);  // 4 directions x 2 parities per site block
+    hipLaunchKernelGGL(clover_force_kernel, dim3((unsigned)nlink), dim3(256), 0, st, f);
     return hipGetLastError();
 }
 
