@@ -213,34 +213,9 @@ class Oracle:
         b = X (odd) | u = B_ee(sgn)^-1 H_eo X (even) and
         a = Y (odd) | w = B_ee(-sgn)^-1 g5 H_eo g5 Y (even).  Shape (V, 4, 3, 3)."""
         g, _ = self.gammas()
-        lx, ly, lz, lt = self.dims
+        a, b, co, _ = self._force_fields(X, Y, sgn)
         V = self.V
-        lex = np.arange(V)
-        co = np.stack([lex % lx, (lex // lx) % ly, (lex // (lx * ly)) % lz, lex // (lx * ly * lz)], axis=1)
-        par = co.sum(axis=1) % 2
-        odd, even = np.nonzero(par == 1)[0], np.nonzero(par == 0)[0]
-
-        def full(v_odd):
-            f = np.zeros((V, 4, 3), dtype=np.complex128)
-            f[odd] = _c(v_odd).reshape(-1, 4, 3)
-            return f
-
-        def g5(f):
-            return np.einsum("st,xtc->xsc", g[4], f)
-
-        def hop_to_even(f):
-            return self.hop(f.reshape(V, 1, 4, 3), out_parity=0).reshape(V, 4, 3)
-
-        def block_solve(f, s):
-            out = np.zeros_like(f)
-            for x in even:
-                out[x] = np.linalg.solve(self.site_block(int(x), 1, s), f[x].reshape(12)).reshape(4, 3)
-            return out
-
-        b = full(X)
-        a = full(Y)
-        b[even] = block_solve(hop_to_even(b), sgn)[even]
-        a[even] = block_solve(g5(hop_to_even(g5(a))), -sgn)[even]
+        lx, ly, lz, lt = self.dims
         F = np.zeros((V, 4, 3, 3), dtype=np.complex128)
         eye4 = np.eye(4)
         L = (lx, ly, lz, lt)
