@@ -120,8 +120,8 @@ typedef struct {
 typedef struct {
     int iters;          /* iterations (operator applications of N or Mhat) */
     int reliable_updates;
-    int restarts;       /* FGCR restarts or fallbacks */
-    int fallback;       /* 1 if FGCR fell back to CG */
+    int restarts;       /* FGCR restarts or fallbacks; PCG_NN: network applications (K K^dagger) */
+    int fallback;       /* 1 if FGCR or PCG_NN fell back to CG */
     double true_residual; /* |b - A x| / |b| recomputed in FP64 at the end */
     double seconds;     /* wall time of the call */
     double gbytes;      /* model bytes moved by operator applications */
@@ -217,7 +217,11 @@ int tmx_solve_mhat(tmx_ctx *ctx, double *x, const double *b, int dagger, const t
  * with shifts[0] the smallest.  x is nshift contiguous odd fields.  Low
  * precision multishift CG followed by FP64-reliable refinement per shift
  * (cfg->inner_prec selects F32 or F16 for both stages; TMX_F64 runs the
- * plain FP64 multishift CG). */
+ * plain FP64 multishift CG).  With cfg->kind = TMX_SOLVER_PCG_NN each
+ * shift's refinement is the CG preconditioned by the learned network (set by
+ * tmx_pc_set_weights or tmx_pc_train; degenerate op only, TMX_EINVAL
+ * otherwise), falling back to mixed-precision CG if it stalls (info fallback
+ * = 1); info restarts then counts the network applications. */
 int tmx_multishift_solve(tmx_ctx *ctx, double *x, const double *b, const double *shifts, int nshift,
                          const tmx_solver_cfg *cfg, tmx_info *info);
 /* Rational function of the normal operator, the partial-fraction form of the

@@ -365,7 +365,8 @@ static int pcg_apply_pc(Sys &S, SpinorPtr z, SpinorPtr r, SpinorPtr tmp)
 }
 
 template <int P>
-static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const tmx_solver_cfg &cfg, bool x_is_guess, tmx_info *info)
+static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const double *sigma, const tmx_solver_cfg &cfg,
+                       bool x_is_guess, tmx_info *info)
 {
     tmx_ctx *c = S.c;
     const double tol = cfg.tol > 0 ? cfg.tol : 1e-10;
@@ -382,7 +383,7 @@ static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const tmx_solver_cfg &c
         if (info) info->true_residual = 0;
         return TMX_OK;
     }
-    TRY(true_residual<P>(S, r, rl, true, b, x, nullptr, 1, &rr));
+    TRY(true_residual<P>(S, r, rl, true, b, x, sigma, 1, &rr));
     TRY(zero_field<F32>(S, xl, 1));
     TRY(pcg_apply_pc<P>(S, z, rl, tz));
     {
@@ -401,7 +402,7 @@ static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const tmx_solver_cfg &c
     bool after_reliable = false;
     const double t0 = now_seconds();
     while (std::sqrt(rr) > tol * std::sqrt(bb) && it < maxiter) {
-        TRY(apply_shifted<P>(S, q, p, nullptr, 1, &pq));
+        TRY(apply_shifted<P>(S, q, p, sigma, 1, &pq));
         ++it;
         if (!(pq > 0) || !(rho > 0)) return set_err(c, TMX_ENOCONV, "preconditioned CG breakdown");
         const double alpha = rho / pq;
@@ -424,7 +425,7 @@ static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const tmx_solver_cfg &c
             ad.nf = 1;
             ad.zero_y = 1;
             HTRY(run_blas(ad, c->Vh, 1, c->red, c->stream), "pcg reliable add");
-            TRY(true_residual<P>(S, r, rl, true, b, x, nullptr, 1, &rr));
+            TRY(true_residual<P>(S, r, rl, true, b, x, sigma, 1, &rr));
             rmax = rr;
             nrel++;
             after_reliable = true;
@@ -457,7 +458,7 @@ static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const tmx_solver_cfg &c
     ad.zero_y = 1;
     HTRY(run_blas(ad, c->Vh, 1, c->red, c->stream), "pcg final add");
     double tr;
-    TRY(true_residual<P>(S, r, rl, false, b, x, nullptr, 1, &tr));
+    TRY(true_residual<P>(S, r, rl, false, b, x, sigma, 1, &tr));
     const double rel = std::sqrt(tr / bb);
     if (info) {
         info->iters += it;
@@ -638,8 +639,9 @@ int tmx_solve(tmx_ctx *c, double *x, const double *b, int nrhs, const tmx_solver
         if (cfg->op != TMX_OP_PLUS && cfg->op != TMX_OP_MINUS)
             return set_err(c, TMX_EINVAL, "the learned preconditioner is built for the degenerate Schur operator");
         TRY(ensure_ready(c, F32, false));
-        rc = (cfg->inner_prec == TMX_F16) ? pcg_nn_core<F16>(S, X, B, *cfg, cfg->use_initial_guess != 0, info)
-                                          : pcg_nn_core<F32>(S, X, B, *cfg, cfg->use_initial_guess != 0, info);
+        rc = (cfg->inner_prec == TMX_F16)
+                 ? pcg_nn_core<F16>(S, X, B, nullptr, *cfg, cfg->use_initial_guess != 0, info)
+                 : pcg_nn_core<F32>(S, X, B, nullptr, *cfg, cfg->use_initial_guess != 0, info);
         if (rc == TMX_ENOCONV && info && std::isfinite(info->true_residual)) {
             // fall back to plain mixed-precision CG from the current x
             tmx_info inf{};
@@ -675,8 +677,12 @@ static int check_shifts(tmx_ctx *c, const double *shifts, int nshift)
 
 // The batched multishift solve of B (packed FP64) for every shift: one
 // low-precision multishift CG, then shift-by-shift refinement with FP64
-// reliable updates.  Each refined FP64 solution is handed to consume(k, X_k)
-// in shift order (X_k is reused for the next shift).
+// reliable updates.  With cfg->kind = TMX_SOLVER_PCG_NN the refinement is
+// the CG preconditioned by the learned network (K K^dagger approximates
+// N^{-1}, and (N + sigma)^{-1} for the small shifts that dominate the
+// cost), falling back to plain MP-CG from its iterate if it stalls.  Each
+// refined FP64 solution is handed to consume(k, X_k) in shift order (X_k is
+// reused for the next shift).
 static int multishift_run(tmx_ctx *c, Sys &S, SpinorPtr B, const double *shifts, int nshift,
                           const tmx_solver_cfg *cfg, tmx_info *info,
                           const std::function<int(int, SpinorPtr)> &consume)
@@ -685,6 +691,11 @@ static int multishift_run(tmx_ctx *c, Sys &S, SpinorPtr B, const double *shifts,
     const double tol = cfg->tol > 0 ? cfg->tol : 1e-10;
     const double inner = cfg->inner_tol > 0 ? cfg->inner_tol : (prec == TMX_F16 ? 5e-4 : (prec == TMX_F32 ? 1e-6 : tol));
     const int maxiter = cfg->maxiter > 0 ? cfg->maxiter : 10000;
+    if (cfg->kind == TMX_SOLVER_PCG_NN) {
+        if (cfg->op != TMX_OP_PLUS && cfg->op != TMX_OP_MINUS)
+            return set_err(c, TMX_EINVAL, "the learned preconditioner is built for the degenerate Schur operator");
+        TRY(ensure_ready(c, F32, false));  // the network runs on the FP32 links
+    }
     // low-precision multishift stage
     const int PX = prec == F64 ? F64 : F32;
     std::vector<SpinorPtr> xs(nshift);
@@ -715,13 +726,30 @@ static int multishift_run(tmx_ctx *c, Sys &S, SpinorPtr B, const double *shifts,
         tmx_info inf{};
         S.gbytes = 0;
         const double sk = shifts[k];
-        int rk = dispatch_cg(S, prec, X, B, 1, &sk, rc_cfg, true, &inf);
+        int rk;
+        if (cfg->kind == TMX_SOLVER_PCG_NN) {
+            rk = prec == F16 ? pcg_nn_core<F16>(S, X, B, &sk, rc_cfg, true, &inf)
+                             : pcg_nn_core<F32>(S, X, B, &sk, rc_cfg, true, &inf);
+            if (rk == TMX_ENOCONV && std::isfinite(inf.true_residual)) {
+                tmx_info fb{};
+                rk = dispatch_cg(S, F32, X, B, 1, &sk, rc_cfg, true, &fb);
+                inf.fallback = 1;
+                inf.iters += fb.iters;
+                inf.reliable_updates += fb.reliable_updates;
+                inf.true_residual = fb.true_residual;
+                inf.gbytes += fb.gbytes;
+            }
+        } else {
+            rk = dispatch_cg(S, prec, X, B, 1, &sk, rc_cfg, true, &inf);
+        }
         if (rk < 0) return rk;
         if (rk == TMX_ENOCONV) rc = TMX_ENOCONV;
         TRY(consume(k, X));
         if (info) {
             info[k].iters = its[k] + inf.iters;
             info[k].reliable_updates = inf.reliable_updates;
+            info[k].restarts = inf.restarts;
+            info[k].fallback = inf.fallback;
             info[k].true_residual = inf.true_residual;
             info[k].gbytes = inf.gbytes + (k == 0 ? ms_gb : 0.0);
         }

@@ -196,3 +196,37 @@ def test_separately_trained_weights_for_minus_mu(S):
     assert o.residual(b, to_host(x, b.shape), sgn=-1) <= 1e-10
     with pytest.raises(tmx.TmxError):
         ctx.pc_train(to_dev(bs), xd, n, epochs=1, op=2)
+
+
+def test_multishift_refinement_with_learned_pc(S, pairs):
+    """The multishift solve with the learned network preconditioning each
+    shift's FP64 refinement: every shift accepted by the oracle's residual of
+    (N + sigma), the network path taken (preconditioner applications counted),
+    and the solutions those of the plain refinement."""
+    tmx, ctx, lat, U = S
+    bs, xd = pairs
+    o = Oracle(DIMS, U, KAPPA, CSW, mu=MU0)
+    ctx.pc_set_weights(nn.identity_init(np.random.default_rng(3), 1e-2))
+    ctx.pc_train(to_dev(bs), xd, len(bs), epochs=12, batch=4, lr=3e-3, seed=1, loss_kind=1)
+    b = synth.gaussian_cb_spinor(DIMS, 72, 0)
+    shifts = [0.0, 1e-3, 1e-2, 1e-1]
+    n = b.size
+    for inner in (tmx.TMX_F32, tmx.TMX_F16):
+        x = to_dev(np.zeros(len(shifts) * n, dtype=np.complex128))
+        rc, info = ctx.multishift_solve(x, to_dev(b), shifts, kind=tmx.TMX_SOLVER_PCG_NN, op=1, tol=1e-10,
+                                        inner_prec=inner)
+        assert rc == tmx.TMX_OK
+        xp = to_dev(np.zeros(len(shifts) * n, dtype=np.complex128))
+        rcp, _ = ctx.multishift_solve(xp, to_dev(b), shifts, op=1, tol=1e-10, inner_prec=inner)
+        assert rcp == tmx.TMX_OK
+        for k, s in enumerate(shifts):
+            xk = to_host(x[k * n:(k + 1) * n], b.shape)
+            res = rel_l2(o.mdagm(xk) + s * xk, b)
+            print(f"inner {inner} shift {s:g}: {info[k]['iters']} iterations, "
+                  f"{info[k]['restarts']} network applications, oracle residual {res:.2e}")
+            assert res <= 1.01e-10
+            assert info[k]["restarts"] >= 1
+            assert rel_l2(xk, to_host(xp[k * n:(k + 1) * n], b.shape)) < 1e-8
+    with pytest.raises(tmx.TmxError):
+        ctx.multishift_solve(to_dev(np.zeros(2 * n, dtype=np.complex128)), to_dev(b), [0.0, 0.1],
+                             kind=tmx.TMX_SOLVER_PCG_NN, op=tmx.TMX_OP_WPLUS)
