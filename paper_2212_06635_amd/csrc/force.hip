@@ -1,4 +1,5 @@
-// Hopping-term force of the Schur operator (gfx950).
+// Fermion-force building blocks of the Schur operator (gfx950): the hopping-
+// term force, then (further down) the clover-term force.
 //
 // For odd fields X, Y the link derivative of S = Re<Y, Mhat(s) X> through the
 // hopping terms H_oe and H_eo (site blocks fixed), for U_mu(x) ->
