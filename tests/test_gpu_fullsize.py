@@ -67,3 +67,49 @@ def test_fullsize_multishift_nd(F):
     xs = to_host(x, (12,) + b.shape)
     for k in (0, 5, 11):
         assert o.residual(b, xs[k], nf=2, shift=shifts[k]) <= 1e-10
+
+
+def test_fullsize_force_directional_derivative(F):
+    """Hopping plus clover force at full size, in the bench's launch shape,
+    against central differences of the oracle's Re<Y, Mhat X> along a random
+    su(3) direction on 2048 random links and on links that cross the time
+    boundary (its sign) and the x wrap: U -> exp(i eps P) U on those links,
+    clover term rebuilt from the perturbed field, the difference of the two
+    outputs taken field-wise before the inner product."""
+    import torch
+    from test_oracle_pins import _expi, _random_su3_algebra
+
+    tmx, o, ctx = F
+    V = o.V
+    lx, ly, lz, lt = DIMS
+    rng = np.random.default_rng(19)
+    ids = set(rng.choice(V * 4, 2048, replace=False).tolist())
+    for k in range(64):  # t = Lt-1, direction t; x = Lx-1, direction x
+        x, y, z = rng.integers(0, lx), rng.integers(0, ly), rng.integers(0, lz)
+        ids.add(4 * int(x + lx * (y + ly * (z + lz * (lt - 1)))) + 3)
+        t = rng.integers(0, lt)
+        ids.add(4 * int((lx - 1) + lx * (y + ly * (z + lz * t))) + 0)
+    ids = np.array(sorted(ids))
+    site, mu = ids // 4, ids % 4
+    P = _random_su3_algebra(len(ids), rng)
+    X = synth.gaussian_cb_spinor(DIMS, 81, 0)
+    Y = synth.gaussian_cb_spinor(DIMS, 81, 1)
+    Fd = torch.zeros(V * 36, dtype=torch.complex128, device="cuda")
+    ctx.hop_force(Fd, to_dev(X), to_dev(Y), op=1)
+    ctx.clover_force(Fd, to_dev(X), to_dev(Y), op=1, accumulate=1)
+    idx = torch.from_numpy(ids).cuda()
+    Fs = Fd.view(V * 4, 3, 3)[idx].cpu().numpy()
+    del Fd
+    predicted = float(np.einsum("kij,kji->", 1j * P, Fs).real)
+
+    h = 1e-4
+    out = []
+    for eps in (h, -h):
+        Ue = o.U.copy()
+        Ue[site, mu] = np.einsum("kij,kjl->kil", _expi(eps * P), o.U[site, mu])
+        out.append(Oracle(DIMS, Ue, KAPPA, CSW, mu=MU, mubar=MUBAR, epsbar=EPSBAR).mhat(X))
+        del Ue
+    numeric = float(np.vdot(Y.reshape(-1), (out[0] - out[1]).reshape(-1)).real) / (2 * h)
+    print(f"[gpu full size] force along {len(ids)} links: predicted {predicted:.10e}, "
+          f"central differences {numeric:.10e}", flush=True)
+    assert abs(predicted - numeric) <= 1e-6 * abs(numeric)
