@@ -1,8 +1,16 @@
-"""ctypes front end of the plain FP64 CPU oracle (test infrastructure only).
+"""Plain FP64 CPU oracle (test infrastructure only: the tests, the smoke
+check and the benchmark's CPU baseline use it; the GPU library never does).
 
-The arithmetic lives in ``tmx_oracle.c`` (plain loops, FP64, OpenMP over
-sites) and ``nn_oracle.py`` (the learned preconditioner).  This module only
-marshals numpy arrays.  It must never be imported by the GPU library.
+The operator arithmetic -- hopping term, clover term, site blocks, D, the
+Schur operator and its normal form, CG -- lives in ``tmx_oracle.c`` (plain
+loops, FP64, OpenMP over sites), called here through ctypes; the learned
+preconditioner is in ``nn_oracle.py``.  The forms built on top of the
+operator are written here in numpy, each in the order its definition states:
+the mass-preconditioned operators (Section 2), the rational function and its
+correction series (Section 4.2), and the link derivatives of Re<Y, Mhat X>
+through the hopping and the clover terms (Section 4.3).  Every function is
+pinned by tests that do not reuse it (closed forms, brute force, finite
+differences, spectral forms); none is parity unpinned.
 """
 from __future__ import annotations
 

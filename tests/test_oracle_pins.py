@@ -482,3 +482,27 @@ def test_full_force_against_finite_differences(rough, sgn):
     total = lin(Fh) + lin(Fc)
     assert abs(lin(Fc)) > 1e-3 * abs(total)          # the clover part matters here
     assert abs(numeric - total) < 1e-7 * abs(total)
+
+
+@pytest.mark.parametrize("nf", [1, 2])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_residual_mhat_against_dense_solve(nf, dagger):
+    """The oracle's acceptance test |b - A x| / |b| (A = Mhat or Mhat^dagger)
+    returns |r0| / |b| for x = A^{-1}(b - r0) solved densely, and exactly 1
+    for x = 0."""
+    dims = (2, 2, 2, 4)
+    U = synth.gauge_links(dims, 0.4, 33)
+    o = Oracle(dims, U, KAPPA, CSW, mu=0.05, mubar=0.1246, epsbar=0.1315)
+    Vh = o.Vh
+    n = 12 * nf * Vh
+    A = dense(lambda e: o.mhat(e.reshape(Vh, nf, 4, 3), nf=nf), n)
+    if dagger:
+        A = np.conj(A.T)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    r0 = 1e-6 * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    x = np.linalg.solve(A, b - r0)
+    shape = (Vh, nf, 4, 3)
+    got = o.residual_mhat(b.reshape(shape), x.reshape(shape), nf=nf, dagger=dagger)
+    assert abs(got - np.linalg.norm(r0) / np.linalg.norm(b)) < 1e-9 * np.linalg.norm(r0) / np.linalg.norm(b) + 1e-15
+    assert o.residual_mhat(b.reshape(shape), np.zeros(shape, dtype=np.complex128), nf=nf, dagger=dagger) == 1.0
