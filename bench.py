@@ -26,7 +26,8 @@ epsbar = 0.1315; links U = proj_SU3(exp(i 0.25 H)), seed 4):
 After the timed steps, once: the rational approximation applied as a whole
 (R(N_h) b with the same poles), its accuracy N_h R(N_h)^2 b = b, and the
 exponent of its correction factor for one Gaussian eta; the hopping-term
-force kernel (link outer products of one shift).
+force kernel (link outer products of one shift) and the clover-term force
+(sigma-plane insertions, then the staple sums).
 
 The headline value is the FP64 Schur-operator bandwidth: model bytes of one
 Mhat application (links, spinors and clover blocks each read once per
