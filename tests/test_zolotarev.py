@@ -47,3 +47,10 @@ def test_spectrum_scaling():
     err = np.abs(np.sqrt(lam) * r(lam) - 1.0)
     assert err.max() <= r.delta * (1 + 1e-6)
     assert r.shifts.min() < lo < hi < r.shifts.max() * 10
+
+
+def test_arguments_validated():
+    for n, eps in ((0, 1e-3), (4, 0.0), (4, 1.0), (4, -1e-3)):
+        with pytest.raises(ValueError):
+            z.inverse_sqrt(n, eps)
+
