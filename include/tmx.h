@@ -139,14 +139,35 @@ const char *tmx_last_error(const tmx_ctx *ctx);
 /* Change the stream subsequent work is enqueued on. */
 int tmx_set_stream(tmx_ctx *ctx, void *hip_stream);
 
+/* Device allocator of the context.  Every device buffer the library needs
+ * from now on (gauge, clover and inverse fields of every precision, solver
+ * and network workspaces, reduction buffers, network state) is obtained as
+ * alloc(bytes, user) and given back as release(ptr, user) once the library
+ * no longer uses it (the context's stream has been synchronised by then).
+ * alloc returns a device pointer aligned to at least 256 bytes, or NULL,
+ * which the library turns into TMX_ENOMEM for the call that needed it.
+ * Buffers that exist when the hook is set stay with the allocator that made
+ * them and are released through it (the reduction buffers, which hold no
+ * state between calls, move to the new allocator at once).  alloc = release
+ * = NULL restores hipMalloc / hipFree; giving only one of them is
+ * TMX_EINVAL.  This lets a framework that owns device memory (a caching
+ * allocator, a memory pool) serve the library, so that the library only ever
+ * computes on memory it is handed.  The named scratch buffers can also be
+ * capped in total with the environment variable TMX_WS_LIMIT (bytes, read by
+ * tmx_create): a call that would exceed it returns TMX_ENOMEM before
+ * launching anything. */
+int tmx_set_allocator(tmx_ctx *ctx, void *(*alloc)(size_t bytes, void *user), void (*release)(void *ptr, void *user),
+                      void *user);
+
 /* Parameters.  Changing mu / mubar / epsbar invalidates only the site-block
  * inverses; changing kappa or csw also invalidates the clover term. */
 int tmx_set_params(tmx_ctx *ctx, const tmx_params *p);
 
 /* Upload a gauge field from host memory (canonical layout, complex128,
  * copied; the caller keeps ownership).  `gauge_id` labels the field (its
- * position along a trajectory or a configuration number, as the paper's
- * gauge-state tracking does): a call with the id already loaded is a no-op;
+ * position along a trajectory or a configuration number, as the gauge-state
+ * tracking of Section 3 does, with the clover term and its inverse following
+ * the gauge field's id): a call with the id already loaded is a no-op;
  * a new id invalidates the clover term and its inverses, which are rebuilt
  * lazily on the next use.  Links must be SU(3) (rows 0,1 are stored, row 2
  * is reconstructed as conj(row0 x row1)). */
@@ -173,13 +194,24 @@ int tmx_unpack(tmx_ctx *ctx, double *canonical, const void *internal, int kind, 
 
 /* ---- operators (device buffers, internal layout, asynchronous) -------- */
 
-/* out = D in (full lattice).  op selects +mu, -mu or the two-flavour
- * operator; fields are TMX_FIELD_FULL (or _FULL_ND for op = TMX_OP_ND). */
+/* out = D in (full lattice): the operator M_clov + i mu gamma5 inside
+ * Q^{+-} = gamma5 (M_clov +- i mu gamma5) of Section 2 (equation for Q^{+-};
+ * D(-mu)^dagger = gamma5 D(mu) gamma5), or its two-flavour form from the
+ * equation for Q-hat_h.  op selects +mu, -mu or the two-flavour operator;
+ * fields are TMX_FIELD_FULL (or _FULL_ND for op = TMX_OP_ND), device buffers
+ * owned by the caller; out and in must differ (TMX_EINVAL). */
 int tmx_apply_D(tmx_ctx *ctx, void *out, const void *in, int op, int prec);
-/* out = Mhat in or Mhat^dagger in on odd fields (nrhs fields side by side
- * in the multi-vector layout of tmx_pack with nvec = nrhs). */
+/* out = Mhat in or Mhat^dagger in on odd fields: the bracket of the
+ * asymmetric even-odd operator Q-hat^{+-} = gamma5 Mhat(+-mu) of Section 2
+ * (equation for Q-hat^{+-}; two-flavour: equation for Q-hat_h; W operators:
+ * equation for W^{+-}), nrhs <= 32 fields side by side in the multi-vector
+ * layout of tmx_pack with nvec = nrhs; device buffers owned by the caller,
+ * out != in (TMX_EINVAL); TMX_ENOTLOADED without a gauge field or
+ * parameters. */
 int tmx_apply_mhat(tmx_ctx *ctx, void *out, const void *in, int op, int prec, int dagger, int nrhs);
-/* out = N in = Mhat^dagger Mhat in. */
+/* out = N in = Mhat^dagger Mhat in, the Hermitian positive operator whose
+ * solves the monomials need (Section 2: Q-hat^+ Q-hat^- = Mhat(-)^dagger
+ * Mhat(-)); same arguments and errors as tmx_apply_mhat. */
 int tmx_apply_mdagm(tmx_ctx *ctx, void *out, const void *in, int op, int prec, int nrhs);
 
 /* Hopping-term force (the link derivative that the fermion force of the
@@ -206,15 +238,26 @@ int tmx_clover_force(tmx_ctx *ctx, double *force, const double *x, const double 
 
 /* ---- solvers (device buffers, canonical complex128 odd fields) -------- */
 
-/* Solve N x = b (cfg->op selects the operator) for nrhs right-hand sides
- * stored contiguously; info is an array of nrhs entries (may be NULL).
- * Returns TMX_ENOCONV if any column missed cfg->tol. */
+/* Solve N x = b (cfg->op selects the operator) for nrhs <= 32 right-hand
+ * sides stored contiguously (device, canonical complex128 odd fields, owned
+ * by the caller; x also holds the start vector if cfg->use_initial_guess):
+ * CG, or the mixed-precision CG with FP64 reliable updates of Sections 1 and
+ * 4.1, or the solves preconditioned by the learned network (standing in for
+ * the multigrid preconditioner of Section 4.1).  info is an array of nrhs
+ * entries (may be NULL).  Returns TMX_ENOCONV if any column missed cfg->tol
+ * (x then holds the best iterate), TMX_ENOMEM if a workspace could not be
+ * allocated (nothing launched). */
 int tmx_solve(tmx_ctx *ctx, double *x, const double *b, int nrhs, const tmx_solver_cfg *cfg, tmx_info *info);
-/* Solve Mhat x = b (dagger = 0) or Mhat^dagger x = b (dagger = 1). */
+/* Solve Mhat x = b (dagger = 0) or Mhat^dagger x = b (dagger = 1), the two
+ * inversions of the fermion derivative (Section 4.1), through the normal
+ * equations: x = N^{-1} Mhat^dagger b, or x = Mhat N^{-1} b.  One odd field
+ * each (device, canonical complex128); errors as tmx_solve. */
 int tmx_solve_mhat(tmx_ctx *ctx, double *x, const double *b, int dagger, const tmx_solver_cfg *cfg,
                    tmx_info *info);
 /* Solve (N + shifts[k]) x_k = b for k < nshift (<= 32), shifts > 0 or >= 0
- * with shifts[0] the smallest.  x is nshift contiguous odd fields.  Low
+ * with shifts[0] the smallest: the mixed-precision multishift solver of the
+ * heavy sector (Section 4.2: a low-precision multishift CG, then
+ * shift-by-shift refinement).  x is nshift contiguous odd fields.  Low
  * precision multishift CG followed by FP64-reliable refinement per shift
  * (cfg->inner_prec selects F32 or F16 for both stages; TMX_F64 runs the
  * plain FP64 multishift CG).  With cfg->kind = TMX_SOLVER_PCG_NN each
@@ -288,6 +331,20 @@ typedef struct {
  * preconditioner needs; the solution loss weights the high modes of Mhat
  * down by Mhat^{-1}. */
 enum { TMX_LOSS_RESIDUAL = 0, TMX_LOSS_SOLUTION = 1 };
+
+/* One Adam step (Kingma and Ba, with bias correction) on the network weights
+ * from a gradient the caller supplies: host_grad holds n FP32 values in the
+ * layout of tmx_pc_set_weights (n = tmx_pc_num_params), for instance the
+ * gradient of tmx_pc_loss_grad averaged over the batches of several GPUs in
+ * data-parallel training.  With t the steps taken since the weights were last
+ * set (the moments m, v start at zero then):
+ *     m = beta1 m + (1 - beta1) g,   v = beta2 v + (1 - beta2) g^2,
+ *     w = w - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps),
+ * elementwise in FP32.  cfg supplies lr, beta1, beta2, eps (0 selects 1e-3,
+ * 0.9, 0.999, 1e-8); its other fields are ignored.  tmx_pc_train takes the
+ * same step after each batch.  TMX_EINVAL for a wrong n or non-finite
+ * values, TMX_ENOTLOADED before weights are set.  Synchronises. */
+int tmx_pc_adam_step(tmx_ctx *ctx, const float *host_grad, size_t n, const tmx_train_cfg *cfg);
 
 /* Train on npairs (b_i, x_i) canonical odd complex128 device fields with
  * the loss selected by cfg->loss_kind and Adam; loss_out[epochs] receives

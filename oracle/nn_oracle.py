@@ -220,3 +220,21 @@ def loss_and_grad(lat: Lattice, w, bs, xs, mhat=None, mhat_dag=None):
             delta = layer_adjoint(lat, C, G, delta)
     g = flatten(gparams)
     return L, g
+
+
+# --------------------------------------------------------------------------
+# training step
+# --------------------------------------------------------------------------
+def adam_step(w, m, v, t, g, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (Kingma and Ba, "Adam: a method for stochastic
+    optimization", Algorithm 1) in FP64, elementwise: the moment estimates
+    m = beta1 m + (1 - beta1) g and v = beta2 v + (1 - beta2) g^2, their
+    bias-corrected values m / (1 - beta1^t) and v / (1 - beta2^t) for step
+    t = 1, 2, ..., and the update w - lr mhat / (sqrt(vhat) + eps).
+    Returns the new (w, m, v)."""
+    w, m, v, g = (np.asarray(a, dtype=np.float64) for a in (w, m, v, g))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return w - lr * mhat / (np.sqrt(vhat) + eps), m, v

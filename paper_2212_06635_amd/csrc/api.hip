@@ -40,38 +40,71 @@ int hip_err(tmx_ctx *c, hipError_t e, const char *where)
                    std::string(where) + ": " + hipGetErrorString(e));
 }
 
-void dev_free(void *p)
-{
-    if (p) (void)hipFree(p);
-}
-
-static void *dev_alloc(tmx_ctx *c, size_t bytes)
+void *dev_alloc(tmx_ctx *c, size_t bytes)
 {
     void *p = nullptr;
     if (bytes == 0) bytes = 16;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        set_err(c, TMX_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-        return nullptr;
+    AllocRec rec;
+    rec.bytes = bytes;
+    if (c->alloc_fn) {
+        p = c->alloc_fn(bytes, c->alloc_user);
+        if (!p) {
+            set_err(c, TMX_ENOMEM, "the caller's allocator returned no memory for " + std::to_string(bytes) + " bytes");
+            return nullptr;
+        }
+        rec.release = c->release_fn;
+        rec.user = c->alloc_user;
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            set_err(c, TMX_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+            return nullptr;
+        }
     }
+    c->allocs[p] = rec;
     return p;
+}
+
+void dev_free(tmx_ctx *c, void *p)
+{
+    if (!p) return;
+    auto it = c->allocs.find(p);
+    if (it == c->allocs.end()) return;  // not ours: never released here
+    const AllocRec rec = it->second;
+    c->allocs.erase(it);
+    if (rec.release)
+        rec.release(p, rec.user);
+    else
+        (void)hipFree(p);
 }
 
 void *ws_get(tmx_ctx *c, const std::string &name, size_t bytes)
 {
     Workspace &w = c->ws[name];
     if (w.bytes >= bytes && w.p) return w.p;
+    if (c->ws_limit && c->ws_bytes - w.bytes + bytes > c->ws_limit) {
+        set_err(c, TMX_ENOMEM, "workspace '" + name + "' of " + std::to_string(bytes) +
+                                   " bytes exceeds the workspace limit (TMX_WS_LIMIT)");
+        return nullptr;
+    }
     if (w.p) {
         (void)hipStreamSynchronize(c->stream);
-        dev_free(w.p);
+        dev_free(c, w.p);
+        c->ws_bytes -= w.bytes;
         w.p = nullptr;
         w.bytes = 0;
     }
     w.p = dev_alloc(c, bytes);
-    if (w.p) w.bytes = bytes;
+    if (w.p) {
+        w.bytes = bytes;
+        c->ws_bytes += bytes;
+    }
     return w.p;
 }
+
+static size_t red_partials_bytes(const tmx_ctx *c) { return sizeof(double) * c->red.max_blocks * MAXR * 4; }
+static size_t red_result_bytes() { return sizeof(double) * MAXR * 4; }
 
 static size_t bytes_per_real(int prec) { return prec == F64 ? 8 : (prec == F32 ? 4 : 2); }
 
@@ -368,6 +401,20 @@ static int op_sign(int op) { return op == TMX_OP_ND ? 1 : (op > 0 ? 1 : -1); }
 // i rho~ coefficient of What^s: s rho~, rho~ = 2 kappa rho
 static double w_rho(const tmx_ctx *c, int s) { return s * 2.0 * c->par.kappa * c->par.rho; }
 
+// Mhat (or its adjoint) with the even-site intermediate in u (derived fields ready)
+static int mhat_with(tmx_ctx *c, SpinorPtr out, SpinorPtr in, SpinorPtr u, int op, int prec, int dagger, int nrhs)
+{
+    const bool nd = op == TMX_OP_ND;
+    const int sgn = op_sign(op);
+    if (op_is_w(op)) {
+        // What^s = g5 Mhat(s) + i s rho~ ; its adjoint is What^-s
+        const int s = dagger ? -sgn : sgn;
+        return schur_pair(c, out, in, u, prec, false, nrhs, s, 0, 1, nullptr, w_rho(c, s));
+    }
+    // Mhat^dagger = g5 Mhat(-sgn) g5
+    return schur_pair(c, out, in, u, prec, nd, nrhs, dagger ? -sgn : sgn, dagger, dagger);
+}
+
 int op_mhat(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int dagger, int nrhs)
 {
     int r = check_op(c, op);
@@ -379,15 +426,7 @@ int op_mhat(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int dagge
     const long stride = c->Vh * nrhs;
     void *ud = ws_get(c, "op_u" + std::to_string(prec), spinor_field_bytes(prec, nf, stride));
     if (!ud) return TMX_ENOMEM;
-    SpinorPtr u = make_spinor(ud, prec, nf, stride);
-    const int sgn = op_sign(op);
-    if (op_is_w(op)) {
-        // What^s = g5 Mhat(s) + i s rho~ ; its adjoint is What^-s
-        const int s = dagger ? -sgn : sgn;
-        return schur_pair(c, out, in, u, prec, false, nrhs, s, 0, 1, nullptr, w_rho(c, s));
-    }
-    // Mhat^dagger = g5 Mhat(-sgn) g5
-    return schur_pair(c, out, in, u, prec, nd, nrhs, dagger ? -sgn : sgn, dagger, dagger);
+    return mhat_with(c, out, in, make_spinor(ud, prec, nf, stride), op, prec, dagger, nrhs);
 }
 
 int op_mdagm(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int nrhs, double *nrm)
@@ -554,12 +593,13 @@ int tmx_create(const int dims[4], void *hip_stream, tmx_ctx **out)
     // enough workgroups for one slot per thread up to V/2 = 2M sites: a
     // grid-stride loop over several sites serialises their memory latency
     c->red.max_blocks = 8192;
-    if (hipMalloc(&c->red.partials, sizeof(double) * c->red.max_blocks * MAXR * 4) != hipSuccess ||
-        hipMalloc(&c->red.result, sizeof(double) * MAXR * 4) != hipSuccess ||
+    c->red.partials = static_cast<double *>(dev_alloc(c, red_partials_bytes(c)));
+    c->red.result = static_cast<double *>(dev_alloc(c, red_result_bytes()));
+    if (!c->red.partials || !c->red.result ||
         hipHostMalloc(&c->host_red, sizeof(double) * MAXR * 4, hipHostMallocCoherent) != hipSuccess) {
         (void)hipGetLastError();
-        dev_free(c->red.partials);
-        dev_free(c->red.result);
+        dev_free(c, c->red.partials);
+        dev_free(c, c->red.result);
         delete c;
         return TMX_ENOMEM;
     }
@@ -570,6 +610,8 @@ int tmx_create(const int dims[4], void *hip_stream, tmx_ctx **out)
         (void)hipGetLastError();
         c->red.host = nullptr;
     }
+    // cap on the named scratch buffers (bytes), for callers that budget HBM
+    if (const char *e = std::getenv("TMX_WS_LIMIT")) c->ws_limit = std::strtoull(e, nullptr, 10);
     const char *tr = std::getenv("TMX_TRACE");
     c->trace = tr && tr[0] == '1';
     tune_cache_load(c);
@@ -590,18 +632,19 @@ int tmx_destroy(tmx_ctx *c)
     if (!c) return TMX_EINVAL;
     (void)hipStreamSynchronize(c->stream);
     for (int p = 0; p < 3; ++p) {
-        dev_free(c->links[p]);
-        dev_free(c->clov[p]);
-        dev_free(c->inv[p]);
-        dev_free(c->invnd[p]);
+        dev_free(c, c->links[p]);
+        dev_free(c, c->clov[p]);
+        dev_free(c, c->inv[p]);
+        dev_free(c, c->invnd[p]);
     }
-    for (auto &kv : c->ws) dev_free(kv.second.p);
+    for (auto &kv : c->ws) dev_free(c, kv.second.p);
     kstat_collect(c);
     for (hipEvent_t e : c->kpool) (void)hipEventDestroy(e);
-    dev_free(c->red.partials);
-    dev_free(c->red.result);
+    dev_free(c, c->red.partials);
+    dev_free(c, c->red.result);
     if (c->host_red) (void)hipHostFree(c->host_red);
     tmx_pc_free(c);
+    while (!c->allocs.empty()) dev_free(c, c->allocs.begin()->first);
     delete c;
     return TMX_OK;
 }
@@ -612,6 +655,31 @@ int tmx_set_stream(tmx_ctx *c, void *s)
 {
     if (!c) return TMX_EINVAL;
     c->stream = static_cast<hipStream_t>(s);
+    return TMX_OK;
+}
+
+int tmx_set_allocator(tmx_ctx *c, void *(*alloc)(size_t, void *), void (*release)(void *, void *), void *user)
+{
+    if (!c) return TMX_EINVAL;
+    if ((alloc == nullptr) != (release == nullptr))
+        return set_err(c, TMX_EINVAL, "tmx_set_allocator: give both functions or neither");
+    if (hipStreamSynchronize(c->stream) != hipSuccess) (void)hipGetLastError();
+    c->alloc_fn = alloc;
+    c->release_fn = release;
+    c->alloc_user = user;
+    // the reduction buffers hold nothing between calls: move them to the new
+    // allocator now (everything allocated later comes from it as well; what
+    // exists already is released by the allocator that made it)
+    double *np = static_cast<double *>(dev_alloc(c, red_partials_bytes(c)));
+    double *nr = np ? static_cast<double *>(dev_alloc(c, red_result_bytes())) : nullptr;
+    if (!np || !nr) {
+        dev_free(c, np);
+        return TMX_ENOMEM;
+    }
+    dev_free(c, c->red.partials);
+    dev_free(c, c->red.result);
+    c->red.partials = np;
+    c->red.result = nr;
     return TMX_OK;
 }
 
@@ -643,14 +711,14 @@ int tmx_load_gauge(tmx_ctx *c, const double *host_links, double gauge_id)
     if (!c->links[F64]) {
         c->links[F64] = dev_alloc(c, link_bytes(F64, c->Vh));
         if (!c->links[F64]) {
-            dev_free(stage);
+            dev_free(c, stage);
             return TMX_ENOMEM;
         }
     }
     hipError_t e = hipMemcpyAsync(stage, host_links, bytes, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_pack_links((const double *)stage, (double *)c->links[F64], c->g, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    dev_free(stage);
+    dev_free(c, stage);
     if (e != hipSuccess) return hip_err(c, e, "gauge upload");
     c->gauge_loaded = true;
     c->gauge_id = gauge_id;
@@ -698,14 +766,14 @@ int tmx_load_clover(tmx_ctx *c, const double *host_T)
     if (!c->clov[F64]) {
         c->clov[F64] = dev_alloc(c, clover_bytes(F64, c->Vh));
         if (!c->clov[F64]) {
-            dev_free(stage);
+            dev_free(c, stage);
             return TMX_ENOMEM;
         }
     }
     hipError_t e = hipMemcpyAsync(stage, host_T, bytes, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_clover_from_canonical((const double *)stage, (double *)c->clov[F64], c->g, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    dev_free(stage);
+    dev_free(c, stage);
     if (e != hipSuccess) return hip_err(c, e, "clover upload");
     c->clover_from_host = true;
     c->clov_ok[F64] = true;
@@ -725,7 +793,7 @@ int tmx_get_clover(tmx_ctx *c, double *host_T)
     hipError_t e = launch_clover_to_canonical((const double *)c->clov[F64], (double *)stage, c->g, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(host_T, stage, bytes, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    dev_free(stage);
+    dev_free(c, stage);
     return hip_err(c, e, "clover download");
 }
 

@@ -735,20 +735,34 @@ int nn_ensure(tmx_ctx *c)
     if (!c->pc) c->pc = new PcState();
     PcState &s = *c->pc;
     if (s.params) return TMX_OK;
-    s.nparam = nn_num_params();
-    size_t bytes = s.nparam * sizeof(float);
-    if (hipMalloc(&s.params, bytes) != hipSuccess || hipMalloc(&s.grad, bytes) != hipSuccess ||
-        hipMalloc(&s.adam_m, bytes) != hipSuccess || hipMalloc(&s.adam_v, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return set_err(c, TMX_ENOMEM, "preconditioner weights");
-    }
+    const size_t bytes = nn_num_params() * sizeof(float);
+    float *bufs[4];
+    for (int i = 0; i < 4; ++i) bufs[i] = static_cast<float *>(dev_alloc(c, bytes));
+    uint16_t *wf[NN_L], *wa[NN_L];
+    bool ok = bufs[0] && bufs[1] && bufs[2] && bufs[3];
     for (int l = 0; l < NN_L; ++l) {
         const size_t nf = (size_t)NN_P * pad16(8 * NN_COUT[l]) * pad16(8 * NN_CIN[l]);
         const size_t na = (size_t)NN_P * pad16(8 * NN_CIN[l]) * pad16(8 * NN_COUT[l]);
-        if (hipMalloc(&s.Wf[l], nf * 2) != hipSuccess || hipMalloc(&s.Wa[l], na * 2) != hipSuccess) {
-            (void)hipGetLastError();
-            return set_err(c, TMX_ENOMEM, "preconditioner weights");
+        wf[l] = static_cast<uint16_t *>(dev_alloc(c, nf * 2));
+        wa[l] = static_cast<uint16_t *>(dev_alloc(c, na * 2));
+        ok = ok && wf[l] && wa[l];
+    }
+    if (!ok) {
+        for (int i = 0; i < 4; ++i) dev_free(c, bufs[i]);
+        for (int l = 0; l < NN_L; ++l) {
+            dev_free(c, wf[l]);
+            dev_free(c, wa[l]);
         }
+        return set_err(c, TMX_ENOMEM, "preconditioner weights: out of device memory");
+    }
+    s.nparam = nn_num_params();
+    s.params = bufs[0];
+    s.grad = bufs[1];
+    s.adam_m = bufs[2];
+    s.adam_v = bufs[3];
+    for (int l = 0; l < NN_L; ++l) {
+        s.Wf[l] = wf[l];
+        s.Wa[l] = wa[l];
     }
     return TMX_OK;
 }
@@ -775,12 +789,11 @@ int nn_links(tmx_ctx *c, NnLinks &L)
 {
     PcState &s = *c->pc;
     const long Vh = c->Vh;
-    if (!s.lrow) {
-        if (hipMalloc(&s.lrow, 72 * Vh * sizeof(uint32_t)) != hipSuccess ||
-            hipMalloc(&s.lcol, 72 * Vh * sizeof(uint32_t)) != hipSuccess) {
-            (void)hipGetLastError();
-            return set_err(c, TMX_ENOMEM, "network links");
-        }
+    if (!s.lrow || !s.lcol) {
+        if (!s.lrow) s.lrow = static_cast<uint32_t *>(dev_alloc(c, 72 * Vh * sizeof(uint32_t)));
+        if (!s.lcol) s.lcol = static_cast<uint32_t *>(dev_alloc(c, 72 * Vh * sizeof(uint32_t)));
+        if (!s.lrow || !s.lcol) return set_err(c, TMX_ENOMEM, "network links: out of device memory");
+        s.links_upload = -1;
     }
     if (s.links_upload != c->uploads) {
         if (!c->gauge_loaded) return set_err(c, TMX_ENOTLOADED, "no gauge field loaded");
@@ -949,11 +962,15 @@ namespace {
 struct Fg {
     tmx_ctx *c;
     long Vh;
-    SpinorPtr f(const std::string &name, int prec) const
+    bool nomem = false;  // a workspace could not be allocated
+    SpinorPtr f(const std::string &name, int prec)
     {
         void *d = ws_get(c, "fg_" + name, spinor_field_bytes(prec, 1, Vh));
+        if (!d) nomem = true;
         return make_spinor(d, prec, 1, Vh);
     }
+    // after a group of f() calls: nothing may run on a missing workspace
+    int need() const { return nomem ? set_err(c, TMX_ENOMEM, "FGCR workspace: out of device memory") : TMX_OK; }
 };
 
 template <class Op> int blas(tmx_ctx *c, const Op &o, long n, double *res, int nres)
@@ -991,7 +1008,10 @@ int fgcr_stage(tmx_ctx *c, int op, int dagger, SpinorPtr x, SpinorPtr b, double 
     for (int j = 0; j < m; ++j) {
         zs[j] = F.f("z" + std::to_string(j), F32);
         ws[j] = F.f("w" + std::to_string(j), F32);
-        if (!zs[j].d || !ws[j].d) return TMX_ENOMEM;
+    }
+    {
+        const int rn = F.need();
+        if (rn) return rn;
     }
     double bb;
     {
@@ -1147,6 +1167,8 @@ extern "C" int tmx_fgcr_solve_internal(tmx_ctx *c, SpinorPtr x, SpinorPtr b, con
     if (rc) return rc;
     Fg F{c, c->Vh};
     SpinorPtr y = F.f("y", F64);
+    rc = F.need();
+    if (rc) return rc;
     // y = 0 ; stage 1: Mhat^dagger y = b
     {
         OpZero<F64> z{};
@@ -1155,14 +1177,16 @@ extern "C" int tmx_fgcr_solve_internal(tmx_ctx *c, SpinorPtr x, SpinorPtr b, con
         rc = blas(c, z, c->Vh, nullptr, 0);
         if (rc) return rc;
     }
-    bool ok = true;
+    // errors (no memory, a failed launch) end the solve; a stage that does
+    // not converge hands over to the CG below
     rc = fgcr_stage(c, cfg->op, 1, y, b, tau, m, maxiter, cfg->inner_prec, info);
-    if (rc < 0 && rc != TMX_ENOCONV) ok = false;
-    if (rc == TMX_ENOCONV) ok = false;
+    if (rc < 0) return rc;
+    bool ok = rc == TMX_OK;
     if (ok) {
         // stage 2: Mhat x = y (x holds the start vector)
         rc = fgcr_stage(c, cfg->op, 0, x, y, tau, m, maxiter, cfg->inner_prec, info);
-        if (rc != TMX_OK) ok = false;
+        if (rc < 0) return rc;
+        ok = rc == TMX_OK;
     }
     // acceptance (and fallback) by plain CG on N from the current x: with
     // the network doing its job this only computes the true residual
@@ -1182,16 +1206,16 @@ void tmx_pc_free(tmx_ctx *c)
 {
     if (!c || !c->pc) return;
     PcState &s = *c->pc;
-    dev_free(s.params);
-    dev_free(s.grad);
-    dev_free(s.adam_m);
-    dev_free(s.adam_v);
+    dev_free(c, s.params);
+    dev_free(c, s.grad);
+    dev_free(c, s.adam_m);
+    dev_free(c, s.adam_v);
     for (int l = 0; l < NN_L; ++l) {
-        dev_free(s.Wf[l]);
-        dev_free(s.Wa[l]);
+        dev_free(c, s.Wf[l]);
+        dev_free(c, s.Wa[l]);
     }
-    dev_free(s.lrow);
-    dev_free(s.lcol);
+    dev_free(c, s.lrow);
+    dev_free(c, s.lcol);
     delete c->pc;
     c->pc = nullptr;
 }
@@ -1392,6 +1416,53 @@ int tmx_pc_loss_grad(tmx_ctx *c, const double *b, const double *x, int npairs, i
     return hip_err(c, hipStreamSynchronize(c->stream), "loss grad");
 }
 
+// Adam defaults for unset (zero) fields of a training configuration
+static void adam_params(const tmx_train_cfg *cfg, float &lr, float &b1, float &b2, float &eps)
+{
+    lr = cfg->lr > 0 ? cfg->lr : 1e-3f;
+    b1 = cfg->beta1 > 0 ? cfg->beta1 : 0.9f;
+    b2 = cfg->beta2 > 0 ? cfg->beta2 : 0.999f;
+    eps = cfg->eps > 0 ? cfg->eps : 1e-8f;
+}
+
+// one Adam step on the master weights from the gradient in s.grad
+static int adam_step(tmx_ctx *c, float lr, float b1, float b2, float eps)
+{
+    PcState &s = *c->pc;
+    if (s.adam_t == 0) {
+        hipLaunchKernelGGL(nn_zero_kernel, dim3((unsigned)((s.nparam + 255) / 256)), dim3(256), 0, c->stream, s.adam_m,
+                           s.nparam);
+        hipLaunchKernelGGL(nn_zero_kernel, dim3((unsigned)((s.nparam + 255) / 256)), dim3(256), 0, c->stream, s.adam_v,
+                           s.nparam);
+    }
+    s.adam_t++;
+    // bias corrections 1 - beta^t
+    const float c1 = 1.f - std::pow(b1, (float)s.adam_t), c2 = 1.f - std::pow(b2, (float)s.adam_t);
+    hipLaunchKernelGGL(nn_adam_kernel, dim3((unsigned)((s.nparam + 255) / 256)), dim3(256), 0, c->stream, s.params,
+                       s.grad, s.adam_m, s.adam_v, (int)s.nparam, lr, b1, b2, eps, c1, c2);
+    s.w_ok = false;
+    return hip_err(c, hipGetLastError(), "adam");
+}
+
+int tmx_pc_adam_step(tmx_ctx *c, const float *host_grad, size_t n, const tmx_train_cfg *cfg)
+{
+    if (!c || !host_grad || !cfg) return c ? set_err(c, TMX_EINVAL, "tmx_pc_adam_step: bad argument") : TMX_EINVAL;
+    if (n != nn_num_params()) return set_err(c, TMX_EINVAL, "wrong number of gradient values");
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(host_grad[i])) return set_err(c, TMX_EINVAL, "non-finite gradient value");
+    int r = nn_ensure(c);
+    if (r) return r;
+    if (!c->pc->have_weights) return set_err(c, TMX_ENOTLOADED, "preconditioner weights not set");
+    float lr, b1, b2, eps;
+    adam_params(cfg, lr, b1, b2, eps);
+    if (!(b1 < 1.f) || !(b2 < 1.f)) return set_err(c, TMX_EINVAL, "Adam decay rates must lie in (0, 1)");
+    r = hip_err(c, hipMemcpyAsync(c->pc->grad, host_grad, n * sizeof(float), hipMemcpyHostToDevice, c->stream),
+                "gradient upload");
+    if (!r) r = adam_step(c, lr, b1, b2, eps);
+    if (r) return r;
+    return hip_err(c, hipStreamSynchronize(c->stream), "adam step");
+}
+
 int tmx_pc_train(tmx_ctx *c, const double *b, const double *x, int npairs, const tmx_train_cfg *cfg, float *loss_out)
 {
     if (!c || !b || !x || npairs < 1 || !cfg || cfg->epochs < 1 || cfg->batch < 1) return TMX_EINVAL;
@@ -1403,15 +1474,9 @@ int tmx_pc_train(tmx_ctx *c, const double *b, const double *x, int npairs, const
     if (!c->pc->have_weights) return set_err(c, TMX_ENOTLOADED, "preconditioner weights not set");
     r = ensure_ready(c, F32, false);
     if (r) return r;
-    PcState &s = *c->pc;
-    if (s.adam_t == 0) {
-        hipLaunchKernelGGL(nn_zero_kernel, dim3((unsigned)((s.nparam + 255) / 256)), dim3(256), 0, c->stream, s.adam_m,
-                           s.nparam);
-        hipLaunchKernelGGL(nn_zero_kernel, dim3((unsigned)((s.nparam + 255) / 256)), dim3(256), 0, c->stream, s.adam_v,
-                           s.nparam);
-    }
-    const float lr = cfg->lr > 0 ? cfg->lr : 1e-3f, b1 = cfg->beta1 > 0 ? cfg->beta1 : 0.9f,
-                b2 = cfg->beta2 > 0 ? cfg->beta2 : 0.999f, eps = cfg->eps > 0 ? cfg->eps : 1e-8f;
+    float lr, b1, b2, eps;
+    adam_params(cfg, lr, b1, b2, eps);
+    if (!(b1 < 1.f) || !(b2 < 1.f)) return set_err(c, TMX_EINVAL, "Adam decay rates must lie in (0, 1)");
     // deterministic shuffle (LCG seeded by cfg->seed)
     std::vector<int> order(npairs);
     for (int i = 0; i < npairs; ++i) order[i] = i;
@@ -1434,13 +1499,8 @@ int tmx_pc_train(tmx_ctx *c, const double *b, const double *x, int npairs, const
             if (!std::isfinite(L)) return set_err(c, TMX_ENOCONV, "training loss is not finite");
             eloss += L;
             ++nb;
-            s.adam_t++;
-            const float c1 = 1.f - std::pow(b1, (float)s.adam_t), c2 = 1.f - std::pow(b2, (float)s.adam_t);
-            hipLaunchKernelGGL(nn_adam_kernel, dim3((unsigned)((s.nparam + 255) / 256)), dim3(256), 0, c->stream,
-                               s.params, s.grad, s.adam_m, s.adam_v, (int)s.nparam, lr, b1, b2, eps, c1, c2);
-            r = hip_err(c, hipGetLastError(), "adam");
+            r = adam_step(c, lr, b1, b2, eps);
             if (r) return r;
-            s.w_ok = false;
         }
         if (loss_out) loss_out[ep] = (float)(eloss / nb);
     }

@@ -18,6 +18,15 @@ struct Workspace {
     size_t bytes = 0;
 };
 
+// one live device allocation: its size and the allocator that made it (the
+// caller's hook, or hipMalloc when none was set), so that it is released by
+// the same one whatever hook is in place later
+struct AllocRec {
+    size_t bytes = 0;
+    void (*release)(void *, void *) = nullptr;  // null: hipFree
+    void *user = nullptr;
+};
+
 struct TraceFrame {
     std::string name;
     double t0;
@@ -84,6 +93,14 @@ struct tmx_ctx {
 
     // named scratch buffers
     std::map<std::string, tmx::Workspace> ws;
+    size_t ws_bytes = 0;  // bytes held by the named scratch buffers
+    size_t ws_limit = 0;  // cap on ws_bytes (0: none), from TMX_WS_LIMIT
+
+    // device allocator: the caller's hook (tmx_set_allocator) or hipMalloc
+    void *(*alloc_fn)(size_t, void *) = nullptr;
+    void (*release_fn)(void *, void *) = nullptr;
+    void *alloc_user = nullptr;
+    std::map<void *, tmx::AllocRec> allocs;  // every live device allocation
 
     // tracing
     bool trace = false;
@@ -117,9 +134,14 @@ namespace tmx {
 int set_err(tmx_ctx *c, int code, const std::string &msg);
 int hip_err(tmx_ctx *c, hipError_t e, const char *where);
 
-// memory
+// memory: every device buffer of a context comes from dev_alloc (the
+// caller's allocator if one is set, else hipMalloc) and goes back through
+// dev_free.  ws_get returns a named scratch buffer of at least `bytes`, or
+// nullptr with TMX_ENOMEM recorded (allocation failure or the TMX_WS_LIMIT
+// cap): callers check it before launching anything on it.
+void *dev_alloc(tmx_ctx *c, size_t bytes);
+void dev_free(tmx_ctx *c, void *p);
 void *ws_get(tmx_ctx *c, const std::string &name, size_t bytes);
-void dev_free(void *p);
 
 // lazily build everything an apply in `prec` needs
 int ensure_ready(tmx_ctx *c, int prec, bool nd);

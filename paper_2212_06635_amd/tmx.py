@@ -61,6 +61,12 @@ class tmx_train_cfg(ctypes.Structure):
                 ("seed", ctypes.c_int), ("loss_kind", ctypes.c_int), ("op", ctypes.c_int)]
 
 
+# the device allocator hooks of tmx_set_allocator
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+NO_ALLOC, NO_RELEASE = ALLOC_FN(0), RELEASE_FN(0)  # NULL hooks: back to hipMalloc / hipFree
+
+
 def _load():
     # torch first: its bundled HIP runtime then satisfies libtmx.so's
     # dependency, so device pointers and streams are shared by both.
@@ -76,6 +82,7 @@ def _load():
         "tmx_last_error": ([P], ctypes.c_char_p),
         "tmx_set_stream": ([P, P], I),
         "tmx_set_params": ([P, ctypes.POINTER(tmx_params)], I),
+        "tmx_set_allocator": ([P, ALLOC_FN, RELEASE_FN, P], I),
         "tmx_load_gauge": ([P, P, D], I),
         "tmx_gauge_uploads": ([P], I),
         "tmx_load_clover": ([P, P], I),
@@ -99,6 +106,7 @@ def _load():
         "tmx_pc_get_weights": ([P, P, Z], I),
         "tmx_pc_apply": ([P, P, P, I], I),
         "tmx_pc_train": ([P, P, P, I, ctypes.POINTER(tmx_train_cfg), P], I),
+        "tmx_pc_adam_step": ([P, P, Z, ctypes.POINTER(tmx_train_cfg)], I),
         "tmx_pc_loss_grad": ([P, P, P, I, I, I, ctypes.POINTER(D), P], I),
         "tmx_tune": ([P, I, I, I], I),
         "tmx_tuned_config": ([P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(I)], I),
@@ -135,6 +143,47 @@ def _stream_handle():
     return torch.cuda.current_stream().cuda_stream
 
 
+class TorchAllocator:
+    """Device buffers of a context from torch's caching allocator.
+
+    The library calls ``alloc(bytes)`` for every device buffer it needs (links,
+    clover blocks, inverses, workspaces, network state) and ``release(ptr)``
+    when it is done with one; each buffer is a torch uint8 tensor kept alive
+    here until released.  Counts and bytes are kept for inspection."""
+
+    def __init__(self):
+        import torch
+
+        self.torch = torch
+        self.live = {}
+        self.n_alloc = 0
+        self.n_release = 0
+        self.bytes_alloc = 0
+
+        def _alloc(nbytes, user):
+            try:
+                t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device="cuda")
+            except Exception:  # out of memory: the library reports TMX_ENOMEM
+                return None
+            p = t.data_ptr()
+            self.live[p] = t
+            self.n_alloc += 1
+            self.bytes_alloc += int(nbytes)
+            return p
+
+        def _release(ptr, user):
+            if self.live.pop(ptr, None) is not None:
+                self.n_release += 1
+
+        # the ctypes function objects must outlive every call into the library
+        self.alloc_fn = ALLOC_FN(_alloc)
+        self.release_fn = RELEASE_FN(_release)
+
+    @property
+    def live_bytes(self):
+        return sum(t.numel() for t in self.live.values())
+
+
 @dataclass
 class Params:
     kappa: float
@@ -149,7 +198,10 @@ class Params:
 class Context:
     """One lattice geometry on the current device; device memory via torch."""
 
-    def __init__(self, dims, stream=None):
+    def __init__(self, dims, stream=None, allocator="torch"):
+        """allocator: "torch" (default) routes every device buffer of the
+        library through torch's caching allocator (tmx_set_allocator); "hip"
+        leaves the library on hipMalloc."""
         import torch
 
         self.torch = torch
@@ -163,6 +215,12 @@ class Context:
         if rc != TMX_OK:
             raise TmxError(rc, "tmx_create failed")
         self.h = h
+        self.allocator = None
+        if allocator == "torch":
+            self.allocator = TorchAllocator()
+            self.check(lib.tmx_set_allocator(self.h, self.allocator.alloc_fn, self.allocator.release_fn, None))
+        elif allocator != "hip":
+            raise ValueError(f"unknown allocator {allocator!r}")
 
     # -- plumbing ----------------------------------------------------------
     def check(self, rc, allow_noconv=False):
@@ -279,10 +337,12 @@ class Context:
                                                int(accumulate)))
 
     def _check_force_sizes(self, force, x, y):
-        # the library takes plain pointers: check the element counts here
-        for t, n, name in ((force, self.V * 36, "force"), (x, self.Vh * 12, "x"), (y, self.Vh * 12, "y")):
-            if hasattr(t, "numel") and t.numel() < n:
-                raise ValueError(f"{name} holds {t.numel()} complex values, needs {n}")
+        # the library takes plain device pointers and writes V * 36 complex128
+        # values through `force`: only contiguous complex128 device tensors of
+        # at least the needed size are passed on
+        check_device_complex128(force, self.V * 36, "force")
+        check_device_complex128(x, self.Vh * 12, "x")
+        check_device_complex128(y, self.Vh * 12, "y")
 
     def rational_apply(self, out, b, a0, coeffs, shifts, **kw):
         """out = a0 b + sum_k coeffs[k] (N + shifts[k])^{-1} b (device odd fields)."""
@@ -327,6 +387,11 @@ class Context:
 
     def pc_apply(self, out, inp, dagger=0):
         return self.check(lib.tmx_pc_apply(self.h, _ptr(out), _ptr(inp), int(dagger)))
+
+    def pc_adam_step(self, grad: np.ndarray, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        g = np.ascontiguousarray(grad, dtype=np.float32)
+        cfg = tmx_train_cfg(1, 1, lr, beta1, beta2, eps, 0, 0, 0)
+        return self.check(lib.tmx_pc_adam_step(self.h, g.ctypes.data, g.size, ctypes.byref(cfg)))
 
     def pc_train(self, b, x, npairs, epochs=10, batch=8, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0,
                  loss_kind=0, op=TMX_OP_PLUS):
@@ -378,6 +443,23 @@ class Context:
 
     def trace_pop(self):
         return self.check(lib.tmx_trace_pop(self.h))
+
+
+def check_device_complex128(t, n, name):
+    """Raise ValueError unless t is a contiguous complex128 CUDA tensor of at
+    least n elements (16 n bytes): what a kernel writing through its pointer needs."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor on the GPU, not {type(t).__name__}")
+    if t.dtype != torch.complex128:
+        raise ValueError(f"{name} must be complex128, not {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.element_size() * t.numel() < 16 * n:
+        raise ValueError(f"{name} holds {t.numel()} complex128 values, needs {n}")
 
 
 def canonical_gauge_order(U: np.ndarray) -> np.ndarray:

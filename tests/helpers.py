@@ -29,3 +29,27 @@ def oracle_T_to_blocks(T):
         idx = np.arange(6 * c, 6 * c + 6)
         out[:, c] = T[:, idx][:, :, idx]
     return out
+
+
+def tile_full(v, base, rep):
+    """Full-lattice field in lexicographic order (x fastest) of the lattice
+    `base` -> the same field repeated rep = (nx, ny, nz) times in x, y, z
+    (index bookkeeping only: a periodic copy of the base lattice)."""
+    lx, ly, lz, lt = base
+    a = np.asarray(v).reshape((lt, lz, ly, lx) + v.shape[1:])
+    a = np.tile(a, (1, rep[2], rep[1], rep[0]) + (1,) * (v.ndim - 1))
+    return a.reshape((-1,) + v.shape[1:])
+
+
+def tile_cb(v_cb, base, rep):
+    """Odd-checkerboard field of the base lattice -> the same of the tiled
+    lattice (the extents stay even, so a site keeps its parity)."""
+    from paper_2212_06635_amd import synth
+
+    dims = (base[0] * rep[0], base[1] * rep[1], base[2] * rep[2], base[3])
+    return synth.full_to_cb(tile_full(synth.cb_to_full(v_cb, base), base, rep), dims)
+
+
+def tile_links(U, rep):
+    """Links [t][z][y][x][mu][3][3] of the base lattice, repeated in x, y, z."""
+    return np.tile(U, (1, rep[2], rep[1], rep[0], 1, 1, 1))

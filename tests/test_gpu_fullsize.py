@@ -65,8 +65,25 @@ def test_fullsize_multishift_nd(F):
     rc, info = ctx.multishift_solve(x, to_dev(b), shifts, op=2, tol=1e-10, inner_prec=1)
     assert rc == tmx.TMX_OK
     xs = to_host(x, (12,) + b.shape)
-    for k in (0, 5, 11):
-        assert o.residual(b, xs[k], nf=2, shift=shifts[k]) <= 1e-10
+    for k in range(12):
+        assert o.residual(b, xs[k], nf=2, shift=shifts[k]) <= 1e-10, (k, info[k])
+
+
+@pytest.mark.parametrize("kind", [1])
+def test_fullsize_multi_rhs_nd(F, kind):
+    """The bench's 12 right-hand sides of the two-flavour operator in one
+    batched MP-CG (FP32 inner iterations, FP64 reliable updates): every column
+    accepted by the oracle's residual."""
+    tmx, o, ctx = F
+    n = 12
+    bs = np.stack([synth.gaussian_cb_spinor(DIMS, 4, 100 + k, 2) for k in range(n)])
+    x = to_dev(np.zeros_like(bs))
+    rc, info = ctx.solve(x, to_dev(bs), n, kind=kind, op=2, tol=1e-10)
+    assert rc == tmx.TMX_OK
+    xs = to_host(x, bs.shape)
+    del x
+    for k in range(n):
+        assert o.residual(bs[k], xs[k], nf=2) <= 1e-10, (k, info[k])
 
 
 def test_fullsize_force_directional_derivative(F):

@@ -1,0 +1,159 @@
+"""Device memory of the library: the caller's allocator serves every buffer,
+and a workspace that cannot be had (allocation failure or the TMX_WS_LIMIT
+cap) makes a call return TMX_ENOMEM before anything is launched on it."""
+import numpy as np
+import pytest
+
+from helpers import CSW, EPSBAR, KAPPA, MUBAR, rel_l2, to_dev, to_host
+from oracle import Oracle
+from oracle import nn_oracle as nn
+from paper_2212_06635_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+MU0 = 0.01
+TOL = {0: 1e-13, 1: 1e-6, 2: 5e-3}
+
+
+def test_allocator_hook_serves_every_device_buffer():
+    """With torch's allocator as the hook, the Schur operator in every
+    precision and both flavour sectors matches the oracle, the device memory
+    the context takes is what torch's allocator handed out (no buffer of its
+    own from hipMalloc), and destroying the context gives every buffer back."""
+    import torch
+
+    import paper_2212_06635_amd.tmx as tmx
+
+    dims = (16, 16, 16, 32)
+    print(f"\n[gpu memory] allocator hook, {dims}", flush=True)
+    U = synth.gauge_links(dims, 0.3, 11)
+    o = Oracle(dims, U, KAPPA, CSW, mu=MU0, mubar=MUBAR, epsbar=EPSBAR)
+    # the library's code objects (with their static scratch) are loaded on the
+    # device by the first context of the process: load them before measuring
+    tmx.Context((4, 4, 4, 4), allocator="hip").close()
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    res0 = torch.cuda.memory_reserved()
+    ctx = tmx.Context(dims, allocator="torch")
+    A = ctx.allocator
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU0, MUBAR, EPSBAR, -1))
+    ctx.load_gauge(U, 11.0)
+    for nf, op in ((1, 1), (2, 2)):
+        kind = tmx.TMX_FIELD_ODD if nf == 1 else tmx.TMX_FIELD_ODD_ND
+        v = synth.gaussian_cb_spinor(dims, 11, nf, nf)
+        ref = o.mhat(v, nf=nf)
+        for prec in (0, 1, 2):
+            out = ctx.empty(kind, prec)
+            ctx.apply_mhat(out, ctx.pack(to_dev(v), kind, prec), op, prec)
+            assert rel_l2(to_host(ctx.unpack(out, kind, prec), v.shape), ref) < TOL[prec]
+    torch.cuda.synchronize()
+    Vh = ctx.Vh
+    # 2-row links, clover (both parities) and the two inverses in three precisions
+    fields = sum(Vh * (8 * 96 + 144 * 8 + 144 * 8 + 72 * 8) * b / 8 for b in (8, 4, 2))
+    print(f"[gpu memory] {A.n_alloc} allocations through the hook, {A.live_bytes / 1e6:.1f} MB live "
+          f"(fields alone {fields / 1e6:.1f} MB)", flush=True)
+    assert A.n_alloc >= 20 and A.live_bytes >= fields
+    # what the device lost is what torch's allocator reserved (the library's
+    # buffers and the test's own tensors); hipMalloc'd buffers would come on top
+    taken = free0 - torch.cuda.mem_get_info()[0]
+    grown = torch.cuda.memory_reserved() - res0
+    assert taken <= grown + (16 << 20), (taken, grown)
+    n = A.n_alloc
+    ctx.close()
+    assert A.n_release == n and not A.live
+
+
+def test_allocator_hook_arguments():
+    import paper_2212_06635_amd.tmx as tmx
+
+    ctx = tmx.Context((4, 4, 4, 4), allocator="hip")
+    only_alloc = tmx.ALLOC_FN(lambda n, u: None)
+    assert tmx.lib.tmx_set_allocator(ctx.h, only_alloc, tmx.NO_RELEASE, None) == tmx.TMX_EINVAL
+    # an allocator that has nothing to give: every later allocation is TMX_ENOMEM
+    none = tmx.ALLOC_FN(lambda n, u: None)
+    drop = tmx.RELEASE_FN(lambda p, u: None)
+    assert tmx.lib.tmx_set_allocator(ctx.h, none, drop, None) == tmx.TMX_ENOMEM
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def small():
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_links(dims, 0.3, 1)
+    o = Oracle(dims, U, KAPPA, CSW, mu=MU0, mubar=MUBAR, epsbar=EPSBAR)
+    return dims, U, o
+
+
+def _ctx(tmx, dims, U, limit, monkeypatch):
+    monkeypatch.setenv("TMX_WS_LIMIT", str(int(limit)))
+    ctx = tmx.Context(dims)
+    monkeypatch.delenv("TMX_WS_LIMIT")
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU0, MUBAR, EPSBAR, -1))
+    ctx.load_gauge(U, 1.0)
+    ctx.pc_set_weights(nn.identity_init(np.random.default_rng(3), 1e-2))
+    return ctx
+
+
+def test_workspace_limit_gives_enomem(small, monkeypatch):
+    """For a ladder of workspace caps, FGCR and the network-preconditioned CG,
+    the multishift solve, the rational function and the force calls either
+    finish (their solutions accepted by the oracle) or return TMX_ENOMEM
+    naming the cap; every call meets the cap at some rung and finishes at the
+    top one."""
+    import torch
+
+    import paper_2212_06635_amd.tmx as tmx
+
+    dims, U, o = small
+    b = synth.gaussian_cb_spinor(dims, 5, 0)
+    b2 = synth.gaussian_cb_spinor(dims, 5, 1, 2)
+    y = synth.gaussian_cb_spinor(dims, 5, 2)
+    V = o.V
+    field = o.Vh * 24 * 8  # one FP64 odd field
+    calls = {
+        "fgcr": lambda c: c.solve(to_dev(np.zeros_like(b)), to_dev(b), 1, kind=tmx.TMX_SOLVER_FGCR_NN, op=1,
+                                  restart=4),
+        "pcg_nn": lambda c: c.solve(to_dev(np.zeros_like(b)), to_dev(b), 1, kind=tmx.TMX_SOLVER_PCG_NN, op=1,
+                                    inner_prec=2),
+        "multishift": lambda c: c.multishift_solve(to_dev(np.zeros((3,) + b2.shape)), to_dev(b2), [1e-3, 1e-2, 1e-1],
+                                                   op=2, inner_prec=1),
+        "rational": lambda c: c.rational_apply(to_dev(np.zeros_like(b2)), to_dev(b2), 0.5, [0.1, 0.2],
+                                               [1e-2, 1e-1], op=2),
+        "hop_force": lambda c: c.hop_force(torch.zeros(V * 36, dtype=torch.complex128, device="cuda"), to_dev(b),
+                                           to_dev(y)),
+        "clover_force": lambda c: c.clover_force(torch.zeros(V * 36, dtype=torch.complex128, device="cuda"),
+                                                 to_dev(b), to_dev(y)),
+    }
+    seen = {k: set() for k in calls}
+    rungs = [1, 2, 3, 4, 6, 8, 11, 14, 18, 24, 40, 200]  # in half fields; 0 would mean no cap
+    for k in rungs:
+        limit = k * field // 2
+        print(f"[gpu memory] workspace cap {limit} bytes", flush=True)
+        ctx = _ctx(tmx, dims, U, limit, monkeypatch)
+        for name, call in calls.items():
+            try:
+                r = call(ctx)
+                rc = r[0] if isinstance(r, tuple) else r
+                assert rc in (tmx.TMX_OK, tmx.TMX_ENOCONV), (name, k, rc)
+                seen[name].add("ok")
+            except tmx.TmxError as e:
+                assert e.code == tmx.TMX_ENOMEM, (name, k, e)
+                assert "workspace" in str(e), (name, k, e)
+                seen[name].add("enomem")
+        # a capped context stays usable: the operator still matches the oracle
+        # whenever its own workspace fits
+        try:
+            out = ctx.empty(tmx.TMX_FIELD_ODD, 0)
+            ctx.apply_mhat(out, ctx.pack(to_dev(b), tmx.TMX_FIELD_ODD, 0), 1, 0)
+            assert rel_l2(to_host(ctx.unpack(out, tmx.TMX_FIELD_ODD, 0), b.shape), o.mhat(b)) < 1e-13
+        except tmx.TmxError as e:
+            assert e.code == tmx.TMX_ENOMEM
+        ctx.close()
+    for name, s in seen.items():
+        assert s == {"ok", "enomem"}, (name, s)
+    # at the top rung the solves are the real thing
+    ctx = _ctx(tmx, dims, U, 200 * field, monkeypatch)
+    x = to_dev(np.zeros_like(b))
+    rc, info = ctx.solve(x, to_dev(b), 1, kind=tmx.TMX_SOLVER_PCG_NN, op=1, inner_prec=2)
+    assert rc == tmx.TMX_OK and o.residual(b, to_host(x, b.shape)) <= 1e-10
+    ctx.close()

@@ -129,17 +129,25 @@ def test_trained_network_beats_untrained(S, pairs):
     rc1, info1 = ctx.solve(x, b, 1, kind=tmx.TMX_SOLVER_PCG_NN, op=1, tol=1e-10)
     print("PCG iterations identity / trained:", info0[0]["iters"], info1[0]["iters"])
     assert rc0 == tmx.TMX_OK and rc1 == tmx.TMX_OK
+    # both on the preconditioned path itself (a fallback would add plain-CG iterations)
+    assert info0[0]["fallback"] == 0 and info1[0]["fallback"] == 0, (info0, info1)
     assert info1[0]["iters"] < info0[0]["iters"], (info0, info1)
 
 
 def test_fgcr_reaches_target(S, pairs):
-    """FGCR with the (trained) network: FP64 true residual <= 1e-10 by the oracle operator."""
+    """FGCR with the trained network converges on its own (no CG fallback):
+    FP64 true residual <= 1e-10 by the oracle operator."""
     tmx, ctx, lat, U = S
+    bs, xd = pairs
     o = Oracle(DIMS, U, KAPPA, CSW, mu=MU0)
+    ctx.pc_set_weights(nn.identity_init(np.random.default_rng(3), 1e-2))
+    ctx.pc_train(to_dev(bs), xd, len(bs), epochs=30, batch=4, lr=3e-3, seed=2, loss_kind=0)
     b = synth.gaussian_cb_spinor(DIMS, 60, 0)
     x = to_dev(np.zeros_like(b))
     rc, info = ctx.solve(x, to_dev(b), 1, kind=tmx.TMX_SOLVER_FGCR_NN, op=1, tol=1e-10, restart=8)
+    print("FGCR:", info[0])
     assert rc == tmx.TMX_OK, info
+    assert info[0]["fallback"] == 0, info
     assert o.residual(b, to_host(x, b.shape)) <= 1e-10
 
 
@@ -213,7 +221,9 @@ def test_multishift_refinement_with_learned_pc(S, pairs):
     n = b.size
     for inner in (tmx.TMX_F32, tmx.TMX_F16):
         x = to_dev(np.zeros(len(shifts) * n, dtype=np.complex128))
-        rc, info = ctx.multishift_solve(x, to_dev(b), shifts, kind=tmx.TMX_SOLVER_PCG_NN, op=1, tol=1e-10,
+        # the library's own FP64 residual and the oracle's differ in rounding:
+        # ask for 0.9e-10 so that the oracle's check can hold at 1e-10
+        rc, info = ctx.multishift_solve(x, to_dev(b), shifts, kind=tmx.TMX_SOLVER_PCG_NN, op=1, tol=0.9e-10,
                                         inner_prec=inner)
         assert rc == tmx.TMX_OK
         xp = to_dev(np.zeros(len(shifts) * n, dtype=np.complex128))
@@ -224,9 +234,42 @@ def test_multishift_refinement_with_learned_pc(S, pairs):
             res = rel_l2(o.mdagm(xk) + s * xk, b)
             print(f"inner {inner} shift {s:g}: {info[k]['iters']} iterations, "
                   f"{info[k]['restarts']} network applications, oracle residual {res:.2e}")
-            assert res <= 1.01e-10
+            assert res <= 1e-10
             assert info[k]["restarts"] >= 1
             assert rel_l2(xk, to_host(xp[k * n:(k + 1) * n], b.shape)) < 1e-8
     with pytest.raises(tmx.TmxError):
         ctx.multishift_solve(to_dev(np.zeros(2 * n, dtype=np.complex128)), to_dev(b), [0.0, 0.1],
                              kind=tmx.TMX_SOLVER_PCG_NN, op=tmx.TMX_OP_WPLUS)
+
+
+def test_adam_step_matches_oracle(S):
+    """Four Adam steps of the library (FP32, on caller-given gradients) against
+    the oracle's FP64 Adam from the same FP32 weights, gradients and
+    hyper-parameters; setting the weights restarts the step count."""
+    tmx, ctx, lat, _ = S
+    rng = np.random.default_rng(47)
+    n = nn.num_params()
+    w0 = nn.identity_init(rng, 0.1).astype(np.float32)
+    grads = [(rng.standard_normal(n) * 10.0 ** rng.uniform(-4, 1, n)).astype(np.float32) for _ in range(4)]
+    hp = {"lr": 2e-3, "beta1": 0.85, "beta2": 0.995, "eps": 1e-7}
+    hp64 = {k: float(np.float32(v)) for k, v in hp.items()}  # what the FP32 configuration holds
+    ctx.pc_set_weights(w0)
+    for g in grads:
+        ctx.pc_adam_step(g, **hp)
+    got = ctx.pc_get_weights().astype(np.float64)
+    w, m, v = w0.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t, g in enumerate(grads, start=1):
+        w, m, v = nn.adam_step(w, m, v, t, g.astype(np.float64), **hp64)
+    err = np.abs(got - w).max()
+    print(f"Adam: max |w_gpu - w_oracle| = {err:.2e} after 4 steps of size ~{hp['lr']}")
+    assert err <= 2e-6
+    ctx.pc_set_weights(w0)
+    ctx.pc_adam_step(grads[1], **hp)
+    w1, _, _ = nn.adam_step(w0.astype(np.float64), np.zeros(n), np.zeros(n), 1, grads[1].astype(np.float64), **hp64)
+    assert np.abs(ctx.pc_get_weights() - w1).max() <= 1e-6
+    with pytest.raises(tmx.TmxError):
+        ctx.pc_adam_step(grads[0][:10], **hp)
+    bad = grads[0].copy()
+    bad[3] = np.inf
+    with pytest.raises(tmx.TmxError):
+        ctx.pc_adam_step(bad, **hp)

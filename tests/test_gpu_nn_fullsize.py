@@ -1,0 +1,70 @@
+"""The learned network at the benchmark's volumes, element by element against
+the FP64 network oracle.
+
+No oracle pass over 2M (or 33.5M) sites is affordable in a test, so the
+fields are periodic copies: an 8^3x64 base lattice repeated 4x in x, y and z
+is a 32^3x64 lattice, an 8^3x128 base repeated 8x is 64^3x128 (the time
+extent is kept: copies in the antiperiodic direction would not reproduce the
+boundary).  The network is translation invariant and gauge covariant, so on
+the tiled links and the tiled source it gives the tiled output of the base
+lattice.  Every index of the layer kernels at full size is exercised with
+values the oracle computes: the tiles that alternate between the parities,
+the first layer's path skipping (odd tiles run d = 0 only, even tiles the
+eight hops), the odd-only last layer, offsets beyond 2^32 bytes at
+64^3x128.  Random weights (every path non-zero, scale 0.3) so that a wrong
+path, transport or weight shows; BF16 staging bounds the agreement to
+relative L2 2e-2 as at 8x8x4x8.
+"""
+import gc
+
+import numpy as np
+import pytest
+
+from helpers import CSW, KAPPA, rel_l2, tile_cb, tile_links, to_dev, to_host
+from oracle import nn_oracle as nn
+from paper_2212_06635_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+MU = 0.00072
+
+
+@pytest.mark.parametrize("base,rep", [((8, 8, 8, 64), (4, 4, 4)), ((8, 8, 8, 128), (8, 8, 8))],
+                         ids=["32x32x32x64", "64x64x64x128"])
+def test_network_tiled_full_size(base, rep):
+    import torch
+
+    import paper_2212_06635_amd.tmx as tmx
+
+    dims = (base[0] * rep[0], base[1] * rep[1], base[2] * rep[2], base[3])
+    print(f"\n[gpu nn full size] {dims} from base {base}", flush=True)
+    U0 = synth.gauge_links(base, 0.25, 6)
+    lat = nn.Lattice(base, U0, t_bc=-1)
+    rng = np.random.default_rng(44)
+    w = (rng.standard_normal(nn.num_params()) * 0.3).astype(np.float32)
+    b0 = synth.gaussian_cb_spinor(base, 44, 0)
+    ref = {d: (nn.adjoint if d else nn.forward)(lat, w.astype(np.float64), b0[:, 0]) for d in (0, 1)}
+    ctx = tmx.Context(dims)
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU, 0.0, 0.0, -1))
+    U = tile_links(U0, rep)
+    ctx.load_gauge(U, 6.0)
+    del U
+    gc.collect()
+    ctx.pc_set_weights(w)
+    b = tile_cb(b0, base, rep)
+    bd = to_dev(b)
+    out = torch.zeros_like(bd)
+    for dagger in (0, 1):
+        ctx.pc_apply(out, bd, dagger)
+        got = to_host(out, b.shape)[:, 0]
+        want = tile_cb(ref[dagger][:, None], base, rep)[:, 0]
+        err = rel_l2(got, want)
+        # every site, not only the bulk: the worst site's error against the field's scale
+        site = np.sqrt((np.abs(got - want) ** 2).sum(axis=(1, 2)) / (np.abs(want) ** 2).sum(axis=(1, 2)).mean())
+        print(f"[gpu nn full size] dagger={dagger}: rel L2 {err:.2e}, worst site {site.max():.2e}", flush=True)
+        assert err < 2e-2
+        assert site.max() < 0.25
+    ctx.close()
+    del bd, out
+    gc.collect()
+    torch.cuda.empty_cache()

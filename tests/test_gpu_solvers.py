@@ -45,18 +45,22 @@ def test_cg_family(S, kind, op):
 
 
 @pytest.mark.parametrize("kind", [0, 1, 2])
-def test_multi_rhs_cg(S, kind):
-    """12 right-hand sides advanced together; every column to 1e-10."""
+@pytest.mark.parametrize("op", [1, 2])
+def test_multi_rhs_cg(S, kind, op):
+    """12 right-hand sides advanced together, in the degenerate and the
+    two-flavour sector (FP64 CG, FP32 and FP16 MP-CG); every column accepted by
+    the oracle's residual."""
     tmx, o, ctx, _ = S
     n = 12
-    bs = np.stack([synth.gaussian_cb_spinor(DIMS, 22, k, 1) for k in range(n)])
+    nf = 2 if op == 2 else 1
+    bs = np.stack([synth.gaussian_cb_spinor(DIMS, 22, k, nf) for k in range(n)])
     bs[3] *= 1e-20  # badly scaled column
     x = to_dev(np.zeros_like(bs))
-    rc, info = ctx.solve(x, to_dev(bs), n, kind=kind, op=1, tol=1e-10)
+    rc, info = ctx.solve(x, to_dev(bs), n, kind=kind, op=op, tol=1e-10)
     assert rc == tmx.TMX_OK
     xs = to_host(x, bs.shape)
     for k in range(n):
-        assert o.residual(bs[k], xs[k]) <= 1e-10
+        assert o.residual(bs[k], xs[k], nf=nf, sgn=1) <= 1e-10, (k, info[k])
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])

@@ -127,3 +127,51 @@ def test_residual_loss_gradient_matches_finite_differences(lat):
         wm[k] -= h
         fd = (nn.loss_and_grad(L, wp, bs, xs, mh, mhd)[0] - nn.loss_and_grad(L, wm, bs, xs, mh, mhd)[0]) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1e-3, abs(g[k])) + 1e-9, (k, fd, g[k])
+
+
+def _adam_run(w0, grads, **kw):
+    w, m, v = np.array(w0, dtype=np.float64), np.zeros(len(w0)), np.zeros(len(w0))
+    out = []
+    for t, g in enumerate(grads, start=1):
+        w, m, v = nn.adam_step(w, m, v, t, g, **kw)
+        out.append(w.copy())
+    return out
+
+
+def test_adam_hand_computed_two_steps():
+    """Worked by hand from the moment recurrences (beta1 = 0.9,
+    beta2 = 0.999, lr = 0.1, eps = 0, w0 = 0.5, g = 1 then -2):
+    m1 = 0.1, v1 = 0.001, bias-corrected 1 and 1, step 0.1;
+    m2 = -0.11, v2 = 0.004999, bias-corrected -0.11/0.19 and
+    0.004999/0.001999, step -0.0366103527035845565..."""
+    w1, w2 = _adam_run([0.5], [[1.0], [-2.0]], lr=0.1, beta1=0.9, beta2=0.999, eps=0.0)
+    assert abs(w1[0] - 0.4) < 1e-15
+    assert abs(w2[0] - 0.43661035270358455653) < 1e-15
+
+
+def test_adam_first_step_and_constant_gradient():
+    """Bias correction makes the estimates exact for a constant gradient:
+    every step (the first one included) moves w by lr g / (|g| + eps)."""
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal(50) * 10.0 ** rng.uniform(-6, 2, 50)
+    w0 = rng.standard_normal(50)
+    lr, eps = 3e-3, 1e-8
+    ws = _adam_run(w0, [g] * 6, lr=lr, eps=eps)
+    step = lr * g / (np.abs(g) + eps)
+    for t, w in enumerate(ws, start=1):
+        assert np.allclose(w, w0 - t * step, rtol=0, atol=1e-13)
+
+
+def test_adam_scale_invariance():
+    """With eps = 0 the update depends on the gradients only through their
+    ratio to their running scale: multiplying every gradient by c > 0 leaves
+    the trajectory unchanged, c < 0 mirrors it."""
+    rng = np.random.default_rng(6)
+    w0 = rng.standard_normal(20)
+    grads = [rng.standard_normal(20) for _ in range(5)]
+    ref = _adam_run(w0, grads, lr=1e-2, eps=0.0)
+    for c in (1e-4, 37.0):
+        got = _adam_run(w0, [c * g for g in grads], lr=1e-2, eps=0.0)
+        assert all(np.allclose(a, b, rtol=0, atol=1e-13) for a, b in zip(got, ref))
+    neg = _adam_run(w0, [-g for g in grads], lr=1e-2, eps=0.0)
+    assert all(np.allclose(a - w0, -(b - w0), rtol=0, atol=1e-13) for a, b in zip(neg, ref))
