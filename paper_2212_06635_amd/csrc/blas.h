@@ -96,7 +96,9 @@ template <int PR, int PQ> struct OpRupdNorm {
     }
 };
 
-// y = a x + b y (real a, b per rhs)
+// y = a x + b y (real a, b per rhs).  A zero coefficient means the operand
+// is not read (as in BLAS): y = a x overwrites y whatever it held, NaN
+// included, so a fresh workspace can be its target.
 template <int PY, int PX> struct OpAxpby {
     static constexpr int NRED = 0;
     SpinorPtr y, x;
@@ -106,8 +108,18 @@ template <int PY, int PX> struct OpAxpby {
     {
         for (int f = 0; f < nf; ++f) {
             cd vy[12], vx[12];
-            ld<PY>(y, f, t, vy);
-            ld<PX>(x, f, t, vx);
+            if (b[k] != 0.0) {
+                ld<PY>(y, f, t, vy);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) vy[c] = cd{0.0, 0.0};
+            }
+            if (a[k] != 0.0) {
+                ld<PX>(x, f, t, vx);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) vx[c] = cd{0.0, 0.0};
+            }
 #pragma unroll
             for (int c = 0; c < 12; ++c) vy[c] = a[k] * vx[c] + b[k] * vy[c];
             st<PY>(y, f, t, vy);
