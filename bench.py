@@ -25,9 +25,10 @@ epsbar = 0.1315; links U = proj_SU3(exp(i 0.25 H)), seed 4):
     inner iterations.
 After the timed steps, once: the rational approximation applied as a whole
 (R(N_h) b with the same poles), its accuracy N_h R(N_h)^2 b = b, and the
-exponent of its correction factor for one Gaussian eta; the hopping-term
-force kernel (link outer products of one shift) and the clover-term force
-(sigma-plane insertions, then the staple sums).
+exponent of its correction factor for one Gaussian eta; the force of that
+rational monomial (the 12 solutions' hopping and clover forces summed on the
+device); the hopping-term force kernel (link outer products of one shift)
+and the clover-term force (sigma-plane insertions, then the staple sums).
 
 The headline value is the FP64 Schur-operator bandwidth: model bytes of one
 Mhat application (links, spinors and clover blocks each read once per
@@ -52,6 +53,11 @@ KAPPA, CSW, MU, MUBAR, EPSBAR = 0.1394, 1.69, 0.00072, 0.1246, 0.1315
 # range of the light-sector determinant ratios the paper discusses (Section 4.1)
 RHO = 0.02
 NAPPLY = 20
+# the network's 8 -> 8 layer per site: factorised C_d (x) Gamma_d mixing
+# (9 paths x (8*8*12 + 4*4*24) complex multiply-adds x 8 flops) and its
+# algorithmic bytes (BF16 activations in and out, eight BF16 links)
+NN_LAYER_FLOPS_PER_SITE = 9 * (8 * 8 * 12 + 4 * 4 * 24) * 8
+NN_LAYER_BYTES_PER_SITE = 384 + 384 + 8 * 36
 
 # algorithmic bytes per output site of one stencil launch (links, blocks and
 # spinors each read once)
@@ -87,6 +93,43 @@ def cpu_baseline(dims, U, b, napply):
     return o, {"value": gbs, "unit": "GB/s", "cores": num_threads(), "kind": "oracle",
                "sample": f"{napply} FP64 Mhat applications at {'x'.join(map(str, dims))} "
                          f"({dt:.3f} s each, same model bytes as the GPU figure)"}
+
+
+def cpu_solves(o, b, b2, shifts, gpu_cg_iters, gpu_shift_iters):
+    """The oracle's plain FP64 CG to a 1e-10 true residual on the host cores:
+    run to the end at 8^4 and 16^3x32 (same generator and parameters), and
+    at the benchmark lattice `o` timed over a few iterations and extrapolated
+    to the iteration count of the same solve; the two-flavour 12-shift solve
+    as twelve sequential single-shift CG solves, extrapolated the same way."""
+    from oracle import Oracle
+    from oracle.oracle import num_threads
+    from paper_2212_06635_amd import synth
+
+    out = {"kind": "oracle", "cores": num_threads()}
+    for dims, seed in (((8, 8, 8, 8), 1), ((16, 16, 16, 32), 2)):
+        U = synth.gauge_links(dims, 0.25, seed)
+        od = Oracle(dims, U, KAPPA, CSW, mu=MU)
+        bs = synth.gaussian_cb_spinor(dims, seed, 0)
+        t = time.perf_counter()
+        _, it, rel = od.cg(bs, tol=1e-10)
+        out["cg_f64_" + "x".join(map(str, dims))] = {"seconds": round(time.perf_counter() - t, 3), "iters": it,
+                                                     "true_residual": rel, "measured": "whole solve"}
+    k = 3
+    t = time.perf_counter()
+    o.cg(b, tol=1e-10, maxiter=k)
+    per_it = (time.perf_counter() - t) / (k + 1)  # k iterations and the final residual check
+    out["cg_f64_" + "x".join(map(str, o.dims))] = {
+        "seconds": round(per_it * gpu_cg_iters, 2), "seconds_per_iteration": round(per_it, 4), "iters": gpu_cg_iters,
+        "measured": f"extrapolated: {k} iterations timed, times the {gpu_cg_iters} iterations of the same solve on the GPU"}
+    t = time.perf_counter()
+    o.cg(b2, nf=2, shift=float(shifts[0]), tol=1e-10, maxiter=2)
+    per_it = (time.perf_counter() - t) / 3
+    total = int(sum(gpu_shift_iters))
+    out["multishift_nd_12_sequential_cg"] = {
+        "seconds": round(per_it * total, 1), "seconds_per_iteration": round(per_it, 4), "iters_total": total,
+        "measured": "extrapolated: 2 two-flavour CG iterations timed, times the sum over the 12 shifts of the "
+                    "iterations each shift took on the GPU (multishift stage plus refinement)"}
+    return out
 
 
 def train_network(tmx, synth, npairs, epochs, inits=3):
@@ -415,14 +458,28 @@ def main():
                 "avg_launch_ms": round(avg_ms, 4), "launches": dcount,
                 "bytes_per_launch": per_launch_bytes}
 
-    # the learned preconditioner's 8->8 layer against the BF16 matrix-core peak
+    # the learned preconditioner's 8->8 layer.  The method's work per site is
+    # the factorised mixing (C_d (x) Gamma_d): per path 8x8 channel and 4x4 spin
+    # complex products on 12 and 24 vectors, 1152 complex multiply-adds = 9216
+    # flops, 82,944 over the nine paths; its algorithmic traffic is 1056 B
+    # (8 channels in and out at 384 B in BF16, eight 36-B links).  At 78
+    # flop/B, below the BF16 ridge of 312 flop/B, the layer is bound by HBM;
+    # the dense real 64x64 form it runs on the matrix cores (221 kflop/site)
+    # is reported beside it, labelled as such.
     nn_roof = None
     if "NN_8x8" in ks:
         n, ms_tot = ks["NN_8x8"]
-        flops = 2 * 64 * 64 * 27 * 2 * Vh  # (8 ch x 4 spin x re/im)^2 x 9 paths x 3 colours, all sites
-        tf = flops / (ms_tot / n * 1e-3) / 1e12
-        nn_roof = {"bound": "mfma", "achieved": round(tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
-                   "frac": round(tf / 2500.0, 5), "kernel": "NN_8x8", "avg_launch_ms": round(ms_tot / n, 4)}
+        sec = ms_tot / n * 1e-3
+        nbytes = NN_LAYER_BYTES_PER_SITE * 2 * Vh
+        gb = nbytes / sec / 1e9
+        tf = NN_LAYER_FLOPS_PER_SITE * 2 * Vh / sec / 1e12
+        tf_dense = 2 * 64 * 64 * 27 * 2 * Vh / sec / 1e12
+        nn_roof = {"bound": "hbm", "achieved": round(gb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": round(gb / HBM_PEAK_GBS, 4), "kernel": "NN_8x8", "avg_launch_ms": round(ms_tot / n, 4),
+                   "bytes_per_site": NN_LAYER_BYTES_PER_SITE, "flops_per_site": NN_LAYER_FLOPS_PER_SITE,
+                   "tflops_method": round(tf, 2), "frac_bf16_mfma_method": round(tf / 2500.0, 5),
+                   "tflops_dense_equivalent": round(tf_dense, 2),
+                   "frac_bf16_mfma_dense_equivalent": round(tf_dense / 2500.0, 5)}
 
     out = {
         "metric": METRIC,
@@ -477,6 +534,20 @@ def main():
     out["rational_correction_nd_12_f16"] = {"seconds": round(time.perf_counter() - t, 4), "rc": rc,
                                             "exponent": e_corr, "terms": nterms,
                                             "eta_norm2": float(eta.norm() ** 2)}
+    # the heavy sector's rational force: the 12 multishift solutions of R(N_h)
+    # phi, each shift's hopping and clover force -2 a_k F(x_k, Mhat_h x_k)
+    # added on the device (Sections 4.2, 4.3)
+    log("rational force of the two-flavour monomial (12 poles)")
+    fnd = torch.zeros(Vh * 2 * 36, dtype=torch.complex128, device="cuda")
+    ctx.rational_force(fnd, b2d, zolo.a, zolo.shifts, op=2, tol=1e-10, inner_prec=2)  # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rc, finfo = ctx.rational_force(fnd, b2d, zolo.a, zolo.shifts, op=2, tol=1e-10, inner_prec=2)
+    torch.cuda.synchronize()
+    out["rational_force_nd_12_f16"] = {"seconds": round(time.perf_counter() - t, 4), "rc": rc, "poles": 12,
+                                       "max_true_residual": max(i["true_residual"] for i in finfo),
+                                       "force_norm": float(fnd.norm())}
+    del fnd
     # hopping-term force: the link outer products of one shift (Section 4.3)
     log("hopping-term force")
     fbuf = torch.zeros(Vh * 2 * 36, dtype=torch.complex128, device="cuda")
@@ -518,6 +589,10 @@ def main():
         x.zero_()
         ctx.solve(x, bd, 1, kind=tmx.TMX_SOLVER_MPCG_F16, op=1, tol=1e-10)
         out["solves"]["mpcg_f16"]["oracle_true_residual"] = o.residual(b, x.cpu().numpy().reshape(b.shape))
+        log("timing the oracle's CG")
+        o.mubar, o.epsbar = MUBAR, EPSBAR
+        out["cpu_baseline_solves"] = cpu_solves(o, b, b2, shifts, out["solves"]["cg_f64"]["iters"],
+                                                out["solves"]["multishift_nd_12"]["iters"])
     else:
         out["cpu_baseline"] = None
     ctx.close()

@@ -222,7 +222,11 @@ int tmx_apply_mdagm(tmx_ctx *ctx, void *out, const void *in, int op, int prec, i
  * anti-Hermitian 3x3 matrix written to force[((lex * 4 + mu) * 3 + i) * 3 + j]
  * (complex128, the canonical link layout of tmx_load_gauge).  force =
  * coeff F, or force += coeff F with accumulate = 1 (summing over shifts).
- * op: TMX_OP_PLUS or TMX_OP_MINUS.  Enqueued on the context stream. */
+ * op: TMX_OP_PLUS, TMX_OP_MINUS, or TMX_OP_ND for the two-flavour operator
+ * of eq. Q-hat_h (x, y two-flavour odd fields; the hopping term is flavour
+ * diagonal, so the outer products are summed over the flavours, with the
+ * flavour-mixing site blocks inside the even-site fields).  Enqueued on the
+ * context stream. */
 int tmx_hop_force(tmx_ctx *ctx, double *force, const double *x, const double *y, int op, double coeff,
                   int accumulate);
 /* Clover-term force (Section 4.3, the clover term of Section 2): the same
@@ -279,6 +283,23 @@ int tmx_multishift_solve(tmx_ctx *ctx, double *x, const double *b, const double 
  * N^(-1/2) to the relative accuracy of the approximation. */
 int tmx_rational_apply(tmx_ctx *ctx, double *out, const double *b, double a0, const double *coeffs,
                        const double *shifts, int nshift, const tmx_solver_cfg *cfg, tmx_info *info);
+/* Fermion force of a rational monomial (Sections 4.2 and 4.3: the link
+ * derivative that the heavy-sector monomials sum over the shifts of the
+ * multishift solve): for S_R = <phi, R(N) phi> with R(N) = a0 + sum_k
+ * coeffs[k] (N + shifts[k])^{-1} and x_k = (N + shifts[k])^{-1} phi,
+ *     dS_R = -sum_k coeffs[k] <x_k, dN x_k> = Re Tr[i T F_R],
+ *     F_R = -2 sum_k coeffs[k] (hop + clover force)(x_k, Mhat x_k)
+ * for U_mu(x) -> exp(i eps T) U_mu(x), in the layout and convention of
+ * tmx_hop_force (a0 does not enter).  The x_k come from the solves of
+ * tmx_multishift_solve (same cfg fields; cfg->op TMX_OP_ND for the heavy
+ * sector, TMX_OP_PLUS / MINUS for the degenerate one) and each shift's force
+ * is added on the device as soon as its solution is refined.  phi: one odd
+ * field (device, canonical); force: V*36 complex128 (device), written
+ * (accumulate = 0) or added to.  info has nshift entries (may be NULL).
+ * TMX_EINVAL with a host-loaded clover term; TMX_ENOCONV if a shift missed
+ * cfg->tol (the force is still complete). */
+int tmx_rational_force(tmx_ctx *ctx, double *force, const double *phi, const double *coeffs, const double *shifts,
+                       int nshift, const tmx_solver_cfg *cfg, int accumulate, tmx_info *info);
 /* Correction term of a rational approximation R(N) ~ N^(-1/2) (Section 4.2;
  * the error of the approximation enters the acceptance step): with
  * Z = N R(N)^2 - 1, det(N)^(1/2) = det(R)^(-1) det(1 + Z)^(1/2), and for a

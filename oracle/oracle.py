@@ -212,16 +212,20 @@ class Oracle:
         return float(np.linalg.norm(b - self.w_normal(x, sgn, rho)) / np.linalg.norm(b))
 
     # -- hopping-term force ---------------------------------------------------
-    def hop_force(self, X, Y, sgn=1):
+    def hop_force(self, X, Y, sgn=1, nf=1):
         """Link derivative of S = Re<Y, Mhat(sgn) X> through the hopping terms
         (clover and twist blocks held fixed), for U_mu(x) -> exp(i eps T) U_mu(x):
         dS/d eps = Re Tr[i T F_mu(x)], F = TA(Q) the traceless anti-Hermitian
         part of Q_mu(x) = -kappa^2 bc U_mu(x) [sum_s ((1 - g_mu) b(x+mu))_s a(x)_s^dagger
         + sum_s ((1 + g_mu) a(x+mu))_s b(x)_s^dagger], with full-lattice fields
         b = X (odd) | u = B_ee(sgn)^-1 H_eo X (even) and
-        a = Y (odd) | w = B_ee(-sgn)^-1 g5 H_eo g5 Y (even).  Shape (V, 4, 3, 3)."""
+        a = Y (odd) | w = B_ee(-sgn)^-1 g5 H_eo g5 Y (even).  Shape (V, 4, 3, 3).
+        Two flavours (nf = 2, the operator of eq. Q-hat_h): the hopping term
+        is flavour diagonal and the site blocks B_ee(+-) mix the flavours, so
+        a and b are two-flavour fields and the outer products are summed over
+        the flavour index."""
         g, _ = self.gammas()
-        a, b, co, _ = self._force_fields(X, Y, sgn)
+        a, b, co, _ = self._force_fields(X, Y, sgn, nf)
         V = self.V
         lx, ly, lz, lt = self.dims
         F = np.zeros((V, 4, 3, 3), dtype=np.complex128)
@@ -232,17 +236,17 @@ class Oracle:
             c2[:, mu] = (c2[:, mu] + 1) % L[mu]
             y = c2[:, 0] + lx * (c2[:, 1] + ly * (c2[:, 2] + lz * c2[:, 3]))
             bc = np.where((mu == 3) & (co[:, 3] == lt - 1), float(self.t_bc), 1.0)
-            pb = np.einsum("st,xtc->xsc", eye4 - g[mu], b[y])
-            pa = np.einsum("st,xtc->xsc", eye4 + g[mu], a[y])
-            M = np.einsum("xsc,xsd->xcd", pb, a.conj()) + np.einsum("xsc,xsd->xcd", pa, b.conj())
+            pb = np.einsum("st,xftc->xfsc", eye4 - g[mu], b[y])
+            pa = np.einsum("st,xftc->xfsc", eye4 + g[mu], a[y])
+            M = np.einsum("xfsc,xfsd->xcd", pb, a.conj()) + np.einsum("xfsc,xfsd->xcd", pa, b.conj())
             Q = -(self.kappa ** 2) * bc[:, None, None] * np.einsum("xij,xjk->xik", self.U[:, mu], M)
             A = 0.5 * (Q - np.conj(np.swapaxes(Q, 1, 2)))
             F[:, mu] = A - (np.trace(A, axis1=1, axis2=2) / 3.0)[:, None, None] * np.eye(3)
         return F
 
-    def _force_fields(self, X, Y, sgn):
+    def _force_fields(self, X, Y, sgn, nf=1):
         """Full-lattice a (Y | B_ee(-sgn)^-1 g5 H_eo g5 Y) and b (X | B_ee(sgn)^-1 H_eo X),
-        shape (V, 4, 3), the lexicographic coordinates and the parity of every site."""
+        shape (V, nf, 4, 3), the lexicographic coordinates and the parity of every site."""
         g, _ = self.gammas()
         lx, ly, lz, lt = self.dims
         V = self.V
@@ -250,18 +254,18 @@ class Oracle:
         co = np.stack([lex % lx, (lex // lx) % ly, (lex // (lx * ly)) % lz, lex // (lx * ly * lz)], axis=1)
         par = co.sum(axis=1) % 2
         odd, even = np.nonzero(par == 1)[0], np.nonzero(par == 0)[0]
-        g5 = lambda f: np.einsum("st,xtc->xsc", g[4], f)
-        hop_even = lambda f: self.hop(f.reshape(V, 1, 4, 3), out_parity=0).reshape(V, 4, 3)
+        g5 = lambda f: np.einsum("st,xftc->xfsc", g[4], f)
+        hop_even = lambda f: self.hop(f, out_parity=0)
 
         def full(v_odd):
-            f = np.zeros((V, 4, 3), dtype=np.complex128)
-            f[odd] = _c(v_odd).reshape(-1, 4, 3)
+            f = np.zeros((V, nf, 4, 3), dtype=np.complex128)
+            f[odd] = _c(v_odd).reshape(-1, nf, 4, 3)
             return f
 
         def block_solve(f, s):
             out = np.zeros_like(f)
             for x in even:
-                out[x] = np.linalg.solve(self.site_block(int(x), 1, s), f[x].reshape(12)).reshape(4, 3)
+                out[x] = np.linalg.solve(self.site_block(int(x), nf, s), f[x].reshape(12 * nf)).reshape(nf, 4, 3)
             return out
 
         b, a = full(X), full(Y)
@@ -269,7 +273,7 @@ class Oracle:
         a[even] = block_solve(g5(hop_even(g5(a))), -sgn)[even]
         return a, b, co, par
 
-    def clover_force(self, X, Y, sgn=1):
+    def clover_force(self, X, Y, sgn=1, nf=1):
         """Link derivative of S = Re<Y, Mhat(sgn) X> through the clover term
         T = i kappa csw sum_{mu<nu} sigma_mu,nu F_mu,nu (F = (Q - Q^dagger)/8, Q the
         four leaves), hopping matrices held fixed, in the convention of hop_force:
@@ -278,9 +282,11 @@ class Oracle:
         G_rn(z) = c sum_s (sigma_rn b)_s a_s^dagger, H = G + G^dagger, and for
         every plane (rho, nu) the plaquettes through U_rho(y) oriented rho -> nu
         with H inserted at each corner:
-        F = TA[(i kappa csw / 8) sum_nu (U C_up - E_low U^dagger)].  Shape (V, 4, 3, 3)."""
+        F = TA[(i kappa csw / 8) sum_nu (U C_up - E_low U^dagger)].  Shape (V, 4, 3, 3).
+        Two flavours (nf = 2): the clover term enters both flavours alike, so G
+        sums over the flavour index."""
         _, sig = self.gammas()
-        a, b, co, par = self._force_fields(X, Y, sgn)
+        a, b, co, par = self._force_fields(X, Y, sgn, nf)
         V = self.V
         L = self.dims
         c = np.where(par == 1, 1.0, self.kappa ** 2)
@@ -297,8 +303,8 @@ class Oracle:
         for r in range(4):
             for n in range(4):
                 if r != n:
-                    sb = np.einsum("st,xtc->xsc", sig[r, n], b)
-                    G = c[:, None, None] * np.einsum("xsi,xsj->xij", sb, np.conj(a))
+                    sb = np.einsum("st,xftc->xfsc", sig[r, n], b)
+                    G = c[:, None, None] * np.einsum("xfsi,xfsj->xij", sb, np.conj(a))
                     H[r, n] = G + dag(G)
         F = np.zeros((V, 4, 3, 3), dtype=np.complex128)
         y = np.arange(V)
@@ -335,6 +341,19 @@ class Oracle:
             x, _, _ = self.cg(b, nf=nf, sgn=sgn, shift=float(s), tol=tol)
             out = out + a * x
         return out
+
+    def rational_force(self, phi, coeffs, shifts, nf=1, sgn=1, tol=1e-13):
+        """Link derivative of S_R = <phi, R(N) phi>, R(N) = a0 + sum_k coeffs[k]
+        (N + shifts[k])^{-1}, the action of a rational monomial (Sections 4.2,
+        4.3), in the convention of hop_force: with x_k = (N + shifts[k])^{-1} phi,
+        dS_R = -sum_k coeffs[k] <x_k, dN x_k> and <x, dN x> = 2 Re<Mhat x, dMhat x>,
+        so F_R = -2 sum_k coeffs[k] (hop_force + clover_force)(x_k, Mhat x_k)."""
+        F = 0.0
+        for a, s in zip(coeffs, shifts):
+            x, _, _ = self.cg(phi, nf=nf, sgn=sgn, shift=float(s), tol=tol)
+            y = self.mhat(x, nf=nf, sgn=sgn)
+            F = F - 2.0 * a * (self.hop_force(x, y, sgn, nf) + self.clover_force(x, y, sgn, nf))
+        return F
 
     def rational_correction(self, eta, a0, coeffs, shifts, nf=1, sgn=1, terms=6):
         """Partial sums of sum_k binom(-1/2, k) <eta, Z^k eta>, Z = N R(N)^2 - 1,

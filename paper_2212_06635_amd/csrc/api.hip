@@ -852,96 +852,98 @@ int tmx_apply_mdagm(tmx_ctx *c, void *out, const void *in, int op, int prec, int
                     prec, nrhs);
 }
 
-// Full-lattice fields of the force terms: X, Y odd (packed from x, y),
-// u = B_ee(s)^{-1} H_eo X and w' = B_ee(-s)^{-1} H_eo g5 Y even (the force
-// kernels apply the outer g5 of w).
+}  // extern "C"
+
+namespace tmx {
+
+// Full-lattice fields of the force terms: X, Y odd, u = B_ee(s)^{-1} H_eo X and
+// w' = B_ee(-s)^{-1} H_eo g5 Y even (the force kernels apply the outer g5 of
+// w); nf flavours each (two for the operator of eq. Q-hat_h, whose site
+// blocks B_ee(+-) mix the flavours).
 struct ForceFields {
     SpinorPtr X, Y, u, w;
+    int nf;
 };
 
-static int force_fields(tmx_ctx *c, const double *x, const double *y, int op, ForceFields &ff)
+// flavour f of an internal FP64 field of nf flavours, as a one-flavour field
+static SpinorPtr flavour_view(SpinorPtr a, long stride, int f)
 {
-    int r = ensure_ready(c, F64, false);
+    return make_spinor(static_cast<char *>(a.d) + (size_t)f * spinor_field_bytes(F64, 1, stride), F64, 1, stride);
+}
+
+// u and w from internal FP64 odd fields X, Y (op: TMX_OP_PLUS / MINUS / ND)
+static int force_fields_internal(tmx_ctx *c, SpinorPtr X, SpinorPtr Y, int op, ForceFields &ff)
+{
+    const bool nd = op == TMX_OP_ND;
+    int r = ensure_ready(c, F64, nd);
     if (r) return r;
-    const size_t fb = spinor_field_bytes(F64, 1, c->Vh);
-    void *px = ws_get(c, "hf_x", fb), *py = ws_get(c, "hf_y", fb), *pu = ws_get(c, "hf_u", fb),
-         *pw = ws_get(c, "hf_w", fb);
-    if (!px || !py || !pu || !pw) return set_err(c, TMX_ENOMEM, "force workspace: out of device memory");
-    ff.X = make_spinor(px, F64, 1, c->Vh);
-    ff.Y = make_spinor(py, F64, 1, c->Vh);
-    ff.u = make_spinor(pu, F64, 1, c->Vh);
-    ff.w = make_spinor(pw, F64, 1, c->Vh);
-    r = hip_err(c, launch_pack_spinor(x, ff.X, F64, TMX_FIELD_ODD, c->g, 1, c->stream), "pack x");
-    if (!r) r = hip_err(c, launch_pack_spinor(y, ff.Y, F64, TMX_FIELD_ODD, c->g, 1, c->stream), "pack y");
-    if (r) return r;
-    const LaunchCfg l1 = launch_cfg(c, kname("K1", F64, false, 1));
-    DslashArgs a = base_args(c, F64, false, 1);
+    const int nf = nd ? 2 : 1;
+    const size_t fb = spinor_field_bytes(F64, nf, c->Vh);
+    void *pu = ws_get(c, "hf_u", fb), *pw = ws_get(c, "hf_w", fb);
+    if (!pu || !pw) return set_err(c, TMX_ENOMEM, "force workspace: out of device memory");
+    ff.X = X;
+    ff.Y = Y;
+    ff.u = make_spinor(pu, F64, nf, c->Vh);
+    ff.w = make_spinor(pw, F64, nf, c->Vh);
+    ff.nf = nf;
+    const int sgn = op_sign(op);
+    const LaunchCfg l1 = launch_cfg(c, kname("K1", F64, nd, 1));
+    DslashArgs a = base_args(c, F64, nd, 1);
     a.parity = 0;
     a.clov = clov_parity(c, F64, 0);
-    a.inv = c->inv[F64];
+    a.inv = nd ? c->invnd[F64] : c->inv[F64];
     a.xcd = l1.xcd;
-    a.sgn = op;
+    a.sgn = sgn;
     a.in = ff.X;
     a.out = ff.u;
-    hipError_t e = launch_dslash(F64, 1, 0, a, c->stream, l1.block);
+    hipError_t e = launch_dslash(F64, nf, 0, a, c->stream, l1.block);
     if (e != hipSuccess) return hip_err(c, e, "K1 launch");
-    a.sgn = -op;
+    a.sgn = -sgn;
     a.g5in = 1;
     a.in = ff.Y;
     a.out = ff.w;
-    e = launch_dslash(F64, 1, 0, a, c->stream, l1.block);
+    e = launch_dslash(F64, nf, 0, a, c->stream, l1.block);
     return e != hipSuccess ? hip_err(c, e, "K1 launch") : TMX_OK;
 }
 
-int tmx_hop_force(tmx_ctx *c, double *force, const double *x, const double *y, int op, double coeff, int accumulate)
+// force (= or +=) coeff * hopping-term force of Re<Y, Mhat X>, per flavour
+static int hop_force_fields(tmx_ctx *c, double *force, const ForceFields &ff, double coeff, int accumulate)
 {
-    if (!c || !force || !x || !y || !std::isfinite(coeff))
-        return c ? set_err(c, TMX_EINVAL, "tmx_hop_force: bad argument") : TMX_EINVAL;
-    if (op != TMX_OP_PLUS && op != TMX_OP_MINUS)
-        return set_err(c, TMX_EINVAL, "the hopping force is built for the degenerate Schur operator");
-    ForceFields ff;
-    int r = force_fields(c, x, y, op, ff);
-    if (r) return r;
-    ForceArgs f{};
-    f.g = c->g;
-    f.U = LinkPtr{c->links[F64], c->Vh};
-    f.X = ff.X;
-    f.Y = ff.Y;
-    f.u = ff.u;
-    f.w = ff.w;
-    f.t_bc = c->par.t_bc;
-    f.kfac = c->par.kappa * c->par.kappa;
-    f.coeff = coeff;
-    f.accumulate = accumulate ? 1 : 0;
-    f.out = force;
-    f.xcd = c->xcd_remap;
-    kstat_begin(c, "HOP_FORCE");
-    hipError_t e = launch_hop_force(f, c->stream);
-    kstat_end(c);
-    return hip_err(c, e, "hop force");
+    for (int fl = 0; fl < ff.nf; ++fl) {
+        ForceArgs f{};
+        f.g = c->g;
+        f.U = LinkPtr{c->links[F64], c->Vh};
+        f.X = flavour_view(ff.X, c->Vh, fl);
+        f.Y = flavour_view(ff.Y, c->Vh, fl);
+        f.u = flavour_view(ff.u, c->Vh, fl);
+        f.w = flavour_view(ff.w, c->Vh, fl);
+        f.t_bc = c->par.t_bc;
+        f.kfac = c->par.kappa * c->par.kappa;
+        f.coeff = coeff;
+        // the force is linear in the flavour-summed outer products: the
+        // second flavour adds its part
+        f.accumulate = (accumulate || fl > 0) ? 1 : 0;
+        f.out = force;
+        f.xcd = c->xcd_remap;
+        kstat_begin(c, "HOP_FORCE");
+        hipError_t e = launch_hop_force(f, c->stream);
+        kstat_end(c);
+        if (e != hipSuccess) return hip_err(c, e, "hop force");
+    }
+    return TMX_OK;
 }
 
-int tmx_clover_force(tmx_ctx *c, double *force, const double *x, const double *y, int op, double coeff,
-                     int accumulate)
+// force (= or +=) coeff * clover-term force of Re<Y, Mhat X>: the insertions
+// summed over the flavours, then one pass of link sums
+static int clover_force_fields(tmx_ctx *c, double *force, const ForceFields &ff, double coeff, int accumulate)
 {
-    if (!c || !force || !x || !y || !std::isfinite(coeff))
-        return c ? set_err(c, TMX_EINVAL, "tmx_clover_force: bad argument") : TMX_EINVAL;
-    if (op != TMX_OP_PLUS && op != TMX_OP_MINUS)
-        return set_err(c, TMX_EINVAL, "the clover force is built for the degenerate Schur operator");
     if (c->clover_from_host)
         return set_err(c, TMX_EINVAL, "the clover force needs the clover term built from the links");
-    ForceFields ff;
-    int r = force_fields(c, x, y, op, ff);
-    if (r) return r;
     void *ph = ws_get(c, "cf_h", (size_t)6 * 9 * 2 * c->Vh * sizeof(double2));
     if (!ph) return set_err(c, TMX_ENOMEM, "clover force workspace: out of device memory");
     CloverForceArgs f{};
     f.g = c->g;
     f.U = LinkPtr{c->links[F64], c->Vh};
-    f.X = ff.X;
-    f.Y = ff.Y;
-    f.u = ff.u;
-    f.w = ff.w;
     f.kfac = c->par.kappa * c->par.kappa;
     f.kc8 = c->par.kappa * c->par.csw / 8.0;
     f.coeff = coeff;
@@ -950,9 +952,72 @@ int tmx_clover_force(tmx_ctx *c, double *force, const double *x, const double *y
     f.out = force;
     f.xcd = c->xcd_remap;
     kstat_begin(c, "CLOVER_FORCE");
-    hipError_t e = launch_clover_force(f, c->stream);
+    hipError_t e = hipSuccess;
+    for (int fl = 0; fl < ff.nf && e == hipSuccess; ++fl) {
+        f.X = flavour_view(ff.X, c->Vh, fl);
+        f.Y = flavour_view(ff.Y, c->Vh, fl);
+        f.u = flavour_view(ff.u, c->Vh, fl);
+        f.w = flavour_view(ff.w, c->Vh, fl);
+        f.h_acc = fl > 0 ? 1 : 0;
+        e = launch_clover_insertions(f, c->stream);
+    }
+    if (e == hipSuccess) e = launch_clover_link_sums(f, c->stream);
     kstat_end(c);
     return hip_err(c, e, "clover force");
+}
+
+int force_internal(tmx_ctx *c, double *force, SpinorPtr X, SpinorPtr Y, int op, double coeff, int accumulate,
+                   int terms)
+{
+    ForceFields ff;
+    int r = force_fields_internal(c, X, Y, op, ff);
+    if (r) return r;
+    if (terms & 1) {
+        r = hop_force_fields(c, force, ff, coeff, accumulate);
+        if (r) return r;
+        accumulate = 1;
+    }
+    if (terms & 2) r = clover_force_fields(c, force, ff, coeff, accumulate);
+    return r;
+}
+
+}  // namespace tmx
+
+extern "C" {
+
+// the entry points: canonical odd fields x, y (one or two flavours) packed first
+static int force_entry(tmx_ctx *c, double *force, const double *x, const double *y, int op, double coeff,
+                       int accumulate, int terms, const char *name)
+{
+    if (!c || !force || !x || !y || !std::isfinite(coeff))
+        return c ? set_err(c, TMX_EINVAL, std::string(name) + ": bad argument") : TMX_EINVAL;
+    if (op != TMX_OP_PLUS && op != TMX_OP_MINUS && op != TMX_OP_ND)
+        return set_err(c, TMX_EINVAL, std::string(name) + ": built for the degenerate and the two-flavour Schur operators");
+    if ((terms & 2) && c->clover_from_host)
+        return set_err(c, TMX_EINVAL, "the clover force needs the clover term built from the links");
+    const int nf = op == TMX_OP_ND ? 2 : 1;
+    int r = ensure_ready(c, F64, op == TMX_OP_ND);
+    if (r) return r;
+    const size_t fb = spinor_field_bytes(F64, nf, c->Vh);
+    void *px = ws_get(c, "hf_x", fb), *py = ws_get(c, "hf_y", fb);
+    if (!px || !py) return set_err(c, TMX_ENOMEM, "force workspace: out of device memory");
+    const SpinorPtr X = make_spinor(px, F64, nf, c->Vh), Y = make_spinor(py, F64, nf, c->Vh);
+    const int kind = nf == 2 ? TMX_FIELD_ODD_ND : TMX_FIELD_ODD;
+    r = hip_err(c, launch_pack_spinor(x, X, F64, kind, c->g, 1, c->stream), "pack x");
+    if (!r) r = hip_err(c, launch_pack_spinor(y, Y, F64, kind, c->g, 1, c->stream), "pack y");
+    if (r) return r;
+    return force_internal(c, force, X, Y, op, coeff, accumulate, terms);
+}
+
+int tmx_hop_force(tmx_ctx *c, double *force, const double *x, const double *y, int op, double coeff, int accumulate)
+{
+    return force_entry(c, force, x, y, op, coeff, accumulate, 1, "tmx_hop_force");
+}
+
+int tmx_clover_force(tmx_ctx *c, double *force, const double *x, const double *y, int op, double coeff,
+                     int accumulate)
+{
+    return force_entry(c, force, x, y, op, coeff, accumulate, 2, "tmx_clover_force");
 }
 
 // ---- autotuner -----------------------------------------------------------------

@@ -19,9 +19,13 @@ struct CloverForceArgs {
     double coeff;
     int accumulate;
     double2 *H;
+    int h_acc;  // insertions: add to H (the next flavour of a two-flavour field) instead of writing it
     double *out;
     int xcd;  // XCD-contiguous workgroup order of the link sums
 };
-hipError_t launch_clover_force(const CloverForceArgs &f, hipStream_t st);
+// the sigma-plane insertions H of one flavour (written, or added with h_acc)
+hipError_t launch_clover_insertions(const CloverForceArgs &f, hipStream_t st);
+// the link sums of the plaquettes with H inserted, into out
+hipError_t launch_clover_link_sums(const CloverForceArgs &f, hipStream_t st);
 
 }  // namespace tmx

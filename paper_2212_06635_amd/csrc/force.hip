@@ -327,9 +327,15 @@ __device__ __forceinline__ void store_insertion(const CloverForceArgs &f, int pl
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            // c (G + G^dagger)
+            // c (G + G^dagger), summed over the flavours of a two-flavour field
             const cd v = G.m[3 * i + j] + conj(G.m[3 * j + i]);
-            h[(3 * i + j) * V2] = make_double2(c * v.re, c * v.im);
+            double2 o = make_double2(c * v.re, c * v.im);
+            if (f.h_acc) {
+                const double2 old = h[(3 * i + j) * V2];
+                o.x += old.x;
+                o.y += old.y;
+            }
+            h[(3 * i + j) * V2] = o;
         }
 }
 
@@ -467,14 +473,18 @@ __global__ void __launch_bounds__(256) clover_force_kernel(CloverForceArgs f)
 
 }  // namespace
 
-hipError_t launch_clover_force(const CloverForceArgs &f, hipStream_t st)
+hipError_t launch_clover_insertions(const CloverForceArgs &f, hipStream_t st)
 {
     const long n = 2L * f.g.Vh;
     if (n == 0) return hipSuccess;
     const unsigned nb = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(clover_insertion_kernel, dim3(nb), dim3(256), 0, st, f);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_clover_link_sums(const CloverForceArgs &f, hipStream_t st)
+{
+    if (f.g.Vh == 0) return hipSuccess;
     const long nlink = 8 * ((f.g.Vh + 255) / 256);  // 4 directions x 2 parities per site block
     hipLaunchKernelGGL(clover_force_kernel, dim3((unsigned)nlink), dim3(256), 0, st, f);
     return hipGetLastError();

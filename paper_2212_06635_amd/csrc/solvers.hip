@@ -844,6 +844,38 @@ int tmx_rational_apply(tmx_ctx *c, double *out, const double *b, double a0, cons
     return rc;
 }
 
+int tmx_rational_force(tmx_ctx *c, double *force, const double *phi, const double *coeffs, const double *shifts,
+                       int nshift, const tmx_solver_cfg *cfg, int accumulate, tmx_info *info)
+{
+    if (!c || !force || !phi) return c ? set_err(c, TMX_EINVAL, "tmx_rational_force: bad argument") : TMX_EINVAL;
+    TRY(check_rational(c, 0.0, coeffs, shifts, nshift, cfg));
+    if (cfg->op != TMX_OP_PLUS && cfg->op != TMX_OP_MINUS && cfg->op != TMX_OP_ND)
+        return set_err(c, TMX_EINVAL, "the force is built for the degenerate and the two-flavour Schur operators");
+    if (c->clover_from_host)
+        return set_err(c, TMX_EINVAL, "the clover force needs the clover term built from the links");
+    const double t0 = now_seconds();
+    if (info) std::memset(info, 0, sizeof(tmx_info) * nshift);
+    const bool nd = cfg->op == TMX_OP_ND;
+    const int kind = nd ? TMX_FIELD_ODD_ND : TMX_FIELD_ODD;
+    TRY(ensure_ready(c, F64, nd));
+    Sys S(c, cfg->op, 1);
+    SpinorPtr B = S.field("msb", F64, 1), Y = S.field("rf_y", F64, 1);
+    TRY(S.need());
+    HTRY(launch_pack_spinor(phi, B, F64, kind, c->g, 1, c->stream), "pack phi");
+    // F = -2 sum_k a_k [hop + clover force](x_k, Mhat x_k), x_k = (N + s_k)^{-1} phi,
+    // added shift by shift as each solution is refined
+    const int rc = multishift_run(c, S, B, shifts, nshift, cfg, info, [&](int k, SpinorPtr X) {
+        int r = op_mhat(c, Y, X, cfg->op, F64, 0, 1);
+        if (r) return r;
+        return force_internal(c, force, X, Y, cfg->op, -2.0 * coeffs[k], (accumulate || k > 0) ? 1 : 0, 3);
+    });
+    if (rc < 0) return rc;
+    HTRY(hipStreamSynchronize(c->stream), "rational force sync");
+    if (info)
+        for (int k = 0; k < nshift; ++k) info[k].seconds = now_seconds() - t0;
+    return rc;
+}
+
 int tmx_rational_correction(tmx_ctx *c, const double *eta, double a0, const double *coeffs, const double *shifts,
                             int nshift, double tol, int maxterms, const tmx_solver_cfg *cfg, double *exponent,
                             int *terms)

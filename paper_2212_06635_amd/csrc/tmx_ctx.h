@@ -169,6 +169,12 @@ int pc_apply_internal(tmx_ctx *c, SpinorPtr z, int pz, SpinorPtr r, int pr, int 
 // plain / mixed CG on N used as the fallback of the flexible GCR solver
 int cg_fallback(tmx_ctx *c, int op, SpinorPtr x, SpinorPtr b, double tol, int maxiter, tmx_info *info);
 
+// link derivative of Re<Y, Mhat(op) X> (internal FP64 odd fields of one or
+// two flavours): force (= or +=) coeff F, F the hopping-term (terms & 1)
+// plus the clover-term (terms & 2) force, canonical link layout
+int force_internal(tmx_ctx *c, double *force, SpinorPtr X, SpinorPtr Y, int op, double coeff, int accumulate,
+                   int terms);
+
 // kernel-timing brackets around a launch (no-ops unless enabled)
 void kstat_begin(tmx_ctx *c, const std::string &name);
 void kstat_end(tmx_ctx *c);

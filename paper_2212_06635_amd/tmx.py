@@ -97,6 +97,7 @@ def _load():
         "tmx_solve_mhat": ([P, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
         "tmx_multishift_solve": ([P, P, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
         "tmx_rational_apply": ([P, P, P, D, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
+        "tmx_rational_force": ([P, P, P, P, P, I, ctypes.POINTER(tmx_solver_cfg), I, P], I),
         "tmx_hop_force": ([P, P, P, P, I, D, I], I),
         "tmx_clover_force": ([P, P, P, P, I, D, I], I),
         "tmx_rational_correction": ([P, P, D, P, P, I, D, I, ctypes.POINTER(tmx_solver_cfg), ctypes.POINTER(D),
@@ -326,23 +327,37 @@ class Context:
 
     def hop_force(self, force, x, y, op=TMX_OP_PLUS, coeff=1.0, accumulate=0):
         """force (= or +=) coeff * TA link derivative of Re<y, Mhat(op) x> (hopping terms)."""
-        self._check_force_sizes(force, x, y)
+        self._check_force_sizes(force, x, y, 2 if op == TMX_OP_ND else 1)
         return self.check(lib.tmx_hop_force(self.h, _ptr(force), _ptr(x), _ptr(y), int(op), float(coeff),
                                             int(accumulate)))
 
     def clover_force(self, force, x, y, op=TMX_OP_PLUS, coeff=1.0, accumulate=0):
         """force (= or +=) coeff * TA link derivative of Re<y, Mhat(op) x> (clover term)."""
-        self._check_force_sizes(force, x, y)
+        self._check_force_sizes(force, x, y, 2 if op == TMX_OP_ND else 1)
         return self.check(lib.tmx_clover_force(self.h, _ptr(force), _ptr(x), _ptr(y), int(op), float(coeff),
                                                int(accumulate)))
 
-    def _check_force_sizes(self, force, x, y):
+    def _check_force_sizes(self, force, x, y, nf=1):
         # the library takes plain device pointers and writes V * 36 complex128
         # values through `force`: only contiguous complex128 device tensors of
         # at least the needed size are passed on
         check_device_complex128(force, self.V * 36, "force")
-        check_device_complex128(x, self.Vh * 12, "x")
-        check_device_complex128(y, self.Vh * 12, "y")
+        check_device_complex128(x, self.Vh * 12 * nf, "x")
+        if y is not None:
+            check_device_complex128(y, self.Vh * 12 * nf, "y")
+
+    def rational_force(self, force, phi, coeffs, shifts, accumulate=0, **kw):
+        """force (= or +=) the link derivative of <phi, R(N) phi>, R = a0 + sum_k coeffs[k] (N + shifts[k])^{-1}."""
+        cfg = self.cfg(**kw)
+        self._check_force_sizes(force, phi, None, 2 if cfg.op == TMX_OP_ND else 1)
+        a = np.ascontiguousarray(coeffs, dtype=np.float64)
+        sh = np.ascontiguousarray(shifts, dtype=np.float64)
+        if a.shape != sh.shape:
+            raise ValueError("coeffs and shifts differ in length")
+        info = (tmx_info * len(sh))()
+        rc = self.check(lib.tmx_rational_force(self.h, _ptr(force), _ptr(phi), a.ctypes.data, sh.ctypes.data,
+                                               len(sh), ctypes.byref(cfg), int(accumulate), info), allow_noconv=True)
+        return rc, [i.as_dict() for i in info]
 
     def rational_apply(self, out, b, a0, coeffs, shifts, **kw):
         """out = a0 b + sum_k coeffs[k] (N + shifts[k])^{-1} b (device odd fields)."""

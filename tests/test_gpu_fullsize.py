@@ -86,7 +86,8 @@ def test_fullsize_multi_rhs_nd(F, kind):
         assert o.residual(bs[k], xs[k], nf=2) <= 1e-10, (k, info[k])
 
 
-def test_fullsize_force_directional_derivative(F):
+@pytest.mark.parametrize("nf", [1, 2])
+def test_fullsize_force_directional_derivative(F, nf):
     """Hopping plus clover force at full size, in the bench's launch shape,
     against central differences of the oracle's Re<Y, Mhat X> along a random
     su(3) direction on 2048 random links and on links that cross the time
@@ -109,11 +110,12 @@ def test_fullsize_force_directional_derivative(F):
     ids = np.array(sorted(ids))
     site, mu = ids // 4, ids % 4
     P = _random_su3_algebra(len(ids), rng)
-    X = synth.gaussian_cb_spinor(DIMS, 81, 0)
-    Y = synth.gaussian_cb_spinor(DIMS, 81, 1)
+    X = synth.gaussian_cb_spinor(DIMS, 81, 0, nf)
+    Y = synth.gaussian_cb_spinor(DIMS, 81, 1, nf)
+    op = 2 if nf == 2 else 1
     Fd = torch.zeros(V * 36, dtype=torch.complex128, device="cuda")
-    ctx.hop_force(Fd, to_dev(X), to_dev(Y), op=1)
-    ctx.clover_force(Fd, to_dev(X), to_dev(Y), op=1, accumulate=1)
+    ctx.hop_force(Fd, to_dev(X), to_dev(Y), op=op)
+    ctx.clover_force(Fd, to_dev(X), to_dev(Y), op=op, accumulate=1)
     idx = torch.from_numpy(ids).cuda()
     Fs = Fd.view(V * 4, 3, 3)[idx].cpu().numpy()
     del Fd
@@ -124,9 +126,9 @@ def test_fullsize_force_directional_derivative(F):
     for eps in (h, -h):
         Ue = o.U.copy()
         Ue[site, mu] = np.einsum("kij,kjl->kil", _expi(eps * P), o.U[site, mu])
-        out.append(Oracle(DIMS, Ue, KAPPA, CSW, mu=MU, mubar=MUBAR, epsbar=EPSBAR).mhat(X))
+        out.append(Oracle(DIMS, Ue, KAPPA, CSW, mu=MU, mubar=MUBAR, epsbar=EPSBAR).mhat(X, nf=nf))
         del Ue
     numeric = float(np.vdot(Y.reshape(-1), (out[0] - out[1]).reshape(-1)).real) / (2 * h)
-    print(f"[gpu full size] force along {len(ids)} links: predicted {predicted:.10e}, "
+    print(f"[gpu full size] force (nf={nf}) along {len(ids)} links: predicted {predicted:.10e}, "
           f"central differences {numeric:.10e}", flush=True)
     assert abs(predicted - numeric) <= 1e-6 * abs(numeric)

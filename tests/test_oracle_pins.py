@@ -484,6 +484,66 @@ def test_full_force_against_finite_differences(rough, sgn):
     assert abs(numeric - total) < 1e-7 * abs(total)
 
 
+def test_two_flavour_force_against_finite_differences(rough):
+    """The two-flavour operator (eq. Q-hat_h: flavour-mixing site blocks,
+    flavour-diagonal hopping): hop_force + clover_force with nf = 2 against
+    central differences of Re<Y, Mhat_h X> with the clover term rebuilt from
+    the perturbed links, along random su(3) directions on every link.  A
+    dropped flavour, a flavour-diagonal inverse or a wrong twist sign in
+    B_ee(-) each fail it."""
+    U, o = rough
+    rng = np.random.default_rng(29)
+    X = synth.gaussian_cb_spinor(SYM_DIMS, 10, 0, 2)
+    Y = synth.gaussian_cb_spinor(SYM_DIMS, 10, 1, 2)
+    Fh, Fc = o.hop_force(X, Y, 1, nf=2), o.clover_force(X, Y, 1, nf=2)
+    for F in (Fh, Fc):
+        assert np.abs(F + np.conj(np.swapaxes(F, 2, 3))).max() < 1e-13
+        assert np.abs(np.trace(F, axis1=2, axis2=3)).max() < 1e-13
+    U4 = U.reshape(o.V, 4, 3, 3)
+    P = _random_su3_algebra(o.V * 4, rng).reshape(o.V, 4, 3, 3)
+    lin = lambda F: float(np.sum(np.einsum("xmij,xmji->xm", 1j * P, F).real))
+
+    def S(eps):
+        Ue = np.einsum("xmij,xmjk->xmik", _expi(eps * P.reshape(-1, 3, 3)).reshape(o.V, 4, 3, 3), U4)
+        oe = Oracle(SYM_DIMS, Ue, KAPPA, CSW, mu=o.mu, mubar=o.mubar, epsbar=o.epsbar)
+        return float(np.vdot(Y.reshape(-1), oe.mhat(X, nf=2).reshape(-1)).real)
+
+    h = 1e-5
+    numeric = (S(h) - S(-h)) / (2 * h)
+    total = lin(Fh) + lin(Fc)
+    assert abs(lin(Fc)) > 1e-3 * abs(total)
+    assert abs(numeric - total) < 1e-7 * abs(total)
+    # each flavour alone is not the answer: the flavour mixing matters
+    one = o.hop_force(X[:, 0], Y[:, 0], 1) + o.clover_force(X[:, 0], Y[:, 0], 1)
+    assert abs(lin(one) - total) > 1e-3 * abs(total)
+
+
+@pytest.mark.parametrize("nf", [1, 2])
+def test_rational_force_against_finite_differences(rough, nf):
+    """The rational monomial's force (Sections 4.2, 4.3): the link derivative
+    of <phi, R(N) phi> with three poles, by central differences of the
+    oracle's own rational function (each shift solved to 1e-13, clover term
+    rebuilt from the perturbed links) against rational_force."""
+    U, o = rough
+    rng = np.random.default_rng(31)
+    phi = synth.gaussian_cb_spinor(SYM_DIMS, 12, 0, nf)
+    coeffs, shifts = [0.3, 0.2, 0.1], [0.05, 0.2, 1.0]
+    F = o.rational_force(phi, coeffs, shifts, nf=nf)
+    U4 = U.reshape(o.V, 4, 3, 3)
+    P = _random_su3_algebra(o.V * 4, rng).reshape(o.V, 4, 3, 3)
+    analytic = float(np.sum(np.einsum("xmij,xmji->xm", 1j * P, F).real))
+
+    def S(eps):
+        Ue = np.einsum("xmij,xmjk->xmik", _expi(eps * P.reshape(-1, 3, 3)).reshape(o.V, 4, 3, 3), U4)
+        oe = Oracle(SYM_DIMS, Ue, KAPPA, CSW, mu=o.mu, mubar=o.mubar, epsbar=o.epsbar)
+        r = oe.rational(phi, 0.7, coeffs, shifts, nf=nf, tol=1e-14)
+        return float(np.vdot(phi.reshape(-1), r.reshape(-1)).real)
+
+    h = 1e-4
+    numeric = (S(h) - S(-h)) / (2 * h)
+    assert abs(numeric - analytic) < 1e-6 * abs(analytic), (numeric, analytic)
+
+
 @pytest.mark.parametrize("nf", [1, 2])
 @pytest.mark.parametrize("dagger", [False, True])
 def test_residual_mhat_against_dense_solve(nf, dagger):
