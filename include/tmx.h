@@ -209,6 +209,23 @@ int tmx_apply_D(tmx_ctx *ctx, void *out, const void *in, int op, int prec);
  * out != in (TMX_EINVAL); TMX_ENOTLOADED without a gauge field or
  * parameters. */
 int tmx_apply_mhat(tmx_ctx *ctx, void *out, const void *in, int op, int prec, int dagger, int nrhs);
+/* tmx_apply_mhat without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, result (bit for bit) and errors as
+ * tmx_apply_mhat; the even-site intermediate field lives in a static device
+ * scratch of 256 MiB that the library holds on every GPU it runs on until
+ * the process ends (its address is resolved by tmx_create, once per device).
+ * Limits: the intermediate, tmx_field_bytes(TMX_FIELD_ODD or _ODD_ND, prec)
+ * times nrhs, must fit the 256 MiB (one right-hand side at 32^3x64 in every
+ * precision of the one-flavour operator, and in FP32 / FP16 of the
+ * two-flavour one), else TMX_EINVAL; the links, clover and site-block
+ * inverses of this precision and sector must already be resident (any
+ * tmx_apply_mhat in them builds them), else TMX_ENOTLOADED.  Every call on
+ * one GPU shares that scratch, which keeps the last call's contents
+ * (nothing in it needs clearing: each call overwrites what it reads): calls
+ * that overlap on one GPU -- other streams, other contexts, other threads --
+ * race and must be serialised by the caller. */
+int tmx_apply_mhat_noalloc(tmx_ctx *ctx, void *out, const void *in, int op, int prec, int dagger, int nrhs);
 /* out = N in = Mhat^dagger Mhat in, the Hermitian positive operator whose
  * solves the monomials need (Section 2: Q-hat^+ Q-hat^- = Mhat(-)^dagger
  * Mhat(-)); same arguments and errors as tmx_apply_mhat. */

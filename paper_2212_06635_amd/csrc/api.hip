@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "tmx_ctx.h"
@@ -101,6 +102,42 @@ void *ws_get(tmx_ctx *c, const std::string &name, size_t bytes)
         c->ws_bytes += bytes;
     }
     return w.p;
+}
+
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free Schur operator (tmx_apply_mhat_noalloc): the
+// even-site intermediate u = B_ee^{-1} H_eo in.  One copy per GPU, held until
+// the process ends; in host code `scratch` names a host-side stand-in, so
+// every use goes through the device address resolved per device below.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+static std::mutex scratch_mu;
+static std::map<int, void *> scratch_dev;  // device ordinal -> device address of scratch
+
+// device address of `scratch` on the current device (resolved once per
+// device); nullptr with the context's error set if it cannot be resolved
+static void *scratch_address(tmx_ctx *c)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(c, TMX_EHIP, "hipGetDevice failed");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    auto it = scratch_dev.find(dev);
+    if (it != scratch_dev.end()) return it->second;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        set_err(c, TMX_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        return nullptr;
+    }
+    scratch_dev[dev] = p;
+    return p;
 }
 
 static size_t red_partials_bytes(const tmx_ctx *c) { return sizeof(double) * c->red.max_blocks * MAXR * 4; }
@@ -610,6 +647,10 @@ int tmx_create(const int dims[4], void *hip_stream, tmx_ctx **out)
         (void)hipGetLastError();
         c->red.host = nullptr;
     }
+    // device address of the allocation-free operator's scratch on this
+    // device (resolved here, at set-up; a failure only disables that entry point)
+    (void)scratch_address(c);
+    c->err.clear();
     // cap on the named scratch buffers (bytes), for callers that budget HBM
     if (const char *e = std::getenv("TMX_WS_LIMIT")) c->ws_limit = std::strtoull(e, nullptr, 10);
     const char *tr = std::getenv("TMX_TRACE");
@@ -840,6 +881,35 @@ int tmx_apply_mhat(tmx_ctx *c, void *out, const void *in, int op, int prec, int 
     const long stride = c->Vh * nrhs;
     return op_mhat(c, make_spinor(out, prec, nf, stride), make_spinor(const_cast<void *>(in), prec, nf, stride), op,
                    prec, dagger ? 1 : 0, nrhs);
+}
+
+int tmx_apply_mhat_noalloc(tmx_ctx *c, void *out, const void *in, int op, int prec, int dagger, int nrhs)
+{
+    if (!c || !out || !in || out == in || nrhs < 1 || nrhs > MAXR || prec < F64 || prec > F16)
+        return c ? set_err(c, TMX_EINVAL, "tmx_apply_mhat_noalloc: bad argument") : TMX_EINVAL;
+    int r = check_op(c, op);
+    if (r) return r;
+    const bool nd = op == TMX_OP_ND;
+    const int nf = nd ? 2 : 1;
+    const long stride = c->Vh * nrhs;
+    const size_t need = (size_t)spinor_field_bytes(prec, nf, stride);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return set_err(c, TMX_EINVAL, "tmx_apply_mhat_noalloc: the intermediate field needs " + std::to_string(need) +
+                                          " bytes, more than the " + std::to_string(NOALLOC_SCRATCH_BYTES) +
+                                          "-byte scratch (use tmx_apply_mhat)");
+    // every derived field of this precision must exist already (building one
+    // would allocate); rebuilding an existing one after new parameters does not
+    const bool have = c->gauge_loaded && c->have_params && c->links[prec] && c->clov[F64] && c->clov[prec] &&
+                      (nd ? (c->invnd[F64] && c->invnd[prec]) : (c->inv[F64] && c->inv[prec]));
+    if (!have)
+        return set_err(c, TMX_ENOTLOADED, "tmx_apply_mhat_noalloc: the fields of this precision are not resident "
+                                          "(one tmx_apply_mhat in this precision and sector builds them)");
+    r = ensure_ready(c, prec, nd);
+    if (r) return r;
+    void *u = scratch_address(c);
+    if (!u) return TMX_EHIP;
+    const SpinorPtr O = make_spinor(out, prec, nf, stride), I = make_spinor(const_cast<void *>(in), prec, nf, stride);
+    return mhat_with(c, O, I, make_spinor(u, prec, nf, stride), op, prec, dagger ? 1 : 0, nrhs);
 }
 
 int tmx_apply_mdagm(tmx_ctx *c, void *out, const void *in, int op, int prec, int nrhs)

@@ -93,6 +93,7 @@ def _load():
         "tmx_apply_D": ([P, P, P, I, I], I),
         "tmx_apply_mhat": ([P, P, P, I, I, I, I], I),
         "tmx_apply_mdagm": ([P, P, P, I, I, I], I),
+        "tmx_apply_mhat_noalloc": ([P, P, P, I, I, I, I], I),
         "tmx_solve": ([P, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
         "tmx_solve_mhat": ([P, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
         "tmx_multishift_solve": ([P, P, P, P, I, ctypes.POINTER(tmx_solver_cfg), P], I),
@@ -294,6 +295,9 @@ class Context:
 
     def apply_mhat(self, out, inp, op, prec, dagger=0, nrhs=1):
         return self.check(lib.tmx_apply_mhat(self.h, _ptr(out), _ptr(inp), op, prec, int(dagger), nrhs))
+
+    def apply_mhat_noalloc(self, out, inp, op, prec, dagger=0, nrhs=1):
+        return self.check(lib.tmx_apply_mhat_noalloc(self.h, _ptr(out), _ptr(inp), op, prec, int(dagger), nrhs))
 
     def apply_mdagm(self, out, inp, op, prec, nrhs=1):
         return self.check(lib.tmx_apply_mdagm(self.h, _ptr(out), _ptr(inp), op, prec, nrhs))
