@@ -15,7 +15,9 @@ epsbar = 0.1315; links U = proj_SU3(exp(i 0.25 H)), seed 4):
     reliable updates; the network is trained before the timed region on 256
     (source, solution) pairs from the plain solver on a 16^3x32 field, the
     best of three initialisations by preconditioned-CG iterations on a
-    held-out source of that field);
+    held-out source of that field), and by its Hermitian form P = A^dagger A
+    (one network application per iteration; trained the same way on pairs
+    (b, N^{-1} b) with the energy-norm loss);
   * CG and FP16 MP-CG on the mass-preconditioned What^dagger What (rho = 0.02);
   * a 12-shift multishift solve of the two-flavour normal operator (FP32
     multishift CG, then FP64-reliable refinement per shift) at the poles of
@@ -132,7 +134,7 @@ def cpu_solves(o, b, b2, shifts, gpu_cg_iters, gpu_shift_iters):
     return out
 
 
-def train_network(tmx, synth, npairs, epochs, inits=3):
+def train_network(tmx, synth, npairs, epochs, inits=3, sym=False):
     """Train the preconditioner on a 16^3x32 field (seed 2) from (b, Mhat^{-1} b) pairs.
 
     The residual loss is an average over Gaussian sources and does not see
@@ -156,8 +158,13 @@ def train_network(tmx, synth, npairs, epochs, inits=3):
     xs = torch.zeros_like(bs)
     for k in range(npairs):
         xk = torch.zeros(n1, dtype=torch.complex128, device="cuda")
-        tc.solve_mhat(xk, bs[k * n1:(k + 1) * n1], dagger=0, op=1, tol=1e-10)
+        if sym:  # the Hermitian form approximates N^{-1}: pairs (b, N^{-1} b)
+            tc.solve(xk, bs[k * n1:(k + 1) * n1], 1, kind=tmx.TMX_SOLVER_MPCG_F32, op=1, tol=1e-10)
+        else:  # K approximates Mhat^{-1}: pairs (b, Mhat^{-1} b)
+            tc.solve_mhat(xk, bs[k * n1:(k + 1) * n1], dagger=0, op=1, tol=1e-10)
         xs[k * n1:(k + 1) * n1] = xk
+    kind = tmx.TMX_SOLVER_PCG_NN_SYM if sym else tmx.TMX_SOLVER_PCG_NN
+    loss_kind = tmx.TMX_LOSS_SYM if sym else tmx.TMX_LOSS_RESIDUAL
     bval = torch.from_numpy(synth.gaussian_cb_spinor(dims, 2, 10 ** 6).reshape(-1)).cuda()
     t1 = time.perf_counter()
     runs, best = [], None
@@ -166,9 +173,9 @@ def train_network(tmx, synth, npairs, epochs, inits=3):
         # identity on the d = 0 path of every layer, N(0, 1e-2) elsewhere
         from_oracle_free_init(w0, np.random.default_rng(3 + init))
         tc.pc_set_weights(w0)
-        losses = tc.pc_train(bs, xs, npairs, epochs=epochs, batch=8, lr=3e-3, seed=1, loss_kind=0)
+        losses = tc.pc_train(bs, xs, npairs, epochs=epochs, batch=8, lr=3e-3, seed=1, loss_kind=loss_kind)
         x = torch.zeros_like(bval)
-        rc, info = tc.solve(x, bval, 1, kind=tmx.TMX_SOLVER_PCG_NN, op=1, tol=1e-10, inner_prec=2)
+        rc, info = tc.solve(x, bval, 1, kind=kind, op=1, tol=1e-10, inner_prec=2)
         it = info[0]["iters"] if rc == tmx.TMX_OK else 10 ** 9
         runs.append({"init": init, "loss_first": float(losses[0]), "loss_last": float(losses[-1]), "val_pcg_iters": it})
         if best is None or it < best[0]:
@@ -177,12 +184,13 @@ def train_network(tmx, synth, npairs, epochs, inits=3):
     rc, info = tc.solve(x, bval, 1, kind=tmx.TMX_SOLVER_MPCG_F16, op=1, tol=1e-10)
     tc.close()
     t2 = time.perf_counter()
-    return best[1], {"pairs": npairs, "lattice": list(dims), "pair_seconds": round(t1 - t0, 1),
+    return best[1], {"form": "P = A^dagger A" if sym else "K K^dagger", "pairs": npairs, "lattice": list(dims),
+                     "pair_seconds": round(t1 - t0, 1),
                      "train_seconds": round(t2 - t1, 1), "epochs": epochs, "runs": runs,
                      "val_cg_iters": info[0]["iters"]}
 
 
-def learned_pc_other_volume(tmx, synth, weights, dims=(24, 24, 24, 48), seed=3):
+def learned_pc_other_volume(tmx, synth, weights, weights_sym, dims=(24, 24, 24, 48), seed=3):
     """The trained weights (translation invariant) used unchanged on a second
     volume: plain CG, MP-CG, CG preconditioned by K K^dagger and flexible GCR
     with K, each to a 1e-10 FP64 true residual (one warm-up solve each, then
@@ -199,7 +207,9 @@ def learned_pc_other_volume(tmx, synth, weights, dims=(24, 24, 24, 48), seed=3):
     x = torch.zeros_like(b)
     out = {"lattice": list(dims), "seed": seed}
     for kind, name, ip in ((tmx.TMX_SOLVER_CG, "cg_f64", 1), (tmx.TMX_SOLVER_MPCG_F16, "mpcg_f16", 1),
-                           (tmx.TMX_SOLVER_PCG_NN, "pcg_nn_f16", 2), (tmx.TMX_SOLVER_FGCR_NN, "fgcr_nn_f32", 1)):
+                           (tmx.TMX_SOLVER_PCG_NN, "pcg_nn_f16", 2), (tmx.TMX_SOLVER_FGCR_NN, "fgcr_nn_f32", 1),
+                           (tmx.TMX_SOLVER_PCG_NN_SYM, "pcg_nn_sym_f16", 2)):
+        ctx.pc_set_weights(weights_sym if kind == tmx.TMX_SOLVER_PCG_NN_SYM else weights)
         times = []
         for rep in range(4):
             x.zero_()
@@ -247,7 +257,8 @@ def main():
     ap.add_argument("--mode", default="full", choices=["full", "kernels", "nn", "force"],
                     help="kernels: only Mhat applies per precision and a copy of known size (for counters); "
                          "nn: only applications of the learned preconditioner (for counters)")
-    ap.add_argument("--tune", action="store_true", help="autotune the stencil launch shapes first")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuning of the stencil launch shapes (done before the timed region by default)")
     ap.add_argument("--train-pairs", type=int, default=256)
     ap.add_argument("--train-epochs", type=int, default=20)
     args = ap.parse_args()
@@ -281,11 +292,22 @@ def main():
     dst_nd = ctx.empty(tmx.TMX_FIELD_ODD_ND, 1)
     x = torch.zeros_like(bd)
     names = {0: "f64", 1: "f32", 2: "f16"}
-    if args.tune:
+    tuned = {}
+    if not args.no_tune and args.mode == "full":
+        # every stencil the timed steps use: one right-hand side in three
+        # precisions, the two-flavour operator in FP32 / FP16 / FP64 (FP64 for
+        # the reliable updates), and the 12 two-flavour right-hand sides
+        t = time.perf_counter()
         for p in (0, 1, 2):
             ctx.tune(p, 1, 1)
-        ctx.tune(1, 2, 1)
-        log("tuned: " + str({k: ctx.tuned_config(k) for k in ("K1_f64", "K2_f64", "K1_f32", "K2_f32", "K1_f16", "K2_f16")}))
+            ctx.tune(p, 2, 1)
+        ctx.tune(1, 2, 12)
+        ctx.tune(2, 2, 12)
+        ctx.tune(0, 2, 12)
+        tuned = {k: ctx.tuned_config(k) for k in ("K1_f64", "K2_f64", "K1_f32", "K2_f32", "K1_f16", "K2_f16",
+                                                   "K1_f32_nd", "K2_f32_nd", "K1_f32_nd_r12", "K2_f32_nd_r12",
+                                                   "K1_f16_nd_r12", "K2_f16_nd_r12")}
+        log(f"tuned in {time.perf_counter() - t:.1f}s: {tuned}")
     log("setup done")
     if args.mode == "nn":
         w0 = np.zeros(ctx.pc_num_params(), dtype=np.float32)
@@ -343,6 +365,7 @@ def main():
         return
 
     weights, train_info = train_network(tmx, synth, args.train_pairs, args.train_epochs)
+    weights_sym, train_info_sym = train_network(tmx, synth, args.train_pairs, args.train_epochs, sym=True)
     ctx.pc_set_weights(weights)
     # largest eigenvalue of N_h by power iteration (FP32), for the shifts
     v = ctx.pack(b2d, tmx.TMX_FIELD_ODD_ND, 1)
@@ -379,9 +402,12 @@ def main():
         solves = {}
         for kind, nm, ip, op in ((tmx.TMX_SOLVER_CG, "cg_f64", 1, 1), (tmx.TMX_SOLVER_MPCG_F32, "mpcg_f32", 1, 1),
                                  (tmx.TMX_SOLVER_MPCG_F16, "mpcg_f16", 1, 1), (tmx.TMX_SOLVER_PCG_NN, "pcg_nn_f16", 2, 1),
+                                 (tmx.TMX_SOLVER_PCG_NN_SYM, "pcg_nn_sym_f16", 2, 1),
                                  # the mass-preconditioned normal operator What^dagger What
                                  (tmx.TMX_SOLVER_CG, "cg_w_f64", 1, tmx.TMX_OP_WPLUS),
                                  (tmx.TMX_SOLVER_MPCG_F16, "mpcg_w_f16", 1, tmx.TMX_OP_WPLUS)):
+            if kind in (tmx.TMX_SOLVER_PCG_NN, tmx.TMX_SOLVER_PCG_NN_SYM):
+                ctx.pc_set_weights(weights_sym if kind == tmx.TMX_SOLVER_PCG_NN_SYM else weights)
             x.zero_()
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -505,6 +531,8 @@ def main():
         "roofline": roofline,
         "roofline_nn_layer": nn_roof,
         "learned_pc_training": train_info,
+        "learned_pc_training_sym": train_info_sym,
+        "tuned_launch": tuned,
     }
     # the rational approximation as a whole: R(N_h) b, then N_h R(N_h)^2 b = b
     log("rational approximation R(N_h) b (FP16 inner) and its accuracy")
@@ -580,7 +608,7 @@ def main():
     del fbuf
     if dims == (32, 32, 32, 64):
         log("learned preconditioner on a 24^3x48 field")
-        out["learned_pc_24x24x24x48"] = learned_pc_other_volume(tmx, synth, weights)
+        out["learned_pc_24x24x24x48"] = learned_pc_other_volume(tmx, synth, weights, weights_sym)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         o, cb = cpu_baseline(dims, U, b, args.cpu_applies)

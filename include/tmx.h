@@ -101,8 +101,10 @@ enum {
     TMX_SOLVER_MPCG_F16 = 2,/* CG with FP16-storage inner iterations, FP64 reliable updates */
     TMX_SOLVER_FGCR_NN = 3, /* two flexible-GCR solves (Mhat^dagger with K^dagger, Mhat with K), restarted;
                                CG acceptance and fallback */
-    TMX_SOLVER_PCG_NN = 4   /* flexible CG on N preconditioned by K K^dagger (learned network), inner
+    TMX_SOLVER_PCG_NN = 4,  /* flexible CG on N preconditioned by K K^dagger (learned network), inner
                                precision cfg->inner_prec (F32 / F16) with FP64 reliable updates */
+    TMX_SOLVER_PCG_NN_SYM = 5 /* the same with the Hermitian form P = A^dagger A of the network (one
+                                 application per iteration; see tmx_pc_apply) */
 };
 
 typedef struct {
@@ -340,8 +342,12 @@ int tmx_rational_correction(tmx_ctx *ctx, const double *eta, double a0, const do
 int tmx_pc_num_params(const tmx_ctx *ctx, size_t *n);
 int tmx_pc_set_weights(tmx_ctx *ctx, const float *host_w, size_t n);
 int tmx_pc_get_weights(tmx_ctx *ctx, float *host_w, size_t n);
-/* out = K in (dagger = 0) or K^dagger in (dagger = 1) on canonical odd
- * complex128 device fields. */
+/* out = K in (dagger = 0), K^dagger in (dagger = 1), or the Hermitian form
+ * P in (dagger = 2) on canonical odd complex128 device fields.  P = A^dagger A
+ * with A = L_2 L_1 the network's first two layers (the last two are not
+ * used): four stencil layers applied, Hermitian and positive semi-definite
+ * by construction, so that one application preconditions CG on N (where
+ * K K^dagger takes two); trained with TMX_LOSS_SYM on pairs (b, N^{-1} b). */
 int tmx_pc_apply(tmx_ctx *ctx, double *out, const double *in, int dagger);
 
 /* Training loss (loss_kind as in tmx_train_cfg, Mhat of op: TMX_OP_PLUS or
@@ -368,7 +374,11 @@ typedef struct {
  * The residual loss controls E = Mhat K - 1 on all modes, which is what a
  * preconditioner needs; the solution loss weights the high modes of Mhat
  * down by Mhat^{-1}. */
-enum { TMX_LOSS_RESIDUAL = 0, TMX_LOSS_SOLUTION = 1 };
+enum { TMX_LOSS_RESIDUAL = 0, TMX_LOSS_SOLUTION = 1, TMX_LOSS_SYM = 2 };
+/* TMX_LOSS_SYM trains the Hermitian form P (layers 1 and 2) on pairs
+ * (b_i, x_i = N^{-1} b_i) with the energy norm of its error,
+ *   mean_i <P b_i - x_i, N (P b_i - x_i)> / |b_i|^2 = mean_i |Mhat (P b_i - x_i)|^2 / |b_i|^2,
+ * the quantity CG on N minimises; the gradients of layers 3 and 4 are zero. */
 
 /* One Adam step (Kingma and Ba, with bias correction) on the network weights
  * from a gradient the caller supplies: host_grad holds n FP32 values in the
@@ -392,16 +402,26 @@ int tmx_pc_train(tmx_ctx *ctx, const double *b, const double *x, int npairs, con
 
 /* ---- autotuner ------------------------------------------------------------ */
 
-/* Time every launch shape (workgroup size 64/128/256 x plain or XCD-aware
- * block order) of the two stencil kernels of Mhat for precision prec,
- * operator op and nrhs right-hand sides on this lattice, and keep the
- * fastest for later applies.  If the environment variable TMX_TUNE_CACHE
- * names a file, results are appended there and loaded by tmx_create for the
- * same lattice.  Synchronises. */
+/* Time the launch shapes of the two stencil kernels of Mhat for precision
+ * prec, operator op and nrhs right-hand sides on this lattice, and keep the
+ * fastest for later applies (the operator's kernels, not a model of them;
+ * every shape computes each output slot in one thread, so results do not
+ * depend on the choice).  Knobs: workgroup size 64 / 128 / 256, plain or
+ * XCD-contiguous block order, one or two sites per thread (one right-hand
+ * side), and for nrhs > 1 the group size rg (a divisor of nrhs: the operator
+ * then runs K1 and K2 on rg right-hand sides at a time, which keeps a group's
+ * neighbour spinors within L2), K1 and K2 sharing it.  The internal site
+ * order ((z, t) tiles of the planes) is fixed per context by the environment
+ * variables TMX_SITE_ZB / TMX_SITE_TB, since the field layout depends on it.
+ * If the environment variable TMX_TUNE_CACHE names a file, results are
+ * appended there and loaded by tmx_create for the same lattice; with
+ * TMX_TUNE_LOG set every timed shape is printed to stderr.  Synchronises. */
 int tmx_tune(tmx_ctx *ctx, int prec, int op, int nrhs);
 /* Launch shape in use for a kernel key ("K1_f64", "K2_f32_nd_r12", ...):
- * TMX_OK if it was tuned, TMX_ENOCONV if it is the default. */
-int tmx_tuned_config(tmx_ctx *ctx, const char *key, int *block, int *xcd);
+ * workgroup size, XCD order, sites per thread and right-hand-side group
+ * size (0 = all); any pointer may be NULL.  TMX_OK if it was tuned,
+ * TMX_ENOCONV if it is the default. */
+int tmx_tuned_config(tmx_ctx *ctx, const char *key, int *block, int *xcd, int *spt, int *rg);
 
 /* ---- kernel timing -------------------------------------------------------- */
 

@@ -223,6 +223,71 @@ def loss_and_grad(lat: Lattice, w, bs, xs, mhat=None, mhat_dag=None):
 
 
 # --------------------------------------------------------------------------
+# the Hermitian form P = A^dagger A with A = L_2 L_1 (layers 1 and 2 of the
+# weight vector; layers 3 and 4 unused): four stencil layers applied,
+# Hermitian and positive semi-definite by construction, so one application
+# serves as the preconditioner of CG on N = Mhat^dagger Mhat
+# --------------------------------------------------------------------------
+def sym_forward(lat: Lattice, w, b, keep=False):
+    """P b = R_odd L_1^dagger L_2^dagger L_2 L_1 E_odd b for an odd source b (Vh, 4, 3)."""
+    (C1, G1), (C2, G2) = unflatten(w)[:2]
+    a0 = lat.embed_odd(b)
+    a1 = layer_forward(lat, C1, G1, a0)
+    a2 = layer_forward(lat, C2, G2, a1)
+    a3 = layer_adjoint(lat, C2, G2, a2)
+    out = layer_adjoint(lat, C1, G1, a3)
+    res = lat.restrict_odd(out)
+    return (res, (a0, a1, a2, a3)) if keep else res
+
+
+def _layer_grad(lat: Lattice, C, G, xin, delta):
+    """Gradient of 2 Re<delta, L xin> with respect to (C, G) of the layer
+    L = sum_d (C_d (x) Gamma_d) T_d (the convention of loss_and_grad)."""
+    gC, gG = np.zeros_like(C), np.zeros_like(G)
+    for d in range(NPATH):
+        z = lat.transport(xin, d)
+        S = np.einsum("ovsc,ivtc->osit", np.conj(delta), z)
+        gC[d] = 2 * np.conj(np.einsum("osit,st->oi", S, G[d]))
+        gG[d] = 2 * np.conj(np.einsum("osit,oi->st", S, C[d]))
+    return gC, gG
+
+
+def sym_loss_and_grad(lat: Lattice, w, bs, xs, mhat, mhat_dag):
+    """Energy-norm loss of the Hermitian form over pairs (b_i, x_i = N^{-1} b_i):
+    L = mean_i <e_i, N e_i> / |b_i|^2 = mean_i |Mhat e_i|^2 / |b_i|^2, e_i = P b_i - x_i,
+    and its gradient with respect to the flat weights (layers 3 and 4: zero).
+    A layer used as its adjoint, y = L^dagger x with output adjoint delta,
+    contributes 2 Re<x, dL delta>: the gradient of the layer used forward
+    on delta with output adjoint x."""
+    params = unflatten(w)
+    (C1, G1), (C2, G2) = params[:2]
+    n = len(bs)
+    L = 0.0
+    g1 = [np.zeros_like(C1), np.zeros_like(G1)]
+    g2 = [np.zeros_like(C2), np.zeros_like(G2)]
+    for b, x in zip(bs, xs):
+        out, (a0, a1, a2, a3) = sym_forward(lat, w, b, keep=True)
+        e = out - np.asarray(x).reshape(out.shape)
+        bb = np.vdot(b, b).real
+        q = mhat(e)
+        L += np.vdot(q, q).real / bb / n
+        d4 = lat.embed_odd(mhat_dag(q) / bb / n)       # output adjoint (N e / |b|^2 n)
+        dC, dG = _layer_grad(lat, C1, G1, d4, a3)          # L_1^dagger (last layer)
+        g1[0] += dC; g1[1] += dG
+        d3 = layer_forward(lat, C1, G1, d4)
+        dC, dG = _layer_grad(lat, C2, G2, d3, a2)          # L_2^dagger
+        g2[0] += dC; g2[1] += dG
+        d2 = layer_forward(lat, C2, G2, d3)
+        dC, dG = _layer_grad(lat, C2, G2, a1, d2)          # L_2
+        g2[0] += dC; g2[1] += dG
+        d1 = layer_adjoint(lat, C2, G2, d2)
+        dC, dG = _layer_grad(lat, C1, G1, a0, d1)          # L_1
+        g1[0] += dC; g1[1] += dG
+    gparams = [tuple(g1), tuple(g2)] + [(np.zeros_like(C), np.zeros_like(G)) for C, G in params[2:]]
+    return L, flatten(gparams)
+
+
+# --------------------------------------------------------------------------
 # training step
 # --------------------------------------------------------------------------
 def adam_step(w, m, v, t, g, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -383,10 +383,16 @@ static DslashArgs base_args(tmx_ctx *c, int prec, bool nd, int nrhs)
 }
 
 // K1: u = B_ee(sgn)^{-1} H_eo in ; K2: out = B_oo(sgn) x - kappa^2 H_oe u
+// (with a right-hand-side group size rg < nrhs from the autotuner: K1 then
+// K2 on each group of rg right-hand sides, so that a group's neighbour
+// spinors stay in L2 between the two halves)
 static int schur_pair(tmx_ctx *c, SpinorPtr out, SpinorPtr in, SpinorPtr u, int prec, bool nd, int nrhs, int sgn,
                       int g5in, int g5out, double *nrm = nullptr, double rho = 0.0)
 {
     const int nf = nd ? 2 : 1;
+    const std::string k1 = kname("K1", prec, nd, nrhs), k2 = kname("K2", prec, nd, nrhs);
+    const LaunchCfg l1 = launch_cfg(c, k1), l2 = launch_cfg(c, k2);
+    const int rg = (l1.rg > 0 && l1.rg < nrhs && nrhs % l1.rg == 0) ? l1.rg : nrhs;
     DslashArgs a = base_args(c, prec, nd, nrhs);
     a.sgn = sgn;
     a.parity = 0;
@@ -395,13 +401,8 @@ static int schur_pair(tmx_ctx *c, SpinorPtr out, SpinorPtr in, SpinorPtr u, int 
     a.clov = clov_parity(c, prec, 0);
     a.inv = nd ? c->invnd[prec] : c->inv[prec];
     a.g5in = g5in;
-    const std::string k1 = kname("K1", prec, nd, nrhs);
-    const LaunchCfg l1 = launch_cfg(c, k1);
     a.xcd = l1.xcd;
-    kstat_begin(c, k1);
-    hipError_t e = launch_dslash(prec, nf, 0, a, c->stream, l1.block);
-    kstat_end(c);
-    if (e != hipSuccess) return hip_err(c, e, "K1 launch");
+    a.spt = l1.spt;
     DslashArgs b = base_args(c, prec, nd, nrhs);
     b.sgn = sgn;
     b.parity = 1;
@@ -414,13 +415,20 @@ static int schur_pair(tmx_ctx *c, SpinorPtr out, SpinorPtr in, SpinorPtr u, int 
     b.g5out = g5out;
     b.nrm = nrm;
     b.rho = rho;
-    const std::string k2 = kname("K2", prec, nd, nrhs);
-    const LaunchCfg l2 = launch_cfg(c, k2);
     b.xcd = l2.xcd;
-    kstat_begin(c, k2);
-    e = launch_dslash(prec, nf, 1, b, c->stream, l2.block);
-    kstat_end(c);
-    if (e != hipSuccess) return hip_err(c, e, "K2 launch");
+    b.spt = l2.spt;
+    for (int r0 = 0; r0 < nrhs; r0 += rg) {
+        a.r0 = b.r0 = r0;
+        a.rg = b.rg = rg;
+        kstat_begin(c, k1);
+        hipError_t e = launch_dslash(prec, nf, 0, a, c->stream, l1.block);
+        kstat_end(c);
+        if (e != hipSuccess) return hip_err(c, e, "K1 launch");
+        kstat_begin(c, k2);
+        e = launch_dslash(prec, nf, 1, b, c->stream, l2.block);
+        kstat_end(c);
+        if (e != hipSuccess) return hip_err(c, e, "K2 launch");
+    }
     return TMX_OK;
 }
 
@@ -536,8 +544,10 @@ static void tune_cache_load(tmx_ctx *c)
     int block, xcd;
     double ms;
     const std::string me = dims_key(c);
-    while (std::fscanf(f, "%63s %63s %d %d %lf", dk, kk, &block, &xcd, &ms) == 5) {
-        if (me == dk && block >= 64 && block <= 256 && block % 64 == 0) c->tune[kk] = LaunchCfg{block, xcd != 0};
+    int spt, rg;
+    while (std::fscanf(f, "%63s %63s %d %d %d %d %lf", dk, kk, &block, &xcd, &spt, &rg, &ms) == 7) {
+        if (me == dk && block >= 64 && block <= 256 && block % 64 == 0 && spt >= 1 && spt <= 8 && rg >= 0)
+            c->tune[kk] = LaunchCfg{block, xcd != 0, spt, rg};
     }
     std::fclose(f);
 }
@@ -548,46 +558,62 @@ static void tune_cache_store(tmx_ctx *c, const std::string &key, const LaunchCfg
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %s %d %d %.6f\n", dims_key(c).c_str(), key.c_str(), l.block, l.xcd, ms);
+    std::fprintf(f, "%s %s %d %d %d %d %.6f\n", dims_key(c).c_str(), key.c_str(), l.block, l.xcd, l.spt, l.rg, ms);
     std::fclose(f);
 }
 
-static int tune_one(tmx_ctx *c, DslashArgs a, int prec, int nf, int mode, const std::string &key)
+// time one launch shape of a stencil kernel: every group of its right-hand
+// sides once per sweep, two warm-up sweeps, the mean of five (ms per sweep)
+static int tune_time(tmx_ctx *c, DslashArgs a, int prec, int nf, int mode, const LaunchCfg &l, hipEvent_t e0,
+                     hipEvent_t e1, double *ms_out)
 {
-    const int blocks[3] = {64, 128, 256};
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hip_err(c, hipGetLastError(), "tune events");
-    double best = 1e30;
-    LaunchCfg bestc;
-    for (int xcd = 0; xcd < 2; ++xcd)
-        for (int bi = 0; bi < 3; ++bi) {
-            a.xcd = xcd;
-            hipError_t e = hipSuccess;
-            for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_dslash(prec, nf, mode, a, c->stream, blocks[bi]);
-            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-            const int reps = 5;
-            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_dslash(prec, nf, mode, a, c->stream, blocks[bi]);
-            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return hip_err(c, e, "tune launch");
-            }
-            if (ms / reps < best) {
-                best = ms / reps;
-                bestc = LaunchCfg{blocks[bi], xcd};
-            }
+    const int nrhs = a.nrhs;
+    const int rg = (l.rg > 0 && l.rg < nrhs && nrhs % l.rg == 0) ? l.rg : nrhs;
+    a.xcd = l.xcd;
+    a.spt = l.spt;
+    a.rg = rg;
+    auto sweep = [&]() {
+        hipError_t e = hipSuccess;
+        for (int r0 = 0; r0 < nrhs && e == hipSuccess; r0 += rg) {
+            a.r0 = r0;
+            e = launch_dslash(prec, nf, mode, a, c->stream, l.block);
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    c->tune[key] = bestc;
-    tune_cache_store(c, key, bestc, best);
+        return e;
+    };
+    hipError_t e = hipSuccess;
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) e = sweep();
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    const int reps = 5;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = sweep();
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) return hip_err(c, e, "tune launch");
+    *ms_out = ms / reps;
     return TMX_OK;
 }
 
+// the fastest of the candidate launch shapes for one kernel
+static int tune_pick(tmx_ctx *c, const DslashArgs &a, int prec, int nf, int mode, const std::vector<LaunchCfg> &cands,
+                     hipEvent_t e0, hipEvent_t e1, LaunchCfg *best, double *best_ms)
+{
+    *best_ms = 1e30;
+    const bool log = std::getenv("TMX_TUNE_LOG") != nullptr;
+    for (const LaunchCfg &l : cands) {
+        double ms;
+        int r = tune_time(c, a, prec, nf, mode, l, e0, e1, &ms);
+        if (r) return r;
+        if (log)
+            std::fprintf(stderr, "# TMX: tune %s prec %d nf %d nrhs %d block %d xcd %d spt %d rg %d: %.4f ms\n",
+                         mode ? "K2" : "K1", prec, nf, a.nrhs, l.block, l.xcd, l.spt, l.rg, ms);
+        if (ms < *best_ms) {
+            *best_ms = ms;
+            *best = l;
+        }
+    }
+    return TMX_OK;
+}
 }  // namespace tmx
 
 // ---------------------------------------------------------------------------
@@ -1114,8 +1140,6 @@ int tmx_tune(tmx_ctx *c, int prec, int op, int nrhs)
     a.in = in;
     a.clov = clov_parity(c, prec, 0);
     a.inv = nd ? c->invnd[prec] : c->inv[prec];
-    r = tune_one(c, a, prec, nf, 0, kname("K1", prec, nd, nrhs));
-    if (r) return r;
     DslashArgs b = base_args(c, prec, nd, nrhs);
     b.sgn = a.sgn;
     b.parity = 1;
@@ -1124,15 +1148,57 @@ int tmx_tune(tmx_ctx *c, int prec, int op, int nrhs)
     b.x = in;
     b.clov = clov_parity(c, prec, 1);
     b.kfac = c->par.kappa * c->par.kappa;
-    return tune_one(c, b, prec, nf, 1, kname("K2", prec, nd, nrhs));
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return hip_err(c, hipGetLastError(), "tune events");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_err(c, hipGetLastError(), "tune events");
+    }
+    // knobs: workgroup size, XCD-contiguous block order, sites per thread;
+    // several right-hand sides: the group size (a divisor of nrhs), timed as
+    // the whole sweep over the groups, K1 and K2 sharing the group size
+    std::vector<int> groups;
+    for (int g = nrhs; g >= 1; --g)
+        if (nrhs % g == 0) groups.push_back(g);
+    LaunchCfg best1, best2;
+    double best_ms = 1e30, ms1 = 0, ms2 = 0;
+    for (int g : groups) {
+        std::vector<LaunchCfg> cands;
+        for (int xcd = 0; xcd < 2; ++xcd)
+            for (int blk : {64, 128, 256})
+                for (int spt = 1; spt <= (nrhs == 1 ? 2 : 1); ++spt) cands.push_back(LaunchCfg{blk, xcd, spt, g});
+        LaunchCfg c1, c2;
+        double t1, t2;
+        r = tune_pick(c, a, prec, nf, 0, cands, e0, e1, &c1, &t1);
+        if (!r) r = tune_pick(c, b, prec, nf, 1, cands, e0, e1, &c2, &t2);
+        if (r) break;
+        if (t1 + t2 < best_ms) {
+            best_ms = t1 + t2;
+            best1 = c1;
+            best2 = c2;
+            ms1 = t1;
+            ms2 = t2;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r) return r;
+    const std::string k1 = kname("K1", prec, nd, nrhs), k2 = kname("K2", prec, nd, nrhs);
+    c->tune[k1] = best1;
+    c->tune[k2] = best2;
+    tune_cache_store(c, k1, best1, ms1);
+    tune_cache_store(c, k2, best2, ms2);
+    return TMX_OK;
 }
 
-int tmx_tuned_config(tmx_ctx *c, const char *key, int *block, int *xcd)
+int tmx_tuned_config(tmx_ctx *c, const char *key, int *block, int *xcd, int *spt, int *rg)
 {
     if (!c || !key) return TMX_EINVAL;
     LaunchCfg l = launch_cfg(c, key);
     if (block) *block = l.block;
     if (xcd) *xcd = l.xcd;
+    if (spt) *spt = l.spt;
+    if (rg) *rg = l.rg;
     return c->tune.count(key) ? TMX_OK : TMX_ENOCONV;
 }
 

@@ -1,7 +1,8 @@
 // Wilson twisted-mass clover stencil kernels (gfx950).
 //
 // One launch computes, for every site s of the output parity p and every
-// right-hand side r (thread t = s * nrhs + r):
+// right-hand side r (slot t = s * nrhs + r; a launch may take a group of the
+// right-hand sides, see dslash_kernel):
 //
 //   MODE_INV  (first half of the Schur operator, "K1"):
 //       out = B_p^{-1}(sgn) (H in)(s)
@@ -171,13 +172,37 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &a, const int x[4], int
 }
 
 template <int P, int NF, int MODE>
+__device__ __forceinline__ void dslash_slot(const DslashArgs &a, int s, long rhs);
+
+// Thread i takes the work items i, i + G, ..., i + (SPT - 1) G (G the grid's
+// thread count); item u is right-hand side r0 + u % rg of site u / rg.  SPT
+// is a template parameter: a runtime loop costs registers (and occupancy)
+// even when it runs once.
+template <int P, int NF, int MODE, int SPT>
 __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 {
+    const long rg = a.rg;
+    const long n = (long)a.g.Vh * rg;
+    long u = (long)xcd_block(a.xcd) * blockDim.x + threadIdx.x;
+    if constexpr (SPT == 1) {
+        if (u >= n) return;
+        const int s = (int)(u / rg);
+        dslash_slot<P, NF, MODE>(a, s, a.r0 + (u - (long)s * rg));
+    } else {
+        const long G = (long)gridDim.x * blockDim.x;
+        for (int k = 0; k < SPT && u < n; ++k, u += G) {
+            const int s = (int)(u / rg);
+            dslash_slot<P, NF, MODE>(a, s, a.r0 + (u - (long)s * rg));
+        }
+    }
+}
+
+// one output slot: site s (of the output parity), right-hand side rhs
+template <int P, int NF, int MODE>
+__device__ __forceinline__ void dslash_slot(const DslashArgs &a, int s, long rhs)
+{
     using R = typename RealOf<P>::type;
-    const long t = (long)xcd_block(a.xcd) * blockDim.x + threadIdx.x;
-    if (t >= (long)a.g.Vh * a.nrhs) return;
-    const int s = (int)(t / a.nrhs);
-    const long rhs = t - (long)s * a.nrhs;
+    const long t = (long)s * a.nrhs + rhs;  // slot of the output, the diagonal input and the norms
     int x[4];
     cb_coords(a.g, s, a.parity, x);
 
@@ -298,16 +323,26 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a)
 template <int P, int NF, int MODE>
 static hipError_t launch_one(const DslashArgs &a, hipStream_t st, int block)
 {
-    const long n = (long)a.g.Vh * a.nrhs;
-    const int grid = (int)((n + block - 1) / block);
+    const long n = (long)a.g.Vh * (a.rg > 0 ? a.rg : a.nrhs);
+    const long per = block * (long)(a.spt > 0 ? a.spt : 1);
+    const int grid = (int)((n + per - 1) / per);
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL((dslash_kernel<P, NF, MODE>), dim3(grid), dim3(block), 0, st, a);
+    if (a.spt == 2)
+        hipLaunchKernelGGL((dslash_kernel<P, NF, MODE, 2>), dim3(grid), dim3(block), 0, st, a);
+    else
+        hipLaunchKernelGGL((dslash_kernel<P, NF, MODE, 1>), dim3(grid), dim3(block), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_dslash(int prec, int nf, int mode, const DslashArgs &a, hipStream_t st, int block)
+hipError_t launch_dslash(int prec, int nf, int mode, const DslashArgs &a0, hipStream_t st, int block)
 {
     if (block <= 0) block = 256;
+    DslashArgs a = a0;
+    if (a.spt != 2) a.spt = 1;
+    if (a.rg <= 0 || a.r0 < 0 || a.r0 + a.rg > a.nrhs) {
+        a.r0 = 0;
+        a.rg = a.nrhs;
+    }
 #define TMX_DS(P, NF)                                                                     \
     if (prec == P && nf == NF) {                                                          \
         return mode == MODE_INV ? launch_one<P, NF, MODE_INV>(a, st, block)               \

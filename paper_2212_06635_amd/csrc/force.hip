@@ -295,135 +295,167 @@ __device__ __forceinline__ Mat3 insertion(const CloverForceArgs &f, const int x[
     return m;
 }
 
-// P_m^chi = sum_{s,t} (s_m)_{st} b_t a_s^dagger over the two spins 2 chi,
-// 2 chi + 1 of one chirality (s_m the Pauli matrix, a colour matrix)
-template <int M>
-__device__ __forceinline__ void pauli_outer(const cd a[12], const cd b[12], int chi, Mat3 &P)
+// the Pauli combinations of one chirality chi at colour entry (i, j):
+// P_m^chi = sum_{s,t} (s_m)_{st} b_t a_s^dagger over spins 2 chi, 2 chi + 1
+// (s_m the Pauli matrices; a colour matrix per m), all three m from the four
+// spin products of that entry
+__device__ __forceinline__ void pauli_entry(const cd a[12], const cd b[12], int chi, int i, int j, cd P[3])
 {
     const int s0 = 2 * chi, s1 = 2 * chi + 1;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const cd a0 = conj(a[3 * s0 + j]), a1 = conj(a[3 * s1 + j]);
-            const cd b0 = b[3 * s0 + i], b1 = b[3 * s1 + i];
-            cd v;
-            if constexpr (M == 1)
-                v = b1 * a0 + b0 * a1;
-            else if constexpr (M == 2)
-                v = imul(b0 * a1 - b1 * a0);
-            else
-                v = b0 * a0 - b1 * a1;
-            P.m[3 * i + j] = v;
-        }
+    const cd a0 = conj(a[3 * s0 + j]), a1 = conj(a[3 * s1 + j]);
+    const cd b0 = b[3 * s0 + i], b1 = b[3 * s1 + i];
+    const cd b0a0 = b0 * a0, b0a1 = b0 * a1, b1a0 = b1 * a0, b1a1 = b1 * a1;
+    P[0] = b1a0 + b0a1;          // s_1
+    P[1] = imul(b0a1 - b1a0);    // s_2
+    P[2] = b0a0 - b1a1;          // s_3
 }
 
-__device__ __forceinline__ void store_insertion(const CloverForceArgs &f, int plane, long site, double c,
-                                                const Mat3 &G)
+template <bool HACC>
+__device__ __forceinline__ void put_insertion(const CloverForceArgs &f, int plane, long site, int k, cd v)
 {
     const long V2 = 2L * f.g.Vh;
-    double2 *h = f.H + (long)plane * 9 * V2 + site;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            // c (G + G^dagger), summed over the flavours of a two-flavour field
-            const cd v = G.m[3 * i + j] + conj(G.m[3 * j + i]);
-            double2 o = make_double2(c * v.re, c * v.im);
-            if (f.h_acc) {
-                const double2 old = h[(3 * i + j) * V2];
-                o.x += old.x;
-                o.y += old.y;
-            }
-            h[(3 * i + j) * V2] = o;
-        }
+    double2 *h = f.H + ((long)plane * 9 + k) * V2 + site;
+    double2 o = make_double2(v.re, v.im);
+    if constexpr (HACC) {  // the next flavour of a two-flavour field adds its part
+        const double2 old = *h;
+        o.x += old.x;
+        o.y += old.y;
+    }
+    *h = o;
 }
 
 // sigma_kl = -eps_klm diag(s_m, s_m), sigma_k4 = diag(s_k, -s_k): the
-// spatial plane opposite m takes -eps (P_m^0 + P_m^1), the (m, t) plane
-// P_m^0 - P_m^1
-template <int M>
-__device__ __forceinline__ void planes_of(const CloverForceArgs &f, const cd a[12], const cd b[12], long site,
-                                          double c)
+// spatial plane opposite m takes G = -eps (P_m^0 + P_m^1), the (m, t) plane
+// G = P_m^0 - P_m^1, and H = c (G + G^dagger).  One unordered colour pair
+// (i, j) at a time, all six planes from its products (H_ji = conj(H_ij)), so
+// that only the site's two spinors stay live.
+template <bool HACC>
+__device__ __forceinline__ void all_planes(const CloverForceArgs &f, const cd a[12], const cd b[12], long site,
+                                           double c)
 {
-    Mat3 P0, P1, G;
-    pauli_outer<M>(a, b, 0, P0);
-    pauli_outer<M>(a, b, 1, P1);
-    // G_yz = -(P_1^0 + P_1^1), G_xz = P_2^0 + P_2^1, G_xy = -(P_3^0 + P_3^1)
-    const double se = M == 2 ? 1.0 : -1.0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) G.m[k] = se * (P0.m[k] + P1.m[k]);
-    store_insertion(f, M == 1 ? 3 : (M == 2 ? 1 : 0), site, c, G);
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int k = 0; k < 9; ++k) G.m[k] = P0.m[k] - P1.m[k];
-    store_insertion(f, M == 1 ? 2 : (M == 2 ? 4 : 5), site, c, G);
+        for (int j = i; j < 3; ++j) {
+            cd p0[3], p1[3], q0[3], q1[3];
+            pauli_entry(a, b, 0, i, j, p0);
+            pauli_entry(a, b, 1, i, j, p1);
+            pauli_entry(a, b, 0, j, i, q0);
+            pauli_entry(a, b, 1, j, i, q1);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const double se = m == 1 ? 1.0 : -1.0;
+                const int ps = m == 0 ? 3 : (m == 1 ? 1 : 0), pt = m == 0 ? 2 : (m == 1 ? 4 : 5);
+                const cd hs = c * (se * (p0[m] + p1[m]) + conj(se * (q0[m] + q1[m])));
+                const cd ht = c * ((p0[m] - p1[m]) + conj(q0[m] - q1[m]));
+                put_insertion<HACC>(f, ps, site, 3 * i + j, hs);
+                put_insertion<HACC>(f, pt, site, 3 * i + j, ht);
+                if (j != i) {
+                    put_insertion<HACC>(f, ps, site, 3 * j + i, conj(hs));
+                    put_insertion<HACC>(f, pt, site, 3 * j + i, conj(ht));
+                }
+            }
+        }
 }
 
+template <bool HACC>
 __global__ void __launch_bounds__(256) clover_insertion_kernel(CloverForceArgs f)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2L * f.g.Vh) return;
     const int p = (int)(t / f.g.Vh);
     const int s = (int)(t - (long)p * f.g.Vh);
+    // odd sites: a = Y, b = X; even sites: a = g5 w, b = u (one load of each)
     cd a[12], b[12];
-    if (p == 1) {
-        load_g5(f.Y, s, false, a);
-        load_g5(f.X, s, false, b);
-    } else {
-        load_g5(f.w, s, true, a);
-        load_g5(f.u, s, false, b);
-    }
+    load_g5(p == 1 ? f.Y : f.w, s, p != 1, a);
+    load_g5(p == 1 ? f.X : f.u, s, false, b);
     const double c = p == 1 ? 1.0 : f.kfac;
-    planes_of<1>(f, a, b, t, c);
-    planes_of<2>(f, a, b, t, c);
-    planes_of<3>(f, a, b, t, c);
+    all_planes<HACC>(f, a, b, t, c);
 }
 
+__device__ __forceinline__ Mat3 dagm(const Mat3 &a)
+{
+    Mat3 c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) c.m[3 * i + j] = conj(a.m[3 * j + i]);
+    return c;
+}
+
+// value of lane l ^ 1 (all lanes active)
+__device__ __forceinline__ double pair_swap(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ Mat3 sel(bool c, const Mat3 &a, const Mat3 &b)
+{
+    Mat3 m;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m.m[k] = c ? a.m[k] : b.m[k];
+    return m;
+}
+
+// Two lanes per link U_R(y): lane half 0 sums the plaquettes above it, lane
+// half 1 those below, with one instruction stream.  The one below enters as
+// E U^+ = (U E^+)^+, and E^+ has the form of the one above,
+//     E^+ = b1 b2 b3 h(y) + b1 b2 h(y-n) b3 + b1 h(y-n+R) b2 b3 + h(y+R) b1 b2 b3,
+//     b1 = U_n(y-n+R)^+, b2 = U_R(y-n)^+, b3 = U_n(y-n),
+// so both lanes form X = U [c1 (c2 (c3 h(y) + h3 c3) + h2 c2 c3) + h(y+R) c1 c2 c3]
+// from their own links c and insertions h3, h2, and add X (above) or -X^+
+// (below); the pair then sums its two halves.
 template <int R>
-__device__ __forceinline__ void clover_link(const CloverForceArgs &f, const int y[4], long lex)
+__device__ __forceinline__ void clover_link_half(const CloverForceArgs &f, const int y[4], long lex, int half,
+                                                 bool valid)
 {
     Mat3 Z;
 #pragma unroll
     for (int k = 0; k < 9; ++k) Z.m[k] = cd{0, 0};
-    int yr[4];
-    shift(f.g, y, R, +1, yr);
-    const Mat3 ur = link(f, y, R);
+    const bool lo = half == 1;
+    if (valid) {
+        int yr[4];
+        shift(f.g, y, R, +1, yr);
 #pragma unroll 1
-    for (int n = 0; n < 4; ++n) {
-        if (n == R) continue;
-        int yn[4], yrn[4], ymn[4], ymnr[4];
-        shift(f.g, y, n, +1, yn);
-        shift(f.g, yr, n, +1, yrn);
-        shift(f.g, y, n, -1, ymn);
-        shift(f.g, ymn, R, +1, ymnr);
-        const Mat3 h0 = insertion(f, y, R, n), h1 = insertion(f, yr, R, n);
-        {
-            // above: y -> y+r -> y+r+n -> y+n -> y, opened at U_r(y):
-            // a1 = U_n(y+r), a2 = U_r(y+n)^dagger, a3 = U_n(y)^dagger
-            const Mat3 a1 = link(f, yr, n), ur_n = link(f, yn, R), un = link(f, y, n);
-            const Mat3 a12 = mm_nd(a1, ur_n);
-            const Mat3 B = mm_nd(a12, un);
-            Mat3 C = mm(B, h0);
-            add_to(C, mm(h1, B));
-            add_to(C, mm_nd(mm(a1, insertion(f, yrn, R, n)), mm(un, ur_n)));  // a1 h a2 a3
-            add_to(C, mm_nd(mm(a12, insertion(f, yn, R, n)), un));            // a1 a2 h a3
-            add_to(Z, mm(ur, C));
-        }
-        {
-            // below: y-n -> y-n+r -> y+r -> y -> y-n, closed by U_r(y)^dagger:
-            // d1 = U_n(y-n)^dagger, d2 = U_r(y-n), d3 = U_n(y-n+r)
-            const Mat3 d1 = link(f, ymn, n), d2 = link(f, ymn, R), d3 = link(f, ymnr, n);
-            const Mat3 d23 = mm(d2, d3);
-            const Mat3 D = mm_dn(d1, d23);
-            Mat3 E = mm(D, h1);
-            add_to(E, mm(h0, D));
-            add_to(E, mm_dn(d1, mm(insertion(f, ymn, R, n), d23)));            // d1 h d2 d3
-            add_to(E, mm(mm(mm_dn(d1, d2), insertion(f, ymnr, R, n)), d3));    // d1 d2 h d3
-            const Mat3 EU = mm_nd(E, ur);
+        for (int n = 0; n < 4; ++n) {
+            if (n == R) continue;
+            // above: c3 = U_n(y)^+ at y, h3 at y+n, c2 = U_R(y+n)^+, h2 at y+R+n, c1 = U_n(y+R)
+            // below: c3 = U_n(y-n) at y-n, h3 at y-n, c2 = U_R(y-n)^+, h2 at y-n+R, c1 = U_n(y-n+R)^+
+            int yn[4], y3[4], y2[4];
+            shift(f.g, y, n, lo ? -1 : +1, yn);  // y+n above, y-n below
+            shift(f.g, yn, R, +1, y2);            // y+n+R / y-n+R
 #pragma unroll
-            for (int k = 0; k < 9; ++k) Z.m[k] = Z.m[k] - EU.m[k];
+            for (int k = 0; k < 4; ++k) y3[k] = lo ? yn[k] : y[k];
+            Mat3 l3 = link(f, y3, n);
+            Mat3 P = sel(lo, l3, dagm(l3));                                   // c3
+            Mat3 T = mm(P, insertion(f, y, R, n));                            // c3 h(y)
+            add_to(T, mm(insertion(f, yn, R, n), P));                         // + h3 c3
+            const Mat3 l2 = link(f, yn, R);
+            const Mat3 c2 = dagm(l2);                                         // U_R(y+-n)^+ in both
+            T = mm(c2, T);
+            P = mm(c2, P);
+            add_to(T, mm(insertion(f, y2, R, n), P));                         // + h2 c2 c3
+            const Mat3 l1 = link(f, lo ? y2 : yr, n);
+            const Mat3 c1 = sel(lo, dagm(l1), l1);
+            T = mm(c1, T);
+            P = mm(c1, P);
+            add_to(T, mm(insertion(f, yr, R, n), P));                         // + h(y+R) c1 c2 c3
+            const Mat3 X = mm(link(f, y, R), T);
+            const Mat3 Xd = dagm(X);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Z.m[k] = lo ? Z.m[k] - Xd.m[k] : Z.m[k] + X.m[k];
         }
     }
+    // the pair's two halves
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        Z.m[k].re += pair_swap(Z.m[k].re);
+        Z.m[k].im += pair_swap(Z.m[k].im);
+    }
+    if (!valid || lo) return;
     // Q = i (kappa csw / 8) Z, F = TA(Q)
     cd Q[9];
 #pragma unroll
@@ -448,26 +480,27 @@ __device__ __forceinline__ void clover_link(const CloverForceArgs &f, const int 
         }
 }
 
-// One thread per link.  Workgroup 8 i + 4 p + rho takes direction rho of
-// sites 256 i ... of parity p: the four directions and both parities of one
-// site block are neighbouring workgroups (with the XCD remap, on one XCD),
-// so the insertions and links of their common staples are read through one
-// L2 instead of once per direction.
+// Two lanes per link, 128 links per workgroup.  Workgroup 8 i + 4 p + rho
+// takes direction rho of sites 128 i ... of parity p: the four directions
+// and both parities of one site block are neighbouring workgroups (with the
+// XCD remap, on one XCD), so the insertions and links of their common
+// staples are read through one L2.
 __global__ void __launch_bounds__(256) clover_force_kernel(CloverForceArgs f)
 {
     const long blk = xcd_block(f.xcd);
     const int r = (int)(blk & 3);
     const int p = (int)((blk >> 2) & 1);
-    const long st = (blk >> 3) * blockDim.x + threadIdx.x;
-    if (st >= f.g.Vh) return;
-    int x[4];
-    cb_coords(f.g, (int)st, p, x);
+    const long st = (blk >> 3) * (blockDim.x / 2) + threadIdx.x / 2;
+    const int half = threadIdx.x & 1;
+    const bool valid = st < f.g.Vh;
+    int x[4] = {0, 0, 0, 0};
+    if (valid) cb_coords(f.g, (int)st, p, x);
     const long lex = x[0] + (long)f.g.L[0] * (x[1] + (long)f.g.L[1] * (x[2] + (long)f.g.L[2] * x[3]));
     switch (r) {
-    case 0: clover_link<0>(f, x, lex); break;
-    case 1: clover_link<1>(f, x, lex); break;
-    case 2: clover_link<2>(f, x, lex); break;
-    default: clover_link<3>(f, x, lex); break;
+    case 0: clover_link_half<0>(f, x, lex, half, valid); break;
+    case 1: clover_link_half<1>(f, x, lex, half, valid); break;
+    case 2: clover_link_half<2>(f, x, lex, half, valid); break;
+    default: clover_link_half<3>(f, x, lex, half, valid); break;
     }
 }
 
@@ -478,14 +511,17 @@ hipError_t launch_clover_insertions(const CloverForceArgs &f, hipStream_t st)
     const long n = 2L * f.g.Vh;
     if (n == 0) return hipSuccess;
     const unsigned nb = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(clover_insertion_kernel, dim3(nb), dim3(256), 0, st, f);
+    if (f.h_acc)
+        hipLaunchKernelGGL(clover_insertion_kernel<true>, dim3(nb), dim3(256), 0, st, f);
+    else
+        hipLaunchKernelGGL(clover_insertion_kernel<false>, dim3(nb), dim3(256), 0, st, f);
     return hipGetLastError();
 }
 
 hipError_t launch_clover_link_sums(const CloverForceArgs &f, hipStream_t st)
 {
     if (f.g.Vh == 0) return hipSuccess;
-    const long nlink = 8 * ((f.g.Vh + 255) / 256);  // 4 directions x 2 parities per site block
+    const long nlink = 8 * ((f.g.Vh + 127) / 128);  // 4 directions x 2 parities per block of 128 sites
     hipLaunchKernelGGL(clover_force_kernel, dim3((unsigned)nlink), dim3(256), 0, st, f);
     return hipGetLastError();
 }

@@ -80,6 +80,7 @@ struct PcState {
     int adam_t = 0;
     uint32_t *lrow = nullptr, *lcol = nullptr;  // BF16 network links (see NnLinks)
     int links_upload = -1;  // gauge upload the links were made from
+    struct ThinW *thin = nullptr;  // factorised weights of the one-channel layers (see ThinW)
 };
 
 // ---------------------------------------------------------------------------
@@ -649,6 +650,274 @@ template <int P> __global__ void nn_embed_kernel(SpinorPtr r, Act a, long Vh)
     dst[2] = make_uint4(w[8], w[9], w[10], w[11]);
 }
 
+// ---------------------------------------------------------------------------
+// the one-channel layers on the vector ALUs
+// ---------------------------------------------------------------------------
+// A layer with one input or one output channel has, per path, a channel
+// vector C_d (8 entries) and the spin matrix Gamma_d, so it is applied in its
+// factorised form in FP32: 1 -> 8 transports the source, mixes the spins and
+// spreads the result over the channels; 8 -> 1 contracts the channels first,
+// then mixes the spins and transports (C_d, Gamma_d and T_d commute).  Four
+// lanes per site, lane q owning output spin q; the 8 -> 1 layer exchanges the
+// four channel-contracted spins of a site among its lanes (DPP within a quad).
+// The input of the first layer is read straight from the odd source field.
+struct ThinW {
+    float2 C[NN_P][8];     // channel vector of path d
+    float2 G[NN_P][4][4];  // spin matrix of path d
+};
+// the four ThinW sets: forward first layer (1 -> 8), forward last layer
+// (8 -> 1), and the adjoints of the last (1 -> 8) and of the first (8 -> 1)
+enum { THIN_UP_F = 0, THIN_DOWN_F = 1, THIN_UP_A = 2, THIN_DOWN_A = 3 };
+
+// one thread per path: the channel vector and spin matrix of path d of a
+// layer with cin * cout = 8 (forward), or of its adjoint W'_d = W_{rev d}^H
+__global__ void nn_build_thin_kernel(const float *p, ThinW *w, int cin, int cout, int adjoint)
+{
+    const int d = threadIdx.x;
+    if (d >= NN_P) return;
+    const int dd = adjoint ? rev_path(d) : d;
+    const int per = cin * cout + 16;
+    const float *pd = p + (size_t)dd * per * 2;
+    const float sg = adjoint ? -1.f : 1.f;
+    for (int c = 0; c < 8; ++c) w->C[d][c] = make_float2(pd[2 * c], sg * pd[2 * c + 1]);
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            const int e = adjoint ? b * 4 + a : a * 4 + b;
+            w->G[d][a][b] = make_float2(pd[2 * (cin * cout + e)], sg * pd[2 * (cin * cout + e) + 1]);
+        }
+}
+
+__device__ __forceinline__ cx<float> bf2c(uint32_t w)
+{
+    return cx<float>{__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u)};
+}
+
+// the 3x3 transport matrix of a path (bc U or bc U^dagger) from the BF16 row-major link
+__device__ __forceinline__ void path_matrix(const NnLinks &L, const Nbr &nb, int d, cx<float> m[9])
+{
+    const int mu = (d - 1) / 2;
+    const uint32_t *lr = L.row + ((long)(nb.lp * 4 + mu) * L.Vh + nb.lcb) * 9;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const cx<float> u = bf2c(lr[3 * r + k]);
+            // U^dagger[r][k] = conj(U[k][r])
+            m[nb.dag ? 3 * k + r : 3 * r + k] = nb.dag ? cx<float>{nb.bc * u.re, -nb.bc * u.im}
+                                                       : cx<float>{nb.bc * u.re, nb.bc * u.im};
+        }
+}
+
+// value of lane q ^ M of this lane's quad (all four lanes active)
+template <int M> __device__ __forceinline__ float quad_xor(float v)
+{
+    constexpr int ctrl = M == 1 ? 0xB1 : (M == 2 ? 0x4E : 0x1B);  // quad_perm [1,0,3,2] / [2,3,0,1] / [3,2,1,0]
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
+}
+
+// spin q (three colours) of the odd source at checkerboard index cb
+template <int P>
+__device__ __forceinline__ void load_spin(const SpinorPtr &src, long cb, int q, cx<float> v[3])
+{
+    // spin q holds the reals 6 q .. 6 q + 5 of the site's 24 (three colours)
+    float r[6];
+    if constexpr (P == F32) {
+        const float *b = static_cast<const float *>(src.d);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int e = 6 * q + k;
+            r[k] = b[((long)(e / 4) * src.stride + cb) * 4 + e % 4];
+        }
+    } else if constexpr (P == F64) {
+        // component 3 q + a is vector 3 q + a
+        const double2 *b = static_cast<const double2 *>(src.d);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double2 w = b[(long)(3 * q + a) * src.stride + cb];
+            r[2 * a] = (float)w.x;
+            r[2 * a + 1] = (float)w.y;
+        }
+    } else {
+        // the whole site (three 16-byte vectors and the scale), spin q picked
+        // by 0/1 weights (a select on q would become register indexing)
+        cx<float> all[12];
+        load_spinor<P>(src, 0, cb, all);
+        const float w0 = q == 0, w1 = q == 1, w2 = q == 2, w3 = q == 3;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            r[2 * a] = w0 * all[a].re + w1 * all[3 + a].re + w2 * all[6 + a].re + w3 * all[9 + a].re;
+            r[2 * a + 1] = w0 * all[a].im + w1 * all[3 + a].im + w2 * all[6 + a].im + w3 * all[9 + a].im;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = cx<float>{r[2 * a], r[2 * a + 1]};
+}
+
+// paths D0 .. D1 - 1 of the first layer at one site, accumulated into acc:
+// lane q transports spin q, the quad exchanges the four transported spins,
+// then lane q applies row q of Gamma_d and spreads over the channels
+template <int P, int D0, int D1>
+__device__ __forceinline__ void up_paths(const Geom &g, const SpinorPtr &src, const NnLinks &L, const ThinW *W, int t_bc,
+                                         const int x[4], int p, long s, int q, cx<float> acc[8][3])
+{
+#pragma unroll
+    for (int d = D0; d < D1; ++d) {
+        const Nbr nb = path_neighbour_at(g, x, p, (int)s, d, t_bc);
+        const long ncb = d == 0 ? s : nb.idx - g.Vh;  // the odd site read
+        cx<float> v[3];
+        load_spin<P>(src, ncb, q, v);
+        cx<float> t[3];
+        if (d == 0) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) t[a] = v[a];
+        } else {
+            cx<float> m[9];
+            path_matrix(L, nb, d, m);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                t[a] = cx<float>{0.f, 0.f};
+#pragma unroll
+                for (int b = 0; b < 3; ++b) cmac(t[a], m[3 * a + b], v[b]);
+            }
+        }
+        // h = sum_m Gamma_d[q][q ^ m] t(spin q ^ m), spin q ^ m held by lane q ^ m
+        const float2 g0 = W->G[d][q][q], g1 = W->G[d][q][q ^ 1], g2 = W->G[d][q][q ^ 2], g3 = W->G[d][q][q ^ 3];
+        cx<float> h[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const cx<float> t1{quad_xor<1>(t[a].re), quad_xor<1>(t[a].im)};
+            const cx<float> t2{quad_xor<2>(t[a].re), quad_xor<2>(t[a].im)};
+            const cx<float> t3{quad_xor<3>(t[a].re), quad_xor<3>(t[a].im)};
+            h[a] = cx<float>{g0.x, g0.y} * t[a];
+            cmac(h[a], cx<float>{g1.x, g1.y}, t1);
+            cmac(h[a], cx<float>{g2.x, g2.y}, t2);
+            cmac(h[a], cx<float>{g3.x, g3.y}, t3);
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float2 cc = W->C[d][c];
+            const cx<float> cv{cc.x, cc.y};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) cmac(acc[c][a], cv, h[a]);
+        }
+    }
+}
+
+// 1 -> 8: y_c(x) = sum_d C_d[c] (Gamma_d T_d r)(x) for an odd source r
+// (precision P): odd sites take the d = 0 path only, even sites the eight hops.
+// Tiles of 64 sites of one parity, alternating (tile 2 i + p).
+template <int P>
+__global__ void __launch_bounds__(256) nn_up_kernel(Geom g, SpinorPtr src, Act y, NnLinks L, const ThinW *W,
+                                                    int t_bc, int xcd)
+{
+    const long tile = xcd_block(xcd);
+    const int p = (int)(tile & 1);
+    const long s = (tile >> 1) * 64 + threadIdx.x / 4;
+    const int q = threadIdx.x % 4;
+    if (s >= g.Vh) return;
+    int x[4];
+    cb_coords(g, (int)s, p, x);
+    cx<float> acc[8][3];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[c][a] = cx<float>{0.f, 0.f};
+    // odd sites: the d = 0 path; even sites: the eight hops, unrolled so that
+    // the loads of later paths are issued before the arithmetic of earlier ones
+    if (p == 1)
+        up_paths<P, 0, 1>(g, src, L, W, t_bc, x, p, s, q, acc);
+    else
+        up_paths<P, 1, NN_P>(g, src, L, W, t_bc, x, p, s, q, acc);
+    const long gs = (long)p * g.Vh + s;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        uint32_t *o = y.d + ((long)c * y.stride + gs) * 12 + 3 * q;
+        o[0] = f2bf2(acc[c][0].re, acc[c][0].im);
+        o[1] = f2bf2(acc[c][1].re, acc[c][1].im);
+        o[2] = f2bf2(acc[c][2].re, acc[c][2].im);
+    }
+}
+
+
+// 8 -> 1 on odd sites: y(x) = sum_d T_d Gamma_d (sum_c C_d[c] x_c)(x), written
+// as an FP32 odd spinor field.  64 odd sites per block, staged in LDS so that
+// the stores are whole 16-byte vectors.
+__global__ void __launch_bounds__(256) nn_down_kernel(Geom g, Act xin, SpinorPtr yo, NnLinks L, const ThinW *W,
+                                                      int t_bc, int xcd)
+{
+    __shared__ __attribute__((aligned(16))) float ys[64 * 24];
+    const long s0 = (long)xcd_block(xcd) * 64;
+    const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
+    const long s = s0 + sl;
+    const bool valid = s < g.Vh;
+    int x[4] = {0, 0, 0, 0};
+    if (valid) cb_coords(g, (int)s, 1, x);
+    cx<float> acc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[a] = cx<float>{0.f, 0.f};
+#pragma unroll
+    for (int d = 0; d < NN_P; ++d) {
+        // channel contraction of spin q at the neighbour
+        cx<float> w[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) w[a] = cx<float>{0.f, 0.f};
+        Nbr nb{};
+        if (valid) {
+            nb = path_neighbour_at(g, x, 1, (int)s, d, t_bc);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const uint32_t *src = xin.d + ((long)c * xin.stride + nb.idx) * 12 + 3 * q;
+                const float2 cc = W->C[d][c];
+                const cx<float> cv{cc.x, cc.y};
+                const uint32_t w0 = src[0], w1 = src[1], w2 = src[2];
+                cmac(w[0], cv, bf2c(w0));
+                cmac(w[1], cv, bf2c(w1));
+                cmac(w[2], cv, bf2c(w2));
+            }
+        }
+        // spin q ^ m of the site is held by lane q ^ m of its quad:
+        // h = sum_m Gamma_d[q][q ^ m] w(spin q ^ m)
+        const float2 g0 = W->G[d][q][q], g1 = W->G[d][q][q ^ 1], g2 = W->G[d][q][q ^ 2], g3 = W->G[d][q][q ^ 3];
+        cx<float> h[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const cx<float> w1{quad_xor<1>(w[a].re), quad_xor<1>(w[a].im)};
+            const cx<float> w2{quad_xor<2>(w[a].re), quad_xor<2>(w[a].im)};
+            const cx<float> w3{quad_xor<3>(w[a].re), quad_xor<3>(w[a].im)};
+            h[a] = cx<float>{g0.x, g0.y} * w[a];
+            cmac(h[a], cx<float>{g1.x, g1.y}, w1);
+            cmac(h[a], cx<float>{g2.x, g2.y}, w2);
+            cmac(h[a], cx<float>{g3.x, g3.y}, w3);
+        }
+        if (!valid) continue;
+        if (d == 0) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[a] = acc[a] + h[a];
+        } else {
+            cx<float> m[9];
+            path_matrix(L, nb, d, m);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) cmac(acc[a], m[3 * a + b], h[b]);
+        }
+    }
+    // [site][spin q][colour][re, im] in LDS, then 16-byte vectors: vector kv of
+    // a site holds its reals 4 kv .. 4 kv + 3
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ys[sl * 24 + 6 * q + 2 * a] = acc[a].re;
+        ys[sl * 24 + 6 * q + 2 * a + 1] = acc[a].im;
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v < 6 * 64; v += blockDim.x) {
+        const int kv = v / 64, sn = v % 64;
+        if (s0 + sn >= g.Vh) continue;
+        reinterpret_cast<float4 *>(yo.d)[(long)kv * yo.stride + s0 + sn] =
+            *reinterpret_cast<const float4 *>(&ys[sn * 24 + 4 * kv]);
+    }
+}
+
 // sum of the per-block partials: P[i] = sum_b partial[b][i]
 __global__ void nn_reduce_partials_kernel(const float *partial, int nblocks, int n, float *P)
 {
@@ -739,7 +1008,8 @@ int nn_ensure(tmx_ctx *c)
     float *bufs[4];
     for (int i = 0; i < 4; ++i) bufs[i] = static_cast<float *>(dev_alloc(c, bytes));
     uint16_t *wf[NN_L], *wa[NN_L];
-    bool ok = bufs[0] && bufs[1] && bufs[2] && bufs[3];
+    ThinW *thin = static_cast<ThinW *>(dev_alloc(c, 4 * sizeof(ThinW)));
+    bool ok = bufs[0] && bufs[1] && bufs[2] && bufs[3] && thin;
     for (int l = 0; l < NN_L; ++l) {
         const size_t nf = (size_t)NN_P * pad16(8 * NN_COUT[l]) * pad16(8 * NN_CIN[l]);
         const size_t na = (size_t)NN_P * pad16(8 * NN_CIN[l]) * pad16(8 * NN_COUT[l]);
@@ -748,6 +1018,7 @@ int nn_ensure(tmx_ctx *c)
         ok = ok && wf[l] && wa[l];
     }
     if (!ok) {
+        dev_free(c, thin);
         for (int i = 0; i < 4; ++i) dev_free(c, bufs[i]);
         for (int l = 0; l < NN_L; ++l) {
             dev_free(c, wf[l]);
@@ -760,6 +1031,7 @@ int nn_ensure(tmx_ctx *c)
     s.grad = bufs[1];
     s.adam_m = bufs[2];
     s.adam_v = bufs[3];
+    s.thin = thin;
     for (int l = 0; l < NN_L; ++l) {
         s.Wf[l] = wf[l];
         s.Wa[l] = wa[l];
@@ -779,6 +1051,11 @@ int nn_build_weights(tmx_ctx *c)
         hipLaunchKernelGGL(nn_build_w_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, pl, s.Wa[l], NN_CIN[l],
                            NN_COUT[l], 1);
     }
+    const float *p0 = s.params + layer_param_offset(0), *p3 = s.params + layer_param_offset(NN_L - 1);
+    hipLaunchKernelGGL(nn_build_thin_kernel, dim3(1), dim3(64), 0, c->stream, p0, s.thin + THIN_UP_F, 1, 8, 0);
+    hipLaunchKernelGGL(nn_build_thin_kernel, dim3(1), dim3(64), 0, c->stream, p3, s.thin + THIN_DOWN_F, 8, 1, 0);
+    hipLaunchKernelGGL(nn_build_thin_kernel, dim3(1), dim3(64), 0, c->stream, p3, s.thin + THIN_UP_A, 8, 1, 1);
+    hipLaunchKernelGGL(nn_build_thin_kernel, dim3(1), dim3(64), 0, c->stream, p0, s.thin + THIN_DOWN_A, 1, 8, 1);
     int r = hip_err(c, hipGetLastError(), "build weights");
     if (!r) s.w_ok = true;
     return r;
@@ -837,6 +1114,38 @@ int launch_layer(tmx_ctx *c, int cin, int cout, Act x, Act y, SpinorPtr yo, cons
     return hip_err(c, hipGetLastError(), "network layer");
 }
 
+// first layer (1 -> 8) on the odd field r of precision pr, straight from the field
+int launch_up(tmx_ctx *c, SpinorPtr r, int pr, Act y, const ThinW *W)
+{
+    NnLinks L;
+    int rc = nn_links(c, L);
+    if (rc) return rc;
+    const dim3 grid((unsigned)(2 * ((c->Vh + 63) / 64))), block(256);
+    const int tb = c->par.t_bc, xcd = c->xcd_remap;
+    kstat_begin(c, "NN_1x8");
+    if (pr == F64)
+        hipLaunchKernelGGL(nn_up_kernel<F64>, grid, block, 0, c->stream, c->g, r, y, L, W, tb, xcd);
+    else if (pr == F32)
+        hipLaunchKernelGGL(nn_up_kernel<F32>, grid, block, 0, c->stream, c->g, r, y, L, W, tb, xcd);
+    else
+        hipLaunchKernelGGL(nn_up_kernel<F16>, grid, block, 0, c->stream, c->g, r, y, L, W, tb, xcd);
+    kstat_end(c);
+    return hip_err(c, hipGetLastError(), "network first layer");
+}
+
+// last layer (8 -> 1) into the FP32 odd field yo
+int launch_down(tmx_ctx *c, Act x, SpinorPtr yo, const ThinW *W)
+{
+    NnLinks L;
+    int rc = nn_links(c, L);
+    if (rc) return rc;
+    const dim3 grid((unsigned)((c->Vh + 63) / 64)), block(256);
+    kstat_begin(c, "NN_8x1");
+    hipLaunchKernelGGL(nn_down_kernel, grid, block, 0, c->stream, c->g, x, yo, L, W, c->par.t_bc, c->xcd_remap);
+    kstat_end(c);
+    return hip_err(c, hipGetLastError(), "network last layer");
+}
+
 constexpr int WG_BLOCKS = 64;
 
 int launch_wgrad(tmx_ctx *c, int cin, int cout, Act x, Act dy, float *partial)
@@ -879,8 +1188,38 @@ int embed(tmx_ctx *c, SpinorPtr r, int pr, Act a)
     return hip_err(c, hipGetLastError(), "embed");
 }
 
-// The network on the odd field r: out = K r (dagger = 0) or K^dagger r, an
-// FP32 odd field.  With acts, the layer inputs are kept (for the gradient).
+// The Hermitian form P r = L_1^dagger L_2^dagger L_2 L_1 r (layers 1 and 2 of
+// the weights), an FP32 odd field; with acts, the inputs of its four layer
+// applications are kept (for the gradient).
+int nn_forward_sym(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, std::vector<Act> *acts)
+{
+    const bool keep = acts != nullptr;
+    const ThinW *thin = c->pc->thin;
+    Act a0{};
+    if (keep) {
+        a0 = act(c, "a0", 1);
+        if (!a0.d) return TMX_ENOMEM;
+        int rc = embed(c, r, pr, a0);
+        if (rc) return rc;
+        acts->push_back(a0);
+    }
+    Act a1 = act(c, keep ? "a1" : "p1", 8), a2 = act(c, keep ? "a2" : "p2", 8), a3 = act(c, keep ? "a3" : "p3", 8);
+    if (!a1.d || !a2.d || !a3.d) return TMX_ENOMEM;
+    int rc = launch_up(c, r, pr, a1, thin + THIN_UP_F);  // L_1
+    if (!rc) rc = launch_layer(c, 8, 8, a1, a2, SpinorPtr{}, c->pc->Wf[1]);  // L_2
+    if (!rc) rc = launch_layer(c, 8, 8, a2, a3, SpinorPtr{}, c->pc->Wa[1]);  // L_2^dagger
+    if (rc) return rc;
+    if (keep) {
+        acts->push_back(a1);
+        acts->push_back(a2);
+        acts->push_back(a3);
+    }
+    return launch_down(c, a3, out, thin + THIN_DOWN_A);  // L_1^dagger
+}
+
+// The network on the odd field r: out = K r (mode 0), K^dagger r (mode 1) or
+// the Hermitian form P r (mode 2), an FP32 odd field.  With acts, the layer
+// inputs are kept (for the gradient).
 int nn_forward(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, int dagger, std::vector<Act> *acts)
 {
     int rc = nn_ensure(c);
@@ -889,21 +1228,28 @@ int nn_forward(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, int dagger, std::
     rc = ensure_ready(c, F32, false);
     if (!rc) rc = nn_build_weights(c);
     if (rc) return rc;
+    if (dagger == 2) return nn_forward_sym(c, out, r, pr, acts);
     const bool keep = acts != nullptr;
-    Act a = act(c, keep ? "a0" : "p0", 1);
-    if (!a.d) return TMX_ENOMEM;
-    rc = embed(c, r, pr, a);
-    if (rc) return rc;
+    const ThinW *thin = c->pc->thin;
+    Act a{};
+    if (keep) {
+        // the embedded source is the first layer's input of the weight gradient
+        a = act(c, "a0", 1);
+        if (!a.d) return TMX_ENOMEM;
+        rc = embed(c, r, pr, a);
+        if (rc) return rc;
+    }
     for (int i = 0; i < NN_L; ++i) {
         const int l = dagger ? NN_L - 1 - i : i;
         const int cin = dagger ? NN_COUT[l] : NN_CIN[l];
         const int cout = dagger ? NN_CIN[l] : NN_COUT[l];
         const uint16_t *W = dagger ? c->pc->Wa[l] : c->pc->Wf[l];
         if (acts) acts->push_back(a);
-        if (cout == 1) return launch_layer(c, cin, cout, a, Act{}, out, W);
+        if (cout == 1) return launch_down(c, a, out, thin + (dagger ? THIN_DOWN_A : THIN_DOWN_F));
         Act b = act(c, (keep ? "a" : "p") + std::to_string(i + 1), cout);
         if (!b.d) return TMX_ENOMEM;
-        rc = launch_layer(c, cin, cout, a, b, SpinorPtr{}, W);
+        rc = cin == 1 ? launch_up(c, r, pr, b, thin + (dagger ? THIN_UP_A : THIN_UP_F))
+                      : launch_layer(c, cin, cout, a, b, SpinorPtr{}, W);
         if (rc) return rc;
         a = b;
     }
@@ -912,7 +1258,7 @@ int nn_forward(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, int dagger, std::
 
 }  // namespace
 
-// z = K r (dagger = 0) or K^dagger r (dagger = 1): odd fields r (precision
+// z = K r (dagger = 0), K^dagger r (dagger = 1) or P r (dagger = 2): odd fields r (precision
 // pr, stride Vh) and z (precision pz: F64 or F32)
 int pc_apply_internal(tmx_ctx *c, SpinorPtr z, int pz, SpinorPtr r, int pr, int dagger)
 {
@@ -1216,6 +1562,7 @@ void tmx_pc_free(tmx_ctx *c)
     }
     dev_free(c, s.lrow);
     dev_free(c, s.lcol);
+    dev_free(c, s.thin);
     delete c->pc;
     c->pc = nullptr;
 }
@@ -1265,7 +1612,7 @@ int tmx_pc_apply(tmx_ctx *c, double *out, const double *in, int dagger)
     SpinorPtr I = make_spinor(pi, F32, 1, Vh), O = make_spinor(po, F32, 1, Vh);
     int r = hip_err(c, launch_pack_spinor(in, I, F32, TMX_FIELD_ODD, c->g, 1, c->stream), "pack");
     if (r) return r;
-    r = pc_apply_internal(c, O, F32, I, F32, dagger ? 1 : 0);
+    r = pc_apply_internal(c, O, F32, I, F32, dagger == 2 ? 2 : (dagger ? 1 : 0));
     if (r) return r;
     r = hip_err(c, launch_unpack_spinor(out, O, F32, TMX_FIELD_ODD, c->g, 1, c->stream), "unpack");
     if (r) return r;
@@ -1312,9 +1659,12 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
         void *pd = ws_get(c, "tr_dl", spinor_field_bytes(F32, 1, Vh));
         if (!pz || !pd) return TMX_ENOMEM;
         const SpinorPtr Z = make_spinor(pz, F32, 1, Vh), DL = make_spinor(pd, F32, 1, Vh);
-        r = nn_forward(c, Z, B, F32, 0, &acts);
+        const bool sym = loss_kind == TMX_LOSS_SYM;
+        r = nn_forward(c, Z, B, F32, sym ? 2 : 0, &acts);
         if (r) return r;
         // DL = dLoss / d(K b) (odd field), then as the one-channel output adjoint
+        // (the energy loss of P = A^dagger A is the residual loss's formula
+        // with P b in place of K b and pairs x = N^{-1} b)
         if (loss_kind == TMX_LOSS_SOLUTION) {
             // (K b - x) / (|x|^2 n)
             OpPairResidual<F32> pr{};
@@ -1364,6 +1714,22 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
         if (!delta.d) return TMX_ENOMEM;
         r = embed(c, DL, F32, delta);
         if (r) return r;
+        if (sym) {
+            // P = L_1^dagger L_2^dagger L_2 L_1, inputs a0 .. a3.  A layer used as
+            // its adjoint (input x, output adjoint d) takes the gradient of its
+            // forward use on d with output adjoint x.
+            Act d3 = act(c, "d3", 8), d2 = act(c, "d2", 8), d1 = act(c, "d1", 8);
+            if (!d3.d || !d2.d || !d1.d) return TMX_ENOMEM;
+            r = launch_wgrad(c, 1, 8, delta, acts[3], partial[0]);                     // L_1^dagger
+            if (!r) r = launch_layer(c, 1, 8, delta, d3, SpinorPtr{}, s.Wf[0]);
+            if (!r) r = launch_wgrad(c, 8, 8, d3, acts[2], partial[1]);                // L_2^dagger
+            if (!r) r = launch_layer(c, 8, 8, d3, d2, SpinorPtr{}, s.Wf[1]);
+            if (!r) r = launch_wgrad(c, 8, 8, acts[1], d2, partial[1]);                // L_2
+            if (!r) r = launch_layer(c, 8, 8, d2, d1, SpinorPtr{}, s.Wa[1]);
+            if (!r) r = launch_wgrad(c, 1, 8, acts[0], d1, partial[0]);                // L_1
+            if (r) return r;
+            continue;
+        }
         // backward through the layers
         for (int l = NN_L - 1; l >= 0; --l) {
             r = launch_wgrad(c, NN_CIN[l], NN_COUT[l], acts[l], delta, partial[l]);
@@ -1398,6 +1764,7 @@ int tmx_pc_loss_grad(tmx_ctx *c, const double *b, const double *x, int npairs, i
                      float *host_grad)
 {
     if (!c || !b || !x || npairs < 1 || !loss) return TMX_EINVAL;
+    if (loss_kind < TMX_LOSS_RESIDUAL || loss_kind > TMX_LOSS_SYM) return set_err(c, TMX_EINVAL, "unknown loss kind");
     if (op != TMX_OP_PLUS && op != TMX_OP_MINUS)
         return set_err(c, TMX_EINVAL, "the network is trained for Mhat(+mu) or Mhat(-mu)");
     int r = nn_ensure(c);
@@ -1466,6 +1833,8 @@ int tmx_pc_adam_step(tmx_ctx *c, const float *host_grad, size_t n, const tmx_tra
 int tmx_pc_train(tmx_ctx *c, const double *b, const double *x, int npairs, const tmx_train_cfg *cfg, float *loss_out)
 {
     if (!c || !b || !x || npairs < 1 || !cfg || cfg->epochs < 1 || cfg->batch < 1) return TMX_EINVAL;
+    if (cfg->loss_kind < TMX_LOSS_RESIDUAL || cfg->loss_kind > TMX_LOSS_SYM)
+        return set_err(c, TMX_EINVAL, "unknown loss kind");
     const int op = cfg->op == 0 ? TMX_OP_PLUS : cfg->op;
     if (op != TMX_OP_PLUS && op != TMX_OP_MINUS)
         return set_err(c, TMX_EINVAL, "the network is trained for Mhat(+mu) or Mhat(-mu)");

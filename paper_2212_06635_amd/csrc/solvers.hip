@@ -356,9 +356,11 @@ template <int P> struct OpPcgDots {
     }
 };
 
+// z = P r: K K^dagger r, or the network's Hermitian form (one application)
 template <int P>
-static int pcg_apply_pc(Sys &S, SpinorPtr z, SpinorPtr r, SpinorPtr tmp)
+static int pcg_apply_pc(Sys &S, SpinorPtr z, SpinorPtr r, SpinorPtr tmp, bool sym)
 {
+    if (sym) return pc_apply_internal(S.c, z, F32, r, P, 2);
     int rc = pc_apply_internal(S.c, tmp, F32, r, P, 1);  // K^dagger r
     if (rc) return rc;
     return pc_apply_internal(S.c, z, F32, tmp, F32, 0);  // K K^dagger r
@@ -368,6 +370,7 @@ template <int P>
 static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const double *sigma, const tmx_solver_cfg &cfg,
                        bool x_is_guess, tmx_info *info)
 {
+    const bool sym = cfg.kind == TMX_SOLVER_PCG_NN_SYM;
     tmx_ctx *c = S.c;
     const double tol = cfg.tol > 0 ? cfg.tol : 1e-10;
     const int maxiter = cfg.maxiter > 0 ? cfg.maxiter : 10000;
@@ -385,7 +388,7 @@ static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const double *sigma, co
     }
     TRY(true_residual<P>(S, r, rl, true, b, x, sigma, 1, &rr));
     TRY(zero_field<F32>(S, xl, 1));
-    TRY(pcg_apply_pc<P>(S, z, rl, tz));
+    TRY(pcg_apply_pc<P>(S, z, rl, tz, sym));
     {
         OpPcgDots<P> d{};
         d.r = rl;
@@ -431,7 +434,7 @@ static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const double *sigma, co
             after_reliable = true;
             if (std::sqrt(rr) <= tol * std::sqrt(bb)) break;
         }
-        TRY(pcg_apply_pc<P>(S, z, rl, tz));
+        TRY(pcg_apply_pc<P>(S, z, rl, tz, sym));
         ++npc;
         OpPcgDots<P> d{};
         d.r = rl;
@@ -635,6 +638,7 @@ int tmx_solve(tmx_ctx *c, double *x, const double *b, int nrhs, const tmx_solver
         rc = dispatch_cg(S, F16, X, B, nrhs, nullptr, *cfg, cfg->use_initial_guess != 0, info);
         break;
     case TMX_SOLVER_PCG_NN:
+    case TMX_SOLVER_PCG_NN_SYM:
         if (nrhs != 1) return set_err(c, TMX_EINVAL, "the preconditioned CG solves one right-hand side at a time");
         if (cfg->op != TMX_OP_PLUS && cfg->op != TMX_OP_MINUS)
             return set_err(c, TMX_EINVAL, "the learned preconditioner is built for the degenerate Schur operator");
@@ -691,7 +695,8 @@ static int multishift_run(tmx_ctx *c, Sys &S, SpinorPtr B, const double *shifts,
     const double tol = cfg->tol > 0 ? cfg->tol : 1e-10;
     const double inner = cfg->inner_tol > 0 ? cfg->inner_tol : (prec == TMX_F16 ? 5e-4 : (prec == TMX_F32 ? 1e-6 : tol));
     const int maxiter = cfg->maxiter > 0 ? cfg->maxiter : 10000;
-    if (cfg->kind == TMX_SOLVER_PCG_NN) {
+    const bool pcg_nn = cfg->kind == TMX_SOLVER_PCG_NN || cfg->kind == TMX_SOLVER_PCG_NN_SYM;
+    if (pcg_nn) {
         if (cfg->op != TMX_OP_PLUS && cfg->op != TMX_OP_MINUS)
             return set_err(c, TMX_EINVAL, "the learned preconditioner is built for the degenerate Schur operator");
         TRY(ensure_ready(c, F32, false));  // the network runs on the FP32 links
@@ -727,7 +732,7 @@ static int multishift_run(tmx_ctx *c, Sys &S, SpinorPtr B, const double *shifts,
         S.gbytes = 0;
         const double sk = shifts[k];
         int rk;
-        if (cfg->kind == TMX_SOLVER_PCG_NN) {
+        if (pcg_nn) {
             rk = prec == F16 ? pcg_nn_core<F16>(S, X, B, &sk, rc_cfg, true, &inf)
                              : pcg_nn_core<F32>(S, X, B, &sk, rc_cfg, true, &inf);
             if (rk == TMX_ENOCONV && std::isfinite(inf.true_residual)) {

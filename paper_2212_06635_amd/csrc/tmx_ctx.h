@@ -42,10 +42,15 @@ struct KStat {
     double ms = 0;
 };
 
-// launch shape of a stencil kernel (chosen by the autotuner)
+// launch shape of a stencil kernel (chosen by the autotuner): workgroup
+// size, XCD-contiguous block order, sites per thread, and for several
+// right-hand sides the group size rg (the operator runs K1 then K2 on each
+// group of rg right-hand sides in turn; 0 = all at once)
 struct LaunchCfg {
     int block = 64;
     int xcd = 1;
+    int spt = 1;
+    int rg = 0;
 };
 
 // learned-preconditioner state (nn.hip)

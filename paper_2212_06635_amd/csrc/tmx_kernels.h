@@ -27,6 +27,8 @@ struct DslashArgs {
     int xcd;           // XCD-aware block order
     double *nrm;       // MODE_DIAG, if set: |out|^2 of every slot (FP64), for <p, N p> = |Mhat p|^2
     double rho;        // MODE_DIAG, one flavour: adds i rho x to the final output (after g5out)
+    int r0, rg;        // right-hand sides r0 .. r0 + rg - 1 of the nrhs per site (rg = 0: all)
+    int spt;           // sites (slots) per thread: 1, or a grid-stride loop over spt of them
 };
 
 hipError_t launch_dslash(int prec, int nf, int mode, const DslashArgs &a, hipStream_t st, int block);

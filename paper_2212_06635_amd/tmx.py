@@ -24,6 +24,8 @@ TMX_F64, TMX_F32, TMX_F16 = 0, 1, 2
 TMX_OP_PLUS, TMX_OP_MINUS, TMX_OP_ND, TMX_OP_WPLUS, TMX_OP_WMINUS = 1, -1, 2, 3, -3
 TMX_FIELD_ODD, TMX_FIELD_ODD_ND, TMX_FIELD_FULL, TMX_FIELD_FULL_ND = 0, 1, 2, 3
 TMX_SOLVER_CG, TMX_SOLVER_MPCG_F32, TMX_SOLVER_MPCG_F16, TMX_SOLVER_FGCR_NN, TMX_SOLVER_PCG_NN = 0, 1, 2, 3, 4
+TMX_SOLVER_PCG_NN_SYM = 5
+TMX_LOSS_RESIDUAL, TMX_LOSS_SOLUTION, TMX_LOSS_SYM = 0, 1, 2
 
 PREC = {"f64": TMX_F64, "f32": TMX_F32, "f16": TMX_F16}
 
@@ -111,7 +113,8 @@ def _load():
         "tmx_pc_adam_step": ([P, P, Z, ctypes.POINTER(tmx_train_cfg)], I),
         "tmx_pc_loss_grad": ([P, P, P, I, I, I, ctypes.POINTER(D), P], I),
         "tmx_tune": ([P, I, I, I], I),
-        "tmx_tuned_config": ([P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(I)], I),
+        "tmx_tuned_config": ([P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
+                              ctypes.POINTER(I)], I),
         "tmx_kstats_enable": ([P, I], I),
         "tmx_kstats_get": ([P, I, ctypes.c_char_p, Z, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(D)], I),
         "tmx_trace_enable": ([P, I], I),
@@ -424,9 +427,10 @@ class Context:
         return self.check(lib.tmx_tune(self.h, prec, op, nrhs))
 
     def tuned_config(self, key):
-        b, x = ctypes.c_int(), ctypes.c_int()
-        rc = lib.tmx_tuned_config(self.h, key.encode(), ctypes.byref(b), ctypes.byref(x))
-        return {"block": b.value, "xcd": x.value, "tuned": rc == TMX_OK}
+        b, x, s, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        rc = lib.tmx_tuned_config(self.h, key.encode(), ctypes.byref(b), ctypes.byref(x), ctypes.byref(s),
+                                  ctypes.byref(g))
+        return {"block": b.value, "xcd": x.value, "spt": s.value, "rg": g.value, "tuned": rc == TMX_OK}
 
     # -- kernel timing --------------------------------------------------------
     def kstats_enable(self, on=True):
