@@ -182,7 +182,8 @@ def network(d: str, v: int) -> str:
         "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/p_f -o f -- python3 <repo>/bench.py --mode nn",
         "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/p_w -o w -- python3 <repo>/bench.py --mode nn",
         "#   python3 -m paper_2212_06635_amd.counters network <dir> <this file>",
-        "# bench.py --mode nn: 5 applications of K (layers 1->8, 8->8, 8->8, 8->1) on the 32^3x64 field,",
+        "# bench.py --mode nn: 5 applications of K (layers 1->8, 8->8, 8->8, 8->1) on the 32^3x64 field",
+        "#   (the one-channel layers 1->8 and 8->1 on the vector ALUs, the 8->8 layers on the matrix cores),",
         "#   then 3 device copies of a 2 GiB buffer (counter calibration)",
         f"# FETCH scale {sf:.3f}, WRITE scale {sw:.3f}; matrix-core work: 2 x 64 x 64 x 27 flops per site",
         "#   for the 8->8 layer (9 paths x 3 colours of a real 64 x 64 product)",
@@ -190,9 +191,15 @@ def network(d: str, v: int) -> str:
         f"{'kernel':10s} {'calls':>5s} {'avg_us':>8s} {'fetch_MB':>9s} {'write_MB':>9s} {'GB/s':>7s} {'TFLOP/s':>8s}",
     ]
     for name, (calls, avg) in sorted(st.items()):
-        if "nn_layer_kernel" not in name:
+        if "nn_layer_kernel" in name:
+            tag = name[name.index("<") + 1:name.index(">")].replace(", ", "x")
+        elif "nn_up_kernel" in name:
+            # one-channel layer on the vector ALUs (forward 1->8, adjoint of 8->1), per source precision
+            tag = "1x8" + ("_" + name[name.index("<") + 1:name.index(">")].split("::")[-1] if "<" in name else "")
+        elif "nn_down_kernel" in name:
+            tag = "8x1"     # forward 8->1, adjoint of 1->8
+        else:
             continue
-        tag = name[name.index("<") + 1:name.index(">")].replace(", ", "x")
         fe = f.get(name, 0.0) * 1024 * sf
         wr = w.get(name, 0.0) * 1024 * sw
         tf = 2 * 64 * 64 * 27 * v / (avg * 1e-9) / 1e12 if tag == "8x8" else float("nan")

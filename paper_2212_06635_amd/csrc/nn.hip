@@ -14,11 +14,12 @@
 //     Y[m][n] = sum_d W_d[m][k] Z_d[k][n]
 // m = (out channel, spin, re/im), k = (in channel, spin, re/im),
 // n = (site, colour); W_d = C_d (x) Gamma_d written as a real matrix, Z_d the
-// transported input.  Activations and links are BF16, the transports run on
-// the vector ALUs as BF16 dot2 steps with FP32 accumulation, the contraction
-// on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  The
+// transported input.  Activations and links are BF16; the transports run on
+// the matrix cores as 4x4x4 blocks (v_mfma_f32_4x4x4_16b_bf16), the
+// contraction on v_mfma_f32_16x16x32_bf16, both with FP32 accumulation.  The
 // adjoint layer is the same kernel with W'_d = W_{-d}^H (transport and
-// weights commute).
+// weights commute).  The layers with one input or one output channel run in
+// factorised form on the vector ALUs (further below).
 //
 // The input is supported on odd sites and only the odd sites of the output
 // are kept, so the first layer skips zero inputs and the last layer computes
@@ -810,13 +811,18 @@ template <int P>
 __global__ void __launch_bounds__(256) nn_up_kernel(Geom g, SpinorPtr src, Act y, NnLinks L, const ThinW *W,
                                                     int t_bc, int xcd)
 {
+    __shared__ __attribute__((aligned(16))) uint32_t ys[8 * 64 * 12];  // [channel][site][12 words]
     const long tile = xcd_block(xcd);
     const int p = (int)(tile & 1);
-    const long s = (tile >> 1) * 64 + threadIdx.x / 4;
-    const int q = threadIdx.x % 4;
-    if (s >= g.Vh) return;
+    const long s0 = (tile >> 1) * 64;
+    const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
+    const long s = s0 + sl;
+    // every lane runs the paths (the quad exchange needs all four lanes):
+    // lanes past the end compute the last site again, and their rows of the
+    // tile are never stored
+    const long sc = s < g.Vh ? s : g.Vh - 1;
     int x[4];
-    cb_coords(g, (int)s, p, x);
+    cb_coords(g, (int)sc, p, x);
     cx<float> acc[8][3];
 #pragma unroll
     for (int c = 0; c < 8; ++c)
@@ -825,16 +831,24 @@ __global__ void __launch_bounds__(256) nn_up_kernel(Geom g, SpinorPtr src, Act y
     // odd sites: the d = 0 path; even sites: the eight hops, unrolled so that
     // the loads of later paths are issued before the arithmetic of earlier ones
     if (p == 1)
-        up_paths<P, 0, 1>(g, src, L, W, t_bc, x, p, s, q, acc);
+        up_paths<P, 0, 1>(g, src, L, W, t_bc, x, p, sc, q, acc);
     else
-        up_paths<P, 1, NN_P>(g, src, L, W, t_bc, x, p, s, q, acc);
-    const long gs = (long)p * g.Vh + s;
+        up_paths<P, 1, NN_P>(g, src, L, W, t_bc, x, p, sc, q, acc);
+    // the tile's output through LDS, stored as whole 16-byte vectors
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        uint32_t *o = y.d + ((long)c * y.stride + gs) * 12 + 3 * q;
+        uint32_t *o = ys + (c * 64 + sl) * 12 + 3 * q;
         o[0] = f2bf2(acc[c][0].re, acc[c][0].im);
         o[1] = f2bf2(acc[c][1].re, acc[c][1].im);
         o[2] = f2bf2(acc[c][2].re, acc[c][2].im);
+    }
+    __syncthreads();
+    const long gs0 = (long)p * g.Vh + s0;
+    const uint4 *yv = reinterpret_cast<const uint4 *>(ys);
+    for (int v = threadIdx.x; v < 8 * 64 * 3; v += blockDim.x) {
+        const int c = v / (64 * 3), o = v % (64 * 3);
+        if (s0 + o / 3 >= g.Vh) continue;
+        reinterpret_cast<uint4 *>(y.d + ((long)c * y.stride + gs0) * 12)[o] = yv[v];
     }
 }
 

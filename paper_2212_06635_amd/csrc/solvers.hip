@@ -65,6 +65,7 @@ struct Sys {
         if (_r) return _r;       \
     } while (0)
 #define HTRY(x, w) TRY(hip_err(c, (x), w))
+#define HTRY_S(S, x, w) TRY(hip_err((S).c, (x), w))
 
 }  // namespace
 
@@ -356,12 +357,24 @@ template <int P> struct OpPcgDots {
     }
 };
 
-// z = P r: K K^dagger r, or the network's Hermitian form (one application)
+// z = P r: K K^dagger r, or the network's Hermitian form (one application).
+// An FP16 residual is widened to FP32 (rf) first: the network's first layer
+// reads single spins, which FP16's per-site blocks make costly.
 template <int P>
-static int pcg_apply_pc(Sys &S, SpinorPtr z, SpinorPtr r, SpinorPtr tmp, bool sym)
+static int pcg_apply_pc(Sys &S, SpinorPtr z, SpinorPtr r, SpinorPtr tmp, SpinorPtr rf, bool sym)
 {
-    if (sym) return pc_apply_internal(S.c, z, F32, r, P, 2);
-    int rc = pc_apply_internal(S.c, tmp, F32, r, P, 1);  // K^dagger r
+    int pr = P;
+    if constexpr (P == F16) {
+        OpCopy<F32, F16> cp{};
+        cp.d = rf;
+        cp.s = r;
+        cp.nf = 1;
+        HTRY_S(S, run_blas(cp, S.c->Vh, 1, S.c->red, S.c->stream), "widen residual");
+        r = rf;
+        pr = F32;
+    }
+    if (sym) return pc_apply_internal(S.c, z, F32, r, pr, 2);
+    int rc = pc_apply_internal(S.c, tmp, F32, r, pr, 1);  // K^dagger r
     if (rc) return rc;
     return pc_apply_internal(S.c, z, F32, tmp, F32, 0);  // K K^dagger r
 }
@@ -377,6 +390,7 @@ static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const double *sigma, co
     const double delta = cfg.delta > 0 ? cfg.delta : default_delta<P>();
     SpinorPtr r = S.field("r", F64, 1), rl = S.field("rl", P, 1), p = S.field("p", P, 1), q = S.field("q", P, 1);
     SpinorPtr xl = S.field("xl", F32, 1), z = S.field("z", F32, 1), tz = S.field("tz", F32, 1);
+    SpinorPtr rf = P == F16 ? S.field("rf", F32, 1) : SpinorPtr{};
     TRY(S.need());
     double bb, rr, rmax, rho, pq, dots[2];
     TRY((copy_field<F64, F64>(S, r, b, 1, &bb)));
@@ -388,7 +402,7 @@ static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const double *sigma, co
     }
     TRY(true_residual<P>(S, r, rl, true, b, x, sigma, 1, &rr));
     TRY(zero_field<F32>(S, xl, 1));
-    TRY(pcg_apply_pc<P>(S, z, rl, tz, sym));
+    TRY(pcg_apply_pc<P>(S, z, rl, tz, rf, sym));
     {
         OpPcgDots<P> d{};
         d.r = rl;
@@ -434,7 +448,7 @@ static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const double *sigma, co
             after_reliable = true;
             if (std::sqrt(rr) <= tol * std::sqrt(bb)) break;
         }
-        TRY(pcg_apply_pc<P>(S, z, rl, tz, sym));
+        TRY(pcg_apply_pc<P>(S, z, rl, tz, rf, sym));
         ++npc;
         OpPcgDots<P> d{};
         d.r = rl;
