@@ -656,15 +656,23 @@ template <int P> __global__ void nn_embed_kernel(SpinorPtr r, Act a, long Vh)
 // ---------------------------------------------------------------------------
 // A layer with one input or one output channel has, per path, a channel
 // vector C_d (8 entries) and the spin matrix Gamma_d, so it is applied in its
-// factorised form in FP32: 1 -> 8 transports the source, mixes the spins and
+// factorised form: 1 -> 8 transports the source, mixes the spins and
 // spreads the result over the channels; 8 -> 1 contracts the channels first,
 // then mixes the spins and transports (C_d, Gamma_d and T_d commute).  Four
-// lanes per site, lane q owning output spin q; the 8 -> 1 layer exchanges the
-// four channel-contracted spins of a site among its lanes (DPP within a quad).
-// The input of the first layer is read straight from the odd source field.
+// lanes per site, lane q owning output spin q; a site's four spins are
+// exchanged among its lanes (DPP within a quad).  The input of the first
+// layer is read straight from the odd source field.
+//
+// Every complex product runs as two BF16 dot products with FP32 accumulation
+// (v_dot2_f32_bf16): for a complex w and z given as the pair (z.re, z.im),
+//     Re(w z) = (w.re, -w.im) . z,   Im(w z) = (w.im, w.re) . z,
+// so the weights are stored in those two packed forms and an operand is
+// rounded to a BF16 pair once, where it is produced (the activations and
+// links are BF16 already).  Half the instructions of FP32 multiply-adds and
+// no BF16 -> FP32 conversions of links or activations.
 struct ThinW {
-    float2 C[NN_P][8];     // channel vector of path d
-    float2 G[NN_P][4][4];  // spin matrix of path d
+    uint32_t C[NN_P][8][2];     // channel vector of path d, packed (re, -im), (im, re)
+    uint32_t G[NN_P][4][4][2];  // spin matrix of path d, packed likewise
 };
 // the four ThinW sets: forward first layer (1 -> 8), forward last layer
 // (8 -> 1), and the adjoints of the last (1 -> 8) and of the first (8 -> 1)
@@ -680,40 +688,91 @@ __global__ void nn_build_thin_kernel(const float *p, ThinW *w, int cin, int cout
     const int per = cin * cout + 16;
     const float *pd = p + (size_t)dd * per * 2;
     const float sg = adjoint ? -1.f : 1.f;
-    for (int c = 0; c < 8; ++c) w->C[d][c] = make_float2(pd[2 * c], sg * pd[2 * c + 1]);
+    for (int c = 0; c < 8; ++c) {
+        const float re = pd[2 * c], im = sg * pd[2 * c + 1];
+        w->C[d][c][0] = f2bf2(re, -im);
+        w->C[d][c][1] = f2bf2(im, re);
+    }
     for (int a = 0; a < 4; ++a)
         for (int b = 0; b < 4; ++b) {
             const int e = adjoint ? b * 4 + a : a * 4 + b;
-            w->G[d][a][b] = make_float2(pd[2 * (cin * cout + e)], sg * pd[2 * (cin * cout + e) + 1]);
+            const float re = pd[2 * (cin * cout + e)], im = sg * pd[2 * (cin * cout + e) + 1];
+            w->G[d][a][b][0] = f2bf2(re, -im);
+            w->G[d][a][b][1] = f2bf2(im, re);
         }
 }
 
-__device__ __forceinline__ cx<float> bf2c(uint32_t w)
+// c + a.lo b.lo + a.hi b.hi over BF16 pairs, FP32 accumulation
+__device__ __forceinline__ float dot2bf(uint32_t a, uint32_t b, float c)
 {
-    return cx<float>{__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u)};
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, a), __builtin_bit_cast(bf16x2v, b), c, false);
 }
 
-// the 3x3 transport matrix of a path (bc U or bc U^dagger) from the BF16 row-major link
-__device__ __forceinline__ void path_matrix(const NnLinks &L, const Nbr &nb, int d, cx<float> m[9])
+// acc += w z, w a complex weight in its two packed forms, z a BF16 (re, im) pair
+__device__ __forceinline__ void cmac_bf(cx<float> &acc, uint32_t w0, uint32_t w1, uint32_t z)
+{
+    acc.re = dot2bf(w0, z, acc.re);
+    acc.im = dot2bf(w1, z, acc.im);
+}
+
+// t = bc U v (forward path) or bc U^dagger v (backward path) for the three
+// colours of one spin, U the BF16 row-major network link.  With u = U[r][k]
+// as the pair (u.re, u.im):
+//   (U v)_a = sum_b U[a][b] v_b:           Re = u . (v.re, -v.im), Im = u . (v.im, v.re)
+//   (U^dagger v)_a = sum_b conj(U[b][a]) v_b: Re = u . (v.re, v.im),  Im = u . (v.im, -v.re)
+__device__ __forceinline__ void transport_bf(const NnLinks &L, const Nbr &nb, int d, const cx<float> v[3],
+                                             cx<float> t[3])
 {
     const int mu = (d - 1) / 2;
+    const bool back = ((d - 1) % 2) == 1;
     const uint32_t *lr = L.row + ((long)(nb.lp * 4 + mu) * L.Vh + nb.lcb) * 9;
+    uint32_t u[9];
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+    for (int e = 0; e < 9; ++e) u[e] = lr[e];
+    uint32_t vr[3], vi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        vr[k] = back ? f2bf2(v[k].re, v[k].im) : f2bf2(v[k].re, -v[k].im);
+        vi[k] = back ? f2bf2(v[k].im, -v[k].re) : f2bf2(v[k].im, v[k].re);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float re = 0.f, im = 0.f;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const cx<float> u = bf2c(lr[3 * r + k]);
-            // U^dagger[r][k] = conj(U[k][r])
-            m[nb.dag ? 3 * k + r : 3 * r + k] = nb.dag ? cx<float>{nb.bc * u.re, -nb.bc * u.im}
-                                                       : cx<float>{nb.bc * u.re, nb.bc * u.im};
+            const uint32_t ue = u[back ? 3 * k + a : 3 * a + k];
+            re = dot2bf(ue, vr[k], re);
+            im = dot2bf(ue, vi[k], im);
         }
+        t[a] = cx<float>{nb.bc * re, nb.bc * im};
+    }
 }
 
 // value of lane q ^ M of this lane's quad (all four lanes active)
-template <int M> __device__ __forceinline__ float quad_xor(float v)
+template <int M> __device__ __forceinline__ uint32_t quad_xor(uint32_t v)
 {
     constexpr int ctrl = M == 1 ? 0xB1 : (M == 2 ? 0x4E : 0x1B);  // quad_perm [1,0,3,2] / [2,3,0,1] / [3,2,1,0]
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xF, 0xF, false);
+}
+
+// h = sum_m Gamma_d[q][q ^ m] z(spin q ^ m): z holds spin q of this lane as
+// BF16 pairs, spin q ^ m is held by lane q ^ m of the quad
+__device__ __forceinline__ void spin_mix(const ThinW *W, int d, int q, const uint32_t z[3], cx<float> h[3])
+{
+    uint32_t g0[4], g1[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        g0[m] = W->G[d][q][q ^ m][0];
+        g1[m] = W->G[d][q][q ^ m][1];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        h[a] = cx<float>{0.f, 0.f};
+        cmac_bf(h[a], g0[0], g1[0], z[a]);
+        cmac_bf(h[a], g0[1], g1[1], quad_xor<1>(z[a]));
+        cmac_bf(h[a], g0[2], g1[2], quad_xor<2>(z[a]));
+        cmac_bf(h[a], g0[3], g1[3], quad_xor<3>(z[a]));
+    }
 }
 
 // spin q (three colours) of the odd source at checkerboard index cb
@@ -767,39 +826,26 @@ __device__ __forceinline__ void up_paths(const Geom &g, const SpinorPtr &src, co
         const long ncb = d == 0 ? s : nb.idx - g.Vh;  // the odd site read
         cx<float> v[3];
         load_spin<P>(src, ncb, q, v);
-        cx<float> t[3];
+        uint32_t z[3];
         if (d == 0) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) t[a] = v[a];
+            for (int a = 0; a < 3; ++a) z[a] = f2bf2(v[a].re, v[a].im);
         } else {
-            cx<float> m[9];
-            path_matrix(L, nb, d, m);
+            cx<float> t[3];
+            transport_bf(L, nb, d, v, t);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                t[a] = cx<float>{0.f, 0.f};
-#pragma unroll
-                for (int b = 0; b < 3; ++b) cmac(t[a], m[3 * a + b], v[b]);
-            }
+            for (int a = 0; a < 3; ++a) z[a] = f2bf2(t[a].re, t[a].im);
         }
-        // h = sum_m Gamma_d[q][q ^ m] t(spin q ^ m), spin q ^ m held by lane q ^ m
-        const float2 g0 = W->G[d][q][q], g1 = W->G[d][q][q ^ 1], g2 = W->G[d][q][q ^ 2], g3 = W->G[d][q][q ^ 3];
         cx<float> h[3];
+        spin_mix(W, d, q, z, h);
+        uint32_t hb[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const cx<float> t1{quad_xor<1>(t[a].re), quad_xor<1>(t[a].im)};
-            const cx<float> t2{quad_xor<2>(t[a].re), quad_xor<2>(t[a].im)};
-            const cx<float> t3{quad_xor<3>(t[a].re), quad_xor<3>(t[a].im)};
-            h[a] = cx<float>{g0.x, g0.y} * t[a];
-            cmac(h[a], cx<float>{g1.x, g1.y}, t1);
-            cmac(h[a], cx<float>{g2.x, g2.y}, t2);
-            cmac(h[a], cx<float>{g3.x, g3.y}, t3);
-        }
+        for (int a = 0; a < 3; ++a) hb[a] = f2bf2(h[a].re, h[a].im);
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            const float2 cc = W->C[d][c];
-            const cx<float> cv{cc.x, cc.y};
+            const uint32_t c0 = W->C[d][c][0], c1 = W->C[d][c][1];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) cmac(acc[c][a], cv, h[a]);
+            for (int a = 0; a < 3; ++a) cmac_bf(acc[c][a], c0, c1, hb[a]);
         }
     }
 }
@@ -871,7 +917,7 @@ __global__ void __launch_bounds__(256) nn_down_kernel(Geom g, Act xin, SpinorPtr
     for (int a = 0; a < 3; ++a) acc[a] = cx<float>{0.f, 0.f};
 #pragma unroll
     for (int d = 0; d < NN_P; ++d) {
-        // channel contraction of spin q at the neighbour
+        // channel contraction of spin q at the neighbour (BF16 activations as they are stored)
         cx<float> w[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) w[a] = cx<float>{0.f, 0.f};
@@ -881,39 +927,27 @@ __global__ void __launch_bounds__(256) nn_down_kernel(Geom g, Act xin, SpinorPtr
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 const uint32_t *src = xin.d + ((long)c * xin.stride + nb.idx) * 12 + 3 * q;
-                const float2 cc = W->C[d][c];
-                const cx<float> cv{cc.x, cc.y};
-                const uint32_t w0 = src[0], w1 = src[1], w2 = src[2];
-                cmac(w[0], cv, bf2c(w0));
-                cmac(w[1], cv, bf2c(w1));
-                cmac(w[2], cv, bf2c(w2));
+                const uint32_t c0 = W->C[d][c][0], c1 = W->C[d][c][1];
+                const uint32_t z0 = src[0], z1 = src[1], z2 = src[2];
+                cmac_bf(w[0], c0, c1, z0);
+                cmac_bf(w[1], c0, c1, z1);
+                cmac_bf(w[2], c0, c1, z2);
             }
         }
-        // spin q ^ m of the site is held by lane q ^ m of its quad:
-        // h = sum_m Gamma_d[q][q ^ m] w(spin q ^ m)
-        const float2 g0 = W->G[d][q][q], g1 = W->G[d][q][q ^ 1], g2 = W->G[d][q][q ^ 2], g3 = W->G[d][q][q ^ 3];
-        cx<float> h[3];
+        uint32_t wb[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const cx<float> w1{quad_xor<1>(w[a].re), quad_xor<1>(w[a].im)};
-            const cx<float> w2{quad_xor<2>(w[a].re), quad_xor<2>(w[a].im)};
-            const cx<float> w3{quad_xor<3>(w[a].re), quad_xor<3>(w[a].im)};
-            h[a] = cx<float>{g0.x, g0.y} * w[a];
-            cmac(h[a], cx<float>{g1.x, g1.y}, w1);
-            cmac(h[a], cx<float>{g2.x, g2.y}, w2);
-            cmac(h[a], cx<float>{g3.x, g3.y}, w3);
-        }
+        for (int a = 0; a < 3; ++a) wb[a] = f2bf2(w[a].re, w[a].im);
+        cx<float> h[3];
+        spin_mix(W, d, q, wb, h);
         if (!valid) continue;
         if (d == 0) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) acc[a] = acc[a] + h[a];
         } else {
-            cx<float> m[9];
-            path_matrix(L, nb, d, m);
+            cx<float> t[3];
+            transport_bf(L, nb, d, h, t);
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) cmac(acc[a], m[3 * a + b], h[b]);
+            for (int a = 0; a < 3; ++a) acc[a] = acc[a] + t[a];
         }
     }
     // [site][spin q][colour][re, im] in LDS, then 16-byte vectors: vector kv of
