@@ -602,9 +602,10 @@ def main():
     ctx.kstats_enable(False)
     if "CLOVER_FORCE" in cks:
         n, ms_tot = cks["CLOVER_FORCE"]
-        cbytes = 3072.0 * 2 * Vh  # a, b (384 B) + H written and read (2 x 864 B) + 4 links (384 B) + 4 outputs (576 B)
+        # a, b (384 B) + Hermitian insertions written and read (2 x 6 x 72 B) + 4 links (384 B) + 4 outputs (576 B)
+        cbytes = 2208.0 * 2 * Vh
         out["clover_force_f64"] = {"kernel_ms": round(ms_tot / n, 4),
-                                   "GBps": round(cbytes / (ms_tot / n * 1e-3) / 1e9, 1), "bytes_per_site": 3072}
+                                   "GBps": round(cbytes / (ms_tot / n * 1e-3) / 1e9, 1), "bytes_per_site": 2208}
     del fbuf
     if dims == (32, 32, 32, 64):
         log("learned preconditioner on a 24^3x48 field")

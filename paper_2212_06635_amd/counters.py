@@ -178,17 +178,18 @@ def network(d: str, v: int) -> str:
     lines = [
         f"# learned-preconditioner layer kernels, V = {v} sites, MI355X",
         "# commands (from /tmp, TMPDIR=/tmp; <repo> = repository root):",
-        "#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/p_k -o k -- python3 <repo>/bench.py --mode nn",
-        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/p_f -o f -- python3 <repo>/bench.py --mode nn",
-        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/p_w -o w -- python3 <repo>/bench.py --mode nn",
+        "#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/p_k -o k -- python3 <repo>/bench.py --mode nn --no-tune",
+        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/p_f -o f -- python3 <repo>/bench.py --mode nn --no-tune",
+        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/p_w -o w -- python3 <repo>/bench.py --mode nn --no-tune",
         "#   python3 -m paper_2212_06635_amd.counters network <dir> <this file>",
         "# bench.py --mode nn: 5 applications of K (layers 1->8, 8->8, 8->8, 8->1) on the 32^3x64 field",
         "#   (the one-channel layers 1->8 and 8->1 on the vector ALUs, the 8->8 layers on the matrix cores),",
         "#   then 3 device copies of a 2 GiB buffer (counter calibration)",
-        f"# FETCH scale {sf:.3f}, WRITE scale {sw:.3f}; matrix-core work: 2 x 64 x 64 x 27 flops per site",
-        "#   for the 8->8 layer (9 paths x 3 colours of a real 64 x 64 product)",
+        f"# FETCH scale {sf:.3f}, WRITE scale {sw:.3f}; 8->8 layer work per site: dense 2 x 64 x 64 x 27 flops",
+        "#   (9 paths x 3 colours of the real 64 x 64 Kronecker product the matrix cores run, TF_dense) and the",
+        "#   method's factorised count 82944 flops (C_d (x) Gamma_d applied as two small products, TF_method)",
         "",
-        f"{'kernel':10s} {'calls':>5s} {'avg_us':>8s} {'fetch_MB':>9s} {'write_MB':>9s} {'GB/s':>7s} {'TFLOP/s':>8s}",
+        f"{'kernel':10s} {'calls':>5s} {'avg_us':>8s} {'fetch_MB':>9s} {'write_MB':>9s} {'GB/s':>7s} {'TF_dense':>8s} {'TF_method':>9s}",
     ]
     for name, (calls, avg) in sorted(st.items()):
         if "nn_layer_kernel" in name:
@@ -203,16 +204,17 @@ def network(d: str, v: int) -> str:
         fe = f.get(name, 0.0) * 1024 * sf
         wr = w.get(name, 0.0) * 1024 * sw
         tf = 2 * 64 * 64 * 27 * v / (avg * 1e-9) / 1e12 if tag == "8x8" else float("nan")
+        tm = 82944 * v / (avg * 1e-9) / 1e12 if tag == "8x8" else float("nan")
         lines.append(f"NN_{tag:7s} {calls:5d} {avg / 1e3:8.1f} {fe / 1e6:9.1f} {wr / 1e6:9.1f} "
-                     f"{(fe + wr) / (avg * 1e-9) / 1e9:7.1f} {tf:8.1f}")
+                     f"{(fe + wr) / (avg * 1e-9) / 1e9:7.1f} {tf:8.1f} {tm:9.1f}")
     return "\n".join(lines) + "\n"
 
 
 # force kernels: (kernel-name fragment, label, model bytes per site, read, write)
 FORCE_KERNELS = (
     ("hop_force_kernel", "HOP_FORCE", 1344, 768, 576),          # a, b 2 x 192, 4 links x 96 | 4 outputs x 144
-    ("clover_insertion_kernel", "CLOV_INSERT", 1248, 384, 864),  # a, b | 6 planes x 144
-    ("clover_force_kernel", "CLOV_LINKS", 1824, 1248, 576),     # 6 planes x 144, 4 links x 96 | 4 outputs x 144
+    ("clover_insertion_kernel", "CLOV_INSERT", 816, 384, 432),   # a, b | 6 Hermitian planes x 72
+    ("clover_force_kernel", "CLOV_LINKS", 1392, 816, 576),      # 6 planes x 72, 4 links x 96 | 4 outputs x 144
 )
 
 
@@ -228,9 +230,9 @@ def force(d: str, v: int) -> str:
         f"# fermion-force kernels (hopping term; clover term = insertions + link sums), V = {v} sites "
         "(all 4V links), MI355X",
         "# commands (from /tmp, TMPDIR=/tmp; <repo> = repository root):",
-        "#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/p_k -o k -- python3 <repo>/bench.py --mode force",
-        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/p_f -o f -- python3 <repo>/bench.py --mode force",
-        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/p_w -o w -- python3 <repo>/bench.py --mode force",
+        "#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/p_k -o k -- python3 <repo>/bench.py --mode force --no-tune",
+        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/p_f -o f -- python3 <repo>/bench.py --mode force --no-tune",
+        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/p_w -o w -- python3 <repo>/bench.py --mode force --no-tune",
         "#   python3 -m paper_2212_06635_amd.counters force <dir> <this file>",
         "# bench.py --mode force: 10 hopping-force and 10 clover-force calls on the 32^3x64 field, "
         "then 3 device copies of 2 GiB",

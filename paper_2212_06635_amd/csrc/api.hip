@@ -1035,7 +1035,7 @@ static int clover_force_fields(tmx_ctx *c, double *force, const ForceFields &ff,
 {
     if (c->clover_from_host)
         return set_err(c, TMX_EINVAL, "the clover force needs the clover term built from the links");
-    void *ph = ws_get(c, "cf_h", (size_t)6 * 9 * 2 * c->Vh * sizeof(double2));
+    void *ph = ws_get(c, "cf_h", (size_t)6 * 9 * 2 * c->Vh * sizeof(double));
     if (!ph) return set_err(c, TMX_ENOMEM, "clover force workspace: out of device memory");
     CloverForceArgs f{};
     f.g = c->g;
@@ -1044,7 +1044,7 @@ static int clover_force_fields(tmx_ctx *c, double *force, const ForceFields &ff,
     f.kc8 = c->par.kappa * c->par.csw / 8.0;
     f.coeff = coeff;
     f.accumulate = accumulate ? 1 : 0;
-    f.H = static_cast<double2 *>(ph);
+    f.H = static_cast<double *>(ph);
     f.out = force;
     f.xcd = c->xcd_remap;
     kstat_begin(c, "CLOVER_FORCE");

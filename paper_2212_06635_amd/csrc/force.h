@@ -9,7 +9,8 @@ namespace tmx {
 // (+ out if accumulate), the link derivative of Re<Y, Mhat X> through the
 // clover term of both parities (hopping matrices fixed).  X, Y odd,
 // u = K1(s) X, w = K1(-s, g5 in) Y even, all FP64.  H is the insertion
-// workspace: 6 planes x 9 entries x 2 Vh double2, site index p Vh + s.
+// workspace: 6 planes x 9 reals (the Hermitian matrix: diagonal, then the
+// upper triangle as (re, im)) x 2 Vh doubles, site index p Vh + s.
 struct CloverForceArgs {
     Geom g;
     LinkPtr U;
@@ -18,7 +19,7 @@ struct CloverForceArgs {
     double kc8;   // kappa csw / 8
     double coeff;
     int accumulate;
-    double2 *H;
+    double *H;
     int h_acc;  // insertions: add to H (the next flavour of a two-flavour field) instead of writing it
     double *out;
     int xcd;  // XCD-contiguous workgroup order of the link sums

@@ -279,18 +279,34 @@ __device__ __forceinline__ Mat3 link(const CloverForceArgs &f, const int x[4], i
     return u;
 }
 
+// Insertions are Hermitian, so a plane stores nine reals per site, each
+// component an array of 2 Vh doubles (site index p Vh + s): the diagonal
+// H00, H11, H22, then (re, im) of H01, H02, H12.
+__device__ __forceinline__ int herm_component(int i, int j)  // first real of entry (i, j), i <= j
+{
+    return i == j ? i : 3 + 2 * (i + j - 1);
+}
+
 // H_r,n at site x (r != n): the stored plane, negated for r > n
 __device__ __forceinline__ Mat3 insertion(const CloverForceArgs &f, const int x[4], int r, int n)
 {
     const long V2 = 2L * f.g.Vh;
     const long site = (long)((x[0] + x[1] + x[2] + x[3]) & 1) * f.g.Vh + cb_index(f.g, x);
-    const double2 *h = f.H + (long)plane_of(r < n ? r : n, r < n ? n : r) * 9 * V2 + site;
+    const double *h = f.H + (long)plane_of(r < n ? r : n, r < n ? n : r) * 9 * V2 + site;
     const double sg = r < n ? 1.0 : -1.0;
+    double v[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k] = sg * h[k * V2];
     Mat3 m;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const double2 v = h[k * V2];
-        m.m[k] = cd{sg * v.x, sg * v.y};
+    for (int i = 0; i < 3; ++i) {
+        m.m[4 * i] = cd{v[i], 0.0};
+#pragma unroll
+        for (int j = i + 1; j < 3; ++j) {
+            const int c = herm_component(i, j);
+            m.m[3 * i + j] = cd{v[c], v[c + 1]};
+            m.m[3 * j + i] = cd{v[c], -v[c + 1]};
+        }
     }
     return m;
 }
@@ -311,24 +327,28 @@ __device__ __forceinline__ void pauli_entry(const cd a[12], const cd b[12], int 
 }
 
 template <bool HACC>
-__device__ __forceinline__ void put_insertion(const CloverForceArgs &f, int plane, long site, int k, cd v)
+__device__ __forceinline__ void put_real(const CloverForceArgs &f, int plane, long site, int k, double v)
 {
     const long V2 = 2L * f.g.Vh;
-    double2 *h = f.H + ((long)plane * 9 + k) * V2 + site;
-    double2 o = make_double2(v.re, v.im);
-    if constexpr (HACC) {  // the next flavour of a two-flavour field adds its part
-        const double2 old = *h;
-        o.x += old.x;
-        o.y += old.y;
-    }
-    *h = o;
+    double *h = f.H + ((long)plane * 9 + k) * V2 + site;
+    if constexpr (HACC) v += *h;  // the next flavour of a two-flavour field adds its part
+    *h = v;
+}
+
+// entry (i, j), i <= j, of the Hermitian insertion of a plane (the diagonal is real)
+template <bool HACC>
+__device__ __forceinline__ void put_insertion(const CloverForceArgs &f, int plane, long site, int i, int j, cd v)
+{
+    const int c = herm_component(i, j);
+    put_real<HACC>(f, plane, site, c, v.re);
+    if (i != j) put_real<HACC>(f, plane, site, c + 1, v.im);
 }
 
 // sigma_kl = -eps_klm diag(s_m, s_m), sigma_k4 = diag(s_k, -s_k): the
 // spatial plane opposite m takes G = -eps (P_m^0 + P_m^1), the (m, t) plane
 // G = P_m^0 - P_m^1, and H = c (G + G^dagger).  One unordered colour pair
-// (i, j) at a time, all six planes from its products (H_ji = conj(H_ij)), so
-// that only the site's two spinors stay live.
+// (i, j) at a time, all six planes from its products (H_ji = conj(H_ij) is
+// not stored), so that only the site's two spinors stay live.
 template <bool HACC>
 __device__ __forceinline__ void all_planes(const CloverForceArgs &f, const cd a[12], const cd b[12], long site,
                                            double c)
@@ -348,12 +368,8 @@ __device__ __forceinline__ void all_planes(const CloverForceArgs &f, const cd a[
                 const int ps = m == 0 ? 3 : (m == 1 ? 1 : 0), pt = m == 0 ? 2 : (m == 1 ? 4 : 5);
                 const cd hs = c * (se * (p0[m] + p1[m]) + conj(se * (q0[m] + q1[m])));
                 const cd ht = c * ((p0[m] - p1[m]) + conj(q0[m] - q1[m]));
-                put_insertion<HACC>(f, ps, site, 3 * i + j, hs);
-                put_insertion<HACC>(f, pt, site, 3 * i + j, ht);
-                if (j != i) {
-                    put_insertion<HACC>(f, ps, site, 3 * j + i, conj(hs));
-                    put_insertion<HACC>(f, pt, site, 3 * j + i, conj(ht));
-                }
+                put_insertion<HACC>(f, ps, site, i, j, hs);
+                put_insertion<HACC>(f, pt, site, i, j, ht);
             }
         }
 }
@@ -405,16 +421,17 @@ __device__ __forceinline__ Mat3 sel(bool c, const Mat3 &a, const Mat3 &b)
 // E U^+ = (U E^+)^+, and E^+ has the form of the one above,
 //     E^+ = b1 b2 b3 h(y) + b1 b2 h(y-n) b3 + b1 h(y-n+R) b2 b3 + h(y+R) b1 b2 b3,
 //     b1 = U_n(y-n+R)^+, b2 = U_R(y-n)^+, b3 = U_n(y-n),
-// so both lanes form X = U [c1 (c2 (c3 h(y) + h3 c3) + h2 c2 c3) + h(y+R) c1 c2 c3]
-// from their own links c and insertions h3, h2, and add X (above) or -X^+
-// (below); the pair then sums its two halves.
+// so both lanes form T = c1 (c2 (c3 h(y) + h3 c3) + h2 c2 c3) + h(y+R) c1 c2 c3
+// from their own links c and insertions h3, h2, sum T over the three planes,
+// and add X = U sum T (above) or -X^+ (below); the pair then sums its two
+// halves.
 template <int R>
 __device__ __forceinline__ void clover_link_half(const CloverForceArgs &f, const int y[4], long lex, int half,
                                                  bool valid)
 {
-    Mat3 Z;
+    Mat3 Z, S;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) Z.m[k] = cd{0, 0};
+    for (int k = 0; k < 9; ++k) Z.m[k] = S.m[k] = cd{0, 0};
     const bool lo = half == 1;
     if (valid) {
         int yr[4];
@@ -443,11 +460,12 @@ __device__ __forceinline__ void clover_link_half(const CloverForceArgs &f, const
             T = mm(c1, T);
             P = mm(c1, P);
             add_to(T, mm(insertion(f, yr, R, n), P));                         // + h(y+R) c1 c2 c3
-            const Mat3 X = mm(link(f, y, R), T);
-            const Mat3 Xd = dagm(X);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) Z.m[k] = lo ? Z.m[k] - Xd.m[k] : Z.m[k] + X.m[k];
+            add_to(S, T);
         }
+        const Mat3 X = mm(link(f, y, R), S);
+        const Mat3 Xd = dagm(X);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Z.m[k] = lo ? cd{-Xd.m[k].re, -Xd.m[k].im} : X.m[k];
     }
     // the pair's two halves
 #pragma unroll
