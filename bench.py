@@ -15,9 +15,10 @@ epsbar = 0.1315; links U = proj_SU3(exp(i 0.25 H)), seed 4):
     reliable updates; the network is trained before the timed region on 256
     (source, solution) pairs from the plain solver on a 16^3x32 field, the
     best of three initialisations by preconditioned-CG iterations on a
-    held-out source of that field), and by its Hermitian form P = A^dagger A
-    (one network application per iteration; trained the same way on pairs
-    (b, N^{-1} b) with the energy-norm loss);
+    held-out source of that field), by its Hermitian form P = A^dagger A
+    (A = L_2 L_1; one network application per iteration; trained the same way
+    on pairs (b, N^{-1} b) with the energy-norm loss) and by the short form
+    P_1 = L_1^dagger L_1 (the one-channel layers only, trained likewise);
   * CG and FP16 MP-CG on the mass-preconditioned What^dagger What (rho = 0.02);
   * a 12-shift multishift solve of the two-flavour normal operator (FP32
     multishift CG, then FP64-reliable refinement per shift) at the poles of
@@ -134,65 +135,85 @@ def cpu_solves(o, b, b2, shifts, gpu_cg_iters, gpu_shift_iters):
     return out
 
 
-def train_network(tmx, synth, npairs, epochs, inits=3, sym=False):
-    """Train the preconditioner on a 16^3x32 field (seed 2) from (b, Mhat^{-1} b) pairs.
+# the preconditioner forms: solver kind, training loss, training pairs
+# (b, Mhat^{-1} b) or (b, N^{-1} b), label
+PC_FORMS = {
+    "kk": ("TMX_SOLVER_PCG_NN", "TMX_LOSS_RESIDUAL", "mhat", "K K^dagger"),
+    "sym": ("TMX_SOLVER_PCG_NN_SYM", "TMX_LOSS_SYM", "normal", "P = A^dagger A, A = L_2 L_1"),
+    "sym1": ("TMX_SOLVER_PCG_NN_SYM1", "TMX_LOSS_SYM1", "normal", "P_1 = L_1^dagger L_1"),
+}
 
-    The residual loss is an average over Gaussian sources and does not see
-    how the network treats the lowest modes, which set the iteration count
-    of preconditioned CG; training runs from `inits` random initialisations
-    are therefore compared by that count on a held-out source of the same
-    training field, and the best is kept.  Nothing of the benchmark field
-    enters the choice.
+
+def train_networks(tmx, synth, npairs, epochs, forms=("kk", "sym", "sym1"), inits=3):
+    """Train the preconditioner forms on a 16^3x32 field (seed 2).
+
+    K is trained on pairs (b, Mhat^{-1} b) with the residual loss, the
+    Hermitian forms on pairs (b, N^{-1} b) with the energy-norm loss.  The
+    losses are averages over Gaussian sources and do not see how the network
+    treats the lowest modes, which set the iteration count of preconditioned
+    CG; training runs from `inits` random initialisations are therefore
+    compared by that count on a held-out source of the same training field,
+    and the best is kept.  Nothing of the benchmark field enters the choice.
+    Returns {form: (weights, record)}.
     """
     import numpy as np
     import torch
 
     dims = (16, 16, 16, 32)
-    t0 = time.perf_counter()
     U = synth.gauge_links(dims, 0.25, 2)
     tc = tmx.Context(dims)
     tc.set_params(tmx.Params(KAPPA, CSW, MU, 0.0, 0.0, -1))
     tc.load_gauge(U, 2.0)
     n1 = tc.Vh * 12
     bs = torch.from_numpy(np.stack([synth.gaussian_cb_spinor(dims, 2, k) for k in range(npairs)]).reshape(-1)).cuda()
-    xs = torch.zeros_like(bs)
-    for k in range(npairs):
-        xk = torch.zeros(n1, dtype=torch.complex128, device="cuda")
-        if sym:  # the Hermitian form approximates N^{-1}: pairs (b, N^{-1} b)
-            tc.solve(xk, bs[k * n1:(k + 1) * n1], 1, kind=tmx.TMX_SOLVER_MPCG_F32, op=1, tol=1e-10)
-        else:  # K approximates Mhat^{-1}: pairs (b, Mhat^{-1} b)
-            tc.solve_mhat(xk, bs[k * n1:(k + 1) * n1], dagger=0, op=1, tol=1e-10)
-        xs[k * n1:(k + 1) * n1] = xk
-    kind = tmx.TMX_SOLVER_PCG_NN_SYM if sym else tmx.TMX_SOLVER_PCG_NN
-    loss_kind = tmx.TMX_LOSS_SYM if sym else tmx.TMX_LOSS_RESIDUAL
+    pairs, pair_seconds = {}, {}
+    for kind in sorted({PC_FORMS[f][2] for f in forms}):
+        t0 = time.perf_counter()
+        xs = torch.zeros_like(bs)
+        for k in range(npairs):
+            xk = torch.zeros(n1, dtype=torch.complex128, device="cuda")
+            if kind == "normal":
+                tc.solve(xk, bs[k * n1:(k + 1) * n1], 1, kind=tmx.TMX_SOLVER_MPCG_F32, op=1, tol=1e-10)
+            else:
+                tc.solve_mhat(xk, bs[k * n1:(k + 1) * n1], dagger=0, op=1, tol=1e-10)
+            xs[k * n1:(k + 1) * n1] = xk
+        pairs[kind] = xs
+        pair_seconds[kind] = round(time.perf_counter() - t0, 1)
     bval = torch.from_numpy(synth.gaussian_cb_spinor(dims, 2, 10 ** 6).reshape(-1)).cuda()
-    t1 = time.perf_counter()
-    runs, best = [], None
-    for init in range(inits):
-        w0 = np.zeros(tc.pc_num_params(), dtype=np.float32)
-        # identity on the d = 0 path of every layer, N(0, 1e-2) elsewhere
-        from_oracle_free_init(w0, np.random.default_rng(3 + init))
-        tc.pc_set_weights(w0)
-        losses = tc.pc_train(bs, xs, npairs, epochs=epochs, batch=8, lr=3e-3, seed=1, loss_kind=loss_kind)
-        x = torch.zeros_like(bval)
-        rc, info = tc.solve(x, bval, 1, kind=kind, op=1, tol=1e-10, inner_prec=2)
-        it = info[0]["iters"] if rc == tmx.TMX_OK else 10 ** 9
-        runs.append({"init": init, "loss_first": float(losses[0]), "loss_last": float(losses[-1]), "val_pcg_iters": it})
-        if best is None or it < best[0]:
-            best = (it, tc.pc_get_weights())
     x = torch.zeros_like(bval)
     rc, info = tc.solve(x, bval, 1, kind=tmx.TMX_SOLVER_MPCG_F16, op=1, tol=1e-10)
+    val_cg = info[0]["iters"]
+    out = {}
+    for form in forms:
+        skind, lkind, ptype, label = PC_FORMS[form]
+        kind, loss_kind = getattr(tmx, skind), getattr(tmx, lkind)
+        t1 = time.perf_counter()
+        runs, best = [], None
+        for init in range(inits):
+            w0 = np.zeros(tc.pc_num_params(), dtype=np.float32)
+            # identity on the d = 0 path of every layer, N(0, 1e-2) elsewhere
+            from_oracle_free_init(w0, np.random.default_rng(3 + init))
+            tc.pc_set_weights(w0)
+            losses = tc.pc_train(bs, pairs[ptype], npairs, epochs=epochs, batch=8, lr=3e-3, seed=1,
+                                 loss_kind=loss_kind)
+            x = torch.zeros_like(bval)
+            rc, info = tc.solve(x, bval, 1, kind=kind, op=1, tol=1e-10, inner_prec=2)
+            it = info[0]["iters"] if rc == tmx.TMX_OK else 10 ** 9
+            runs.append({"init": init, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+                         "val_pcg_iters": it})
+            if best is None or it < best[0]:
+                best = (it, tc.pc_get_weights())
+        out[form] = (best[1], {"form": label, "pairs": npairs, "lattice": list(dims),
+                               "pair_seconds": pair_seconds[ptype], "train_seconds": round(time.perf_counter() - t1, 1),
+                               "epochs": epochs, "runs": runs, "val_cg_iters": val_cg})
     tc.close()
-    t2 = time.perf_counter()
-    return best[1], {"form": "P = A^dagger A" if sym else "K K^dagger", "pairs": npairs, "lattice": list(dims),
-                     "pair_seconds": round(t1 - t0, 1),
-                     "train_seconds": round(t2 - t1, 1), "epochs": epochs, "runs": runs,
-                     "val_cg_iters": info[0]["iters"]}
+    return out
 
 
-def learned_pc_other_volume(tmx, synth, weights, weights_sym, dims=(24, 24, 24, 48), seed=3):
-    """The trained weights (translation invariant) used unchanged on a second
-    volume: plain CG, MP-CG, CG preconditioned by K K^dagger and flexible GCR
+def learned_pc_other_volume(tmx, synth, wts, dims=(24, 24, 24, 48), seed=3):
+    """The trained weights (translation invariant; wts: solver kind ->
+    weights) used unchanged on a second volume: plain CG, MP-CG, CG
+    preconditioned by K K^dagger and by the Hermitian forms, and flexible GCR
     with K, each to a 1e-10 FP64 true residual (one warm-up solve each, then
     the median of three)."""
     import numpy as np
@@ -202,14 +223,17 @@ def learned_pc_other_volume(tmx, synth, weights, weights_sym, dims=(24, 24, 24, 
     ctx = tmx.Context(dims)
     ctx.set_params(tmx.Params(KAPPA, CSW, MU, 0.0, 0.0, -1))
     ctx.load_gauge(U, float(seed))
-    ctx.pc_set_weights(weights)
     b = torch.from_numpy(synth.gaussian_cb_spinor(dims, seed, 0).reshape(-1)).cuda()
     x = torch.zeros_like(b)
     out = {"lattice": list(dims), "seed": seed}
     for kind, name, ip in ((tmx.TMX_SOLVER_CG, "cg_f64", 1), (tmx.TMX_SOLVER_MPCG_F16, "mpcg_f16", 1),
                            (tmx.TMX_SOLVER_PCG_NN, "pcg_nn_f16", 2), (tmx.TMX_SOLVER_FGCR_NN, "fgcr_nn_f32", 1),
-                           (tmx.TMX_SOLVER_PCG_NN_SYM, "pcg_nn_sym_f16", 2)):
-        ctx.pc_set_weights(weights_sym if kind == tmx.TMX_SOLVER_PCG_NN_SYM else weights)
+                           (tmx.TMX_SOLVER_PCG_NN_SYM, "pcg_nn_sym_f16", 2),
+                           (tmx.TMX_SOLVER_PCG_NN_SYM1, "pcg_nn_sym1_f16", 2)):
+        if kind in wts:
+            ctx.pc_set_weights(wts[kind])
+        elif kind == tmx.TMX_SOLVER_FGCR_NN:
+            ctx.pc_set_weights(wts[tmx.TMX_SOLVER_PCG_NN])
         times = []
         for rep in range(4):
             x.zero_()
@@ -364,9 +388,9 @@ def main():
         ctx.close()
         return
 
-    weights, train_info = train_network(tmx, synth, args.train_pairs, args.train_epochs)
-    weights_sym, train_info_sym = train_network(tmx, synth, args.train_pairs, args.train_epochs, sym=True)
-    ctx.pc_set_weights(weights)
+    trained = train_networks(tmx, synth, args.train_pairs, args.train_epochs)
+    wts = {getattr(tmx, PC_FORMS[f][0]): trained[f][0] for f in trained}
+    ctx.pc_set_weights(trained["kk"][0])
     # largest eigenvalue of N_h by power iteration (FP32), for the shifts
     v = ctx.pack(b2d, tmx.TMX_FIELD_ODD_ND, 1)
     w2 = ctx.empty(tmx.TMX_FIELD_ODD_ND, 1)
@@ -384,7 +408,7 @@ def main():
     xs_ms = torch.zeros(12 * b2d.numel(), dtype=torch.complex128, device="cuda")
     b12 = torch.from_numpy(np.stack([synth.gaussian_cb_spinor(dims, 4, 100 + k, 2) for k in range(12)]).reshape(-1)).cuda()
     x12 = torch.zeros_like(b12)
-    log(f"lambda_max(N_h) ~ {lam:.4f}; network trained ({train_info})")
+    log(f"lambda_max(N_h) ~ {lam:.4f}; network trained ({ {f: trained[f][1]['runs'] for f in trained} })")
 
     def timed(fn):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -403,11 +427,12 @@ def main():
         for kind, nm, ip, op in ((tmx.TMX_SOLVER_CG, "cg_f64", 1, 1), (tmx.TMX_SOLVER_MPCG_F32, "mpcg_f32", 1, 1),
                                  (tmx.TMX_SOLVER_MPCG_F16, "mpcg_f16", 1, 1), (tmx.TMX_SOLVER_PCG_NN, "pcg_nn_f16", 2, 1),
                                  (tmx.TMX_SOLVER_PCG_NN_SYM, "pcg_nn_sym_f16", 2, 1),
+                                 (tmx.TMX_SOLVER_PCG_NN_SYM1, "pcg_nn_sym1_f16", 2, 1),
                                  # the mass-preconditioned normal operator What^dagger What
                                  (tmx.TMX_SOLVER_CG, "cg_w_f64", 1, tmx.TMX_OP_WPLUS),
                                  (tmx.TMX_SOLVER_MPCG_F16, "mpcg_w_f16", 1, tmx.TMX_OP_WPLUS)):
-            if kind in (tmx.TMX_SOLVER_PCG_NN, tmx.TMX_SOLVER_PCG_NN_SYM):
-                ctx.pc_set_weights(weights_sym if kind == tmx.TMX_SOLVER_PCG_NN_SYM else weights)
+            if kind in wts:
+                ctx.pc_set_weights(wts[kind])
             x.zero_()
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -530,8 +555,9 @@ def main():
         "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in ks.items()},
         "roofline": roofline,
         "roofline_nn_layer": nn_roof,
-        "learned_pc_training": train_info,
-        "learned_pc_training_sym": train_info_sym,
+        "learned_pc_training": trained["kk"][1],
+        "learned_pc_training_sym": trained["sym"][1],
+        "learned_pc_training_sym1": trained["sym1"][1],
         "tuned_launch": tuned,
     }
     # the rational approximation as a whole: R(N_h) b, then N_h R(N_h)^2 b = b
@@ -609,7 +635,7 @@ def main():
     del fbuf
     if dims == (32, 32, 32, 64):
         log("learned preconditioner on a 24^3x48 field")
-        out["learned_pc_24x24x24x48"] = learned_pc_other_volume(tmx, synth, weights, weights_sym)
+        out["learned_pc_24x24x24x48"] = learned_pc_other_volume(tmx, synth, wts)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         o, cb = cpu_baseline(dims, U, b, args.cpu_applies)

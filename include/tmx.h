@@ -103,8 +103,10 @@ enum {
                                CG acceptance and fallback */
     TMX_SOLVER_PCG_NN = 4,  /* flexible CG on N preconditioned by K K^dagger (learned network), inner
                                precision cfg->inner_prec (F32 / F16) with FP64 reliable updates */
-    TMX_SOLVER_PCG_NN_SYM = 5 /* the same with the Hermitian form P = A^dagger A of the network (one
-                                 application per iteration; see tmx_pc_apply) */
+    TMX_SOLVER_PCG_NN_SYM = 5, /* the same with the Hermitian form P = A^dagger A of the network (one
+                                  application per iteration; see tmx_pc_apply) */
+    TMX_SOLVER_PCG_NN_SYM1 = 6 /* the same with the short Hermitian form P_1 = L_1^dagger L_1 (the
+                                  network's one-channel layers only; tmx_pc_apply mode 3) */
 };
 
 typedef struct {
@@ -342,12 +344,15 @@ int tmx_rational_correction(tmx_ctx *ctx, const double *eta, double a0, const do
 int tmx_pc_num_params(const tmx_ctx *ctx, size_t *n);
 int tmx_pc_set_weights(tmx_ctx *ctx, const float *host_w, size_t n);
 int tmx_pc_get_weights(tmx_ctx *ctx, float *host_w, size_t n);
-/* out = K in (dagger = 0), K^dagger in (dagger = 1), or the Hermitian form
- * P in (dagger = 2) on canonical odd complex128 device fields.  P = A^dagger A
- * with A = L_2 L_1 the network's first two layers (the last two are not
- * used): four stencil layers applied, Hermitian and positive semi-definite
- * by construction, so that one application preconditions CG on N (where
- * K K^dagger takes two); trained with TMX_LOSS_SYM on pairs (b, N^{-1} b). */
+/* out = K in (dagger = 0), K^dagger in (dagger = 1), the Hermitian form
+ * P in (dagger = 2) or the short Hermitian form P_1 in (dagger = 3) on
+ * canonical odd complex128 device fields.  P = A^dagger A with A = L_2 L_1
+ * the network's first two layers (the last two are not used): four stencil
+ * layers applied, Hermitian and positive semi-definite by construction, so
+ * that one application preconditions CG on N (where K K^dagger takes two);
+ * trained with TMX_LOSS_SYM on pairs (b, N^{-1} b).  P_1 = L_1^dagger L_1
+ * uses the first layer alone (two one-channel layers, about a third of P's
+ * cost); trained with TMX_LOSS_SYM1.  Other values of dagger: TMX_EINVAL. */
 int tmx_pc_apply(tmx_ctx *ctx, double *out, const double *in, int dagger);
 
 /* Training loss (loss_kind as in tmx_train_cfg, Mhat of op: TMX_OP_PLUS or
@@ -363,7 +368,7 @@ typedef struct {
     float lr;
     float beta1, beta2, eps;
     int seed;
-    int loss_kind; /* TMX_LOSS_RESIDUAL (default) or TMX_LOSS_SOLUTION */
+    int loss_kind; /* TMX_LOSS_* (default TMX_LOSS_RESIDUAL) */
     int op;        /* operator the network is trained for: TMX_OP_PLUS (0 = default) or
                       TMX_OP_MINUS (separately trained weights for the Mhat(-mu) solves) */
 } tmx_train_cfg;
@@ -374,11 +379,13 @@ typedef struct {
  * The residual loss controls E = Mhat K - 1 on all modes, which is what a
  * preconditioner needs; the solution loss weights the high modes of Mhat
  * down by Mhat^{-1}. */
-enum { TMX_LOSS_RESIDUAL = 0, TMX_LOSS_SOLUTION = 1, TMX_LOSS_SYM = 2 };
+enum { TMX_LOSS_RESIDUAL = 0, TMX_LOSS_SOLUTION = 1, TMX_LOSS_SYM = 2, TMX_LOSS_SYM1 = 3 };
 /* TMX_LOSS_SYM trains the Hermitian form P (layers 1 and 2) on pairs
  * (b_i, x_i = N^{-1} b_i) with the energy norm of its error,
  *   mean_i <P b_i - x_i, N (P b_i - x_i)> / |b_i|^2 = mean_i |Mhat (P b_i - x_i)|^2 / |b_i|^2,
- * the quantity CG on N minimises; the gradients of layers 3 and 4 are zero. */
+ * the quantity CG on N minimises; the gradients of layers 3 and 4 are zero.
+ * TMX_LOSS_SYM1: the same loss for the short form P_1 (layer 1 only; the
+ * gradients of layers 2 to 4 are zero). */
 
 /* One Adam step (Kingma and Ba, with bias correction) on the network weights
  * from a gradient the caller supplies: host_grad holds n FP32 values in the

@@ -228,11 +228,17 @@ def loss_and_grad(lat: Lattice, w, bs, xs, mhat=None, mhat_dag=None):
 # Hermitian and positive semi-definite by construction, so one application
 # serves as the preconditioner of CG on N = Mhat^dagger Mhat
 # --------------------------------------------------------------------------
-def sym_forward(lat: Lattice, w, b, keep=False):
-    """P b = R_odd L_1^dagger L_2^dagger L_2 L_1 E_odd b for an odd source b (Vh, 4, 3)."""
+def sym_forward(lat: Lattice, w, b, keep=False, depth=2):
+    """P b = R_odd L_1^dagger L_2^dagger L_2 L_1 E_odd b (depth 2) or the short
+    form P_1 b = R_odd L_1^dagger L_1 E_odd b (depth 1) for an odd source b
+    (Vh, 4, 3)."""
     (C1, G1), (C2, G2) = unflatten(w)[:2]
     a0 = lat.embed_odd(b)
     a1 = layer_forward(lat, C1, G1, a0)
+    if depth == 1:
+        out = layer_adjoint(lat, C1, G1, a1)
+        res = lat.restrict_odd(out)
+        return (res, (a0, a1)) if keep else res
     a2 = layer_forward(lat, C2, G2, a1)
     a3 = layer_adjoint(lat, C2, G2, a2)
     out = layer_adjoint(lat, C1, G1, a3)
@@ -252,10 +258,11 @@ def _layer_grad(lat: Lattice, C, G, xin, delta):
     return gC, gG
 
 
-def sym_loss_and_grad(lat: Lattice, w, bs, xs, mhat, mhat_dag):
+def sym_loss_and_grad(lat: Lattice, w, bs, xs, mhat, mhat_dag, depth=2):
     """Energy-norm loss of the Hermitian form over pairs (b_i, x_i = N^{-1} b_i):
     L = mean_i <e_i, N e_i> / |b_i|^2 = mean_i |Mhat e_i|^2 / |b_i|^2, e_i = P b_i - x_i,
-    and its gradient with respect to the flat weights (layers 3 and 4: zero).
+    and its gradient with respect to the flat weights (layers 3 and 4: zero;
+    with depth 1, the short form P_1 = L_1^dagger L_1, layer 2 as well).
     A layer used as its adjoint, y = L^dagger x with output adjoint delta,
     contributes 2 Re<x, dL delta>: the gradient of the layer used forward
     on delta with output adjoint x."""
@@ -266,12 +273,21 @@ def sym_loss_and_grad(lat: Lattice, w, bs, xs, mhat, mhat_dag):
     g1 = [np.zeros_like(C1), np.zeros_like(G1)]
     g2 = [np.zeros_like(C2), np.zeros_like(G2)]
     for b, x in zip(bs, xs):
-        out, (a0, a1, a2, a3) = sym_forward(lat, w, b, keep=True)
+        out, acts = sym_forward(lat, w, b, keep=True, depth=depth)
         e = out - np.asarray(x).reshape(out.shape)
         bb = np.vdot(b, b).real
         q = mhat(e)
         L += np.vdot(q, q).real / bb / n
         d4 = lat.embed_odd(mhat_dag(q) / bb / n)       # output adjoint (N e / |b|^2 n)
+        if depth == 1:
+            a0, a1 = acts
+            dC, dG = _layer_grad(lat, C1, G1, d4, a1)      # L_1^dagger
+            g1[0] += dC; g1[1] += dG
+            d1 = layer_forward(lat, C1, G1, d4)
+            dC, dG = _layer_grad(lat, C1, G1, a0, d1)      # L_1
+            g1[0] += dC; g1[1] += dG
+            continue
+        a0, a1, a2, a3 = acts
         dC, dG = _layer_grad(lat, C1, G1, d4, a3)          # L_1^dagger (last layer)
         g1[0] += dC; g1[1] += dG
         d3 = layer_forward(lat, C1, G1, d4)

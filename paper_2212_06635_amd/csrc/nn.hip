@@ -1237,9 +1237,10 @@ int embed(tmx_ctx *c, SpinorPtr r, int pr, Act a)
 }
 
 // The Hermitian form P r = L_1^dagger L_2^dagger L_2 L_1 r (layers 1 and 2 of
-// the weights), an FP32 odd field; with acts, the inputs of its four layer
-// applications are kept (for the gradient).
-int nn_forward_sym(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, std::vector<Act> *acts)
+// the weights; depth 2) or its short form P_1 r = L_1^dagger L_1 r (depth 1),
+// an FP32 odd field; with acts, the inputs of its layer applications are kept
+// (for the gradient).
+int nn_forward_sym(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, int depth, std::vector<Act> *acts)
 {
     const bool keep = acts != nullptr;
     const ThinW *thin = c->pc->thin;
@@ -1251,23 +1252,27 @@ int nn_forward_sym(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, std::vector<A
         if (rc) return rc;
         acts->push_back(a0);
     }
-    Act a1 = act(c, keep ? "a1" : "p1", 8), a2 = act(c, keep ? "a2" : "p2", 8), a3 = act(c, keep ? "a3" : "p3", 8);
-    if (!a1.d || !a2.d || !a3.d) return TMX_ENOMEM;
+    Act a1 = act(c, keep ? "a1" : "p1", 8);
+    if (!a1.d) return TMX_ENOMEM;
     int rc = launch_up(c, r, pr, a1, thin + THIN_UP_F);  // L_1
-    if (!rc) rc = launch_layer(c, 8, 8, a1, a2, SpinorPtr{}, c->pc->Wf[1]);  // L_2
+    if (rc) return rc;
+    if (keep) acts->push_back(a1);
+    if (depth == 1) return launch_down(c, a1, out, thin + THIN_DOWN_A);  // L_1^dagger
+    Act a2 = act(c, keep ? "a2" : "p2", 8), a3 = act(c, keep ? "a3" : "p3", 8);
+    if (!a2.d || !a3.d) return TMX_ENOMEM;
+    rc = launch_layer(c, 8, 8, a1, a2, SpinorPtr{}, c->pc->Wf[1]);  // L_2
     if (!rc) rc = launch_layer(c, 8, 8, a2, a3, SpinorPtr{}, c->pc->Wa[1]);  // L_2^dagger
     if (rc) return rc;
     if (keep) {
-        acts->push_back(a1);
         acts->push_back(a2);
         acts->push_back(a3);
     }
     return launch_down(c, a3, out, thin + THIN_DOWN_A);  // L_1^dagger
 }
 
-// The network on the odd field r: out = K r (mode 0), K^dagger r (mode 1) or
-// the Hermitian form P r (mode 2), an FP32 odd field.  With acts, the layer
-// inputs are kept (for the gradient).
+// The network on the odd field r: out = K r (mode 0), K^dagger r (mode 1),
+// the Hermitian form P r (mode 2) or its short form P_1 r (mode 3), an FP32
+// odd field.  With acts, the layer inputs are kept (for the gradient).
 int nn_forward(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, int dagger, std::vector<Act> *acts)
 {
     int rc = nn_ensure(c);
@@ -1276,7 +1281,7 @@ int nn_forward(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, int dagger, std::
     rc = ensure_ready(c, F32, false);
     if (!rc) rc = nn_build_weights(c);
     if (rc) return rc;
-    if (dagger == 2) return nn_forward_sym(c, out, r, pr, acts);
+    if (dagger == 2 || dagger == 3) return nn_forward_sym(c, out, r, pr, dagger == 2 ? 2 : 1, acts);
     const bool keep = acts != nullptr;
     const ThinW *thin = c->pc->thin;
     Act a{};
@@ -1653,6 +1658,7 @@ int tmx_pc_get_weights(tmx_ctx *c, float *host_w, size_t n)
 int tmx_pc_apply(tmx_ctx *c, double *out, const double *in, int dagger)
 {
     if (!c || !out || !in) return TMX_EINVAL;
+    if (dagger < 0 || dagger > 3) return set_err(c, TMX_EINVAL, "tmx_pc_apply: mode is 0 .. 3");
     const long Vh = c->Vh;
     void *pi = ws_get(c, "pca_in", spinor_field_bytes(F32, 1, Vh));
     void *po = ws_get(c, "pca_out", spinor_field_bytes(F32, 1, Vh));
@@ -1660,7 +1666,7 @@ int tmx_pc_apply(tmx_ctx *c, double *out, const double *in, int dagger)
     SpinorPtr I = make_spinor(pi, F32, 1, Vh), O = make_spinor(po, F32, 1, Vh);
     int r = hip_err(c, launch_pack_spinor(in, I, F32, TMX_FIELD_ODD, c->g, 1, c->stream), "pack");
     if (r) return r;
-    r = pc_apply_internal(c, O, F32, I, F32, dagger == 2 ? 2 : (dagger ? 1 : 0));
+    r = pc_apply_internal(c, O, F32, I, F32, dagger);
     if (r) return r;
     r = hip_err(c, launch_unpack_spinor(out, O, F32, TMX_FIELD_ODD, c->g, 1, c->stream), "unpack");
     if (r) return r;
@@ -1707,8 +1713,8 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
         void *pd = ws_get(c, "tr_dl", spinor_field_bytes(F32, 1, Vh));
         if (!pz || !pd) return TMX_ENOMEM;
         const SpinorPtr Z = make_spinor(pz, F32, 1, Vh), DL = make_spinor(pd, F32, 1, Vh);
-        const bool sym = loss_kind == TMX_LOSS_SYM;
-        r = nn_forward(c, Z, B, F32, sym ? 2 : 0, &acts);
+        const bool sym = loss_kind == TMX_LOSS_SYM || loss_kind == TMX_LOSS_SYM1;
+        r = nn_forward(c, Z, B, F32, loss_kind == TMX_LOSS_SYM ? 2 : (sym ? 3 : 0), &acts);
         if (r) return r;
         // DL = dLoss / d(K b) (odd field), then as the one-channel output adjoint
         // (the energy loss of P = A^dagger A is the residual loss's formula
@@ -1762,6 +1768,16 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
         if (!delta.d) return TMX_ENOMEM;
         r = embed(c, DL, F32, delta);
         if (r) return r;
+        if (loss_kind == TMX_LOSS_SYM1) {
+            // P_1 = L_1^dagger L_1, inputs a0, a1 (layer gradients as below)
+            Act d1 = act(c, "d1", 8);
+            if (!d1.d) return TMX_ENOMEM;
+            r = launch_wgrad(c, 1, 8, delta, acts[1], partial[0]);                     // L_1^dagger
+            if (!r) r = launch_layer(c, 1, 8, delta, d1, SpinorPtr{}, s.Wf[0]);
+            if (!r) r = launch_wgrad(c, 1, 8, acts[0], d1, partial[0]);                // L_1
+            if (r) return r;
+            continue;
+        }
         if (sym) {
             // P = L_1^dagger L_2^dagger L_2 L_1, inputs a0 .. a3.  A layer used as
             // its adjoint (input x, output adjoint d) takes the gradient of its
@@ -1812,7 +1828,7 @@ int tmx_pc_loss_grad(tmx_ctx *c, const double *b, const double *x, int npairs, i
                      float *host_grad)
 {
     if (!c || !b || !x || npairs < 1 || !loss) return TMX_EINVAL;
-    if (loss_kind < TMX_LOSS_RESIDUAL || loss_kind > TMX_LOSS_SYM) return set_err(c, TMX_EINVAL, "unknown loss kind");
+    if (loss_kind < TMX_LOSS_RESIDUAL || loss_kind > TMX_LOSS_SYM1) return set_err(c, TMX_EINVAL, "unknown loss kind");
     if (op != TMX_OP_PLUS && op != TMX_OP_MINUS)
         return set_err(c, TMX_EINVAL, "the network is trained for Mhat(+mu) or Mhat(-mu)");
     int r = nn_ensure(c);
@@ -1881,7 +1897,7 @@ int tmx_pc_adam_step(tmx_ctx *c, const float *host_grad, size_t n, const tmx_tra
 int tmx_pc_train(tmx_ctx *c, const double *b, const double *x, int npairs, const tmx_train_cfg *cfg, float *loss_out)
 {
     if (!c || !b || !x || npairs < 1 || !cfg || cfg->epochs < 1 || cfg->batch < 1) return TMX_EINVAL;
-    if (cfg->loss_kind < TMX_LOSS_RESIDUAL || cfg->loss_kind > TMX_LOSS_SYM)
+    if (cfg->loss_kind < TMX_LOSS_RESIDUAL || cfg->loss_kind > TMX_LOSS_SYM1)
         return set_err(c, TMX_EINVAL, "unknown loss kind");
     const int op = cfg->op == 0 ? TMX_OP_PLUS : cfg->op;
     if (op != TMX_OP_PLUS && op != TMX_OP_MINUS)

@@ -357,11 +357,12 @@ template <int P> struct OpPcgDots {
     }
 };
 
-// z = P r: K K^dagger r, or the network's Hermitian form (one application).
-// An FP16 residual is widened to FP32 (rf) first: the network's first layer
-// reads single spins, which FP16's per-site blocks make costly.
+// z = P r: K K^dagger r (sym = 0), or the network's Hermitian form P (sym =
+// 2) or short form P_1 (sym = 3), one application each.  An FP16 residual is
+// widened to FP32 (rf) first: the network's first layer reads single spins,
+// which FP16's per-site blocks make costly.
 template <int P>
-static int pcg_apply_pc(Sys &S, SpinorPtr z, SpinorPtr r, SpinorPtr tmp, SpinorPtr rf, bool sym)
+static int pcg_apply_pc(Sys &S, SpinorPtr z, SpinorPtr r, SpinorPtr tmp, SpinorPtr rf, int sym)
 {
     int pr = P;
     if constexpr (P == F16) {
@@ -373,7 +374,7 @@ static int pcg_apply_pc(Sys &S, SpinorPtr z, SpinorPtr r, SpinorPtr tmp, SpinorP
         r = rf;
         pr = F32;
     }
-    if (sym) return pc_apply_internal(S.c, z, F32, r, pr, 2);
+    if (sym) return pc_apply_internal(S.c, z, F32, r, pr, sym);
     int rc = pc_apply_internal(S.c, tmp, F32, r, pr, 1);  // K^dagger r
     if (rc) return rc;
     return pc_apply_internal(S.c, z, F32, tmp, F32, 0);  // K K^dagger r
@@ -383,7 +384,7 @@ template <int P>
 static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const double *sigma, const tmx_solver_cfg &cfg,
                        bool x_is_guess, tmx_info *info)
 {
-    const bool sym = cfg.kind == TMX_SOLVER_PCG_NN_SYM;
+    const int sym = cfg.kind == TMX_SOLVER_PCG_NN_SYM ? 2 : (cfg.kind == TMX_SOLVER_PCG_NN_SYM1 ? 3 : 0);
     tmx_ctx *c = S.c;
     const double tol = cfg.tol > 0 ? cfg.tol : 1e-10;
     const int maxiter = cfg.maxiter > 0 ? cfg.maxiter : 10000;
@@ -653,6 +654,7 @@ int tmx_solve(tmx_ctx *c, double *x, const double *b, int nrhs, const tmx_solver
         break;
     case TMX_SOLVER_PCG_NN:
     case TMX_SOLVER_PCG_NN_SYM:
+    case TMX_SOLVER_PCG_NN_SYM1:
         if (nrhs != 1) return set_err(c, TMX_EINVAL, "the preconditioned CG solves one right-hand side at a time");
         if (cfg->op != TMX_OP_PLUS && cfg->op != TMX_OP_MINUS)
             return set_err(c, TMX_EINVAL, "the learned preconditioner is built for the degenerate Schur operator");
@@ -709,7 +711,8 @@ static int multishift_run(tmx_ctx *c, Sys &S, SpinorPtr B, const double *shifts,
     const double tol = cfg->tol > 0 ? cfg->tol : 1e-10;
     const double inner = cfg->inner_tol > 0 ? cfg->inner_tol : (prec == TMX_F16 ? 5e-4 : (prec == TMX_F32 ? 1e-6 : tol));
     const int maxiter = cfg->maxiter > 0 ? cfg->maxiter : 10000;
-    const bool pcg_nn = cfg->kind == TMX_SOLVER_PCG_NN || cfg->kind == TMX_SOLVER_PCG_NN_SYM;
+    const bool pcg_nn = cfg->kind == TMX_SOLVER_PCG_NN || cfg->kind == TMX_SOLVER_PCG_NN_SYM ||
+                        cfg->kind == TMX_SOLVER_PCG_NN_SYM1;
     if (pcg_nn) {
         if (cfg->op != TMX_OP_PLUS && cfg->op != TMX_OP_MINUS)
             return set_err(c, TMX_EINVAL, "the learned preconditioner is built for the degenerate Schur operator");

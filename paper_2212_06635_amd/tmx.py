@@ -25,7 +25,8 @@ TMX_OP_PLUS, TMX_OP_MINUS, TMX_OP_ND, TMX_OP_WPLUS, TMX_OP_WMINUS = 1, -1, 2, 3,
 TMX_FIELD_ODD, TMX_FIELD_ODD_ND, TMX_FIELD_FULL, TMX_FIELD_FULL_ND = 0, 1, 2, 3
 TMX_SOLVER_CG, TMX_SOLVER_MPCG_F32, TMX_SOLVER_MPCG_F16, TMX_SOLVER_FGCR_NN, TMX_SOLVER_PCG_NN = 0, 1, 2, 3, 4
 TMX_SOLVER_PCG_NN_SYM = 5
-TMX_LOSS_RESIDUAL, TMX_LOSS_SOLUTION, TMX_LOSS_SYM = 0, 1, 2
+TMX_SOLVER_PCG_NN_SYM1 = 6
+TMX_LOSS_RESIDUAL, TMX_LOSS_SOLUTION, TMX_LOSS_SYM, TMX_LOSS_SYM1 = 0, 1, 2, 3
 
 PREC = {"f64": TMX_F64, "f32": TMX_F32, "f16": TMX_F16}
 

@@ -275,9 +275,11 @@ def test_adam_step_matches_oracle(S):
         ctx.pc_adam_step(bad, **hp)
 
 
-def test_hermitian_form_matches_oracle(S):
-    """P = L_1^dagger L_2^dagger L_2 L_1 (tmx_pc_apply mode 2) against the
-    network oracle, random weights; Hermitian to the BF16 staging error."""
+@pytest.mark.parametrize("mode,depth", [(2, 2), (3, 1)])
+def test_hermitian_form_matches_oracle(S, mode, depth):
+    """P = L_1^dagger L_2^dagger L_2 L_1 (tmx_pc_apply mode 2) and the short
+    form P_1 = L_1^dagger L_1 (mode 3) against the network oracle, random
+    weights; Hermitian to the BF16 staging error."""
     tmx, ctx, lat, _ = S
     rng = np.random.default_rng(45)
     w = (rng.standard_normal(nn.num_params()) * 0.3).astype(np.float32)
@@ -285,9 +287,11 @@ def test_hermitian_form_matches_oracle(S):
     u = synth.gaussian_cb_spinor(DIMS, 45, 0)
     v = synth.gaussian_cb_spinor(DIMS, 45, 1)
     Pu, Pv = to_dev(np.zeros_like(u)), to_dev(np.zeros_like(v))
-    ctx.pc_apply(Pu, to_dev(u), 2)
-    ctx.pc_apply(Pv, to_dev(v), 2)
-    ref = nn.sym_forward(lat, f32(w), v[:, 0])
+    ctx.pc_apply(Pu, to_dev(u), mode)
+    ctx.pc_apply(Pv, to_dev(v), mode)
+    ref = nn.sym_forward(lat, f32(w), v[:, 0], depth=depth)
+    with pytest.raises(tmx.TmxError):
+        ctx.pc_apply(Pu, to_dev(u), 4)  # no such mode
     got = to_host(Pv, v.shape)[:, 0]
     assert rel_l2(got, ref) < 2e-2
     a = np.vdot(u.reshape(-1), to_host(Pv, v.shape).reshape(-1))
@@ -295,34 +299,40 @@ def test_hermitian_form_matches_oracle(S):
     assert abs(a - b) <= 2e-2 * abs(a)
 
 
-def test_hermitian_form_gradient_matches_oracle(S):
+@pytest.mark.parametrize("depth", [2, 1])
+def test_hermitian_form_gradient_matches_oracle(S, depth):
     """Energy-norm loss of the Hermitian form and its gradient (layers 1 and
-    2; the others zero) against the oracle's."""
+    2, or layer 1 for the short form; the others zero) against the oracle's."""
     tmx, ctx, lat, U = S
     rng = np.random.default_rng(46)
     w = nn.identity_init(rng, 0.1).astype(np.float32)
     ctx.pc_set_weights(w)
     bs = np.stack([synth.gaussian_cb_spinor(DIMS, 46, k) for k in range(2)])
     xs = np.stack([synth.gaussian_cb_spinor(DIMS, 47, k) for k in range(2)])
-    loss, g = ctx.pc_loss_grad(to_dev(bs), to_dev(xs), 2, tmx.TMX_LOSS_SYM, 1)
+    kind = tmx.TMX_LOSS_SYM if depth == 2 else tmx.TMX_LOSS_SYM1
+    loss, g = ctx.pc_loss_grad(to_dev(bs), to_dev(xs), 2, kind, 1)
     o = Oracle(DIMS, U, KAPPA, CSW, mu=MU0)
     mh = lambda v: o.mhat(v.reshape(-1, 1, 4, 3)).reshape(-1, 4, 3)
     mhd = lambda v: o.mhat(v.reshape(-1, 1, 4, 3), dagger=True).reshape(-1, 4, 3)
-    L, gref = nn.sym_loss_and_grad(lat, f32(w), [b[:, 0] for b in bs], [x[:, 0] for x in xs], mh, mhd)
+    L, gref = nn.sym_loss_and_grad(lat, f32(w), [b[:, 0] for b in bs], [x[:, 0] for x in xs], mh, mhd, depth=depth)
     assert abs(loss - L) / L < 2e-2
-    n12 = 2 * 9 * ((8 + 16) + (64 + 16))
-    assert np.all(g[n12:] == 0)
+    n1 = 2 * 9 * (8 + 16)
+    nused = n1 if depth == 1 else n1 + 2 * 9 * (64 + 16)
+    assert np.all(g[nused:] == 0)
     cos = float(np.dot(g, gref) / np.linalg.norm(g) / np.linalg.norm(gref))
     assert cos > 0.999, cos
     assert rel_l2(g, gref) < 5e-2
 
 
-def test_trained_hermitian_form_preconditions_cg(S):
-    """Trained on pairs (b, N^{-1} b) of the field, the Hermitian form cuts
-    the iterations of the preconditioned CG (one network application per
-    iteration) below the identity network's, without falling back; the
-    solution is accepted by the oracle."""
+@pytest.mark.parametrize("depth", [2, 1])
+def test_trained_hermitian_form_preconditions_cg(S, depth):
+    """Trained on pairs (b, N^{-1} b) of the field, the Hermitian form (or
+    its short form) cuts the iterations of the preconditioned CG (one network
+    application per iteration) below the identity network's, without falling
+    back; the solution is accepted by the oracle."""
     tmx, ctx, lat, U = S
+    kind = tmx.TMX_SOLVER_PCG_NN_SYM if depth == 2 else tmx.TMX_SOLVER_PCG_NN_SYM1
+    loss_kind = tmx.TMX_LOSS_SYM if depth == 2 else tmx.TMX_LOSS_SYM1
     o = Oracle(DIMS, U, KAPPA, CSW, mu=MU0)
     n = 16
     bs = np.stack([synth.gaussian_cb_spinor(DIMS, 73, k) for k in range(n)])
@@ -335,14 +345,14 @@ def test_trained_hermitian_form_preconditions_cg(S):
     b = synth.gaussian_cb_spinor(DIMS, 74, 0)
     ctx.pc_set_weights(nn.identity_init(None))
     x = to_dev(np.zeros_like(b))
-    rc0, info0 = ctx.solve(x, to_dev(b), 1, kind=tmx.TMX_SOLVER_PCG_NN_SYM, op=1, tol=1e-10)
+    rc0, info0 = ctx.solve(x, to_dev(b), 1, kind=kind, op=1, tol=1e-10)
     ctx.pc_set_weights(nn.identity_init(np.random.default_rng(3), 1e-2))
-    losses = ctx.pc_train(to_dev(bs), xd, n, epochs=30, batch=4, lr=3e-3, seed=2, loss_kind=tmx.TMX_LOSS_SYM)
+    losses = ctx.pc_train(to_dev(bs), xd, n, epochs=30, batch=4, lr=3e-3, seed=2, loss_kind=loss_kind)
     assert losses[-1] < 0.7 * losses[0], losses
     x = to_dev(np.zeros_like(b))
-    rc1, info1 = ctx.solve(x, to_dev(b), 1, kind=tmx.TMX_SOLVER_PCG_NN_SYM, op=1, tol=0.9e-10, inner_prec=2)
-    print("PCG (Hermitian form) iterations identity / trained:", info0[0]["iters"], info1[0]["iters"],
-          "network applications", info1[0]["restarts"])
+    rc1, info1 = ctx.solve(x, to_dev(b), 1, kind=kind, op=1, tol=0.9e-10, inner_prec=2)
+    print(f"PCG (Hermitian form, depth {depth}) iterations identity / trained:", info0[0]["iters"],
+          info1[0]["iters"], "network applications", info1[0]["restarts"])
     assert rc0 == tmx.TMX_OK and rc1 == tmx.TMX_OK
     assert info0[0]["fallback"] == 0 and info1[0]["fallback"] == 0
     assert info1[0]["iters"] < info0[0]["iters"]

@@ -43,8 +43,9 @@ def test_network_tiled_full_size(base, rep):
     rng = np.random.default_rng(44)
     w = (rng.standard_normal(nn.num_params()) * 0.3).astype(np.float32)
     b0 = synth.gaussian_cb_spinor(base, 44, 0)
-    fns = {0: nn.forward, 1: nn.adjoint, 2: nn.sym_forward}
-    ref = {d: fns[d](lat, w.astype(np.float64), b0[:, 0]) for d in (0, 1, 2)}
+    fns = {0: nn.forward, 1: nn.adjoint, 2: nn.sym_forward,
+           3: lambda lt, ww, bb: nn.sym_forward(lt, ww, bb, depth=1)}
+    ref = {d: fns[d](lat, w.astype(np.float64), b0[:, 0]) for d in (0, 1, 2, 3)}
     ctx = tmx.Context(dims)
     ctx.set_params(tmx.Params(KAPPA, CSW, MU, 0.0, 0.0, -1))
     U = tile_links(U0, rep)
@@ -55,7 +56,7 @@ def test_network_tiled_full_size(base, rep):
     b = tile_cb(b0, base, rep)
     bd = to_dev(b)
     out = torch.zeros_like(bd)
-    for dagger in (0, 1, 2):  # K, K^dagger and the Hermitian form
+    for dagger in (0, 1, 2, 3):  # K, K^dagger, the Hermitian form and its short form
         ctx.pc_apply(out, bd, dagger)
         got = to_host(out, b.shape)[:, 0]
         want = tile_cb(ref[dagger][:, None], base, rep)[:, 0]

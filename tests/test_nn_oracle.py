@@ -177,26 +177,32 @@ def test_adam_scale_invariance():
     assert all(np.allclose(a - w0, -(b - w0), rtol=0, atol=1e-13) for a, b in zip(neg, ref))
 
 
-def test_hermitian_form_is_hermitian_and_positive(lat):
-    """P = A^dagger A: <u, P v> = <P u, v>, <v, P v> = |A v|^2 >= 0, and the
-    identity initialisation gives P = 1 (layers 1 and 2 the identity path)."""
+@pytest.mark.parametrize("depth", [2, 1])
+def test_hermitian_form_is_hermitian_and_positive(lat, depth):
+    """P = A^dagger A (A = L_2 L_1, or L_1 for the short form): <u, P v> =
+    <P u, v>, <v, P v> = |A v|^2 >= 0 with A applied directly, and the
+    identity initialisation gives P = 1 (the layers the identity path)."""
     L, _ = lat
     w = rand_params(8, 0.3)
     u = synth.gaussian_cb_spinor(DIMS, 5, 0)[:, 0]
     v = synth.gaussian_cb_spinor(DIMS, 5, 1)[:, 0]
-    Pu, Pv = nn.sym_forward(L, w, u), nn.sym_forward(L, w, v)
+    Pu, Pv = nn.sym_forward(L, w, u, depth=depth), nn.sym_forward(L, w, v, depth=depth)
     assert abs(np.vdot(u, Pv) - np.vdot(Pu, v)) < 1e-12 * abs(np.vdot(u, Pv))
     (C1, G1), (C2, G2) = nn.unflatten(w)[:2]
-    Av = nn.layer_forward(L, C2, G2, nn.layer_forward(L, C1, G1, L.embed_odd(v)))
+    Av = nn.layer_forward(L, C1, G1, L.embed_odd(v))
+    if depth == 2:
+        Av = nn.layer_forward(L, C2, G2, Av)
+    # only the odd sites of P v are kept, so <v, P v> = |A E_odd v|^2 exactly
     assert abs(np.vdot(v, Pv).real - np.vdot(Av, Av).real) < 1e-12 * np.vdot(Av, Av).real
     assert abs(np.vdot(v, Pv).imag) < 1e-12 * abs(np.vdot(v, Pv))
-    assert np.allclose(nn.sym_forward(L, nn.identity_init(None), v), v, rtol=0, atol=1e-15)
+    assert np.allclose(nn.sym_forward(L, nn.identity_init(None), v, depth=depth), v, rtol=0, atol=1e-15)
 
 
-def test_hermitian_form_gradient_matches_finite_differences(lat):
+@pytest.mark.parametrize("depth", [2, 1])
+def test_hermitian_form_gradient_matches_finite_differences(lat, depth):
     """Energy-norm loss of P = A^dagger A with the C oracle's Schur operator:
-    the gradient (layers 1 and 2 each used forward and as an adjoint) against
-    central differences; layers 3 and 4 do not enter."""
+    the gradient (each layer used forward and as an adjoint) against central
+    differences; the layers past A do not enter."""
     from oracle import Oracle
 
     L, U = lat
@@ -206,16 +212,20 @@ def test_hermitian_form_gradient_matches_finite_differences(lat):
     w = rand_params(9, 0.2)
     bs = [synth.gaussian_cb_spinor(DIMS, 3, 50 + i)[:, 0] for i in range(2)]
     xs = [synth.gaussian_cb_spinor(DIMS, 3, 60 + i)[:, 0] for i in range(2)]
-    loss, g = nn.sym_loss_and_grad(L, w, bs, xs, mh, mhd)
-    n12 = 2 * 9 * ((8 + 16) + (64 + 16))
-    assert np.all(g[n12:] == 0)
+    loss, g = nn.sym_loss_and_grad(L, w, bs, xs, mh, mhd, depth=depth)
+    n1 = 2 * 9 * (8 + 16)
+    nused = n1 if depth == 1 else n1 + 2 * 9 * (64 + 16)
+    assert np.all(g[nused:] == 0)
+    assert np.any(g[:n1] != 0)
     rng = np.random.default_rng(11)
-    idx = np.concatenate([rng.choice(2 * 9 * 24, 12, replace=False),
-                          2 * 9 * 24 + rng.choice(2 * 9 * 80, 16, replace=False)])
+    idx = rng.choice(n1, 12, replace=False)
+    if depth == 2:
+        idx = np.concatenate([idx, n1 + rng.choice(2 * 9 * 80, 16, replace=False)])
     h = 1e-5
     for k in idx:
         wp, wm = w.copy(), w.copy()
         wp[k] += h
         wm[k] -= h
-        fd = (nn.sym_loss_and_grad(L, wp, bs, xs, mh, mhd)[0] - nn.sym_loss_and_grad(L, wm, bs, xs, mh, mhd)[0]) / (2 * h)
+        fd = (nn.sym_loss_and_grad(L, wp, bs, xs, mh, mhd, depth=depth)[0]
+              - nn.sym_loss_and_grad(L, wm, bs, xs, mh, mhd, depth=depth)[0]) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1e-3, abs(g[k])) + 1e-9, (k, fd, g[k])
