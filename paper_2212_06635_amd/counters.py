@@ -2,11 +2,14 @@
 traffic they record.
 
 A summary is made from three runs of the same program (``bench.py --mode
-kernels``, which ends with device copies of a 2 GiB buffer):
+kernels``, which ends with device copies of a 2 GiB buffer), after one run
+that tunes the launch shapes into a cache file, so that the profiled runs
+launch what the benchmark launches without the tuner's sweeps:
 
-    rocprofv3 --kernel-trace --stats --output-format csv -d D/p_k -o k -- python3 bench.py --mode kernels
-    rocprofv3 --pmc FETCH_SIZE --output-format csv -d D/p_f -o f -- python3 bench.py --mode kernels
-    rocprofv3 --pmc WRITE_SIZE --output-format csv -d D/p_w -o w -- python3 bench.py --mode kernels
+    TMX_TUNE_CACHE=D/tune.txt python3 bench.py --mode kernels
+    TMX_TUNE_CACHE=D/tune.txt rocprofv3 --kernel-trace --stats --output-format csv -d D/p_k -o k -- python3 bench.py --mode kernels --no-tune
+    TMX_TUNE_CACHE=D/tune.txt rocprofv3 --pmc FETCH_SIZE --output-format csv -d D/p_f -o f -- python3 bench.py --mode kernels --no-tune
+    TMX_TUNE_CACHE=D/tune.txt rocprofv3 --pmc WRITE_SIZE --output-format csv -d D/p_w -o w -- python3 bench.py --mode kernels --no-tune
     python3 -m paper_2212_06635_amd.counters stencil D out.txt
 
 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what they read for
@@ -26,9 +29,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 STENCIL_SOURCES = ("csrc/dslash.hip", "csrc/tmx_device.h", "csrc/tmx_kernels.h")
 COPY_BYTES = 2 ** 31
 
-# rocprof kernel name -> bench label; dslash_kernel<P, NF, MODE>
-LABELS = {f"void tmx::dslash_kernel<{p}, 1, {m}>(tmx::DslashArgs)": f"K{m + 1}_{n}"
-          for p, n in ((0, "f64"), (1, "f32"), (2, "f16")) for m in (0, 1)}
+# rocprof kernel name -> bench label; dslash_kernel<P, NF, MODE, SPT> (sites per
+# thread: the tuned launch of a kernel uses one of the two)
+LABELS = {f"void tmx::dslash_kernel<{p}, 1, {m}, {t}>(tmx::DslashArgs)": f"K{m + 1}_{n}"
+          for p, n in ((0, "f64"), (1, "f32"), (2, "f16")) for m in (0, 1) for t in (1, 2)}
 
 
 def source_digest() -> str:
@@ -101,10 +105,12 @@ def summarize(d: str, vh: int) -> str:
     copy_ns = next(v for k, v in st.items() if "copyBuffer" in k)[1]
     lines = [
         f"# Schur-operator stencil kernels, V/2 = {vh} sites per launch, MI355X",
-        "# commands (from /tmp, TMPDIR=/tmp; <repo> = repository root):",
-        "#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/p_k -o k -- python3 <repo>/bench.py --mode kernels",
-        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/p_f -o f -- python3 <repo>/bench.py --mode kernels",
-        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/p_w -o w -- python3 <repo>/bench.py --mode kernels",
+        "# commands (from /tmp, TMPDIR=/tmp; <repo> = repository root; the first run tunes the launch shapes",
+        "#   into the cache the profiled runs read, so they launch what the benchmark launches):",
+        "#   TMX_TUNE_CACHE=<dir>/tune.txt python3 <repo>/bench.py --mode kernels",
+        "#   TMX_TUNE_CACHE=<dir>/tune.txt rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/p_k -o k -- python3 <repo>/bench.py --mode kernels --no-tune",
+        "#   TMX_TUNE_CACHE=<dir>/tune.txt rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/p_f -o f -- python3 <repo>/bench.py --mode kernels --no-tune",
+        "#   TMX_TUNE_CACHE=<dir>/tune.txt rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/p_w -o w -- python3 <repo>/bench.py --mode kernels --no-tune",
         "#   python3 -m paper_2212_06635_amd.counters stencil <dir> <this file>",
         "# bench.py --mode kernels: 10 Mhat applications per precision on the 32^3x64 field (eps 0.25, seed 4),",
         "#   then 3 device copies of a 2 GiB buffer",
