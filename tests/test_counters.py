@@ -8,7 +8,7 @@ import pytest
 
 from paper_2212_06635_amd import counters as C
 
-STENCIL = "void tmx::dslash_kernel<0, 1, 0>(tmx::DslashArgs)"  # K1 in FP64
+STENCIL = "void tmx::dslash_kernel<0, 1, 0, 1>(tmx::DslashArgs)"  # K1 in FP64, one site per thread
 COPY = "__amd_rocclr_copyBuffer"
 
 
