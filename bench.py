@@ -317,10 +317,13 @@ def main():
     x = torch.zeros_like(bd)
     names = {0: "f64", 1: "f32", 2: "f16"}
     tuned = {}
-    if not args.no_tune and args.mode == "full":
+    if not args.no_tune and args.mode in ("full", "kernels"):
         # every stencil the timed steps use: one right-hand side in three
         # precisions, the two-flavour operator in FP32 / FP16 / FP64 (FP64 for
-        # the reliable updates), and the 12 two-flavour right-hand sides
+        # the reliable updates), and the 12 two-flavour right-hand sides.
+        # With TMX_TUNE_CACHE set, the choices are appended to that file and a
+        # later context of the same lattice (a profiled --no-tune run) starts
+        # from them.
         t = time.perf_counter()
         for p in (0, 1, 2):
             ctx.tune(p, 1, 1)
