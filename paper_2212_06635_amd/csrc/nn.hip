@@ -674,9 +674,10 @@ struct ThinW {
     uint32_t C[NN_P][8][2];     // channel vector of path d, packed (re, -im), (im, re)
     uint32_t G[NN_P][4][4][2];  // spin matrix of path d, packed likewise
 };
-// the four ThinW sets: forward first layer (1 -> 8), forward last layer
-// (8 -> 1), and the adjoints of the last (1 -> 8) and of the first (8 -> 1)
-enum { THIN_UP_F = 0, THIN_DOWN_F = 1, THIN_UP_A = 2, THIN_DOWN_A = 3 };
+// the ThinW sets: forward first layer (1 -> 8), forward last layer (8 -> 1),
+// the adjoints of the last (1 -> 8) and of the first (8 -> 1), and the two
+// halves of the short Hermitian form P_1 = L_1^dagger L_1 (see nn_p1_down_kernel)
+enum { THIN_UP_F = 0, THIN_DOWN_F = 1, THIN_UP_A = 2, THIN_DOWN_A = 3, THIN_P1_UP = 4, THIN_P1_DOWN = 5, THIN_SETS = 6 };
 
 // one thread per path: the channel vector and spin matrix of path d of a
 // layer with cin * cout = 8 (forward), or of its adjoint W'_d = W_{rev d}^H
@@ -700,6 +701,71 @@ __global__ void nn_build_thin_kernel(const float *p, ThinW *w, int cin, int cout
             w->G[d][a][b][0] = f2bf2(re, -im);
             w->G[d][a][b][1] = f2bf2(im, re);
         }
+}
+
+// The short Hermitian form P_1 = L_1^dagger L_1 without its 8-channel
+// intermediate.  With h_d = Gamma_d T_d b (layer 1's path d before the
+// channel spread) and L_1^dagger's path d' = (C'_d' (x) Gamma'_d') T_d',
+// C'_d' = conj(C_{rev d'}), Gamma'_d' = Gamma_{rev d'}^H, the channel
+// contraction of L_1^dagger meets the channel spread of L_1 in
+//     M[d'][d] = sum_c C'_d'[c] C_d[c],
+//     P_1 b(s) = sum_d' Gamma'_d' T_d' z_d'(s + d'),  z_d'(e) = sum_d M[d'][d] h_d(e).
+// b lives on odd sites, so z_0 is needed at odd sites only, where it is
+// M[0][0] Gamma_0 b, and z_1 .. z_8 at even sites only, where d = 0
+// contributes nothing.  THIN_P1_UP holds C[d][c] = M[c + 1][d] (d, c + 1 >= 1)
+// and Gamma_d: the 1 -> 8 kernel on even sites then writes z_1 .. z_8 as its
+// eight channels.  THIN_P1_DOWN holds Gamma'_d' for d' >= 1 and, in place of
+// Gamma'_0, the site term G00 = M[0][0] Gamma'_0 Gamma_0.  One thread per
+// (d', d); p = the first layer's parameters.
+__global__ void nn_build_p1_kernel(const float *p, ThinW *w)
+{
+    const int t = threadIdx.x;
+    if (t >= NN_P * NN_P) return;
+    const int dp = t / NN_P, d = t % NN_P;
+    const int per = 8 + 16;  // one input channel, eight output channels
+    auto chan = [&](int path, int c) { return cx<float>{p[(size_t)path * per * 2 + 2 * c], p[(size_t)path * per * 2 + 2 * c + 1]}; };
+    auto gam = [&](int path, int a, int b) {
+        const float *g = p + (size_t)path * per * 2 + 2 * (8 + 4 * a + b);
+        return cx<float>{g[0], g[1]};
+    };
+    auto pack = [](cx<float> v, uint32_t *o) {
+        o[0] = f2bf2(v.re, -v.im);
+        o[1] = f2bf2(v.im, v.re);
+    };
+    const int rdp = rev_path(dp);
+    cx<float> m{0.f, 0.f};
+    for (int c = 0; c < 8; ++c) {
+        const cx<float> a = chan(rdp, c);
+        cmac(m, cx<float>{a.re, -a.im}, chan(d, c));
+    }
+    if (dp >= 1 && d >= 1) pack(m, w[THIN_P1_UP].C[d][dp - 1]);
+    if (dp == 0) {
+        // Gamma_d for the first half, Gamma'_d = Gamma_{rev d}^H for the second
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                pack(gam(d, a, b), w[THIN_P1_UP].G[d][a][b]);
+                if (d >= 1) {
+                    const cx<float> g = gam(rev_path(d), b, a);
+                    pack(cx<float>{g.re, -g.im}, w[THIN_P1_DOWN].G[d][a][b]);
+                }
+            }
+    }
+    if (dp == 0 && d == 0) {
+        // G00 = M[0][0] Gamma'_0 Gamma_0, Gamma'_0 = Gamma_0^H
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                cx<float> v{0.f, 0.f};
+                for (int k = 0; k < 4; ++k) {
+                    const cx<float> ga = gam(0, k, a);
+                    cmac(v, cx<float>{ga.re, -ga.im}, gam(0, k, b));
+                }
+                pack(m * v, w[THIN_P1_DOWN].G[0][a][b]);
+            }
+    }
+    if (dp >= 1 && d == 0) {
+        // unused channel weights of the first half's d = 0 path (odd tiles are not launched)
+        w[THIN_P1_UP].C[0][dp - 1][0] = w[THIN_P1_UP].C[0][dp - 1][1] = 0u;
+    }
 }
 
 // c + a.lo b.lo + a.hi b.hi over BF16 pairs, FP32 accumulation
@@ -852,15 +918,16 @@ __device__ __forceinline__ void up_paths(const Geom &g, const SpinorPtr &src, co
 
 // 1 -> 8: y_c(x) = sum_d C_d[c] (Gamma_d T_d r)(x) for an odd source r
 // (precision P): odd sites take the d = 0 path only, even sites the eight hops.
-// Tiles of 64 sites of one parity, alternating (tile 2 i + p).
+// Tiles of 64 sites of one parity, alternating (tile 2 i + p); with
+// even_only, even tiles only (tile i), the odd half of y left untouched.
 template <int P>
 __global__ void __launch_bounds__(256) nn_up_kernel(Geom g, SpinorPtr src, Act y, NnLinks L, const ThinW *W,
-                                                    int t_bc, int xcd)
+                                                    int t_bc, int xcd, int even_only)
 {
     __shared__ __attribute__((aligned(16))) uint32_t ys[8 * 64 * 12];  // [channel][site][12 words]
     const long tile = xcd_block(xcd);
-    const int p = (int)(tile & 1);
-    const long s0 = (tile >> 1) * 64;
+    const int p = even_only ? 0 : (int)(tile & 1);
+    const long s0 = (even_only ? tile : (tile >> 1)) * 64;
     const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
     const long s = s0 + sl;
     // every lane runs the paths (the quad exchange needs all four lanes):
@@ -966,6 +1033,59 @@ __global__ void __launch_bounds__(256) nn_down_kernel(Geom g, Act xin, SpinorPtr
     }
 }
 
+// Second half of P_1 = L_1^dagger L_1 on odd sites (see nn_build_p1_kernel):
+//     y(s) = G00 r(s) + sum_{d' >= 1} T_d' Gamma'_d' z_d'(s + d'),
+// r the odd source (precision P), z_d' channel d' - 1 of the even half of z
+// (written by nn_up_kernel with THIN_P1_UP, even tiles only).  One channel
+// per path instead of eight: no channel contraction.  FP32 odd output,
+// staged in LDS as in nn_down_kernel.
+template <int P>
+__global__ void __launch_bounds__(256) nn_p1_down_kernel(Geom g, SpinorPtr src, Act z, SpinorPtr yo, NnLinks L,
+                                                         const ThinW *W, int t_bc, int xcd)
+{
+    __shared__ __attribute__((aligned(16))) float ys[64 * 24];
+    const long s0 = (long)xcd_block(xcd) * 64;
+    const int sl = threadIdx.x / 4, q = threadIdx.x % 4;
+    const long s = s0 + sl;
+    // lanes past the end repeat the last site (the quad exchange needs all
+    // four lanes of a site); their rows of the tile are never stored
+    const long sc = s < g.Vh ? s : g.Vh - 1;
+    int x[4];
+    cb_coords(g, (int)sc, 1, x);
+    cx<float> acc[3];
+    {
+        cx<float> v[3];
+        load_spin<P>(src, sc, q, v);
+        uint32_t vb[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) vb[a] = f2bf2(v[a].re, v[a].im);
+        spin_mix(W, 0, q, vb, acc);
+    }
+#pragma unroll
+    for (int d = 1; d < NN_P; ++d) {
+        const Nbr nb = path_neighbour_at(g, x, 1, (int)sc, d, t_bc);
+        const uint32_t *zp = z.d + ((long)(d - 1) * z.stride + nb.idx) * 12 + 3 * q;
+        const uint32_t w[3] = {zp[0], zp[1], zp[2]};
+        cx<float> h[3], t[3];
+        spin_mix(W, d, q, w, h);
+        transport_bf(L, nb, d, h, t);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[a] = acc[a] + t[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ys[sl * 24 + 6 * q + 2 * a] = acc[a].re;
+        ys[sl * 24 + 6 * q + 2 * a + 1] = acc[a].im;
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v < 6 * 64; v += blockDim.x) {
+        const int kv = v / 64, sn = v % 64;
+        if (s0 + sn >= g.Vh) continue;
+        reinterpret_cast<float4 *>(yo.d)[(long)kv * yo.stride + s0 + sn] =
+            *reinterpret_cast<const float4 *>(&ys[sn * 24 + 4 * kv]);
+    }
+}
+
 // sum of the per-block partials: P[i] = sum_b partial[b][i]
 __global__ void nn_reduce_partials_kernel(const float *partial, int nblocks, int n, float *P)
 {
@@ -1056,7 +1176,7 @@ int nn_ensure(tmx_ctx *c)
     float *bufs[4];
     for (int i = 0; i < 4; ++i) bufs[i] = static_cast<float *>(dev_alloc(c, bytes));
     uint16_t *wf[NN_L], *wa[NN_L];
-    ThinW *thin = static_cast<ThinW *>(dev_alloc(c, 4 * sizeof(ThinW)));
+    ThinW *thin = static_cast<ThinW *>(dev_alloc(c, THIN_SETS * sizeof(ThinW)));
     bool ok = bufs[0] && bufs[1] && bufs[2] && bufs[3] && thin;
     for (int l = 0; l < NN_L; ++l) {
         const size_t nf = (size_t)NN_P * pad16(8 * NN_COUT[l]) * pad16(8 * NN_CIN[l]);
@@ -1104,6 +1224,7 @@ int nn_build_weights(tmx_ctx *c)
     hipLaunchKernelGGL(nn_build_thin_kernel, dim3(1), dim3(64), 0, c->stream, p3, s.thin + THIN_DOWN_F, 8, 1, 0);
     hipLaunchKernelGGL(nn_build_thin_kernel, dim3(1), dim3(64), 0, c->stream, p3, s.thin + THIN_UP_A, 8, 1, 1);
     hipLaunchKernelGGL(nn_build_thin_kernel, dim3(1), dim3(64), 0, c->stream, p0, s.thin + THIN_DOWN_A, 1, 8, 1);
+    hipLaunchKernelGGL(nn_build_p1_kernel, dim3(1), dim3(NN_P * NN_P), 0, c->stream, p0, s.thin);
     int r = hip_err(c, hipGetLastError(), "build weights");
     if (!r) s.w_ok = true;
     return r;
@@ -1162,23 +1283,44 @@ int launch_layer(tmx_ctx *c, int cin, int cout, Act x, Act y, SpinorPtr yo, cons
     return hip_err(c, hipGetLastError(), "network layer");
 }
 
-// first layer (1 -> 8) on the odd field r of precision pr, straight from the field
-int launch_up(tmx_ctx *c, SpinorPtr r, int pr, Act y, const ThinW *W)
+// first layer (1 -> 8) on the odd field r of precision pr, straight from the
+// field; with even_only, the even half of y only (the first half of P_1)
+int launch_up(tmx_ctx *c, SpinorPtr r, int pr, Act y, const ThinW *W, int even_only = 0)
 {
     NnLinks L;
     int rc = nn_links(c, L);
     if (rc) return rc;
-    const dim3 grid((unsigned)(2 * ((c->Vh + 63) / 64))), block(256);
+    const long tiles = (c->Vh + 63) / 64;
+    const dim3 grid((unsigned)(even_only ? tiles : 2 * tiles)), block(256);
     const int tb = c->par.t_bc, xcd = c->xcd_remap;
-    kstat_begin(c, "NN_1x8");
+    kstat_begin(c, even_only ? "NN_P1_UP" : "NN_1x8");
     if (pr == F64)
-        hipLaunchKernelGGL(nn_up_kernel<F64>, grid, block, 0, c->stream, c->g, r, y, L, W, tb, xcd);
+        hipLaunchKernelGGL(nn_up_kernel<F64>, grid, block, 0, c->stream, c->g, r, y, L, W, tb, xcd, even_only);
     else if (pr == F32)
-        hipLaunchKernelGGL(nn_up_kernel<F32>, grid, block, 0, c->stream, c->g, r, y, L, W, tb, xcd);
+        hipLaunchKernelGGL(nn_up_kernel<F32>, grid, block, 0, c->stream, c->g, r, y, L, W, tb, xcd, even_only);
     else
-        hipLaunchKernelGGL(nn_up_kernel<F16>, grid, block, 0, c->stream, c->g, r, y, L, W, tb, xcd);
+        hipLaunchKernelGGL(nn_up_kernel<F16>, grid, block, 0, c->stream, c->g, r, y, L, W, tb, xcd, even_only);
     kstat_end(c);
     return hip_err(c, hipGetLastError(), "network first layer");
+}
+
+// second half of P_1 on the odd source r (precision pr) and the path fields z
+int launch_p1_down(tmx_ctx *c, SpinorPtr r, int pr, Act z, SpinorPtr yo, const ThinW *W)
+{
+    NnLinks L;
+    int rc = nn_links(c, L);
+    if (rc) return rc;
+    const dim3 grid((unsigned)((c->Vh + 63) / 64)), block(256);
+    const int tb = c->par.t_bc, xcd = c->xcd_remap;
+    kstat_begin(c, "NN_P1_DOWN");
+    if (pr == F64)
+        hipLaunchKernelGGL(nn_p1_down_kernel<F64>, grid, block, 0, c->stream, c->g, r, z, yo, L, W, tb, xcd);
+    else if (pr == F32)
+        hipLaunchKernelGGL(nn_p1_down_kernel<F32>, grid, block, 0, c->stream, c->g, r, z, yo, L, W, tb, xcd);
+    else
+        hipLaunchKernelGGL(nn_p1_down_kernel<F16>, grid, block, 0, c->stream, c->g, r, z, yo, L, W, tb, xcd);
+    kstat_end(c);
+    return hip_err(c, hipGetLastError(), "network P_1");
 }
 
 // last layer (8 -> 1) into the FP32 odd field yo
@@ -1254,6 +1396,12 @@ int nn_forward_sym(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, int depth, st
     }
     Act a1 = act(c, keep ? "a1" : "p1", 8);
     if (!a1.d) return TMX_ENOMEM;
+    // P_1 without kept activations: the two path-channel halves (no 8-channel
+    // intermediate on odd sites, one channel per path in the second half)
+    if (depth == 1 && !keep) {
+        int rc = launch_up(c, r, pr, a1, thin + THIN_P1_UP, 1);
+        return rc ? rc : launch_p1_down(c, r, pr, a1, out, thin + THIN_P1_DOWN);
+    }
     int rc = launch_up(c, r, pr, a1, thin + THIN_UP_F);  // L_1
     if (rc) return rc;
     if (keep) acts->push_back(a1);

@@ -198,6 +198,30 @@ def test_hermitian_form_is_hermitian_and_positive(lat, depth):
     assert np.allclose(nn.sym_forward(L, nn.identity_init(None), v, depth=depth), v, rtol=0, atol=1e-15)
 
 
+def test_short_form_through_path_channels(lat):
+    """The library applies P_1 = L_1^dagger L_1 without the 8-channel
+    intermediate: with h_d = Gamma_d T_d b and M[d'][d] = sum_c
+    conj(C_{rev d'}[c]) C_d[c] (the adjoint's channel contraction met by the
+    first layer's channel spread), P_1 b = sum_d' Gamma_{rev d'}^H T_d'
+    z_d', z_d' = sum_d M[d'][d] h_d.  That rewriting against the layer-by-layer
+    form."""
+    L, _ = lat
+    w = rand_params(12, 0.3)
+    b = synth.gaussian_cb_spinor(DIMS, 12, 0)[:, 0]
+    C, G = nn.unflatten(w)[0]
+    x = L.embed_odd(b)
+    h = [np.einsum("st,ovtc->ovsc", G[d], L.transport(x, d)) for d in range(nn.NPATH)]
+    M = np.array([[np.sum(np.conj(C[nn.reverse_path(dp)][:, 0]) * C[d][:, 0]) for d in range(nn.NPATH)]
+                  for dp in range(nn.NPATH)])
+    out = np.zeros_like(x)
+    for dp in range(nn.NPATH):
+        z = sum(M[dp, d] * h[d] for d in range(nn.NPATH))
+        Gp = np.conj(G[nn.reverse_path(dp)]).T
+        out += L.transport(np.einsum("st,ovtc->ovsc", Gp, z), dp)
+    ref = nn.sym_forward(L, w, b, depth=1)
+    assert np.allclose(L.restrict_odd(out), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("depth", [2, 1])
 def test_hermitian_form_gradient_matches_finite_differences(lat, depth):
     """Energy-norm loss of P = A^dagger A with the C oracle's Schur operator:
