@@ -123,6 +123,20 @@ static __global__ void cg_alpha_kernel(const double *pq, AlphaArgs a, double *al
     if (k < a.cols) alpha[k] = (a.active[k] && pq[k] != 0.0) ? a.rho[k] / pq[k] : 0.0;
 }
 
+// preconditioned CG step length alpha = rho / <p, q> on the device (0 for a
+// non-positive <p, q>: breakdown, seen on the host when it reads alpha), also
+// stored in the last slot of the pinned reduction buffer so that the host
+// reads it with the next readback instead of a round trip of its own
+constexpr int PCG_ALPHA_SLOT = MAXR * 4 - 1;
+static __global__ void pcg_alpha_kernel(const double *pq, double rho, double *alpha, double *host_red)
+{
+    if (threadIdx.x == 0) {
+        const double a = pq[0] > 0.0 ? rho / pq[0] : 0.0;
+        alpha[0] = a;
+        if (host_red) host_red[PCG_ALPHA_SLOT] = a;
+    }
+}
+
 // true residual r = b - (N + sigma) x (FP64); writes rlo if PL given; returns |r|^2 per column
 template <int PL>
 static int true_residual(Sys &S, SpinorPtr r, SpinorPtr rlo, bool write_lo, SpinorPtr b, SpinorPtr x,
@@ -393,7 +407,13 @@ static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const double *sigma, co
     SpinorPtr xl = S.field("xl", F32, 1), z = S.field("z", F32, 1), tz = S.field("tz", F32, 1);
     SpinorPtr rf = P == F16 ? S.field("rf", F32, 1) : SpinorPtr{};
     TRY(S.need());
-    double bb, rr, rmax, rho, pq, dots[2];
+    // <p, N p> = |Mhat p|^2 from the per-slot norms of the operator's first
+    // half when unshifted (as in cg_core); the step length stays on the device
+    const bool shifted = sigma && sigma[0] != 0.0;
+    double *alpha_d = static_cast<double *>(ws_get(c, "pcg_alpha", sizeof(double)));
+    double *pnrm = shifted ? nullptr : static_cast<double *>(ws_get(c, "cg_pnrm", sizeof(double) * c->Vh));
+    if (!alpha_d || (!shifted && !pnrm)) return set_err(c, TMX_ENOMEM, "solver workspace: out of device memory");
+    double bb, rr, rmax, rho, dots[2];
     TRY((copy_field<F64, F64>(S, r, b, 1, &bb)));
     if (!x_is_guess) TRY(zero_field<F64>(S, x, 1));
     if (bb == 0) {
@@ -420,19 +440,37 @@ static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const double *sigma, co
     bool after_reliable = false;
     const double t0 = now_seconds();
     while (std::sqrt(rr) > tol * std::sqrt(bb) && it < maxiter) {
-        TRY(apply_shifted<P>(S, q, p, sigma, 1, &pq));
+        if (!(rho > 0)) return set_err(c, TMX_ENOCONV, "preconditioned CG breakdown");
+        if (shifted) {
+            TRY(apply_shifted<P>(S, q, p, sigma, 1, nullptr));
+        } else {
+            TRY(S.N(q, p, P, 1, pnrm));
+            OpSlotSum sum{};
+            sum.v = pnrm;
+            HTRY(run_blas(sum, c->Vh, 1, c->red, c->stream), "<p, N p>");
+        }
         ++it;
-        if (!(pq > 0) || !(rho > 0)) return set_err(c, TMX_ENOCONV, "preconditioned CG breakdown");
-        const double alpha = rho / pq;
+        hipLaunchKernelGGL(pcg_alpha_kernel, dim3(1), dim3(64), 0, c->stream, c->red.result, rho, alpha_d,
+                           c->red.host);
+        HTRY(hipGetLastError(), "pcg step length");
         OpAxpyNorm<F32, P, P, P> up{};
         up.x = xl;
         up.p = p;
         up.r = rl;
         up.q = q;
         up.nf = 1;
-        up.a[0] = alpha;
+        up.ad = alpha_d;
         HTRY(run_blas(up, c->Vh, 1, c->red, c->stream), "pcg update");
         TRY(fetch(c, 1, &rr));
+        // the step length, from the pinned slot (written before the readback
+        // just taken) or copied when the reduction buffer is not mapped
+        double alpha = 0.0;
+        if (c->red.host) {
+            alpha = c->host_red[PCG_ALPHA_SLOT];
+        } else {
+            HTRY(hipMemcpy(&alpha, alpha_d, sizeof(double), hipMemcpyDeviceToHost), "pcg step length readback");
+        }
+        if (!(alpha > 0)) return set_err(c, TMX_ENOCONV, "preconditioned CG breakdown");
         if (!std::isfinite(rr)) return set_err(c, TMX_ENOCONV, "preconditioned CG: non-finite residual");
         rmax = std::max(rmax, rr);
         after_reliable = false;
