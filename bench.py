@@ -341,8 +341,9 @@ def main():
         from_oracle_free_init(w0, np.random.default_rng(3))
         ctx.pc_set_weights(w0)
         o = torch.zeros_like(bd)
-        for _ in range(5):
-            ctx.pc_apply(o, bd, 0)
+        for mode in (0, 3):  # K, then the short Hermitian form P_1 through path channels
+            for _ in range(5):
+                ctx.pc_apply(o, bd, mode)
         # a device copy of 2 GiB, whose FETCH_SIZE / WRITE_SIZE calibrate the counters
         a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")
         a.fill_(1.0)
@@ -350,7 +351,7 @@ def main():
         for _ in range(3):
             c.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"mode": "nn", "lattice": list(dims), "applies": 5}), flush=True)
+        print(json.dumps({"mode": "nn", "lattice": list(dims), "applies": {"K": 5, "P_1": 5}}), flush=True)
         ctx.close()
         return
     if args.mode == "force":

@@ -190,6 +190,7 @@ def network(d: str, v: int) -> str:
         "#   python3 -m paper_2212_06635_amd.counters network <dir> <this file>",
         "# bench.py --mode nn: 5 applications of K (layers 1->8, 8->8, 8->8, 8->1) on the 32^3x64 field",
         "#   (the one-channel layers 1->8 and 8->1 on the vector ALUs, the 8->8 layers on the matrix cores),",
+        "#   then 5 of P_1 = L_1^dagger L_1 through path channels (P1_UP: 1->8 on even tiles, P1_DN),",
         "#   then 3 device copies of a 2 GiB buffer (counter calibration)",
         f"# FETCH scale {sf:.3f}, WRITE scale {sw:.3f}; 8->8 layer work per site: dense 2 x 64 x 64 x 27 flops",
         "#   (9 paths x 3 colours of the real 64 x 64 Kronecker product the matrix cores run, TF_dense) and the",
@@ -201,8 +202,12 @@ def network(d: str, v: int) -> str:
         if "nn_layer_kernel" in name:
             tag = name[name.index("<") + 1:name.index(">")].replace(", ", "x")
         elif "nn_up_kernel" in name:
-            # one-channel layer on the vector ALUs (forward 1->8, adjoint of 8->1), per source precision
-            tag = "1x8" + ("_" + name[name.index("<") + 1:name.index(">")].split("::")[-1] if "<" in name else "")
+            # one-channel layer on the vector ALUs (forward 1->8, adjoint of 8->1), per source precision;
+            # on even tiles only: the first half of P_1 (path channels)
+            targs = name[name.index("<") + 1:name.index(">")].split(", ") if "<" in name else ["", "false"]
+            tag = ("P1_UP" if targs[-1] == "true" else "1x8") + "_" + targs[0]
+        elif "nn_p1_down_kernel" in name:
+            tag = "P1_DN_" + name[name.index("<") + 1:name.index(">")] if "<" in name else "P1_DN"
         elif "nn_down_kernel" in name:
             tag = "8x1"     # forward 8->1, adjoint of 1->8
         else:
@@ -260,11 +265,57 @@ def force(d: str, v: int) -> str:
     return "\n".join(lines) + "\n"
 
 
+SQ_COUNTERS = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU",
+               "SQ_ACTIVE_INST_VMEM", "SQ_INSTS_VALU", "SQ_INSTS_VMEM_RD")
+
+
+def sq_table(dirs) -> str:
+    """Wave-level counters of the hot kernels from one --pmc pass per program
+    (`dirs`: label=directory pairs): the share of each wave's life spent
+    waiting on an operand (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES) and issuing
+    vector ALU work (SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES), and the VALU and
+    vector-memory-read instructions per wave."""
+    lines = [
+        "# wave-level SQ counters of the hot kernels, 32^3x64, MI355X",
+        "# commands (from /tmp, TMPDIR=/tmp; <repo> = repository root), one per bench mode m in nn, force, kernels:",
+        "#   rocprofv3 --pmc " + " ".join(SQ_COUNTERS) + " --output-format csv -d <dir>/sq_m -o q -- "
+        "python3 <repo>/bench.py --mode m --no-tune",
+        "#   python3 -m paper_2212_06635_amd.counters sq nn=<dir>/sq_nn force=<dir>/sq_force "
+        "kernels=<dir>/sq_kernels <this file>",
+        "# wait = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES, valu = SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES (per wave, summed",
+        "#   over the dispatches of a kernel); insts per wave = SQ_INSTS_* / SQ_WAVES",
+        "",
+        f"{'mode':8s} {'kernel':44s} {'disp':>4s} {'waves/disp':>10s} {'wait':>5s} {'valu':>5s} "
+        f"{'valu/wave':>9s} {'vmem_rd/wave':>12s}",
+    ]
+    for item in dirs:
+        label, d = item.split("=", 1)
+        agg = collections.defaultdict(lambda: collections.defaultdict(float))
+        disp = collections.defaultdict(set)
+        for r in csv.DictReader(open(_find(d, "counter_collection.csv"))):
+            agg[r["Kernel_Name"]][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp[r["Kernel_Name"]].add(r.get("Dispatch_Id", ""))
+        for name in sorted(agg):
+            short = name.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
+            if not any(t in short for t in ("dslash_kernel", "nn_", "force_kernel", "insertion_kernel")):
+                continue
+            if "build" in short or "links" in short:
+                continue
+            v, n = agg[name], max(len(disp[name]), 1)
+            wc = max(v["SQ_WAVE_CYCLES"], 1.0)
+            nw = max(v["SQ_WAVES"], 1.0)
+            lines.append(f"{label:8s} {short[:44]:44s} {n:4d} {nw / n:10.0f} {v['SQ_WAIT_INST_ANY'] / wc:5.2f} "
+                         f"{v['SQ_ACTIVE_INST_VALU'] / wc:5.2f} {v['SQ_INSTS_VALU'] / nw:9.0f} "
+                         f"{v['SQ_INSTS_VMEM_RD'] / nw:12.0f}")
+    return "\n".join(lines) + "\n"
+
+
 if __name__ == "__main__":
     usage = ("usage: python3 -m paper_2212_06635_amd.counters stencil <rocprof dir> <summary>\n"
              "       python3 -m paper_2212_06635_amd.counters network <rocprof dir> <summary>\n"
              "       python3 -m paper_2212_06635_amd.counters force <rocprof dir> <summary>\n"
-             "       python3 -m paper_2212_06635_amd.counters stats <kernel_stats.csv> <summary> <title> <command>")
+             "       python3 -m paper_2212_06635_amd.counters stats <kernel_stats.csv> <summary> <title> <command>\n"
+             "       python3 -m paper_2212_06635_amd.counters sq <label>=<rocprof dir> ... <summary>")
     a = sys.argv[1:]
     if len(a) >= 3 and a[0] == "stencil":
         txt = summarize(a[1], 1048576)
@@ -272,11 +323,13 @@ if __name__ == "__main__":
         txt = network(a[1], 2097152)
     elif len(a) >= 3 and a[0] == "force":
         txt = force(a[1], 2097152)
+    elif len(a) >= 3 and a[0] == "sq":
+        txt = sq_table(a[1:-1])
     elif len(a) == 5 and a[0] == "stats":
         txt = kernel_table(a[1], a[3], a[4])
     else:
         print(usage, file=sys.stderr)
         sys.exit(2)
-    with open(a[2], "w") as fh:
+    with open(a[-1] if a[0] == "sq" else a[2], "w") as fh:
         fh.write(txt)
     print(txt, end="")

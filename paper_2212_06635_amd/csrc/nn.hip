@@ -920,10 +920,11 @@ __device__ __forceinline__ void up_paths(const Geom &g, const SpinorPtr &src, co
 // (precision P): odd sites take the d = 0 path only, even sites the eight hops.
 // Tiles of 64 sites of one parity, alternating (tile 2 i + p); with
 // even_only, even tiles only (tile i), the odd half of y left untouched.
-template <int P>
+template <int P, bool EVEN_ONLY>
 __global__ void __launch_bounds__(256) nn_up_kernel(Geom g, SpinorPtr src, Act y, NnLinks L, const ThinW *W,
-                                                    int t_bc, int xcd, int even_only)
+                                                    int t_bc, int xcd)
 {
+    constexpr int even_only = EVEN_ONLY ? 1 : 0;
     __shared__ __attribute__((aligned(16))) uint32_t ys[8 * 64 * 12];  // [channel][site][12 words]
     const long tile = xcd_block(xcd);
     const int p = even_only ? 0 : (int)(tile & 1);
@@ -1283,6 +1284,16 @@ int launch_layer(tmx_ctx *c, int cin, int cout, Act x, Act y, SpinorPtr yo, cons
     return hip_err(c, hipGetLastError(), "network layer");
 }
 
+template <int P>
+static void up_launch(tmx_ctx *c, dim3 grid, dim3 block, SpinorPtr r, Act y, const NnLinks &L, const ThinW *W, int tb,
+                      int xcd, int even_only)
+{
+    if (even_only)
+        hipLaunchKernelGGL((nn_up_kernel<P, true>), grid, block, 0, c->stream, c->g, r, y, L, W, tb, xcd);
+    else
+        hipLaunchKernelGGL((nn_up_kernel<P, false>), grid, block, 0, c->stream, c->g, r, y, L, W, tb, xcd);
+}
+
 // first layer (1 -> 8) on the odd field r of precision pr, straight from the
 // field; with even_only, the even half of y only (the first half of P_1)
 int launch_up(tmx_ctx *c, SpinorPtr r, int pr, Act y, const ThinW *W, int even_only = 0)
@@ -1295,11 +1306,11 @@ int launch_up(tmx_ctx *c, SpinorPtr r, int pr, Act y, const ThinW *W, int even_o
     const int tb = c->par.t_bc, xcd = c->xcd_remap;
     kstat_begin(c, even_only ? "NN_P1_UP" : "NN_1x8");
     if (pr == F64)
-        hipLaunchKernelGGL(nn_up_kernel<F64>, grid, block, 0, c->stream, c->g, r, y, L, W, tb, xcd, even_only);
+        up_launch<F64>(c, grid, block, r, y, L, W, tb, xcd, even_only);
     else if (pr == F32)
-        hipLaunchKernelGGL(nn_up_kernel<F32>, grid, block, 0, c->stream, c->g, r, y, L, W, tb, xcd, even_only);
+        up_launch<F32>(c, grid, block, r, y, L, W, tb, xcd, even_only);
     else
-        hipLaunchKernelGGL(nn_up_kernel<F16>, grid, block, 0, c->stream, c->g, r, y, L, W, tb, xcd, even_only);
+        up_launch<F16>(c, grid, block, r, y, L, W, tb, xcd, even_only);
     kstat_end(c);
     return hip_err(c, hipGetLastError(), "network first layer");
 }
