@@ -163,6 +163,18 @@ int tmx_set_stream(tmx_ctx *ctx, void *hip_stream);
 int tmx_set_allocator(tmx_ctx *ctx, void *(*alloc)(size_t bytes, void *user), void (*release)(void *ptr, void *user),
                       void *user);
 
+/* Memory management (library infrastructure, no passage of the paper).
+ * Give every scratch buffer of the context back to its allocator: solver
+ * fields, network activations, force and tuning workspaces (TMX_WS_LIMIT
+ * counts from zero again).  The gauge field, the clover terms
+ * and inverses, the network weights and the reduction buffers stay; later
+ * calls allocate again what they need.  For a caller that runs a large solve
+ * after others on one context, so that the earlier calls' buffers do not sit
+ * beside the new ones (the 64^3x128 multishift solve after CG and the
+ * network-preconditioned solve).  Waits for the context's stream first.
+ * TMX_EINVAL for a null context. */
+int tmx_free_workspaces(tmx_ctx *ctx);
+
 /* Parameters.  Changing mu / mubar / epsbar invalidates only the site-block
  * inverses; changing kappa or csw also invalidates the clover term. */
 int tmx_set_params(tmx_ctx *ctx, const tmx_params *p);

@@ -716,6 +716,17 @@ int tmx_destroy(tmx_ctx *c)
     return TMX_OK;
 }
 
+int tmx_free_workspaces(tmx_ctx *c)
+{
+    if (!c) return TMX_EINVAL;
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_err(c, e, "tmx_free_workspaces");
+    for (auto &kv : c->ws) dev_free(c, kv.second.p);
+    c->ws.clear();
+    c->ws_bytes = 0;
+    return TMX_OK;
+}
+
 const char *tmx_last_error(const tmx_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 int tmx_set_stream(tmx_ctx *c, void *s)

@@ -86,6 +86,7 @@ def _load():
         "tmx_set_stream": ([P, P], I),
         "tmx_set_params": ([P, ctypes.POINTER(tmx_params)], I),
         "tmx_set_allocator": ([P, ALLOC_FN, RELEASE_FN, P], I),
+        "tmx_free_workspaces": ([P], I),
         "tmx_load_gauge": ([P, P, D], I),
         "tmx_gauge_uploads": ([P], I),
         "tmx_load_clover": ([P, P], I),
@@ -407,6 +408,10 @@ class Context:
         w = np.empty(self.pc_num_params(), dtype=np.float32)
         self.check(lib.tmx_pc_get_weights(self.h, w.ctypes.data, w.size))
         return w
+
+    def free_workspaces(self):
+        """Give the context's scratch buffers back (tmx_free_workspaces)."""
+        return self.check(lib.tmx_free_workspaces(self.h))
 
     def pc_apply(self, out, inp, dagger=0):
         return self.check(lib.tmx_pc_apply(self.h, _ptr(out), _ptr(inp), int(dagger)))

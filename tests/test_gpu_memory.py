@@ -29,8 +29,17 @@ def test_allocator_hook_serves_every_device_buffer():
     U = synth.gauge_links(dims, 0.3, 11)
     o = Oracle(dims, U, KAPPA, CSW, mu=MU0, mubar=MUBAR, epsbar=EPSBAR)
     # the library's code objects (with their static scratch) are loaded on the
-    # device by the first context of the process: load them before measuring
-    tmx.Context((4, 4, 4, 4), allocator="hip").close()
+    # device by the first context of the process, and the HIP runtime reserves
+    # per-lane scratch memory for the clover build and inversion kernels
+    # (which spill) at their first launch: both before measuring
+    w = tmx.Context((4, 4, 4, 4), allocator="hip")
+    w.set_params(tmx.Params(KAPPA, CSW, MU0, MUBAR, EPSBAR, -1))
+    w.load_gauge(synth.gauge_links((4, 4, 4, 4), 0.3, 1), 1.0)
+    for nf, op in ((1, 1), (2, 2)):
+        kind = tmx.TMX_FIELD_ODD if nf == 1 else tmx.TMX_FIELD_ODD_ND
+        v = to_dev(synth.gaussian_cb_spinor((4, 4, 4, 4), 1, 0, nf))
+        w.apply_mhat(w.empty(kind, 0), w.pack(v, kind, 0), op, 0)
+    w.close()
     torch.cuda.synchronize()
     free0 = torch.cuda.mem_get_info()[0]
     res0 = torch.cuda.memory_reserved()
@@ -156,4 +165,42 @@ def test_workspace_limit_gives_enomem(small, monkeypatch):
     x = to_dev(np.zeros_like(b))
     rc, info = ctx.solve(x, to_dev(b), 1, kind=tmx.TMX_SOLVER_PCG_NN, op=1, inner_prec=2)
     assert rc == tmx.TMX_OK and o.residual(b, to_host(x, b.shape)) <= 1e-10
+    ctx.close()
+
+
+def test_free_workspaces_returns_scratch():
+    """tmx_free_workspaces gives the scratch of earlier calls (solver fields,
+    network activations) back through the allocator hook and keeps the
+    fields: the same solve afterwards still converges to the oracle's
+    residual, with the scratch allocated again."""
+    import torch
+
+    import paper_2212_06635_amd.tmx as tmx
+
+    dims = (8, 8, 8, 8)
+    print(f"\n[gpu memory] free workspaces, {dims}", flush=True)
+    U = synth.gauge_links(dims, 0.3, 12)
+    o = Oracle(dims, U, KAPPA, CSW, mu=MU0)
+    ctx = tmx.Context(dims, allocator="torch")
+    A = ctx.allocator
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU0, 0.0, 0.0, -1))
+    ctx.load_gauge(U, 12.0)
+    ctx.pc_set_weights(nn.identity_init(np.random.default_rng(1), 1e-2))
+    b = synth.gaussian_cb_spinor(dims, 12, 0)
+    x = to_dev(np.zeros_like(b))
+    for kind, ip in ((tmx.TMX_SOLVER_CG, 1), (tmx.TMX_SOLVER_PCG_NN_SYM1, 2)):
+        x.zero_()
+        rc, _ = ctx.solve(x, to_dev(b), 1, kind=kind, op=1, tol=1e-10, inner_prec=ip)
+        assert rc == tmx.TMX_OK and o.residual(b, to_host(x, b.shape)) <= 1e-10
+    torch.cuda.synchronize()
+    live, n_rel = A.live_bytes, A.n_release
+    ctx.free_workspaces()
+    freed = live - A.live_bytes
+    print(f"[gpu memory] {freed / 1e6:.1f} MB of scratch released in {A.n_release - n_rel} buffers", flush=True)
+    # at least the solver's FP64 fields and the network's 8-channel activation
+    assert freed >= ctx.Vh * (4 * 192 + 16 * 48) and A.n_release - n_rel >= 5
+    x.zero_()
+    rc, _ = ctx.solve(x, to_dev(b), 1, kind=tmx.TMX_SOLVER_PCG_NN_SYM1, op=1, tol=1e-10, inner_prec=2)
+    assert rc == tmx.TMX_OK and o.residual(b, to_host(x, b.shape)) <= 1e-10
+    assert A.live_bytes > live - freed
     ctx.close()
