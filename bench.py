@@ -249,6 +249,100 @@ def learned_pc_other_volume(tmx, synth, wts, dims=(24, 24, 24, 48), seed=3):
     return out
 
 
+def large_volume(tmx, synth, w_p1, base=(16, 16, 16, 128), rep=(4, 4, 4), seed=5, napply=10):
+    """The 64^3x128 configuration on one GPU: a 16^3x128 field (eps 0.25, seed
+    5) repeated 4x in x, y and z (periodic space directions; the antiperiodic
+    time extent kept), Gaussian sources drawn on the whole 64^3x128 lattice.
+    FP64 Mhat bandwidth (HIP events), plain FP64 CG, FP16 MP-CG and CG
+    preconditioned by P_1 (weights trained on 16^3x32, translation invariant)
+    to a 1e-10 FP64 true residual, and the 12-shift two-flavour multishift
+    solve (FP16 inner) at the poles of Zolotarev's approximation of
+    N_h^(-1/2) on [1e-5, 1] lambda_max of this field (the recipe of the
+    32^3x64 run).  Run before the 32^3x64 context exists, and the multishift
+    solve (about 250 GB at its peak) first, its scratch given back
+    (tmx_free_workspaces) before the one-flavour fields are built."""
+    import gc
+
+    import numpy as np
+    import torch
+
+    from paper_2212_06635_amd import zolotarev
+
+    dims = tuple(base[i] * (rep[i] if i < 3 else 1) for i in range(4))
+    U0 = synth.gauge_links(base, 0.25, seed)
+    U = np.tile(U0, (1, rep[2], rep[1], rep[0], 1, 1, 1))
+    ctx = tmx.Context(dims)
+    ctx.set_params(tmx.Params(KAPPA, CSW, MU, MUBAR, EPSBAR, -1))
+    ctx.load_gauge(U, float(seed))
+    del U, U0
+    gc.collect()
+    out = {"lattice": list(dims), "field": f"{'x'.join(map(str, base))} (eps 0.25, seed {seed}) tiled "
+                                          f"{'x'.join(map(str, rep))} in x, y, z; Gaussian sources on the whole lattice"}
+    b2 = torch.from_numpy(synth.gaussian_cb_spinor(dims, seed, 1, 2).reshape(-1)).cuda()
+    v = ctx.pack(b2, tmx.TMX_FIELD_ODD_ND, 1)
+    w2 = ctx.empty(tmx.TMX_FIELD_ODD_ND, 1)
+    lam = 0.0
+    for _ in range(30):
+        ctx.apply_mdagm(w2, v, 2, 1)
+        wc = ctx.unpack(w2, tmx.TMX_FIELD_ODD_ND, 1)
+        vc = ctx.unpack(v, tmx.TMX_FIELD_ODD_ND, 1)
+        lam = float(torch.vdot(vc, wc).real / torch.vdot(vc, vc).real)
+        v = ctx.pack(wc / wc.norm(), tmx.TMX_FIELD_ODD_ND, 1)
+    del v, w2, wc, vc
+    lam_max = 1.05 * lam
+    shifts = zolotarev.for_spectrum(12, 1e-5 * lam_max, lam_max).shifts
+    out["lambda_max_nd"] = round(lam, 5)
+    xs = torch.zeros(len(shifts) * b2.numel(), dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rc, info = ctx.multishift_solve(xs, b2, shifts, op=2, tol=1e-10, inner_prec=2)
+    torch.cuda.synchronize()
+    out["multishift_nd_12_f16"] = {"seconds": round(time.perf_counter() - t, 3), "rc": rc,
+                                   "iters": [i["iters"] for i in info],
+                                   "max_true_residual": max(i["true_residual"] for i in info)}
+    log(f"64^3x128 multishift: {time.perf_counter() - t:.2f}s")
+    del xs, b2
+    # the multishift solve's scratch (about 250 GB at its peak) goes back
+    # before the one-flavour operator's fields and the network are built
+    ctx.free_workspaces()
+    gc.collect()
+    torch.cuda.empty_cache()
+    b = torch.from_numpy(synth.gaussian_cb_spinor(dims, seed, 0).reshape(-1)).cuda()
+    src = ctx.pack(b, tmx.TMX_FIELD_ODD, 0)
+    dst = ctx.empty(tmx.TMX_FIELD_ODD, 0)
+    for _ in range(2):
+        ctx.apply_mhat(dst, src, 1, 0)
+    torch.cuda.synchronize()
+    ctx.kstats_enable(True)
+    for _ in range(napply):
+        ctx.apply_mhat(dst, src, 1, 0)
+    torch.cuda.synchronize()
+    ks = ctx.kstats()
+    ctx.kstats_enable(False)
+    ms = sum(ks[k][1] for k in ("K1_f64", "K2_f64") if k in ks) / napply
+    gbs = mhat_bytes_per_site("f64") * ctx.Vh / (ms * 1e-3) / 1e9
+    out["mhat_f64"] = {"ms": round(ms, 3), "GBps": round(gbs, 1), "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 1)}
+    del src, dst
+    ctx.pc_set_weights(w_p1)
+    x = torch.zeros_like(b)
+    for kind, name, ip in ((tmx.TMX_SOLVER_MPCG_F16, "warm-up", 1), (tmx.TMX_SOLVER_CG, "cg_f64", 1),
+                           (tmx.TMX_SOLVER_MPCG_F16, "mpcg_f16", 1), (tmx.TMX_SOLVER_PCG_NN_SYM1, "pcg_nn_sym1_f16", 2)):
+        x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, info = ctx.solve(x, b, 1, kind=kind, op=1, tol=1e-10, inner_prec=ip)
+        torch.cuda.synchronize()
+        if name != "warm-up":
+            out[name] = {"seconds": round(time.perf_counter() - t, 4), "iters": info[0]["iters"], "rc": rc,
+                         "true_residual": info[0]["true_residual"], "fallback": info[0]["fallback"]}
+        log(f"64^3x128 {name}: {time.perf_counter() - t:.2f}s")
+    del x, b
+    ctx.close()
+    gc.collect()
+    torch.cuda.empty_cache()
+    return out
+
+
 def from_oracle_free_init(w, rng):
     """Identity initialisation of the network weights (layout of tmx_pc_set_weights)."""
     chans = [(1, 8), (8, 8), (8, 8), (8, 1)]
@@ -283,6 +377,8 @@ def main():
                          "nn: only applications of the learned preconditioner (for counters)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuning of the stencil launch shapes (done before the timed region by default)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 64^3x128 configuration run after the timed steps")
     ap.add_argument("--train-pairs", type=int, default=256)
     ap.add_argument("--train-epochs", type=int, default=20)
     args = ap.parse_args()
@@ -300,6 +396,14 @@ def main():
 
     dims = tuple(int(x) for x in args.dims.split(","))
     torch.cuda.set_device(0)
+    large = None
+    if args.mode == "full":
+        # the networks first (their own 16^3x32 context), then the 64^3x128
+        # configuration, each with the GPU to itself
+        trained = train_networks(tmx, synth, args.train_pairs, args.train_epochs)
+        if dims == (32, 32, 32, 64) and not args.no_large:
+            log("the 64^3x128 configuration")
+            large = large_volume(tmx, synth, trained["sym1"][0])
     log(f"generating {dims} gauge field")
     U = synth.gauge_links(dims, 0.25, 4)
     b = synth.gaussian_cb_spinor(dims, 4, 0)
@@ -392,7 +496,6 @@ def main():
         ctx.close()
         return
 
-    trained = train_networks(tmx, synth, args.train_pairs, args.train_epochs)
     wts = {getattr(tmx, PC_FORMS[f][0]): trained[f][0] for f in trained}
     ctx.pc_set_weights(trained["kk"][0])
     # largest eigenvalue of N_h by power iteration (FP32), for the shifts
@@ -422,11 +525,16 @@ def main():
         return e0, e1
 
     def step():
+        # the operator loops run without the library's per-kernel events (two
+        # event records per launch cost 2 % of an FP64 Mhat and 7 % of an FP16
+        # one); the solves that follow record every kernel for the roofline
+        ctx.kstats_enable(False)
         ev = {}
         for p in (0, 1, 2):
             ev[names[p]] = timed(lambda: [ctx.apply_mhat(dst[p], src[p], 1, p) for _ in range(NAPPLY)])
         ev["N_f64"] = timed(lambda: [ctx.apply_mdagm(dst[0], src[0], 1, 0) for _ in range(NAPPLY)])
         ev["nd_f32"] = timed(lambda: [ctx.apply_mhat(dst_nd, src_nd, 2, 1) for _ in range(NAPPLY)])
+        ctx.kstats_enable(True)
         solves = {}
         for kind, nm, ip, op in ((tmx.TMX_SOLVER_CG, "cg_f64", 1, 1), (tmx.TMX_SOLVER_MPCG_F32, "mpcg_f32", 1, 1),
                                  (tmx.TMX_SOLVER_MPCG_F16, "mpcg_f16", 1, 1), (tmx.TMX_SOLVER_PCG_NN, "pcg_nn_f16", 2, 1),
@@ -466,23 +574,25 @@ def main():
         solves["multishift_nd_12_f16"] = {"seconds": time.perf_counter() - t, "rc": rc,
                                           "iters": [i["iters"] for i in info],
                                           "max_true_residual": max(i["true_residual"] for i in info)}
-        return ev, solves
+        step_ks = ctx.kstats()
+        ctx.kstats_enable(False)
+        return ev, solves, step_ks
 
     for w in range(args.warmup):
         step()
         log(f"warmup step {w + 1}/{args.warmup} done")
-    ctx.kstats_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    evs, last = [], None
+    evs, last, ks = [], None, {}
     for k in range(args.steps):
-        ev, last = step()
+        ev, last, step_ks = step()
         evs.append(ev)
+        for name, (n, ms) in step_ks.items():  # per-kernel launches and time over the timed steps
+            n0, ms0 = ks.get(name, (0, 0.0))
+            ks[name] = (n0 + n, ms0 + ms)
         log(f"step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ks = ctx.kstats()
-    ctx.kstats_enable(False)
 
     def gbs(key, per_site):
         ms = sum(e[key][0].elapsed_time(e[key][1]) for e in evs)
@@ -655,6 +765,8 @@ def main():
     else:
         out["cpu_baseline"] = None
     ctx.close()
+    if large is not None:
+        out["large_64x64x64x128"] = large
     print(json.dumps(out), flush=True)
 
 
