@@ -225,7 +225,10 @@ def network(d: str, v: int) -> str:
 FORCE_KERNELS = (
     ("hop_force_kernel", "HOP_FORCE", 1344, 768, 576),          # a, b 2 x 192, 4 links x 96 | 4 outputs x 144
     ("clover_insertion_kernel", "CLOV_INSERT", 816, 384, 432),   # a, b | 6 Hermitian planes x 72
-    ("clover_force_kernel", "CLOV_LINKS", 1392, 816, 576),      # 6 planes x 72, 4 links x 96 | 4 outputs x 144
+    # 4 links x 96, 6 insertion planes x 72 | 6 plaquettes x 144 (K, A)
+    ("clover_loop_kernel", "CLOV_LOOPS", 1680, 816, 864),
+    # 6 plaquettes x 144, 6 insertion planes x 72, 4 links x 96 | 4 outputs x 144
+    ("clover_link_kernel", "CLOV_LINKS", 2256, 1680, 576),
 )
 
 
@@ -238,7 +241,7 @@ def force(d: str, v: int) -> str:
     copy_f, copy_w = _copy_kib(pf, "FETCH_SIZE"), _copy_kib(pw, "WRITE_SIZE")
     sf, sw = COPY_BYTES / 1024 / copy_f, COPY_BYTES / 1024 / copy_w
     lines = [
-        f"# fermion-force kernels (hopping term; clover term = insertions + link sums), V = {v} sites "
+        f"# fermion-force kernels (hopping term; clover term = insertions + plaquette loops + link sums), V = {v} sites "
         "(all 4V links), MI355X",
         "# commands (from /tmp, TMPDIR=/tmp; <repo> = repository root):",
         "#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/p_k -o k -- python3 <repo>/bench.py --mode force --no-tune",
@@ -297,7 +300,8 @@ def sq_table(dirs) -> str:
             disp[r["Kernel_Name"]].add(r.get("Dispatch_Id", ""))
         for name in sorted(agg):
             short = name.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
-            if not any(t in short for t in ("dslash_kernel", "nn_", "force_kernel", "insertion_kernel")):
+            if not any(t in short for t in ("dslash_kernel", "nn_", "force_kernel", "insertion_kernel", "loop_kernel",
+                                            "link_kernel")):
                 continue
             if "build" in short or "links" in short:
                 continue

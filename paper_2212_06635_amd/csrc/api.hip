@@ -1041,13 +1041,14 @@ static int hop_force_fields(tmx_ctx *c, double *force, const ForceFields &ff, do
 }
 
 // force (= or +=) coeff * clover-term force of Re<Y, Mhat X>: the insertions
-// summed over the flavours, then one pass of link sums
+// summed over the flavours, then the plaquette loops and the link sums
 static int clover_force_fields(tmx_ctx *c, double *force, const ForceFields &ff, double coeff, int accumulate)
 {
     if (c->clover_from_host)
         return set_err(c, TMX_EINVAL, "the clover force needs the clover term built from the links");
     void *ph = ws_get(c, "cf_h", (size_t)6 * 9 * 2 * c->Vh * sizeof(double));
-    if (!ph) return set_err(c, TMX_ENOMEM, "clover force workspace: out of device memory");
+    void *pka = ph ? ws_get(c, "cf_ka", (size_t)6 * 18 * 2 * c->Vh * sizeof(double)) : nullptr;
+    if (!ph || !pka) return set_err(c, TMX_ENOMEM, "clover force workspace: out of device memory");
     CloverForceArgs f{};
     f.g = c->g;
     f.U = LinkPtr{c->links[F64], c->Vh};
@@ -1056,6 +1057,7 @@ static int clover_force_fields(tmx_ctx *c, double *force, const ForceFields &ff,
     f.coeff = coeff;
     f.accumulate = accumulate ? 1 : 0;
     f.H = static_cast<double *>(ph);
+    f.KA = static_cast<double *>(pka);
     f.out = force;
     f.xcd = c->xcd_remap;
     kstat_begin(c, "CLOVER_FORCE");

@@ -21,12 +21,14 @@ struct CloverForceArgs {
     int accumulate;
     double *H;
     int h_acc;  // insertions: add to H (the next flavour of a two-flavour field) instead of writing it
+    double *KA;  // plaquette loops: 6 planes x 18 reals (Hermitian part K of the loop with
+                 // insertions, anti-Hermitian part A of the plain loop) x 2 Vh doubles
     double *out;
     int xcd;  // XCD-contiguous workgroup order of the link sums
 };
 // the sigma-plane insertions H of one flavour (written, or added with h_acc)
 hipError_t launch_clover_insertions(const CloverForceArgs &f, hipStream_t st);
-// the link sums of the plaquettes with H inserted, into out
+// the plaquette loops with H inserted (into KA), then the link sums from them (into out)
 hipError_t launch_clover_link_sums(const CloverForceArgs &f, hipStream_t st);
 
 }  // namespace tmx

@@ -203,6 +203,9 @@ hipError_t launch_hop_force(const ForceArgs &f, hipStream_t st)
 // products opened at U / U^dagger with H inserted at each corner in turn,
 //   F_rho(y) = TA[(i kappa csw / 8) sum_nu (U C_up - E_low U^dagger)].
 // H_nu,rho = -H_rho,nu (sigma is antisymmetric), so six planes are stored.
+// Three kernels: the insertions per site, the loops per plaquette (each
+// plaquette once, not once per link), and the link sums, which take the
+// loops of a link's six plaquettes from the stored ones by conjugation.
 namespace {
 
 struct Mat3 {
@@ -219,21 +222,6 @@ __device__ __forceinline__ Mat3 mm(const Mat3 &a, const Mat3 &b)  // a b
             cd s{0, 0};
 #pragma unroll
             for (int k = 0; k < 3; ++k) cmac(s, a.m[3 * i + k], b.m[3 * k + j]);
-            c.m[3 * i + j] = s;
-        }
-    return c;
-}
-
-__device__ __forceinline__ Mat3 mm_nd(const Mat3 &a, const Mat3 &b)  // a b^dagger
-{
-    Mat3 c;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            cd s{0, 0};
-#pragma unroll
-            for (int k = 0; k < 3; ++k) cmac_conj(s, b.m[3 * j + k], a.m[3 * i + k]);
             c.m[3 * i + j] = s;
         }
     return c;
@@ -261,7 +249,7 @@ __device__ __forceinline__ void add_to(Mat3 &a, const Mat3 &b)
 }
 
 // stored plane of the pair r < n: xy, xz, xt, yz, yt, zt
-__device__ __forceinline__ int plane_of(int r, int n) { return r == 0 ? n - 1 : (r == 1 ? n + 1 : 5); }
+__device__ __forceinline__ constexpr int plane_of(int r, int n) { return r == 0 ? n - 1 : (r == 1 ? n + 1 : 5); }
 
 __device__ __forceinline__ void shift(const Geom &g, const int x[4], int mu, int d, int y[4])
 {
@@ -272,43 +260,12 @@ __device__ __forceinline__ void shift(const Geom &g, const int x[4], int mu, int
     if (y[mu] >= g.L[mu]) y[mu] -= g.L[mu];
 }
 
-__device__ __forceinline__ Mat3 link(const CloverForceArgs &f, const int x[4], int mu)
-{
-    Mat3 u;
-    load_link<F64>(f.U, (x[0] + x[1] + x[2] + x[3]) & 1, mu, cb_index(f.g, x), u.m);
-    return u;
-}
-
 // Insertions are Hermitian, so a plane stores nine reals per site, each
 // component an array of 2 Vh doubles (site index p Vh + s): the diagonal
 // H00, H11, H22, then (re, im) of H01, H02, H12.
 __device__ __forceinline__ int herm_component(int i, int j)  // first real of entry (i, j), i <= j
 {
     return i == j ? i : 3 + 2 * (i + j - 1);
-}
-
-// H_r,n at site x (r != n): the stored plane, negated for r > n
-__device__ __forceinline__ Mat3 insertion(const CloverForceArgs &f, const int x[4], int r, int n)
-{
-    const long V2 = 2L * f.g.Vh;
-    const long site = (long)((x[0] + x[1] + x[2] + x[3]) & 1) * f.g.Vh + cb_index(f.g, x);
-    const double *h = f.H + (long)plane_of(r < n ? r : n, r < n ? n : r) * 9 * V2 + site;
-    const double sg = r < n ? 1.0 : -1.0;
-    double v[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) v[k] = sg * h[k * V2];
-    Mat3 m;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        m.m[4 * i] = cd{v[i], 0.0};
-#pragma unroll
-        for (int j = i + 1; j < 3; ++j) {
-            const int c = herm_component(i, j);
-            m.m[3 * i + j] = cd{v[c], v[c + 1]};
-            m.m[3 * j + i] = cd{v[c], -v[c + 1]};
-        }
-    }
-    return m;
 }
 
 // the Pauli combinations of one chirality chi at colour entry (i, j):
@@ -399,127 +356,428 @@ __device__ __forceinline__ Mat3 dagm(const Mat3 &a)
     return c;
 }
 
-// value of lane l ^ 1 (all lanes active)
-__device__ __forceinline__ double pair_swap(double v)
+// ---- plaquette loops --------------------------------------------------------
+// Per plaquette (x; r < n) with links a = U_r(x), b = U_n(x+r), c = U_r(x+n),
+// d = U_n(x) and the (r, n) insertions h0..h3 at its corners x, x+r, x+r+n,
+// x+n, the loop opened at x with each corner's insertion in turn,
+//     X = a h1 b c+ d+ + a b h2 c+ d+ + a b c+ h3 d+ + a b c+ d+ h0,
+// and the plain loop W = a b c+ d+.  The force takes only the Hermitian part
+// K = (X + X+)/2 of X and the anti-Hermitian part A = (W - W+)/2 of W (the
+// link sums below), nine reals each.
+//
+// The loop opened at the next corner is the conjugate L+ X L (L the link
+// between the two corners) plus the commutator [W', h'] of the new corner's
+// plain loop and insertion: conjugation moves the insertion of the old open
+// corner to the inside of the loop, but leaves the new corner's at the front
+// instead of the back.  Every loop a link force needs is such a rotation of
+// one stored plaquette (see the link sums).
+//
+// Hermitian and anti-Hermitian matrices are held as nine reals: the diagonal
+// (real part of K, imaginary part of A), then the upper triangle (0,1), (0,2),
+// (1,2) as (re, im); K_ji = conj(K_ij), A_ji = -conj(A_ij).  In memory each
+// of the nine (or eighteen) reals is its own array of 2 Vh doubles.
+struct Sym3 {
+    double d[3];
+    cd o[3];
+};
+
+__device__ __forceinline__ constexpr int upper(int i, int j) { return i + j - 1; }  // i < j
+
+__device__ __forceinline__ cd herm_get(const Sym3 &k, int i, int j)  // i != j
 {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    const cd v = k.o[upper(i < j ? i : j, i < j ? j : i)];
+    return i < j ? v : conj(v);
 }
 
-__device__ __forceinline__ Mat3 sel(bool c, const Mat3 &a, const Mat3 &b)
+__device__ __forceinline__ cd aherm_get(const Sym3 &a, int i, int j)  // i != j
 {
-    Mat3 m;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) m.m[k] = c ? a.m[k] : b.m[k];
-    return m;
+    const cd v = a.o[upper(i < j ? i : j, i < j ? j : i)];
+    return i < j ? v : cd{-v.re, v.im};
 }
 
-// Two lanes per link U_R(y): lane half 0 sums the plaquettes above it, lane
-// half 1 those below, with one instruction stream.  The one below enters as
-// E U^+ = (U E^+)^+, and E^+ has the form of the one above,
-//     E^+ = b1 b2 b3 h(y) + b1 b2 h(y-n) b3 + b1 h(y-n+R) b2 b3 + h(y+R) b1 b2 b3,
-//     b1 = U_n(y-n+R)^+, b2 = U_R(y-n)^+, b3 = U_n(y-n),
-// so both lanes form T = c1 (c2 (c3 h(y) + h3 c3) + h2 c2 c3) + h(y+R) c1 c2 c3
-// from their own links c and insertions h3, h2, sum T over the three planes,
-// and add X = U sum T (above) or -X^+ (below); the pair then sums its two
-// halves.
-template <int R>
-__device__ __forceinline__ void clover_link_half(const CloverForceArgs &f, const int y[4], long lex, int half,
-                                                 bool valid)
+__device__ __forceinline__ Sym3 load_sym(const double *p, long V2, long site)
 {
-    Mat3 Z, S;
+    Sym3 k;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) Z.m[k] = S.m[k] = cd{0, 0};
-    const bool lo = half == 1;
-    if (valid) {
-        int yr[4];
-        shift(f.g, y, R, +1, yr);
-#pragma unroll 1
-        for (int n = 0; n < 4; ++n) {
-            if (n == R) continue;
-            // above: c3 = U_n(y)^+ at y, h3 at y+n, c2 = U_R(y+n)^+, h2 at y+R+n, c1 = U_n(y+R)
-            // below: c3 = U_n(y-n) at y-n, h3 at y-n, c2 = U_R(y-n)^+, h2 at y-n+R, c1 = U_n(y-n+R)^+
-            int yn[4], y3[4], y2[4];
-            shift(f.g, y, n, lo ? -1 : +1, yn);  // y+n above, y-n below
-            shift(f.g, yn, R, +1, y2);            // y+n+R / y-n+R
+    for (int i = 0; i < 3; ++i) k.d[i] = p[i * V2 + site];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) y3[k] = lo ? yn[k] : y[k];
-            Mat3 l3 = link(f, y3, n);
-            Mat3 P = sel(lo, l3, dagm(l3));                                   // c3
-            Mat3 T = mm(P, insertion(f, y, R, n));                            // c3 h(y)
-            add_to(T, mm(insertion(f, yn, R, n), P));                         // + h3 c3
-            const Mat3 l2 = link(f, yn, R);
-            const Mat3 c2 = dagm(l2);                                         // U_R(y+-n)^+ in both
-            T = mm(c2, T);
-            P = mm(c2, P);
-            add_to(T, mm(insertion(f, y2, R, n), P));                         // + h2 c2 c3
-            const Mat3 l1 = link(f, lo ? y2 : yr, n);
-            const Mat3 c1 = sel(lo, dagm(l1), l1);
-            T = mm(c1, T);
-            P = mm(c1, P);
-            add_to(T, mm(insertion(f, yr, R, n), P));                         // + h(y+R) c1 c2 c3
-            add_to(S, T);
-        }
-        const Mat3 X = mm(link(f, y, R), S);
-        const Mat3 Xd = dagm(X);
+    for (int i = 0; i < 3; ++i) k.o[i] = cd{p[(3 + 2 * i) * V2 + site], p[(4 + 2 * i) * V2 + site]};
+    return k;
+}
+
+__device__ __forceinline__ void store_sym(double *p, long V2, long site, const Sym3 &k)
+{
 #pragma unroll
-        for (int k = 0; k < 9; ++k) Z.m[k] = lo ? cd{-Xd.m[k].re, -Xd.m[k].im} : X.m[k];
+    for (int i = 0; i < 3; ++i) p[i * V2 + site] = k.d[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        p[(3 + 2 * i) * V2 + site] = k.o[i].re;
+        p[(4 + 2 * i) * V2 + site] = k.o[i].im;
     }
-    // the pair's two halves
+}
+
+__device__ __forceinline__ long site_of(const Geom &g, const int x[4])
+{
+    return (long)((x[0] + x[1] + x[2] + x[3]) & 1) * g.Vh + cb_index(g, x);
+}
+
+// link through the caches (neighbouring plaquettes and links share it)
+__device__ __forceinline__ Mat3 link_c(const CloverForceArgs &f, const int x[4], int mu)
+{
+    const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+    const double2 *b = static_cast<const double2 *>(f.U.d) + (long)(p * 4 + mu) * 6 * f.U.Vh + cb_index(f.g, x);
+    Mat3 u;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        Z.m[k].re += pair_swap(Z.m[k].re);
-        Z.m[k].im += pair_swap(Z.m[k].im);
+    for (int k = 0; k < 6; ++k) {
+        const double2 v = b[k * f.U.Vh];
+        u.m[k] = cd{v.x, v.y};
     }
-    if (!valid || lo) return;
-    // Q = i (kappa csw / 8) Z, F = TA(Q)
-    cd Q[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Q[k] = f.kc8 * imul(Z.m[k]);
-    double tr = 0.0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) tr += Q[4 * i].im;
-    double2 *o = reinterpret_cast<double2 *>(f.out) + (lex * 4 + R) * 9;
+    // the third row of an SU(3) matrix: conj(row 0 x row 1)
+    u.m[6] = conj(u.m[1] * u.m[5] - u.m[2] * u.m[4]);
+    u.m[7] = conj(u.m[2] * u.m[3] - u.m[0] * u.m[5]);
+    u.m[8] = conj(u.m[0] * u.m[4] - u.m[1] * u.m[3]);
+    return u;
+}
+
+__device__ __forceinline__ Mat3 hmul(const Sym3 &h, const Mat3 &m)  // h m, h Hermitian
+{
+    Mat3 c;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            cd a{0.5 * (Q[3 * i + j].re - Q[3 * j + i].re), 0.5 * (Q[3 * i + j].im + Q[3 * j + i].im)};
-            if (i == j) a.im -= tr / 3.0;
-            cd v{f.coeff * a.re, f.coeff * a.im};
-            if (f.accumulate) {
-                const double2 old = o[3 * i + j];
-                v.re += old.x;
-                v.im += old.y;
-            }
-            o[3 * i + j] = make_double2(v.re, v.im);
+            cd s = h.d[i] * m.m[3 * i + j];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (k != i) cmac(s, herm_get(h, i, k), m.m[3 * k + j]);
+            c.m[3 * i + j] = s;
         }
+    return c;
 }
 
-// Two lanes per link, 128 links per workgroup.  Workgroup 8 i + 4 p + rho
-// takes direction rho of sites 128 i ... of parity p: the four directions
-// and both parities of one site block are neighbouring workgroups (with the
-// XCD remap, on one XCD), so the insertions and links of their common
-// staples are read through one L2.
-__global__ void __launch_bounds__(256) clover_force_kernel(CloverForceArgs f)
+__device__ __forceinline__ Mat3 mulh(const Mat3 &m, const Sym3 &h)  // m h, h Hermitian
+{
+    Mat3 c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cd s = h.d[j] * m.m[3 * i + j];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (k != j) cmac(s, m.m[3 * i + k], herm_get(h, k, j));
+            c.m[3 * i + j] = s;
+        }
+    return c;
+}
+
+// Hermitian part of a t
+__device__ __forceinline__ Sym3 herm_of_product(const Mat3 &a, const Mat3 &t)
+{
+    Sym3 k;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) s += a.m[3 * i + l].re * t.m[3 * l + i].re - a.m[3 * i + l].im * t.m[3 * l + i].im;
+        k.d[i] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 3; ++j) {
+            cd xij{0, 0}, xji{0, 0};
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                cmac(xij, a.m[3 * i + l], t.m[3 * l + j]);
+                cmac(xji, a.m[3 * j + l], t.m[3 * l + i]);
+            }
+            k.o[upper(i, j)] = cd{0.5 * (xij.re + xji.re), 0.5 * (xij.im - xji.im)};
+        }
+    return k;
+}
+
+// anti-Hermitian part of a t
+__device__ __forceinline__ Sym3 aherm_of_product(const Mat3 &a, const Mat3 &t)
+{
+    Sym3 k;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) s += a.m[3 * i + l].re * t.m[3 * l + i].im + a.m[3 * i + l].im * t.m[3 * l + i].re;
+        k.d[i] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 3; ++j) {
+            cd xij{0, 0}, xji{0, 0};
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                cmac(xij, a.m[3 * i + l], t.m[3 * l + j]);
+                cmac(xji, a.m[3 * j + l], t.m[3 * l + i]);
+            }
+            k.o[upper(i, j)] = cd{0.5 * (xij.re - xji.re), 0.5 * (xij.im + xji.im)};
+        }
+    return k;
+}
+
+template <int R, int N>
+__device__ __forceinline__ void plaquette_loop(const CloverForceArgs &f, const int x[4], long site)
+{
+    constexpr int pl = plane_of(R, N);
+    const long V2 = 2L * f.g.Vh;
+    const double *h = f.H + (long)pl * 9 * V2;
+    int xr[4], xn[4], xrn[4];
+    shift(f.g, x, R, +1, xr);
+    shift(f.g, x, N, +1, xn);
+    shift(f.g, xr, N, +1, xrn);
+    // Horner form from the back: t = a (h1 b c+ d+ + b (h2 c+ d+ + c+ (h3 d+ + d+ h0)))
+    const Mat3 dd = dagm(link_c(f, x, N));
+    Mat3 t = hmul(load_sym(h, V2, site_of(f.g, xn)), dd);
+    add_to(t, mulh(dd, load_sym(h, V2, site)));
+    const Mat3 c = link_c(f, xn, R);
+    Mat3 P = mm_dn(c, dd);  // c+ d+
+    t = mm_dn(c, t);
+    add_to(t, hmul(load_sym(h, V2, site_of(f.g, xrn)), P));
+    const Mat3 b = link_c(f, xr, N);
+    t = mm(b, t);
+    P = mm(b, P);  // b c+ d+
+    add_to(t, hmul(load_sym(h, V2, site_of(f.g, xr)), P));
+    const Mat3 a = link_c(f, x, R);
+    double *o = f.KA + (long)pl * 18 * V2;
+    store_sym(o, V2, site, herm_of_product(a, t));
+    store_sym(o + 9 * V2, V2, site, aherm_of_product(a, P));
+}
+
+// One thread per (site, plane); workgroup 12 i + 6 p + plane takes sites
+// 256 i ... of parity p, so the six planes and both parities of a site block
+// are neighbouring workgroups (with the XCD remap, on one XCD) and read its
+// links and insertions through one L2.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) clover_loop_kernel(CloverForceArgs f)
 {
     const long blk = xcd_block(f.xcd);
-    const int r = (int)(blk & 3);
-    const int p = (int)((blk >> 2) & 1);
-    const long st = (blk >> 3) * (blockDim.x / 2) + threadIdx.x / 2;
-    const int half = threadIdx.x & 1;
-    const bool valid = st < f.g.Vh;
-    int x[4] = {0, 0, 0, 0};
-    if (valid) cb_coords(f.g, (int)st, p, x);
-    const long lex = x[0] + (long)f.g.L[0] * (x[1] + (long)f.g.L[1] * (x[2] + (long)f.g.L[2] * x[3]));
-    switch (r) {
-    case 0: clover_link_half<0>(f, x, lex, half, valid); break;
-    case 1: clover_link_half<1>(f, x, lex, half, valid); break;
-    case 2: clover_link_half<2>(f, x, lex, half, valid); break;
-    default: clover_link_half<3>(f, x, lex, half, valid); break;
+    const int pl = (int)(blk % 6);
+    const int p = (int)((blk / 6) & 1);
+    const long s = (blk / 12) * blockDim.x + threadIdx.x;
+    if (s >= f.g.Vh) return;
+    const long t = (long)p * f.g.Vh + s;
+    int x[4];
+    cb_coords(f.g, (int)s, p, x);
+    switch (pl) {
+    case 0: plaquette_loop<0, 1>(f, x, t); break;
+    case 1: plaquette_loop<0, 2>(f, x, t); break;
+    case 2: plaquette_loop<0, 3>(f, x, t); break;
+    case 3: plaquette_loop<1, 2>(f, x, t); break;
+    case 4: plaquette_loop<1, 3>(f, x, t); break;
+    default: plaquette_loop<2, 3>(f, x, t); break;
     }
+}
+
+// ---- link sums --------------------------------------------------------------
+// u+ g u for Hermitian g (Hermitian result)
+__device__ __forceinline__ Sym3 conj_herm(const Mat3 &u, const Sym3 &g)
+{
+    const Mat3 m = hmul(g, u);
+    Sym3 r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s += u.m[3 * k + i].re * m.m[3 * k + i].re + u.m[3 * k + i].im * m.m[3 * k + i].im;
+        r.d[i] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 3; ++j) {
+            cd s{0, 0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac_conj(s, u.m[3 * k + i], m.m[3 * k + j]);
+            r.o[upper(i, j)] = s;
+        }
+    return r;
+}
+
+// u+ a u for anti-Hermitian a (anti-Hermitian result)
+__device__ __forceinline__ Sym3 conj_aherm(const Mat3 &u, const Sym3 &a)
+{
+    Mat3 m;  // a u
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const cd v = u.m[3 * i + j];
+            cd s{-a.d[i] * v.im, a.d[i] * v.re};
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (k != i) cmac(s, aherm_get(a, i, k), u.m[3 * k + j]);
+            m.m[3 * i + j] = s;
+        }
+    Sym3 r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s += u.m[3 * k + i].re * m.m[3 * k + i].im - u.m[3 * k + i].im * m.m[3 * k + i].re;
+        r.d[i] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 3; ++j) {
+            cd s{0, 0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac_conj(s, u.m[3 * k + i], m.m[3 * k + j]);
+            r.o[upper(i, j)] = s;
+        }
+    return r;
+}
+
+// [a, h] = a h + (a h)+ for anti-Hermitian a and Hermitian h (Hermitian)
+__device__ __forceinline__ Sym3 commute(const Sym3 &a, const Sym3 &h)
+{
+    Sym3 r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {  // 2 Re (a h)_ii: the term a_ii h_ii is imaginary
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (k != i) {
+                const cd x = aherm_get(a, i, k), y = herm_get(h, k, i);
+                s += x.re * y.re - x.im * y.im;
+            }
+        r.d[i] = 2.0 * s;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 3; ++j) {
+            cd e{0, 0}, g{0, 0};  // (a h)_ij, (a h)_ji
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (k == i) {
+                    const cd v = herm_get(h, i, j);
+                    e = e + cd{-a.d[i] * v.im, a.d[i] * v.re};
+                    g = g + h.d[i] * aherm_get(a, j, i);
+                } else if (k == j) {
+                    const cd v = herm_get(h, j, i);
+                    e = e + h.d[j] * aherm_get(a, i, j);
+                    g = g + cd{-a.d[j] * v.im, a.d[j] * v.re};
+                } else {
+                    cmac(e, aherm_get(a, i, k), herm_get(h, k, j));
+                    cmac(g, aherm_get(a, j, k), herm_get(h, k, i));
+                }
+            }
+            r.o[upper(i, j)] = cd{e.re + g.re, e.im - g.im};
+        }
+    return r;
+}
+
+__device__ __forceinline__ void axpy(Sym3 &z, double s, const Sym3 &k)  // z += s k
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        z.d[i] += s * k.d[i];
+        z.o[i] = z.o[i] + s * k.o[i];
+    }
+}
+
+// The force on U_R(y) from plane (R, N), as Hermitian part of the loops
+// (the anti-Hermitian projection below needs no more).  With the stored
+// plaquettes P(y) and P(y - N) of the plane (lower direction first),
+// u = U_N(y - N), their parts K, A and K', A', and the insertions h(y),
+// h' = h(y - N) of the plane:
+//   R < N:  K - u+ (K' - [A', h']) u + [u+ A' u, h(y)]
+//   R > N: -K + u+ K' u + [A + u+ A' u, h(y)]
+// (the first loop opened at y with h(y) at its end, the second the loop
+// below taken at its corner y, where the conjugation by u is corrected by the
+// commutator terms; for R > N both come from the plaquettes of the opposite
+// orientation, reversed).
+__device__ __forceinline__ void link_plane(const CloverForceArgs &f, const int y[4], long site, int R, int N, Sym3 &z)
+{
+    const bool below = R < N;  // the stored plaquettes are oriented R -> N
+    const double sg = below ? 1.0 : -1.0;
+    const long V2 = 2L * f.g.Vh;
+    const int pl = below ? plane_of(R, N) : plane_of(N, R);
+    const double *ka = f.KA + (long)pl * 18 * V2;
+    const double *h = f.H + (long)pl * 9 * V2;
+    int ym[4];
+    shift(f.g, y, N, -1, ym);
+    const long sm = site_of(f.g, ym);
+    const Mat3 u = link_c(f, ym, N);
+    const Sym3 a1 = load_sym(ka + 9 * V2, V2, sm);
+    Sym3 b = conj_aherm(u, a1);
+    Sym3 g = load_sym(ka, V2, sm);
+    if (below)
+        axpy(g, -1.0, commute(a1, load_sym(h, V2, sm)));
+    else
+        axpy(b, 1.0, load_sym(ka + 9 * V2, V2, site));
+    const Sym3 k0 = load_sym(ka, V2, site);
+    const Sym3 hy = load_sym(h, V2, site);
+    axpy(z, -sg, conj_herm(u, g));
+    axpy(z, sg, k0);
+    axpy(z, 1.0, commute(b, hy));
+}
+
+__device__ __forceinline__ void link_sum(const CloverForceArgs &f, const int y[4], long site, long lex, int R)
+{
+    Sym3 z;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        z.d[i] = 0.0;
+        z.o[i] = cd{0, 0};
+    }
+    // one plane at a time (a loop, so that the planes' loads and products
+    // do not overlap and the thread holds one plane's operands), plane
+    // (R, R ^ k) in step k: the waves of directions R and R ^ k read the
+    // plane's loops and insertions at y together
+#pragma unroll 1
+    for (int k = 1; k < 4; ++k) link_plane(f, y, site, R, R ^ k, z);
+    // F = coeff TA(i (kappa csw / 8) Z); only the Hermitian part of Z enters,
+    // so F = i coeff (kappa csw / 8) (Z - tr Z / 3)
+    const double cc = f.coeff * f.kc8;
+    const double tr3 = (z.d[0] + z.d[1] + z.d[2]) / 3.0;
+    double2 *o = reinterpret_cast<double2 *>(f.out) + (lex * 4 + R) * 9;
+    double2 v[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            if (i == j) {
+                v[3 * i + j] = make_double2(0.0, cc * (z.d[i] - tr3));
+            } else {
+                const cd w = herm_get(z, i, j);
+                v[3 * i + j] = make_double2(-cc * w.im, cc * w.re);
+            }
+        }
+    if (f.accumulate) {  // the nine old entries in one round trip
+        double2 old[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) old[k] = o[k];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v[k] = make_double2(v[k].x + old[k].x, v[k].y + old[k].y);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) o[k] = v[k];
+}
+
+// One thread per link: a workgroup holds 64 sites of one parity, one wave
+// per direction, so that the two waves of a plane read its data at y through
+// one L1; workgroups alternate between the parities.
+__global__ void __launch_bounds__(256) clover_link_kernel(CloverForceArgs f)
+{
+    const long blk = xcd_block(f.xcd);
+    const int p = (int)(blk & 1);
+    const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const long s = (blk >> 1) * 64 + (threadIdx.x & 63);
+    if (s >= f.g.Vh) return;
+    const long t = (long)p * f.g.Vh + s;
+    int y[4];
+    cb_coords(f.g, (int)s, p, y);
+    const long lex = y[0] + (long)f.g.L[0] * (y[1] + (long)f.g.L[1] * (y[2] + (long)f.g.L[2] * y[3]));
+    link_sum(f, y, t, lex, r);
 }
 
 }  // namespace
@@ -539,8 +797,11 @@ hipError_t launch_clover_insertions(const CloverForceArgs &f, hipStream_t st)
 hipError_t launch_clover_link_sums(const CloverForceArgs &f, hipStream_t st)
 {
     if (f.g.Vh == 0) return hipSuccess;
-    const long nlink = 8 * ((f.g.Vh + 127) / 128);  // 4 directions x 2 parities per block of 128 sites
-    hipLaunchKernelGGL(clover_force_kernel, dim3((unsigned)nlink), dim3(256), 0, st, f);
+    const long nb = 2 * ((f.g.Vh + 63) / 64);  // link sums: blocks of 64 sites, both parities
+    hipLaunchKernelGGL(clover_loop_kernel, dim3((unsigned)(12 * ((f.g.Vh + 255) / 256))), dim3(256), 0, st, f);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(clover_link_kernel, dim3((unsigned)nb), dim3(256), 0, st, f);
     return hipGetLastError();
 }
 
