@@ -225,10 +225,10 @@ def network(d: str, v: int) -> str:
 FORCE_KERNELS = (
     ("hop_force_kernel", "HOP_FORCE", 1344, 768, 576),          # a, b 2 x 192, 4 links x 96 | 4 outputs x 144
     ("clover_insertion_kernel", "CLOV_INSERT", 816, 384, 432),   # a, b | 6 Hermitian planes x 72
-    # 4 links x 96, 6 insertion planes x 72 | 6 plaquettes x 144 (K, A)
-    ("clover_loop_kernel", "CLOV_LOOPS", 1680, 816, 864),
-    # 6 plaquettes x 144, 6 insertion planes x 72, 4 links x 96 | 4 outputs x 144
-    ("clover_link_kernel", "CLOV_LINKS", 2256, 1680, 576),
+    # 4 links x 96, 6 insertion planes x 72 | 6 plaquettes x 128 (traceless K, A)
+    ("clover_loop_kernel", "CLOV_LOOPS", 1584, 816, 768),
+    # 6 plaquettes x 128, 6 insertion planes x 72, 4 links x 96 | 4 outputs x 144
+    ("clover_link_kernel", "CLOV_LINKS", 2160, 1584, 576),
 )
 
 

@@ -1047,7 +1047,7 @@ static int clover_force_fields(tmx_ctx *c, double *force, const ForceFields &ff,
     if (c->clover_from_host)
         return set_err(c, TMX_EINVAL, "the clover force needs the clover term built from the links");
     void *ph = ws_get(c, "cf_h", (size_t)6 * 9 * 2 * c->Vh * sizeof(double));
-    void *pka = ph ? ws_get(c, "cf_ka", (size_t)6 * 18 * 2 * c->Vh * sizeof(double)) : nullptr;
+    void *pka = ph ? ws_get(c, "cf_ka", (size_t)6 * 16 * 2 * c->Vh * sizeof(double)) : nullptr;
     if (!ph || !pka) return set_err(c, TMX_ENOMEM, "clover force workspace: out of device memory");
     CloverForceArgs f{};
     f.g = c->g;

@@ -21,8 +21,8 @@ struct CloverForceArgs {
     int accumulate;
     double *H;
     int h_acc;  // insertions: add to H (the next flavour of a two-flavour field) instead of writing it
-    double *KA;  // plaquette loops: 6 planes x 18 reals (Hermitian part K of the loop with
-                 // insertions, anti-Hermitian part A of the plain loop) x 2 Vh doubles
+    double *KA;  // plaquette loops: 6 planes x 16 reals (traceless Hermitian part K of the loop
+                 // with insertions, traceless anti-Hermitian part A of the plain loop) x 2 Vh doubles
     double *out;
     int xcd;  // XCD-contiguous workgroup order of the link sums
 };

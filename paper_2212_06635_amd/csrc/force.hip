@@ -363,7 +363,7 @@ __device__ __forceinline__ Mat3 dagm(const Mat3 &a)
 //     X = a h1 b c+ d+ + a b h2 c+ d+ + a b c+ h3 d+ + a b c+ d+ h0,
 // and the plain loop W = a b c+ d+.  The force takes only the Hermitian part
 // K = (X + X+)/2 of X and the anti-Hermitian part A = (W - W+)/2 of W (the
-// link sums below), nine reals each.
+// link sums below), and of those only the traceless parts: eight reals each.
 //
 // The loop opened at the next corner is the conjugate L+ X L (L the link
 // between the two corners) plus the commutator [W', h'] of the new corner's
@@ -375,7 +375,7 @@ __device__ __forceinline__ Mat3 dagm(const Mat3 &a)
 // Hermitian and anti-Hermitian matrices are held as nine reals: the diagonal
 // (real part of K, imaginary part of A), then the upper triangle (0,1), (0,2),
 // (1,2) as (re, im); K_ji = conj(K_ij), A_ji = -conj(A_ij).  In memory each
-// of the nine (or eighteen) reals is its own array of 2 Vh doubles.
+// real is its own array of 2 Vh doubles.
 struct Sym3 {
     double d[3];
     cd o[3];
@@ -405,14 +405,32 @@ __device__ __forceinline__ Sym3 load_sym(const double *p, long V2, long site)
     return k;
 }
 
-__device__ __forceinline__ void store_sym(double *p, long V2, long site, const Sym3 &k)
+// traceless part as eight reals (d0, d1 of the traceless diagonal, then the
+// upper triangle): the trace of K and of A never reaches the force (it only
+// adds to tr Z, which the projection removes, or commutes away)
+__device__ __forceinline__ Sym3 load_tl(const double *p, long V2, long site)
 {
+    Sym3 k;
+    k.d[0] = p[site];
+    k.d[1] = p[V2 + site];
+    k.d[2] = -(k.d[0] + k.d[1]);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) p[i * V2 + site] = k.d[i];
+    for (int i = 0; i < 3; ++i) k.o[i] = cd{p[(2 + 2 * i) * V2 + site], p[(3 + 2 * i) * V2 + site]};
+    return k;
+}
+
+// written once, read by the link sums of the next kernel: streamed past L2
+// (non-temporal), which keeps the links and insertions the neighbouring
+// plaquettes share in it
+__device__ __forceinline__ void store_tl(double *p, long V2, long site, const Sym3 &k)
+{
+    const double t3 = (k.d[0] + k.d[1] + k.d[2]) / 3.0;
+    __builtin_nontemporal_store(k.d[0] - t3, p + site);
+    __builtin_nontemporal_store(k.d[1] - t3, p + V2 + site);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        p[(3 + 2 * i) * V2 + site] = k.o[i].re;
-        p[(4 + 2 * i) * V2 + site] = k.o[i].im;
+        __builtin_nontemporal_store(k.o[i].re, p + (2 + 2 * i) * V2 + site);
+        __builtin_nontemporal_store(k.o[i].im, p + (3 + 2 * i) * V2 + site);
     }
 }
 
@@ -546,9 +564,9 @@ __device__ __forceinline__ void plaquette_loop(const CloverForceArgs &f, const i
     P = mm(b, P);  // b c+ d+
     add_to(t, hmul(load_sym(h, V2, site_of(f.g, xr)), P));
     const Mat3 a = link_c(f, x, R);
-    double *o = f.KA + (long)pl * 18 * V2;
-    store_sym(o, V2, site, herm_of_product(a, t));
-    store_sym(o + 9 * V2, V2, site, aherm_of_product(a, P));
+    double *o = f.KA + (long)pl * 16 * V2;
+    store_tl(o, V2, site, herm_of_product(a, t));
+    store_tl(o + 8 * V2, V2, site, aherm_of_product(a, P));
 }
 
 // One thread per (site, plane); workgroup 12 i + 6 p + plane takes sites
@@ -701,20 +719,20 @@ __device__ __forceinline__ void link_plane(const CloverForceArgs &f, const int y
     const double sg = below ? 1.0 : -1.0;
     const long V2 = 2L * f.g.Vh;
     const int pl = below ? plane_of(R, N) : plane_of(N, R);
-    const double *ka = f.KA + (long)pl * 18 * V2;
+    const double *ka = f.KA + (long)pl * 16 * V2;
     const double *h = f.H + (long)pl * 9 * V2;
     int ym[4];
     shift(f.g, y, N, -1, ym);
     const long sm = site_of(f.g, ym);
     const Mat3 u = link_c(f, ym, N);
-    const Sym3 a1 = load_sym(ka + 9 * V2, V2, sm);
+    const Sym3 a1 = load_tl(ka + 8 * V2, V2, sm);
     Sym3 b = conj_aherm(u, a1);
-    Sym3 g = load_sym(ka, V2, sm);
+    Sym3 g = load_tl(ka, V2, sm);
     if (below)
         axpy(g, -1.0, commute(a1, load_sym(h, V2, sm)));
     else
-        axpy(b, 1.0, load_sym(ka + 9 * V2, V2, site));
-    const Sym3 k0 = load_sym(ka, V2, site);
+        axpy(b, 1.0, load_tl(ka + 8 * V2, V2, site));
+    const Sym3 k0 = load_tl(ka, V2, site);
     const Sym3 hy = load_sym(h, V2, site);
     axpy(z, -sg, conj_herm(u, g));
     axpy(z, sg, k0);
