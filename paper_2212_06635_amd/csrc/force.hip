@@ -22,6 +22,31 @@ namespace tmx {
 
 using cd = cx<double>;
 
+// Order in which the force kernels visit blocks of B sites of one parity.
+// The site order runs x, y fastest, then the (z, t) planes, so a site's z
+// and t neighbours lie one or more whole planes away, and a kernel that
+// reads a few hundred bytes per site has evicted them from L2 by the time
+// the neighbour block reads them again.  Within each eighth of the planes
+// (the share of one XCD, with the XCD-contiguous workgroup order) the blocks
+// are visited chunk by chunk: the first CH sites (whole rows of x) of every
+// plane, then the next CH of every plane, so z and t neighbours are read a
+// few blocks apart in time (y neighbours across a chunk edge, and t
+// neighbours across an eighth, are not).  CH = max(B, 8 Lx/2); lattices
+// whose planes do not split that way keep the plain order.
+template <int B>
+__device__ __forceinline__ long order_block(const Geom &g, long ib)
+{
+    const int ps = g.Lxh * g.L[1];  // sites of one parity in an (x, y) plane
+    const int ch = B > 8 * g.Lxh ? B : 8 * g.Lxh;
+    const int np = g.Vh / ps;  // planes
+    if (ch % B != 0 || ps % ch != 0 || np % 8 != 0) return ib;
+    const long bpc = ch / B, cpp = ps / ch, G = np / 8;
+    const long gs = G * cpp * bpc;
+    const long grp = ib / gs, j = ib - grp * gs;
+    const long b = j % bpc, pl = (j / bpc) % G, c = j / (bpc * G);
+    return grp * gs + (pl * cpp + c) * bpc + b;
+}
+
 // (g_mu psi) in the chiral basis: upper = a_mu psi_lower, lower = a_mu^dagger
 // psi_upper, a_k = -i sigma_k, a_4 = 1 (the blocks of the stencil's spin
 // projection)
@@ -578,7 +603,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
     const long blk = xcd_block(f.xcd);
     const int pl = (int)(blk % 6);
     const int p = (int)((blk / 6) & 1);
-    const long s = (blk / 12) * blockDim.x + threadIdx.x;
+    const long s = order_block<256>(f.g, blk / 12) * 256 + threadIdx.x;
     if (s >= f.g.Vh) return;
     const long t = (long)p * f.g.Vh + s;
     int x[4];
@@ -594,62 +619,66 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
 }
 
 // ---- link sums --------------------------------------------------------------
-// u+ g u for Hermitian g (Hermitian result)
+// u+ g u for Hermitian g (Hermitian result), one column of g u at a time
+// (the products of a column feed the entries (i, j), i <= j, at once, so only
+// three complex values of g u are live)
 __device__ __forceinline__ Sym3 conj_herm(const Mat3 &u, const Sym3 &g)
 {
-    const Mat3 m = hmul(g, u);
     Sym3 r;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        double s = 0.0;
+    for (int j = 0; j < 3; ++j) {
+        cd m[3];  // column j of g u
 #pragma unroll
-        for (int k = 0; k < 3; ++k) s += u.m[3 * k + i].re * m.m[3 * k + i].re + u.m[3 * k + i].im * m.m[3 * k + i].im;
-        r.d[i] = s;
-    }
+        for (int i = 0; i < 3; ++i) {
+            cd s = g.d[i] * u.m[3 * i + j];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k)
+                if (k != i) cmac(s, herm_get(g, i, k), u.m[3 * k + j]);
+            m[i] = s;
+        }
+        double dj = 0.0;
 #pragma unroll
-        for (int j = i + 1; j < 3; ++j) {
+        for (int k = 0; k < 3; ++k) dj += u.m[3 * k + j].re * m[k].re + u.m[3 * k + j].im * m[k].im;
+        r.d[j] = dj;
+#pragma unroll
+        for (int i = 0; i < j; ++i) {
             cd s{0, 0};
 #pragma unroll
-            for (int k = 0; k < 3; ++k) cmac_conj(s, u.m[3 * k + i], m.m[3 * k + j]);
+            for (int k = 0; k < 3; ++k) cmac_conj(s, u.m[3 * k + i], m[k]);
             r.o[upper(i, j)] = s;
         }
+    }
     return r;
 }
 
-// u+ a u for anti-Hermitian a (anti-Hermitian result)
+// u+ a u for anti-Hermitian a (anti-Hermitian result), column by column
 __device__ __forceinline__ Sym3 conj_aherm(const Mat3 &u, const Sym3 &a)
 {
-    Mat3 m;  // a u
+    Sym3 r;
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+        cd m[3];  // column j of a u
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
+        for (int i = 0; i < 3; ++i) {
             const cd v = u.m[3 * i + j];
             cd s{-a.d[i] * v.im, a.d[i] * v.re};
 #pragma unroll
             for (int k = 0; k < 3; ++k)
                 if (k != i) cmac(s, aherm_get(a, i, k), u.m[3 * k + j]);
-            m.m[3 * i + j] = s;
+            m[i] = s;
         }
-    Sym3 r;
+        double dj = 0.0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        double s = 0.0;
+        for (int k = 0; k < 3; ++k) dj += u.m[3 * k + j].re * m[k].im - u.m[3 * k + j].im * m[k].re;
+        r.d[j] = dj;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) s += u.m[3 * k + i].re * m.m[3 * k + i].im - u.m[3 * k + i].im * m.m[3 * k + i].re;
-        r.d[i] = s;
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i + 1; j < 3; ++j) {
+        for (int i = 0; i < j; ++i) {
             cd s{0, 0};
 #pragma unroll
-            for (int k = 0; k < 3; ++k) cmac_conj(s, u.m[3 * k + i], m.m[3 * k + j]);
+            for (int k = 0; k < 3; ++k) cmac_conj(s, u.m[3 * k + i], m[k]);
             r.o[upper(i, j)] = s;
         }
+    }
     return r;
 }
 
@@ -789,7 +818,7 @@ __global__ void __launch_bounds__(256) clover_link_kernel(CloverForceArgs f)
     const long blk = xcd_block(f.xcd);
     const int p = (int)(blk & 1);
     const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    const long s = (blk >> 1) * 64 + (threadIdx.x & 63);
+    const long s = order_block<64>(f.g, blk >> 1) * 64 + (threadIdx.x & 63);
     if (s >= f.g.Vh) return;
     const long t = (long)p * f.g.Vh + s;
     int y[4];
