@@ -690,6 +690,17 @@ def main():
         "learned_pc_training_sym1": trained["sym1"][1],
         "tuned_launch": tuned,
     }
+    # the learned-preconditioner forms against plain FP64 CG (same source, same
+    # 1e-10 target; the last timed step)
+    forms = {"pcg_nn_f16": "P = K K^dagger", "pcg_nn_sym_f16": "P = L1^dagger L2^dagger L2 L1",
+             "pcg_nn_sym1_f16": "P = L1^dagger L1"}
+    t_cg = last["cg_f64"]["seconds"]
+    out["learned_pc_vs_plain_cg"] = {
+        "plain_cg_f64_seconds": round(t_cg, 4),
+        "forms": {k: {"preconditioner": v, "seconds": round(last[k]["seconds"], 4), "iters": last[k]["iters"],
+                      "speedup_vs_plain_cg": round(t_cg / last[k]["seconds"], 2)} for k, v in forms.items()},
+        "fastest": min(forms, key=lambda k: last[k]["seconds"]),
+    }
     # the rational approximation as a whole: R(N_h) b, then N_h R(N_h)^2 b = b
     log("rational approximation R(N_h) b (FP16 inner) and its accuracy")
     rb = torch.zeros_like(b2d)

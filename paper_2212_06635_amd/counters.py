@@ -168,7 +168,7 @@ def kernel_table(stats_csv: str, title: str, command: str) -> str:
     lines = [f"# {title}", f"# command: {command}", "",
              f"{'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'%':>6s}  kernel"]
     for name, calls, avg, tot, pct in rows:
-        short = name.split("(")[0].replace("void ", "")
+        short = name.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
         lines.append(f"{calls:6d} {avg / 1e3:10.1f} {tot / 1e6:10.2f} {pct:6.2f}  {short}")
     return "\n".join(lines) + "\n"
 

@@ -22,31 +22,6 @@ namespace tmx {
 
 using cd = cx<double>;
 
-// Order in which the force kernels visit blocks of B sites of one parity.
-// The site order runs x, y fastest, then the (z, t) planes, so a site's z
-// and t neighbours lie one or more whole planes away, and a kernel that
-// reads a few hundred bytes per site has evicted them from L2 by the time
-// the neighbour block reads them again.  Within each eighth of the planes
-// (the share of one XCD, with the XCD-contiguous workgroup order) the blocks
-// are visited chunk by chunk: the first CH sites (whole rows of x) of every
-// plane, then the next CH of every plane, so z and t neighbours are read a
-// few blocks apart in time (y neighbours across a chunk edge, and t
-// neighbours across an eighth, are not).  CH = max(B, 8 Lx/2); lattices
-// whose planes do not split that way keep the plain order.
-template <int B>
-__device__ __forceinline__ long order_block(const Geom &g, long ib)
-{
-    const int ps = g.Lxh * g.L[1];  // sites of one parity in an (x, y) plane
-    const int ch = B > 8 * g.Lxh ? B : 8 * g.Lxh;
-    const int np = g.Vh / ps;  // planes
-    if (ch % B != 0 || ps % ch != 0 || np % 8 != 0) return ib;
-    const long bpc = ch / B, cpp = ps / ch, G = np / 8;
-    const long gs = G * cpp * bpc;
-    const long grp = ib / gs, j = ib - grp * gs;
-    const long b = j % bpc, pl = (j / bpc) % G, c = j / (bpc * G);
-    return grp * gs + (pl * cpp + c) * bpc + b;
-}
-
 // (g_mu psi) in the chiral basis: upper = a_mu psi_lower, lower = a_mu^dagger
 // psi_upper, a_k = -i sigma_k, a_4 = 1 (the blocks of the stencil's spin
 // projection)
@@ -603,7 +578,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
     const long blk = xcd_block(f.xcd);
     const int pl = (int)(blk % 6);
     const int p = (int)((blk / 6) & 1);
-    const long s = order_block<256>(f.g, blk / 12) * 256 + threadIdx.x;
+    const long s = order_block(f.g, blk / 12, 256) * 256 + threadIdx.x;
     if (s >= f.g.Vh) return;
     const long t = (long)p * f.g.Vh + s;
     int x[4];
@@ -818,7 +793,7 @@ __global__ void __launch_bounds__(256) clover_link_kernel(CloverForceArgs f)
     const long blk = xcd_block(f.xcd);
     const int p = (int)(blk & 1);
     const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    const long s = order_block<64>(f.g, blk >> 1) * 64 + (threadIdx.x & 63);
+    const long s = order_block(f.g, blk >> 1, 64) * 64 + (threadIdx.x & 63);
     if (s >= f.g.Vh) return;
     const long t = (long)p * f.g.Vh + s;
     int y[4];
