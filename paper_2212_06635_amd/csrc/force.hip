@@ -375,7 +375,8 @@ __device__ __forceinline__ Mat3 dagm(const Mat3 &a)
 // Hermitian and anti-Hermitian matrices are held as nine reals: the diagonal
 // (real part of K, imaginary part of A), then the upper triangle (0,1), (0,2),
 // (1,2) as (re, im); K_ji = conj(K_ij), A_ji = -conj(A_ij).  In memory each
-// real is its own array of 2 Vh doubles.
+// real is its own array of 2 Vh doubles: all nine of an insertion, eight of
+// a traceless loop part (the third diagonal entry is minus the other two).
 struct Sym3 {
     double d[3];
     cd o[3];
