@@ -269,7 +269,9 @@ int tmx_hop_force(tmx_ctx *ctx, double *force, const double *x, const double *y,
  * matrices held fixed.  Same arguments, layout and accumulation as
  * tmx_hop_force; the full link derivative of S is the sum of the two.
  * TMX_EINVAL if the clover term was loaded with tmx_load_clover (the force
- * needs it built from the links).  Uses a 1728 Vh-byte workspace. */
+ * needs it built from the links).  Uses 2400 Vh bytes of workspace (the
+ * insertions, 864 Vh, and the plaquette loops, 1536 Vh) besides the two
+ * even-site fields it shares with tmx_hop_force. */
 int tmx_clover_force(tmx_ctx *ctx, double *force, const double *x, const double *y, int op, double coeff,
                      int accumulate);
 
