@@ -1580,6 +1580,7 @@ int fgcr_stage(tmx_ctx *c, int op, int dagger, SpinorPtr x, SpinorPtr b, double 
         int rc = blas(c, o, Vh, &bb, 1);
         if (rc) return rc;
     }
+    if (!std::isfinite(bb)) return set_err(c, TMX_EINVAL, "source with a non-finite entry");
     if (bb == 0) return TMX_OK;
     double rr;
     int rc = fg_true_residual(c, op, dagger, r, b, x, q, &rr, &info->gbytes);

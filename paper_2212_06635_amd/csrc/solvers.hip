@@ -216,6 +216,8 @@ static int cg_core(Sys &S, SpinorPtr x, SpinorPtr b, int cols, const double *sig
     double bb[MAXR], rho[MAXR], rho1[MAXR], rmax[MAXR];
     int active[MAXR], iters[MAXR], nrel[MAXR];
     TRY((copy_field<F64, F64>(S, r, b, cols, bb)));
+    for (int k = 0; k < cols; ++k)  // a NaN or infinite entry makes |b|^2 non-finite (x untouched)
+        if (!std::isfinite(bb[k])) return set_err(c, TMX_EINVAL, "source with a non-finite entry");
     if (!x_is_guess) TRY(zero_field<F64>(S, x, cols));
     // r = b - N x (also for x = 0, to start from an exact residual)
     TRY(true_residual<P>(S, r, rl, mixed, b, x, sigma, cols, rho));
@@ -415,6 +417,7 @@ static int pcg_nn_core(Sys &S, SpinorPtr x, SpinorPtr b, const double *sigma, co
     if (!alpha_d || (!shifted && !pnrm)) return set_err(c, TMX_ENOMEM, "solver workspace: out of device memory");
     double bb, rr, rmax, rho, dots[2];
     TRY((copy_field<F64, F64>(S, r, b, 1, &bb)));
+    if (!std::isfinite(bb)) return set_err(c, TMX_EINVAL, "source with a non-finite entry");
     if (!x_is_guess) TRY(zero_field<F64>(S, x, 1));
     if (bb == 0) {
         TRY(zero_field<F64>(S, x, 1));
@@ -551,6 +554,7 @@ static int mscg_core(Sys &S, std::vector<SpinorPtr> &xs, SpinorPtr b64, const do
     TRY(S.need());
     double bb;
     TRY((copy_field<P, F64>(S, r, b64, 1, &bb)));
+    if (!std::isfinite(bb)) return set_err(c, TMX_EINVAL, "source with a non-finite entry");
     for (int k = 0; k < ns; ++k) {
         TRY(zero_field<PX>(S, xs[k], 1));
         TRY((copy_field<P, P>(S, ps[k], r, 1, nullptr)));
@@ -665,6 +669,51 @@ static int check_cfg(tmx_ctx *c, const tmx_solver_cfg *cfg)
 
 int tmx_fgcr_solve_internal(tmx_ctx *c, SpinorPtr x, SpinorPtr b, const tmx_solver_cfg *cfg, tmx_info *info);
 
+// The entry points solve for b / |b| (per column) and scale the solution
+// back: the FP32 and FP16 fields of the mixed-precision solvers then hold the
+// same magnitudes whatever the source's scale (an FP16 solve of a source of
+// norm 1e-27 broke down once its residual passed the FP32 range).  Columns of
+// norm 0, or of a non-finite norm (rejected by the solver), keep scale 1.
+static int normalize_columns(Sys &S, SpinorPtr B, int cols, double *scale)
+{
+    tmx_ctx *c = S.c;
+    double nn[MAXR];
+    TRY((copy_field<F64, F64>(S, B, B, cols, nn)));  // |b|^2 per column
+    bool any = false;
+    for (int k = 0; k < cols; ++k) {
+        scale[k] = (nn[k] > 0 && std::isfinite(nn[k])) ? std::sqrt(nn[k]) : 1.0;
+        any = any || scale[k] != 1.0;
+    }
+    if (!any) return TMX_OK;
+    OpAxpby<F64, F64> o{};
+    o.y = B;
+    o.x = B;
+    o.nf = S.nf;
+    for (int k = 0; k < cols; ++k) {
+        o.a[k] = 0.0;
+        o.b[k] = 1.0 / scale[k];
+    }
+    return hip_err(c, run_blas(o, c->Vh * cols, cols, c->red, c->stream), "normalize source");
+}
+
+// X *= scale (per column), or X /= scale with inverse
+static int scale_columns(Sys &S, SpinorPtr X, int cols, const double *scale, bool inverse)
+{
+    tmx_ctx *c = S.c;
+    bool any = false;
+    OpAxpby<F64, F64> o{};
+    o.y = X;
+    o.x = X;
+    o.nf = S.nf;
+    for (int k = 0; k < cols; ++k) {
+        o.a[k] = 0.0;
+        o.b[k] = inverse ? 1.0 / scale[k] : scale[k];
+        any = any || scale[k] != 1.0;
+    }
+    if (!any) return TMX_OK;
+    return hip_err(c, run_blas(o, c->Vh * cols, cols, c->red, c->stream), "scale solution");
+}
+
 int tmx_solve(tmx_ctx *c, double *x, const double *b, int nrhs, const tmx_solver_cfg *cfg, tmx_info *info)
 {
     if (!c || !x || !b || nrhs < 1 || nrhs > MAXR) return c ? set_err(c, TMX_EINVAL, "tmx_solve: bad argument") : TMX_EINVAL;
@@ -679,6 +728,9 @@ int tmx_solve(tmx_ctx *c, double *x, const double *b, int nrhs, const tmx_solver
     if (!X.d || !B.d) return TMX_ENOMEM;
     HTRY(launch_pack_spinor(b, B, F64, kind, c->g, nrhs, c->stream), "pack b");
     if (cfg->use_initial_guess) HTRY(launch_pack_spinor(x, X, F64, kind, c->g, nrhs, c->stream), "pack x");
+    double bscale[MAXR];
+    TRY(normalize_columns(S, B, nrhs, bscale));
+    if (cfg->use_initial_guess) TRY(scale_columns(S, X, nrhs, bscale, true));
     int rc;
     switch (cfg->kind) {
     case TMX_SOLVER_CG:
@@ -718,6 +770,7 @@ int tmx_solve(tmx_ctx *c, double *x, const double *b, int nrhs, const tmx_solver
         return set_err(c, TMX_EINVAL, "unknown solver kind");
     }
     if (rc < 0) return rc;
+    TRY(scale_columns(S, X, nrhs, bscale, false));
     HTRY(launch_unpack_spinor(x, X, F64, kind, c->g, nrhs, c->stream), "unpack x");
     HTRY(hipStreamSynchronize(c->stream), "solve sync");
     if (info)
@@ -833,7 +886,11 @@ int tmx_multishift_solve(tmx_ctx *c, double *x, const double *b, const double *s
     SpinorPtr B = S.field("msb", F64, 1);
     TRY(S.need());
     HTRY(launch_pack_spinor(b, B, F64, kind, c->g, 1, c->stream), "pack b");
+    double bscale;
+    TRY(normalize_columns(S, B, 1, &bscale));
     const int rc = multishift_run(c, S, B, shifts, nshift, cfg, info, [&](int k, SpinorPtr X) {
+        const int r = scale_columns(S, X, 1, &bscale, false);
+        if (r) return r;
         return hip_err(c, launch_unpack_spinor(x + (size_t)k * c->Vh * 24 * S.nf, X, F64, kind, c->g, 1, c->stream),
                        "unpack x_k");
     });

@@ -108,6 +108,42 @@ def test_maxiter_reports_noconv(S):
     assert info[0]["true_residual"] > 1e-10
 
 
+@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("scale", [1e-30, 1e30])
+def test_scaled_source(S, kind, scale):
+    """A source scaled by 1e-30 or 1e+30 (FP32 / FP16 fields hold it through
+    their per-site scales, the reductions run in FP64): every kind reaches the
+    1e-10 FP64 true residual relative to |b|."""
+    tmx, o, ctx, _ = S
+    b = synth.gaussian_cb_spinor(DIMS, 28, 0, 1) * scale
+    x = to_dev(np.zeros_like(b))
+    rc, info = ctx.solve(x, to_dev(b), 1, kind=kind, op=1, tol=1e-10)
+    print(f"[gpu solvers] scaled source {scale:g} kind {kind}: {info[0]['iters']} iters", flush=True)
+    assert rc == tmx.TMX_OK, info
+    assert o.residual(b, to_host(x, b.shape)) <= 1e-10
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+@pytest.mark.parametrize("kind", [0, 1, 2, "ms"])
+def test_non_finite_source_rejected(S, kind, bad):
+    """A NaN or infinite source entry is an argument error (TMX_EINVAL), not a
+    converged zero solution, and the solution buffer is left as it was."""
+    tmx, o, ctx, _ = S
+    nf = 2 if kind == "ms" else 1
+    b = synth.gaussian_cb_spinor(DIMS, 29, 0, nf)
+    b.reshape(-1)[17] = bad
+    if kind == "ms":
+        x = to_dev(np.full((3,) + b.shape, 7.0 + 0j))
+        with pytest.raises(tmx.TmxError) as e:
+            ctx.multishift_solve(x, to_dev(b), [0.01, 0.02, 0.04], op=2, tol=1e-10)
+    else:
+        x = to_dev(np.full(b.shape, 7.0 + 0j))
+        with pytest.raises(tmx.TmxError) as e:
+            ctx.solve(x, to_dev(b), 1, kind=kind, op=1, tol=1e-10)
+    assert e.value.code == tmx.TMX_EINVAL
+    assert np.all(to_host(x, x.shape) == 7.0)
+
+
 def test_gauge_id_state_tracking(S):
     """Same gauge id: no upload; new id: upload and the operator follows the new field."""
     tmx, o, ctx, U = S
