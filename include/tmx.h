@@ -283,9 +283,12 @@ int tmx_clover_force(tmx_ctx *ctx, double *force, const double *x, const double 
  * CG, or the mixed-precision CG with FP64 reliable updates of Sections 1 and
  * 4.1, or the solves preconditioned by the learned network (standing in for
  * the multigrid preconditioner of Section 4.1).  info is an array of nrhs
- * entries (may be NULL).  Returns TMX_ENOCONV if any column missed cfg->tol
- * (x then holds the best iterate), TMX_ENOMEM if a workspace could not be
- * allocated (nothing launched). */
+ * entries (may be NULL).  Each column is solved for b / |b| and the
+ * solution scaled back, so any source scale works in every precision.
+ * Returns TMX_ENOCONV if any column missed cfg->tol (x then holds the best
+ * iterate), TMX_ENOMEM if a workspace could not be allocated (nothing
+ * launched), TMX_EINVAL for a source with a NaN or infinite entry (x left as
+ * it was). */
 int tmx_solve(tmx_ctx *ctx, double *x, const double *b, int nrhs, const tmx_solver_cfg *cfg, tmx_info *info);
 /* Solve Mhat x = b (dagger = 0) or Mhat^dagger x = b (dagger = 1), the two
  * inversions of the fermion derivative (Section 4.1), through the normal
@@ -303,7 +306,9 @@ int tmx_solve_mhat(tmx_ctx *ctx, double *x, const double *b, int dagger, const t
  * shift's refinement is the CG preconditioned by the learned network (set by
  * tmx_pc_set_weights or tmx_pc_train; degenerate op only, TMX_EINVAL
  * otherwise), falling back to mixed-precision CG if it stalls (info fallback
- * = 1); info restarts then counts the network applications. */
+ * = 1); info restarts then counts the network applications.  The source is
+ * normalized and the solutions scaled back as in tmx_solve; TMX_EINVAL for a
+ * non-finite source. */
 int tmx_multishift_solve(tmx_ctx *ctx, double *x, const double *b, const double *shifts, int nshift,
                          const tmx_solver_cfg *cfg, tmx_info *info);
 /* Rational function of the normal operator, the partial-fraction form of the
