@@ -180,7 +180,7 @@ static int ensure_links(tmx_ctx *c, int prec)
     if (c->links_ok[prec]) return TMX_OK;
     if (!c->links[prec]) {
         c->links[prec] = dev_alloc(c, link_bytes(prec, c->Vh));
-        if (!c->links[prec]) return TMX_ENOMEM;
+        if (!c->links[prec]) return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
     }
     int r = hip_err(c, launch_convert_links((const double *)c->links[F64], c->links[prec], prec, c->g, c->stream),
                     "convert links");
@@ -196,7 +196,7 @@ static int ensure_clover(tmx_ctx *c, int prec)
     if (!c->clov_ok[F64]) {
         if (!c->clov[F64]) {
             c->clov[F64] = dev_alloc(c, clover_bytes(F64, c->Vh));
-            if (!c->clov[F64]) return TMX_ENOMEM;
+            if (!c->clov[F64]) return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
         }
         int r = hip_err(c, launch_clover_build((const double *)c->links[F64], (double *)c->clov[F64], c->g,
                                                c->par.kappa, c->par.csw, c->stream),
@@ -212,7 +212,7 @@ static int ensure_clover(tmx_ctx *c, int prec)
     if (prec != F64 && !c->clov_ok[prec]) {
         if (!c->clov[prec]) {
             c->clov[prec] = dev_alloc(c, clover_bytes(prec, c->Vh));
-            if (!c->clov[prec]) return TMX_ENOMEM;
+            if (!c->clov[prec]) return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
         }
         int r = hip_err(c, launch_convert_seq((const double *)c->clov[F64], c->clov[prec], prec, 144, c->Vh, c->stream),
                         "convert clover");
@@ -231,7 +231,7 @@ static int ensure_inv(tmx_ctx *c, int prec)
     if (!c->inv_ok[F64]) {
         if (!c->inv[F64]) {
             c->inv[F64] = dev_alloc(c, inv_bytes(F64, c->Vh));
-            if (!c->inv[F64]) return TMX_ENOMEM;
+            if (!c->inv[F64]) return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
         }
         r = hip_err(c, launch_clover_inv((const double *)c->clov[F64], (double *)c->inv[F64], c->g, nu, c->stream),
                     "clover inverse");
@@ -243,7 +243,7 @@ static int ensure_inv(tmx_ctx *c, int prec)
     if (prec != F64 && !c->inv_ok[prec]) {
         if (!c->inv[prec]) {
             c->inv[prec] = dev_alloc(c, inv_bytes(prec, c->Vh));
-            if (!c->inv[prec]) return TMX_ENOMEM;
+            if (!c->inv[prec]) return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
         }
         r = hip_err(c, launch_convert_seq((const double *)c->inv[F64], c->inv[prec], prec, 144, c->Vh, c->stream),
                     "convert inverse");
@@ -263,7 +263,7 @@ static int ensure_invnd(tmx_ctx *c, int prec)
     if (!c->invnd_ok[F64]) {
         if (!c->invnd[F64]) {
             c->invnd[F64] = dev_alloc(c, invnd_bytes(F64, c->Vh));
-            if (!c->invnd[F64]) return TMX_ENOMEM;
+            if (!c->invnd[F64]) return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
         }
         r = hip_err(c, launch_clover_inv_nd((const double *)c->clov[F64], (double *)c->invnd[F64], c->g, nb, ep,
                                             c->stream),
@@ -276,7 +276,7 @@ static int ensure_invnd(tmx_ctx *c, int prec)
     if (prec != F64 && !c->invnd_ok[prec]) {
         if (!c->invnd[prec]) {
             c->invnd[prec] = dev_alloc(c, invnd_bytes(prec, c->Vh));
-            if (!c->invnd[prec]) return TMX_ENOMEM;
+            if (!c->invnd[prec]) return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
         }
         r = hip_err(c, launch_convert_seq((const double *)c->invnd[F64], c->invnd[prec], prec, 72, c->Vh, c->stream),
                     "convert nd inverse");
@@ -470,7 +470,7 @@ int op_mhat(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int dagge
     const int nf = nd ? 2 : 1;
     const long stride = c->Vh * nrhs;
     void *ud = ws_get(c, "op_u" + std::to_string(prec), spinor_field_bytes(prec, nf, stride));
-    if (!ud) return TMX_ENOMEM;
+    if (!ud) return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
     return mhat_with(c, out, in, make_spinor(ud, prec, nf, stride), op, prec, dagger, nrhs);
 }
 
@@ -485,7 +485,7 @@ int op_mdagm(tmx_ctx *c, SpinorPtr out, SpinorPtr in, int op, int prec, int nrhs
     const long stride = c->Vh * nrhs;
     void *ud = ws_get(c, "op_u" + std::to_string(prec), spinor_field_bytes(prec, nf, stride));
     void *vd = ws_get(c, "op_v" + std::to_string(prec), spinor_field_bytes(prec, nf, stride));
-    if (!ud || !vd) return TMX_ENOMEM;
+    if (!ud || !vd) return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
     SpinorPtr u = make_spinor(ud, prec, nf, stride), v = make_spinor(vd, prec, nf, stride);
     const int sgn = op_sign(op);
     // v = g5 Mhat(sgn) in ; out = g5 Mhat(-sgn) v = N in (g5 Mhat(-sgn) g5 is the
@@ -752,7 +752,7 @@ int tmx_set_allocator(tmx_ctx *c, void *(*alloc)(size_t, void *), void (*release
     double *nr = np ? static_cast<double *>(dev_alloc(c, red_result_bytes())) : nullptr;
     if (!np || !nr) {
         dev_free(c, np);
-        return TMX_ENOMEM;
+        return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
     }
     dev_free(c, c->red.partials);
     dev_free(c, c->red.result);
@@ -785,12 +785,12 @@ int tmx_load_gauge(tmx_ctx *c, const double *host_links, double gauge_id)
     if (c->gauge_loaded && gauge_id == c->gauge_id) return TMX_OK;
     const size_t bytes = (size_t)c->V * 4 * 9 * 16;
     void *stage = dev_alloc(c, bytes);
-    if (!stage) return TMX_ENOMEM;
+    if (!stage) return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
     if (!c->links[F64]) {
         c->links[F64] = dev_alloc(c, link_bytes(F64, c->Vh));
         if (!c->links[F64]) {
             dev_free(c, stage);
-            return TMX_ENOMEM;
+            return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
         }
     }
     hipError_t e = hipMemcpyAsync(stage, host_links, bytes, hipMemcpyHostToDevice, c->stream);
@@ -840,12 +840,12 @@ int tmx_load_clover(tmx_ctx *c, const double *host_T)
     }
     const size_t bytes = (size_t)c->V * 144 * 8;
     void *stage = dev_alloc(c, bytes);
-    if (!stage) return TMX_ENOMEM;
+    if (!stage) return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
     if (!c->clov[F64]) {
         c->clov[F64] = dev_alloc(c, clover_bytes(F64, c->Vh));
         if (!c->clov[F64]) {
             dev_free(c, stage);
-            return TMX_ENOMEM;
+            return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
         }
     }
     hipError_t e = hipMemcpyAsync(stage, host_T, bytes, hipMemcpyHostToDevice, c->stream);
@@ -867,7 +867,7 @@ int tmx_get_clover(tmx_ctx *c, double *host_T)
     if (r) return r;
     const size_t bytes = (size_t)c->V * 144 * 8;
     void *stage = dev_alloc(c, bytes);
-    if (!stage) return TMX_ENOMEM;
+    if (!stage) return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
     hipError_t e = launch_clover_to_canonical((const double *)c->clov[F64], (double *)stage, c->g, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(host_T, stage, bytes, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1141,7 +1141,7 @@ int tmx_tune(tmx_ctx *c, int prec, int op, int nrhs)
     const long stride = c->Vh * nrhs;
     const size_t fb = spinor_field_bytes(prec, nf, stride);
     void *pin = ws_get(c, "tune_in", fb), *pu = ws_get(c, "tune_u", fb), *pout = ws_get(c, "tune_out", fb);
-    if (!pin || !pu || !pout) return TMX_ENOMEM;
+    if (!pin || !pu || !pout) return set_err(c, TMX_ENOMEM, "device buffer: out of device memory");
     r = hip_err(c, hipMemsetAsync(pin, 0, fb, c->stream), "tune fill");
     if (r) return r;
     SpinorPtr in = make_spinor(pin, prec, nf, stride), u = make_spinor(pu, prec, nf, stride),

@@ -1400,13 +1400,13 @@ int nn_forward_sym(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, int depth, st
     Act a0{};
     if (keep) {
         a0 = act(c, "a0", 1);
-        if (!a0.d) return TMX_ENOMEM;
+        if (!a0.d) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
         int rc = embed(c, r, pr, a0);
         if (rc) return rc;
         acts->push_back(a0);
     }
     Act a1 = act(c, keep ? "a1" : "p1", 8);
-    if (!a1.d) return TMX_ENOMEM;
+    if (!a1.d) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
     // P_1 without kept activations: the two path-channel halves (no 8-channel
     // intermediate on odd sites, one channel per path in the second half)
     if (depth == 1 && !keep) {
@@ -1418,7 +1418,7 @@ int nn_forward_sym(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, int depth, st
     if (keep) acts->push_back(a1);
     if (depth == 1) return launch_down(c, a1, out, thin + THIN_DOWN_A);  // L_1^dagger
     Act a2 = act(c, keep ? "a2" : "p2", 8), a3 = act(c, keep ? "a3" : "p3", 8);
-    if (!a2.d || !a3.d) return TMX_ENOMEM;
+    if (!a2.d || !a3.d) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
     rc = launch_layer(c, 8, 8, a1, a2, SpinorPtr{}, c->pc->Wf[1]);  // L_2
     if (!rc) rc = launch_layer(c, 8, 8, a2, a3, SpinorPtr{}, c->pc->Wa[1]);  // L_2^dagger
     if (rc) return rc;
@@ -1447,7 +1447,7 @@ int nn_forward(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, int dagger, std::
     if (keep) {
         // the embedded source is the first layer's input of the weight gradient
         a = act(c, "a0", 1);
-        if (!a.d) return TMX_ENOMEM;
+        if (!a.d) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
         rc = embed(c, r, pr, a);
         if (rc) return rc;
     }
@@ -1459,7 +1459,7 @@ int nn_forward(tmx_ctx *c, SpinorPtr out, SpinorPtr r, int pr, int dagger, std::
         if (acts) acts->push_back(a);
         if (cout == 1) return launch_down(c, a, out, thin + (dagger ? THIN_DOWN_A : THIN_DOWN_F));
         Act b = act(c, (keep ? "a" : "p") + std::to_string(i + 1), cout);
-        if (!b.d) return TMX_ENOMEM;
+        if (!b.d) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
         rc = cin == 1 ? launch_up(c, r, pr, b, thin + (dagger ? THIN_UP_A : THIN_UP_F))
                       : launch_layer(c, cin, cout, a, b, SpinorPtr{}, W);
         if (rc) return rc;
@@ -1477,7 +1477,7 @@ int pc_apply_internal(tmx_ctx *c, SpinorPtr z, int pz, SpinorPtr r, int pr, int 
     if (pz != F32 && pz != F64) return set_err(c, TMX_EINVAL, "preconditioner output precision");
     if (pz == F32) return nn_forward(c, z, r, pr, dagger, nullptr);
     void *po = ws_get(c, "nn_pout", spinor_field_bytes(F32, 1, c->Vh));
-    if (!po) return TMX_ENOMEM;
+    if (!po) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
     SpinorPtr o = make_spinor(po, F32, 1, c->Vh);
     int rc = nn_forward(c, o, r, pr, dagger, nullptr);
     if (rc) return rc;
@@ -1822,7 +1822,7 @@ int tmx_pc_apply(tmx_ctx *c, double *out, const double *in, int dagger)
     const long Vh = c->Vh;
     void *pi = ws_get(c, "pca_in", spinor_field_bytes(F32, 1, Vh));
     void *po = ws_get(c, "pca_out", spinor_field_bytes(F32, 1, Vh));
-    if (!pi || !po) return TMX_ENOMEM;
+    if (!pi || !po) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
     SpinorPtr I = make_spinor(pi, F32, 1, Vh), O = make_spinor(po, F32, 1, Vh);
     int r = hip_err(c, launch_pack_spinor(in, I, F32, TMX_FIELD_ODD, c->g, 1, c->stream), "pack");
     if (r) return r;
@@ -1845,12 +1845,12 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
     for (int l = 0; l < NN_L; ++l) {
         const size_t np = (size_t)WG_BLOCKS * NN_P * pad16(8 * NN_COUT[l]) * pad16(8 * NN_CIN[l]);
         partial[l] = static_cast<float *>(ws_get(c, "nn_partial" + std::to_string(l), np * sizeof(float)));
-        if (!partial[l]) return TMX_ENOMEM;
+        if (!partial[l]) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
         hipLaunchKernelGGL(nn_zero_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, c->stream, partial[l], np);
     }
     void *pb = ws_get(c, "tr_b", spinor_field_bytes(F32, 1, Vh));
     void *px = ws_get(c, "tr_x", spinor_field_bytes(F32, 1, Vh));
-    if (!pb || !px) return TMX_ENOMEM;
+    if (!pb || !px) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
     SpinorPtr B = make_spinor(pb, F32, 1, Vh), X = make_spinor(px, F32, 1, Vh);
     double L = 0;
     for (int i = 0; i < n; ++i) {
@@ -1871,7 +1871,7 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
         std::vector<Act> acts;
         void *pz = ws_get(c, "tr_z", spinor_field_bytes(F32, 1, Vh));
         void *pd = ws_get(c, "tr_dl", spinor_field_bytes(F32, 1, Vh));
-        if (!pz || !pd) return TMX_ENOMEM;
+        if (!pz || !pd) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
         const SpinorPtr Z = make_spinor(pz, F32, 1, Vh), DL = make_spinor(pd, F32, 1, Vh);
         const bool sym = loss_kind == TMX_LOSS_SYM || loss_kind == TMX_LOSS_SYM1;
         r = nn_forward(c, Z, B, F32, loss_kind == TMX_LOSS_SYM ? 2 : (sym ? 3 : 0), &acts);
@@ -1895,7 +1895,7 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
             // e = K b - x ; q = Mhat e ; loss |q|^2/|b|^2 ; DL = Mhat^dagger q / (|b|^2 n)
             void *pe = ws_get(c, "tr_e", spinor_field_bytes(F32, 1, Vh));
             void *pq = ws_get(c, "tr_q", spinor_field_bytes(F32, 1, Vh));
-            if (!pe || !pq) return TMX_ENOMEM;
+            if (!pe || !pq) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
             SpinorPtr E = make_spinor(pe, F32, 1, Vh), Q = make_spinor(pq, F32, 1, Vh);
             OpPairResidual<F32> pr{};
             pr.out = Z;
@@ -1925,13 +1925,13 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
             L += qq / xx / n;
         }
         Act delta = act(c, "d4", 1);
-        if (!delta.d) return TMX_ENOMEM;
+        if (!delta.d) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
         r = embed(c, DL, F32, delta);
         if (r) return r;
         if (loss_kind == TMX_LOSS_SYM1) {
             // P_1 = L_1^dagger L_1, inputs a0, a1 (layer gradients as below)
             Act d1 = act(c, "d1", 8);
-            if (!d1.d) return TMX_ENOMEM;
+            if (!d1.d) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
             r = launch_wgrad(c, 1, 8, delta, acts[1], partial[0]);                     // L_1^dagger
             if (!r) r = launch_layer(c, 1, 8, delta, d1, SpinorPtr{}, s.Wf[0]);
             if (!r) r = launch_wgrad(c, 1, 8, acts[0], d1, partial[0]);                // L_1
@@ -1943,7 +1943,7 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
             // its adjoint (input x, output adjoint d) takes the gradient of its
             // forward use on d with output adjoint x.
             Act d3 = act(c, "d3", 8), d2 = act(c, "d2", 8), d1 = act(c, "d1", 8);
-            if (!d3.d || !d2.d || !d1.d) return TMX_ENOMEM;
+            if (!d3.d || !d2.d || !d1.d) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
             r = launch_wgrad(c, 1, 8, delta, acts[3], partial[0]);                     // L_1^dagger
             if (!r) r = launch_layer(c, 1, 8, delta, d3, SpinorPtr{}, s.Wf[0]);
             if (!r) r = launch_wgrad(c, 8, 8, d3, acts[2], partial[1]);                // L_2^dagger
@@ -1960,7 +1960,7 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
             if (r) return r;
             if (l > 0) {
                 Act nd = act(c, "d" + std::to_string(l), NN_CIN[l]);
-                if (!nd.d) return TMX_ENOMEM;
+                if (!nd.d) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
                 r = launch_layer(c, NN_COUT[l], NN_CIN[l], delta, nd, SpinorPtr{}, s.Wa[l]);
                 if (r) return r;
                 delta = nd;
@@ -1972,7 +1972,7 @@ static int pc_loss_grad(tmx_ctx *c, const double *b, const double *x, const int 
         const int nthr = NN_P * per;
         const int np = NN_P * pad16(8 * NN_COUT[l]) * pad16(8 * NN_CIN[l]);
         float *P = static_cast<float *>(ws_get(c, "nn_P" + std::to_string(l), (size_t)np * sizeof(float)));
-        if (!P) return TMX_ENOMEM;
+        if (!P) return set_err(c, TMX_ENOMEM, "network workspace: out of device memory");
         hipLaunchKernelGGL(nn_reduce_partials_kernel, dim3((np + 255) / 256), dim3(256), 0, c->stream, partial[l],
                            WG_BLOCKS, np, P);
         hipLaunchKernelGGL(nn_grad_combine_kernel, dim3((nthr + 127) / 128), dim3(128), 0, c->stream, P, 1,

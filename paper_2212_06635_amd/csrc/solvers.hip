@@ -725,7 +725,7 @@ int tmx_solve(tmx_ctx *c, double *x, const double *b, int nrhs, const tmx_solver
     TRY(ensure_ready(c, F64, cfg->op == TMX_OP_ND));
     SpinorPtr X = S.field("x", F64), B = S.field("b", F64);
     TRY(S.need());
-    if (!X.d || !B.d) return TMX_ENOMEM;
+    if (!X.d || !B.d) return set_err(c, TMX_ENOMEM, "solver fields: out of device memory");
     HTRY(launch_pack_spinor(b, B, F64, kind, c->g, nrhs, c->stream), "pack b");
     if (cfg->use_initial_guess) HTRY(launch_pack_spinor(x, X, F64, kind, c->g, nrhs, c->stream), "pack x");
     double bscale[MAXR];
@@ -1069,7 +1069,7 @@ int tmx_solve_mhat(tmx_ctx *c, double *x, const double *b, int dagger, const tmx
     TRY(S.need());
     const size_t cbytes = (size_t)c->Vh * 24 * nf * sizeof(double);
     void *canon = ws_get(c, "mh_canon", cbytes);
-    if (!canon) return TMX_ENOMEM;
+    if (!canon) return set_err(c, TMX_ENOMEM, "solver fields: out of device memory");
     HTRY(launch_pack_spinor(b, B, F64, kind, c->g, 1, c->stream), "pack b");
     if (!dagger) {
         TRY(op_mhat(c, T, B, cfg->op, F64, 1, 1));  // T = Mhat^dagger b
