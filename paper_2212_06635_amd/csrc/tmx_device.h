@@ -177,7 +177,7 @@ __device__ __forceinline__ int xcd_block(int xcd)
 // time (y neighbours across a chunk edge, and t neighbours across an eighth,
 // are not).  CH = max(B, 8 Lx/2); lattices whose planes do not split that
 // way keep the plain order.  A permutation of the blocks in every case.
-__device__ __forceinline__ long order_block(const Geom &g, long ib, int B)
+__host__ __device__ __forceinline__ long order_block(const Geom &g, long ib, int B)
 {
     const int ps = g.Lxh * g.L[1];  // sites of one parity in an (x, y) plane
     const int ch = B > 8 * g.Lxh ? B : 8 * g.Lxh;
