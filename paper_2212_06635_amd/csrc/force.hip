@@ -570,10 +570,11 @@ __device__ __forceinline__ void plaquette_loop(const CloverForceArgs &f, const i
     store_tl(o + 8 * V2, V2, site, aherm_of_product(a, P));
 }
 
-// One thread per (site, plane); workgroup 12 i + 6 p + plane takes sites
-// 256 i ... of parity p, so the six planes and both parities of a site block
-// are neighbouring workgroups (with the XCD remap, on one XCD) and read its
-// links and insertions through one L2.
+// One thread per (site, plane); workgroup 12 i + 6 p + plane takes the i-th
+// 256-site block of parity p in the chunked block order (order_block), so the
+// six planes and both parities of a site block are neighbouring workgroups
+// (with the XCD remap, on one XCD) and read its links and insertions through
+// one L2.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) clover_loop_kernel(CloverForceArgs f)
 {
     const long blk = xcd_block(f.xcd);
@@ -786,9 +787,10 @@ __device__ __forceinline__ void link_sum(const CloverForceArgs &f, const int y[4
     for (int k = 0; k < 9; ++k) o[k] = v[k];
 }
 
-// One thread per link: a workgroup holds 64 sites of one parity, one wave
-// per direction, so that the two waves of a plane read its data at y through
-// one L1; workgroups alternate between the parities.
+// One thread per link: a workgroup holds 64 sites of one parity (the
+// blocks in the chunked block order), one wave per direction, so that the two
+// waves of a plane read its data at y through one L1; workgroups alternate
+// between the parities.
 __global__ void __launch_bounds__(256) clover_link_kernel(CloverForceArgs f)
 {
     const long blk = xcd_block(f.xcd);
