@@ -17,6 +17,7 @@
 #include "tmx_device.h"
 #include "tmx_kernels.h"
 #include "force.h"
+#include "block_order.h"
 
 namespace tmx {
 

@@ -1,5 +1,5 @@
 """Host check of the block order the clover-force kernels visit sites in
-(order_block in csrc/tmx_device.h): a permutation of the site blocks for every
+(order_block in csrc/block_order.h): a permutation of the site blocks for every
 lattice, the plain order where the (x, y) planes do not split into chunks.
 The header's host/device function is compiled for the host only and run on
 the CPU; a wrong permutation would drop or repeat sites of the force."""
@@ -15,7 +15,7 @@ INC = os.path.join(HERE, "..", "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SRC = r"""
-#include "tmx_device.h"
+#include "block_order.h"
 #include <cstdio>
 #include <vector>
 int main()
