@@ -111,9 +111,9 @@ def test_maxiter_reports_noconv(S):
 @pytest.mark.parametrize("kind", [0, 1, 2])
 @pytest.mark.parametrize("scale", [1e-30, 1e30])
 def test_scaled_source(S, kind, scale):
-    """A source scaled by 1e-30 or 1e+30 (FP32 / FP16 fields hold it through
-    their per-site scales, the reductions run in FP64): every kind reaches the
-    1e-10 FP64 true residual relative to |b|."""
+    """A source scaled by 1e-30 or 1e+30 (the library solves for b / |b| and
+    scales the solution back, so the FP32 / FP16 fields never see the scale):
+    every kind reaches the 1e-10 FP64 true residual relative to |b|."""
     tmx, o, ctx, _ = S
     b = synth.gaussian_cb_spinor(DIMS, 28, 0, 1) * scale
     x = to_dev(np.zeros_like(b))
